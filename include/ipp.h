@@ -1,0 +1,244 @@
+/*
+ * ipp.h -- C ABI of the astronomical image pre-processing hot path on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the steps of the GPU pre-processing framework of
+ * arXiv 2502.10783 (Cao, Jia et al., "Image Pre-Processing Framework for
+ * Time-Domain Astronomy in the Artificial Intelligence Era"):
+ *
+ *   ipp_background   Sec. 2.2.2 -- mesh of sigma-clipped region statistics
+ *                    (Eq. 1-4), median filter, spline interpolation.
+ *   ipp_detect       Sec. 2.2.5 -- background removal, threshold detection,
+ *                    connection of pixels into candidates, pre-analysis
+ *                    (peak value, total flux, barycentre).
+ *   ipp_photometry   Sec. 2.2.5 -- per-object circular aperture photometry.
+ *   ipp_process_batch Sec. 2.1 pipeline mode -- all of the above for a batch
+ *                    of frames with one fixed parameter set.
+ *   ipp_photometry_backward, ipp_asinh, ipp_asinh_backward -- gradients of the
+ *                    photometry and a gray-scale stretch (Sec. 2.2.6) so the
+ *                    pre-processing can sit inside a training graph.
+ *
+ * Conventions (all calls):
+ *  - Image, map, mesh and table arrays are DEVICE pointers owned by the
+ *    caller.  Descriptor arrays (ipp_frame[], ipp_maps[], ipp_mesh[]) and
+ *    ipp_params are HOST memory read during the call only.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*, NULL = the null stream).  Results are valid once the stream has
+ *    reached the point of the call.  Calls on one context must not overlap
+ *    (one stream per context): they share the context's workspace.
+ *  - Every argument is validated on the host before anything is enqueued.
+ *    A failed check returns IPP_E_INVALID_ARG (or IPP_E_UNSUPPORTED /
+ *    IPP_E_WORKSPACE) and enqueues nothing; ipp_last_error() describes it.
+ *    No call aborts the process or lets an exception cross the ABI.
+ *  - Pixel (x, y) is column x, row y of a row-major frame; its centre is at
+ *    (x, y) and it covers [x-1/2, x+1/2] x [y-1/2, y+1/2].
+ *  - Problems in the data (NaN pixels, no valid mesh node, apertures off the
+ *    frame) do not fail a call; they set flags (IPP_FRAME_*, IPP_SRC_*).
+ */
+#ifndef IPP_H
+#define IPP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IPP_API_VERSION 1
+
+typedef enum ipp_status {
+  IPP_OK = 0,
+  IPP_E_INVALID_ARG = -1,   /* bad pointer, size or parameter            */
+  IPP_E_UNSUPPORTED = -2,   /* valid but not implemented (e.g. mesh < 16) */
+  IPP_E_CAPACITY = -3,      /* a caller-sized output is too small         */
+  IPP_E_DEVICE = -4,        /* a HIP runtime call failed                  */
+  IPP_E_WORKSPACE = -5      /* context workspace too small: reserve more  */
+} ipp_status;
+
+/* Background estimators, Sec. 2.2.2 Eq. 1-4. */
+enum {
+  IPP_EST_SEXTRACTOR = 0,   /* Eq. 3: 2.5*median - 1.5*mean (default)     */
+  IPP_EST_MEDIAN = 1,       /* Eq. 1                                      */
+  IPP_EST_MEAN = 2,         /* Eq. 2                                      */
+  IPP_EST_MODE = 3          /* Eq. 4, read as median_factor*median
+                               - mean_factor*mean                          */
+};
+
+/* ipp_params.flags */
+#define IPP_F_WRITE_RMS 1u  /* ipp_process_batch also writes the rms maps  */
+
+/* Per-frame flags (uint32 per frame). */
+#define IPP_FRAME_NO_VALID_MESH 1u  /* no node had min_valid pixels: every
+                                       node with >= 1 pixel was used        */
+#define IPP_FRAME_EMPTY_MESH 2u     /* no node had any usable pixel: the
+                                       background and rms are 0             */
+
+/* Per-source flags (uint32 per table row). */
+#define IPP_SRC_APERTURE_OFF_EDGE 1u  /* an aperture pixel is off the frame
+                                         or not finite                      */
+#define IPP_SRC_ANNULUS_OFF_EDGE 2u   /* same for the sky annulus           */
+#define IPP_SRC_NO_SKY 4u             /* no annulus pixel: sky taken as 0   */
+#define IPP_SRC_INEXACT_SUM_RANGE 8u  /* a pixel of the candidate lies
+                                         outside the exact-sum range        */
+#define IPP_SRC_NONPOSITIVE_FLUX 16u  /* isophotal flux <= 0: unweighted
+                                         centroid                           */
+
+/*
+ * Method parameters.  Defaults (ipp_params_default) are the settings of
+ * Sec. 2.2.2 and 2.2.5: 64x64 regions, 3x3 median filter, 3 clip passes at
+ * 3 sigma, at least 100 pixels per valid region, 1.5 sigma detection,
+ * minimum area 5, 8-connectivity, aperture radius 5 px, annulus 8-12 px.
+ */
+typedef struct ipp_params {
+  int32_t mesh_h, mesh_w;        /* region size in pixels, 16..128         */
+  int32_t filter_h, filter_w;    /* median filter size in nodes (odd)      */
+  int32_t clip_iters;            /* max rejection passes (0..16)           */
+  int32_t estimator;             /* IPP_EST_*                              */
+  double clip_sigma;             /* k of the k-sigma bounds (> 0)          */
+  double median_factor;          /* Eq. 4 weights                          */
+  double mean_factor;
+  int32_t min_valid;             /* pixels for a valid region (>= 1)       */
+  int32_t min_area;              /* pixels for a kept candidate (>= 1)     */
+  double det_nsigma;             /* detection threshold in rms units       */
+  int32_t connectivity;          /* 8 or 4                                 */
+  int32_t sky_clip_iters;        /* annulus clip passes (0..16)            */
+  double sky_clip_sigma;         /* annulus clip k (> 0)                   */
+  double r_ap, r_in, r_out;      /* aperture and annulus radii in px,
+                                    0 < r_ap <= 32, 0 <= r_in < r_out <= 32 */
+  int32_t tile_h, tile_w;        /* detection tile shape; 0 = default.
+                                    Supported: 64x64, 32x128, 128x32       */
+  uint32_t flags;                /* IPP_F_*                                */
+  int32_t reserved;
+} ipp_params;
+
+/* One input frame: h rows of w float32 pixels, row stride `pitch`
+ * elements (pitch >= w).  `mask` (nullable) is h x w bytes with the same
+ * pitch; a nonzero byte excludes the pixel from the background statistics.
+ * Frames up to 32767 x 32767 pixels. */
+typedef struct ipp_frame {
+  const float* pix;
+  const uint8_t* mask;
+  int64_t pitch;
+  int32_t h, w;
+} ipp_frame;
+
+/* Full-resolution maps of one frame, dense h x w (row stride w). */
+typedef struct ipp_maps {
+  float* bkg;        /* background B32                                     */
+  float* rms;        /* background rms R32                                 */
+  int32_t* labels;   /* candidate labels: 0 = none, 1..K in raster order of
+                        each candidate's first pixel                       */
+} ipp_maps;
+
+/* Mesh of one frame, ny x nx row-major with ny = ceil(h/mesh_h),
+ * nx = ceil(w/mesh_w).  Every member is nullable. */
+typedef struct ipp_mesh {
+  double* bkg_raw;   /* estimator of each region's clipped pixels          */
+  double* rms_raw;   /* population sigma of the clipped pixels             */
+  int32_t* n_used;   /* surviving pixel count                              */
+  double* bkg;       /* after invalid-node fill and median filter          */
+  double* rms;
+} ipp_mesh;
+
+/* Source table: struct of arrays with `capacity` rows, DEVICE memory.
+ * Rows are ordered by frame, then by label; frame f owns rows
+ * [frame_offsets[f], frame_offsets[f+1]).  In ipp_photometry the columns
+ * frame, x, y and the device scalar n_total (nullable: then `capacity`
+ * rows) are inputs. */
+typedef struct ipp_sources {
+  int64_t capacity;
+  int64_t* n_total;          /* device scalar: rows found (may exceed
+                                capacity: then rows >= capacity are lost)  */
+  int64_t* frame_offsets;    /* device [n_frames + 1]                      */
+  int32_t* frame;
+  int32_t* label;
+  int32_t* npix;
+  int32_t *xmin, *xmax, *ymin, *ymax;
+  int32_t *peak_x, *peak_y;
+  double* peak;              /* max of I - B32 over the candidate          */
+  double* flux_iso;          /* sum of I - B32 over the candidate          */
+  double *x, *y;             /* flux-weighted barycentre                   */
+  double* flux_ap;           /* aperture flux minus sky * aperture area    */
+  double* sky;               /* local sky per pixel                        */
+  double* area_ap;           /* sum of aperture weights                    */
+  double* area_ann;          /* sum of weights of the surviving annulus px */
+  uint32_t* flags;           /* IPP_SRC_*                                  */
+} ipp_sources;
+
+/* Library version (IPP_API_VERSION). */
+int32_t ipp_version(void);
+/* Static text for a status code. */
+const char* ipp_status_string(int32_t status);
+
+/* Fill *p with the defaults listed above. */
+void ipp_params_default(ipp_params* p);
+/* Host-only check of a parameter set; no device is touched. */
+ipp_status ipp_params_validate(const ipp_params* p);
+
+/* Context: owns a device workspace and the last error message.
+ * ipp_ctx_create makes `device` current and allocates nothing;
+ * ipp_ctx_reserve (re)allocates the workspace to at least `bytes` (call it
+ * before any ipp_* call that needs more; never during stream capture). */
+ipp_status ipp_ctx_create(void** ctx, int32_t device);
+ipp_status ipp_ctx_destroy(void* ctx);
+ipp_status ipp_ctx_reserve(void* ctx, size_t bytes);
+/* Message of the last failed call on ctx ("" if none); owned by ctx. */
+const char* ipp_last_error(void* ctx);
+
+/* Workspace bytes the calls below need for this batch, with room for
+ * `record_capacity` partial candidates (a candidate cut by detection-tile
+ * borders counts once per tile piece; 0 = a default of one per 16 pixels).
+ * Host-only: returns 0 for invalid arguments. */
+size_t ipp_workspace_bytes(const ipp_frame* frames, int32_t n,
+                           const ipp_params* p, int64_t record_capacity);
+
+/*
+ * Background estimation (Sec. 2.2.2) of n frames: writes maps[f].bkg and
+ * maps[f].rms (both required), and the mesh arrays given in mesh[f]
+ * (mesh may be NULL).  frame_flags: device uint32[n], nullable.
+ */
+ipp_status ipp_background(void* ctx, const ipp_frame* frames, int32_t n,
+                          const ipp_params* p, const ipp_maps* maps,
+                          const ipp_mesh* mesh, uint32_t* frame_flags,
+                          void* stream);
+
+/*
+ * Detection and pre-analysis (Sec. 2.2.5) of n frames against the given
+ * background maps[f].bkg and rms maps[f].rms (inputs); writes
+ * maps[f].labels and the table columns frame, label, npix, bbox, peak,
+ * peak_x, peak_y, flux_iso, x, y, flags plus n_total and frame_offsets.
+ * diag: device int64[4], nullable: [0] partial candidates used,
+ * [1] their capacity, [2] nonzero if it overflowed (labels then invalid).
+ */
+ipp_status ipp_detect(void* ctx, const ipp_frame* frames, int32_t n,
+                      const ipp_params* p, const ipp_maps* maps,
+                      ipp_sources* src, int64_t* diag, void* stream);
+
+/*
+ * Aperture photometry (Sec. 2.2.5) of the table rows against the frames
+ * and their background maps[f].bkg: reads frame, x, y; writes flux_ap,
+ * sky, area_ap, area_ann and ORs IPP_SRC_* edge/sky bits into flags.
+ * sky_lohi: device double[2*capacity], nullable: the value range of the
+ * surviving annulus pixels of each row, kept for ipp_photometry_backward.
+ */
+ipp_status ipp_photometry(void* ctx, const ipp_frame* frames, int32_t n,
+                          const ipp_maps* maps, const ipp_params* p,
+                          ipp_sources* src, double* sky_lohi, void* stream);
+
+/*
+ * Pipeline mode (Sec. 2.1): background, detection and photometry of a
+ * batch of frames of any sizes, fused (the background is evaluated inside
+ * the detection kernel) and replayed from a captured HIP graph when the
+ * same batch is seen again.  Writes maps[f].bkg and maps[f].labels
+ * (required) and maps[f].rms if IPP_F_WRITE_RMS is set.
+ */
+ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
+                             const ipp_params* p, const ipp_maps* maps,
+                             ipp_sources* src, uint32_t* frame_flags,
+                             int64_t* diag, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPP_H */

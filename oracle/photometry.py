@@ -16,8 +16,17 @@ out.  Readings taken here:
   G = x*y when the corner is inside the circle, else
   G = y*xs + P(x) - P(xs) with xs = sqrt(r^2 - y^2) and
   P(s) = int_0^s sqrt(r^2 - u^2) du = (s sqrt(r^2 - s^2) + r^2 asin(s/r))/2.
-* Only pixels inside the frame with a finite value count; a positive weight
-  on any other pixel flags the source.
+* A pixel belongs to an aperture (disk of radius r) iff its square meets the
+  open disk: with dx = max(|x - cx| - 1/2, 0) and dy likewise,
+  dx^2 + dy^2 < r^2.  It lies wholly inside iff (|x-cx|+1/2)^2 +
+  (|y-cy|+1/2)^2 <= r^2; its weight is then 1, for non-members 0, and
+  otherwise the exact area below.  A pixel belongs to the annulus iff it
+  meets the disk of radius r_out and is not wholly inside the disk of
+  radius r_in.  Membership is decided by these predicates (evaluated in
+  binary64 in exactly this form), not by the sign of a computed area, so
+  that a rounding residue never adds a pixel to the sky sample.
+* Only member pixels inside the frame with a finite value count; a member
+  pixel outside the frame or not finite flags the source.
 * Values are v = (double)I - (double)B32.  The sky is the weighted mean
   sum(m w v) / sum(m w) over annulus pixels, with m the survivors of the same
   k-sigma clipping as the background regions (median centre, population
@@ -66,8 +75,26 @@ def corner_area(x: float, y: float, r: float) -> float:
     return sx * sy * a
 
 
+def touches(cx: float, cy: float, r: float, px: int, py: int) -> bool:
+    """The pixel's square meets the open disk of radius r about c."""
+    dx = max(abs(px - cx) - 0.5, 0.0)
+    dy = max(abs(py - cy) - 0.5, 0.0)
+    return dx * dx + dy * dy < r * r
+
+
+def within(cx: float, cy: float, r: float, px: int, py: int) -> bool:
+    """The pixel's square lies in the closed disk of radius r about c."""
+    fx = abs(px - cx) + 0.5
+    fy = abs(py - cy) + 0.5
+    return fx * fx + fy * fy <= r * r
+
+
 def overlap(cx: float, cy: float, r: float, px: int, py: int) -> float:
     """Area of disk(c, r) intersected with pixel (px, py)."""
+    if not touches(cx, cy, r, px, py):
+        return 0.0
+    if within(cx, cy, r, px, py):
+        return 1.0
     x0, x1 = px - 0.5 - cx, px + 0.5 - cx
     y0, y1 = py - 0.5 - cy, py + 0.5 - cy
     return (corner_area(x1, y1, r) - corner_area(x0, y1, r)
@@ -105,15 +132,21 @@ def _source_pixels(img, B, cx, cy, p: Params):
     """Weights, values and validity of every pixel of the outer window."""
     h, w = img.shape
     rows = []
-    for py in window(cy, p.r_out):
-        for px in window(cx, p.r_out):
-            wap = overlap(cx, cy, p.r_ap, px, py)
-            wann = (overlap(cx, cy, p.r_out, px, py)
-                    - overlap(cx, cy, p.r_in, px, py))
+    R = max(p.r_ap, p.r_out)
+    for py in window(cy, R):
+        for px in window(cx, R):
+            in_ap = touches(cx, cy, p.r_ap, px, py)
+            in_ann = (touches(cx, cy, p.r_out, px, py)
+                      and not within(cx, cy, p.r_in, px, py))
+            if not (in_ap or in_ann):
+                continue
+            wap = overlap(cx, cy, p.r_ap, px, py) if in_ap else 0.0
+            wann = ((overlap(cx, cy, p.r_out, px, py)
+                     - overlap(cx, cy, p.r_in, px, py)) if in_ann else 0.0)
             inside = 0 <= px < w and 0 <= py < h
             ok = inside and math.isfinite(float(img[py, px]))
             v = (float(img[py, px]) - float(B[py, px])) if ok else 0.0
-            rows.append((px, py, wap, wann, ok, v))
+            rows.append((px, py, wap, wann, ok, v, in_ap, in_ann))
     return rows
 
 
@@ -121,11 +154,11 @@ def measure(img, B, cx: float, cy: float, p: Params):
     """Photometry of one source; returns a dict with the sky mask."""
     rows = _source_pixels(img, B, cx, cy, p)
     flags = 0
-    if any(r[2] > 0 and not r[4] for r in rows):
+    if any(r[6] and not r[4] for r in rows):
         flags |= SRC_APERTURE_OFF_EDGE
-    if any(r[3] > 0 and not r[4] for r in rows):
+    if any(r[7] and not r[4] for r in rows):
         flags |= SRC_ANNULUS_OFF_EDGE
-    ann = [r for r in rows if r[3] > 0 and r[4]]
+    ann = [r for r in rows if r[7] and r[4]]
     vals = np.array([r[5] for r in ann], dtype=np.float64)
     m = clip_mask(vals, p.sky_clip_iters, p.sky_clip_sigma)
     a_ann = math.fsum(r[3] for r, k in zip(ann, m) if k)
@@ -134,7 +167,7 @@ def measure(img, B, cx: float, cy: float, p: Params):
     else:
         sky = 0.0
         flags |= SRC_NO_SKY
-    ap = [r for r in rows if r[2] > 0 and r[4]]
+    ap = [r for r in rows if r[6] and r[4]]
     a_ap = math.fsum(r[2] for r in ap)
     raw = math.fsum(r[2] * r[5] for r in ap)
     flux = raw - sky * a_ap
@@ -171,13 +204,13 @@ def measure_adjoint(img, B, cx: float, cy: float, p: Params, sky_pixels,
     h, w = img.shape
     keep = set(sky_pixels)
     rows = _source_pixels(img, B, cx, cy, p)
-    a_ap = math.fsum(r[2] for r in rows if r[2] > 0 and r[4])
+    a_ap = math.fsum(r[2] for r in rows if r[6] and r[4])
     a_ann = math.fsum(r[3] for r in rows if r[4] and (r[0], r[1]) in keep)
     sky = (math.fsum(r[3] * r[5] for r in rows
                      if r[4] and (r[0], r[1]) in keep) / a_ann
            if a_ann > 0 else 0.0)
     gv = {}
-    for px, py, wap, wann, ok, v in rows:
+    for px, py, wap, wann, ok, v, _, _ in rows:
         if not ok:
             continue
         g = wap
@@ -188,7 +221,7 @@ def measure_adjoint(img, B, cx: float, cy: float, p: Params, sky_pixels,
     # centre derivative
     t_vx, t_vy, t_ax, t_ay = [], [], [], []      # aperture terms
     s_vx, s_vy, s_x, s_y = [], [], [], []        # sky terms
-    for px, py, wap, wann, ok, v in rows:
+    for px, py, wap, wann, ok, v, _, _ in rows:
         if not ok:
             continue
         ax, ay = overlap_grad(cx, cy, p.r_ap, px, py)

@@ -1,0 +1,290 @@
+"""Python binding of libipp with torch tensors as device memory.
+
+Marshals torch tensors into the C ABI of include/ipp.h; every computation
+runs in libipp's HIP kernels on the tensors' GPU, asynchronously on the
+current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, fields
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Params:
+    """Method parameters (ipp_params); defaults are the paper's settings."""
+    mesh_h: int = 64
+    mesh_w: int = 64
+    filter_h: int = 3
+    filter_w: int = 3
+    clip_iters: int = 3
+    estimator: int = L.IPP_EST_SEXTRACTOR
+    clip_sigma: float = 3.0
+    median_factor: float = 3.0
+    mean_factor: float = 2.0
+    min_valid: int = 100
+    min_area: int = 5
+    det_nsigma: float = 1.5
+    connectivity: int = 8
+    sky_clip_iters: int = 3
+    sky_clip_sigma: float = 3.0
+    r_ap: float = 5.0
+    r_in: float = 8.0
+    r_out: float = 12.0
+    tile_h: int = 0
+    tile_w: int = 0
+    flags: int = 0
+
+    def to_c(self) -> L.IppParams:
+        c = L.IppParams()
+        for f in fields(self):
+            setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
+class IppError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{L.lib().ipp_status_string(status).decode()}"
+                         f" ({status}): {msg}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_gpu_f32(t: torch.Tensor, what: str):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2
+            and t.stride(1) == 1):
+        raise ValueError(f"{what}: need a 2-D float32 CUDA tensor with "
+                         "unit column stride")
+
+
+def frames_c(frames: Sequence[torch.Tensor], masks=None):
+    arr = (L.IppFrame * len(frames))()
+    for i, fr in enumerate(frames):
+        _check_gpu_f32(fr, f"frame {i}")
+        arr[i].pix = fr.data_ptr()
+        arr[i].mask = (masks[i].data_ptr() if masks is not None
+                       and masks[i] is not None else None)
+        arr[i].pitch = fr.stride(0)
+        arr[i].h, arr[i].w = fr.shape
+    return arr
+
+
+class SourceTable:
+    """Struct-of-arrays source table in device memory."""
+
+    DT = {"int32": torch.int32, "float64": torch.float64,
+          "uint32": torch.int32}
+
+    def __init__(self, capacity: int, n_frames: int, device):
+        self.capacity = int(capacity)
+        self.n_frames = n_frames
+        self.cols = {name: torch.zeros(max(1, capacity), dtype=self.DT[dt],
+                                       device=device)
+                     for name, dt in L.SOURCE_COLUMNS}
+        self.n_total = torch.zeros(1, dtype=torch.int64, device=device)
+        self.frame_offsets = torch.zeros(n_frames + 1, dtype=torch.int64,
+                                         device=device)
+
+    def to_c(self, n_total=True) -> L.IppSources:
+        s = L.IppSources()
+        s.capacity = self.capacity
+        s.n_total = self.n_total.data_ptr() if n_total else None
+        s.frame_offsets = self.frame_offsets.data_ptr()
+        for name, _ in L.SOURCE_COLUMNS:
+            setattr(s, name, self.cols[name].data_ptr())
+        return s
+
+    def count(self) -> int:
+        return int(self.n_total.item())
+
+    def rows(self):
+        """Host copy (numpy) of the filled rows."""
+        n = min(self.count(), self.capacity)
+        out = {k: v[:n].cpu().numpy() for k, v in self.cols.items()}
+        out["flags"] = out["flags"].view("uint32")
+        return out
+
+
+class Context:
+    """A libipp context on one GPU (owns the device workspace)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.lib()
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.ipp_ctx_create(C.byref(h), device)
+        if st != L.IPP_OK:
+            raise IppError(st, "ipp_ctx_create")
+        self.h = h
+        self.ws_bytes = 0
+
+    def close(self):
+        if self.h:
+            self.lib.ipp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != L.IPP_OK:
+            raise IppError(st, self.lib.ipp_last_error(self.h).decode())
+
+    def workspace_bytes(self, frames, params: Params, record_capacity=0):
+        fc = frames_c(frames)
+        pc = params.to_c()
+        n = self.lib.ipp_workspace_bytes(fc, len(frames), C.byref(pc),
+                                         int(record_capacity))
+        if n == 0:
+            raise IppError(L.IPP_E_INVALID_ARG, "ipp_workspace_bytes")
+        return n
+
+    def reserve(self, nbytes: int):
+        self._check(self.lib.ipp_ctx_reserve(self.h, int(nbytes)))
+        self.ws_bytes = max(self.ws_bytes, int(nbytes))
+
+    def ensure(self, frames, params: Params, record_capacity=0):
+        need = self.workspace_bytes(frames, params, record_capacity)
+        if need > self.ws_bytes:
+            self.reserve(need)
+
+    # ---------------------------------------------------------- steps
+    def background(self, frames: List[torch.Tensor], params: Params,
+                   mesh: bool = False, masks=None):
+        """Sec. 2.2.2: background and rms maps (and the meshes)."""
+        self.ensure(frames, params)
+        dev = frames[0].device
+        n = len(frames)
+        fc = frames_c(frames, masks)
+        maps = (L.IppMaps * n)()
+        out = {"bkg": [], "rms": []}
+        meshes = (L.IppMesh * n)() if mesh else None
+        if mesh:
+            out.update({k: [] for k in ("bkg_raw", "rms_raw", "n_used",
+                                        "bkg_mesh", "rms_mesh")})
+        for i, fr in enumerate(frames):
+            b = torch.empty_like(fr)
+            r = torch.empty_like(fr)
+            maps[i].bkg, maps[i].rms = b.data_ptr(), r.data_ptr()
+            out["bkg"].append(b)
+            out["rms"].append(r)
+            if mesh:
+                h, w = fr.shape
+                ny = -(-h // params.mesh_h)
+                nx = -(-w // params.mesh_w)
+                t = {k: torch.empty((ny, nx), dtype=torch.float64, device=dev)
+                     for k in ("bkg_raw", "rms_raw", "bkg_mesh", "rms_mesh")}
+                t["n_used"] = torch.empty((ny, nx), dtype=torch.int32,
+                                          device=dev)
+                meshes[i].bkg_raw = t["bkg_raw"].data_ptr()
+                meshes[i].rms_raw = t["rms_raw"].data_ptr()
+                meshes[i].n_used = t["n_used"].data_ptr()
+                meshes[i].bkg = t["bkg_mesh"].data_ptr()
+                meshes[i].rms = t["rms_mesh"].data_ptr()
+                for k, v in t.items():
+                    out[k].append(v)
+        flags = torch.zeros(n, dtype=torch.int32, device=dev)
+        pc = params.to_c()
+        self._check(self.lib.ipp_background(
+            self.h, fc, n, C.byref(pc), maps, meshes, _ptr(flags),
+            _stream()))
+        out["flags"] = flags
+        return out
+
+    def detect(self, frames, bkg, rms, params: Params, capacity=None,
+               table: Optional[SourceTable] = None):
+        """Sec. 2.2.5: labels and source table against given maps."""
+        self.ensure(frames, params)
+        n = len(frames)
+        dev = frames[0].device
+        if table is None:
+            if capacity is None:
+                capacity = sum(f.numel() for f in frames) // 64 + 1024
+            table = SourceTable(capacity, n, dev)
+        maps = (L.IppMaps * n)()
+        labels = []
+        for i, fr in enumerate(frames):
+            _check_gpu_f32(bkg[i], "bkg")
+            _check_gpu_f32(rms[i], "rms")
+            lab = torch.empty(fr.shape, dtype=torch.int32, device=dev)
+            maps[i].bkg, maps[i].rms = bkg[i].data_ptr(), rms[i].data_ptr()
+            maps[i].labels = lab.data_ptr()
+            labels.append(lab)
+        diag = torch.zeros(4, dtype=torch.int64, device=dev)
+        src = table.to_c()
+        pc = params.to_c()
+        self._check(self.lib.ipp_detect(
+            self.h, frames_c(frames), n, C.byref(pc), maps, C.byref(src),
+            _ptr(diag), _stream()))
+        return {"labels": labels, "table": table, "diag": diag}
+
+    def photometry(self, frames, bkg, table: SourceTable, params: Params,
+                   keep_sky=False, use_count=True):
+        """Sec. 2.2.5: aperture photometry of the table rows."""
+        n = len(frames)
+        maps = (L.IppMaps * n)()
+        for i in range(n):
+            _check_gpu_f32(bkg[i], "bkg")
+            maps[i].bkg = bkg[i].data_ptr()
+        self.ensure(frames, params)
+        lohi = None
+        if keep_sky:
+            lohi = torch.empty(2 * max(1, table.capacity),
+                               dtype=torch.float64, device=frames[0].device)
+        src = table.to_c(n_total=use_count)
+        pc = params.to_c()
+        self._check(self.lib.ipp_photometry(
+            self.h, frames_c(frames), n, maps, C.byref(pc), C.byref(src),
+            _ptr(lohi), _stream()))
+        return lohi
+
+    def process_batch(self, frames, params: Params, capacity=None,
+                      table: Optional[SourceTable] = None, outputs=None,
+                      write_rms=False):
+        """Pipeline mode (Sec. 2.1): the whole path for a batch."""
+        self.ensure(frames, params)
+        n = len(frames)
+        dev = frames[0].device
+        if table is None:
+            if capacity is None:
+                capacity = sum(f.numel() for f in frames) // 64 + 1024
+            table = SourceTable(capacity, n, dev)
+        if outputs is None:
+            outputs = {"bkg": [torch.empty_like(f) for f in frames],
+                       "labels": [torch.empty(f.shape, dtype=torch.int32,
+                                              device=dev) for f in frames],
+                       "rms": ([torch.empty_like(f) for f in frames]
+                               if write_rms else None)}
+        maps = (L.IppMaps * n)()
+        for i in range(n):
+            maps[i].bkg = outputs["bkg"][i].data_ptr()
+            maps[i].labels = outputs["labels"][i].data_ptr()
+            if write_rms:
+                maps[i].rms = outputs["rms"][i].data_ptr()
+        p = Params(**{f.name: getattr(params, f.name) for f in fields(params)})
+        if write_rms:
+            p.flags |= L.IPP_F_WRITE_RMS
+        flags = torch.zeros(n, dtype=torch.int32, device=dev)
+        diag = torch.zeros(4, dtype=torch.int64, device=dev)
+        src = table.to_c()
+        pc = p.to_c()
+        self._check(self.lib.ipp_process_batch(
+            self.h, frames_c(frames), n, C.byref(pc), maps, C.byref(src),
+            _ptr(flags), _ptr(diag), _stream()))
+        outputs.update({"table": table, "flags": flags, "diag": diag})
+        return outputs

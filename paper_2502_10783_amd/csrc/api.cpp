@@ -1,0 +1,656 @@
+// Host side of libipp: argument validation, workspace planning, kernel
+// sequencing and the HIP-graph cache of the batched pipeline call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ipp_internal.h"
+#include "kernels.h"
+
+using namespace ipp;
+
+struct IppGraph {
+  std::vector<uint8_t> key;       // batch signature
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t ws_gen = 0;            // workspace generation the graph saw
+};
+
+struct IppCtx {
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint64_t ws_gen = 1;            // bumped when the workspace is reused
+  std::string err;
+  IppGraph graph;
+};
+
+namespace {
+
+constexpr int64_t kMaxDim = 32767;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+ipp_status fail(IppCtx* c, ipp_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+void tile_shape(const ipp_params& p, int* th, int* tw) {
+  if (p.tile_h == 32 && p.tile_w == 128) { *th = 32; *tw = 128; return; }
+  if (p.tile_h == 128 && p.tile_w == 32) { *th = 128; *tw = 32; return; }
+  *th = 64; *tw = 64;
+}
+
+std::string check_params(const ipp_params* p) {
+  if (!p) return "params is NULL";
+  auto bad = [](double v) { return !std::isfinite(v); };
+  if (p->mesh_h < 16 || p->mesh_h > 128 || p->mesh_w < 16 || p->mesh_w > 128)
+    return "mesh_h and mesh_w must be in [16, 128]";
+  if (p->filter_h < 1 || p->filter_h > 7 || !(p->filter_h & 1) ||
+      p->filter_w < 1 || p->filter_w > 7 || !(p->filter_w & 1))
+    return "filter_h and filter_w must be odd and in [1, 7]";
+  if (p->clip_iters < 0 || p->clip_iters > 16)
+    return "clip_iters must be in [0, 16]";
+  if (bad(p->clip_sigma) || p->clip_sigma <= 0) return "clip_sigma must be > 0";
+  if (p->estimator < IPP_EST_SEXTRACTOR || p->estimator > IPP_EST_MODE)
+    return "unknown estimator";
+  if (bad(p->median_factor) || bad(p->mean_factor))
+    return "median_factor and mean_factor must be finite";
+  if (p->min_valid < 1) return "min_valid must be >= 1";
+  if (p->min_area < 1) return "min_area must be >= 1";
+  if (bad(p->det_nsigma)) return "det_nsigma must be finite";
+  if (p->connectivity != 4 && p->connectivity != 8)
+    return "connectivity must be 4 or 8";
+  if (p->sky_clip_iters < 0 || p->sky_clip_iters > 16)
+    return "sky_clip_iters must be in [0, 16]";
+  if (bad(p->sky_clip_sigma) || p->sky_clip_sigma <= 0)
+    return "sky_clip_sigma must be > 0";
+  if (bad(p->r_ap) || p->r_ap <= 0 || p->r_ap > 16)
+    return "r_ap must be in (0, 16]";
+  if (bad(p->r_in) || bad(p->r_out) || p->r_in < 0 || p->r_out <= p->r_in ||
+      p->r_out > 16)
+    return "annulus radii must satisfy 0 <= r_in < r_out <= 16";
+  const bool shape_ok = (p->tile_h == 0 && p->tile_w == 0) ||
+                        (p->tile_h == 64 && p->tile_w == 64) ||
+                        (p->tile_h == 32 && p->tile_w == 128) ||
+                        (p->tile_h == 128 && p->tile_w == 32);
+  if (!shape_ok) return "tile shape must be 0x0, 64x64, 32x128 or 128x32";
+  return "";
+}
+
+std::string check_frames(const ipp_frame* f, int32_t n) {
+  if (!f) return "frames is NULL";
+  if (n < 1 || n > 65536) return "frame count must be in [1, 65536]";
+  for (int i = 0; i < n; ++i) {
+    if (!f[i].pix) return "frame " + std::to_string(i) + ": pix is NULL";
+    if (f[i].h < 1 || f[i].w < 1 || f[i].h > kMaxDim || f[i].w > kMaxDim)
+      return "frame " + std::to_string(i) + ": size must be 1..32767";
+    if (f[i].pitch < f[i].w)
+      return "frame " + std::to_string(i) + ": pitch < w";
+  }
+  return "";
+}
+
+// Workspace layout of one call.
+struct Plan {
+  std::vector<FrameDev> fd;
+  int32_t nodes = 0, dtiles = 0, rows = 0;
+  int64_t pix = 0;
+  int64_t rec_cap = 0;
+  int th = 64, tw = 64;
+  // byte offsets
+  size_t o_frames, o_mbkg, o_mrms, o_mn, o_fbkg, o_frms, o_fpass, o_tb[4],
+      o_tr[4], o_sc0, o_sc1, o_flags, o_lmap, o_rbase, o_recs, o_rparent,
+      o_rlabel, o_bucket, o_rowc, o_rows, o_rowcur, o_scanb, o_cnt, total;
+};
+
+enum PlanMode { kPlanMesh = 0, kPlanDetect = 1, kPlanFrames = 2 };
+
+Plan make_plan(const ipp_frame* f, int32_t n, const ipp_params& p,
+               int64_t rec_cap, int mode = kPlanDetect) {
+  Plan P;
+  tile_shape(p, &P.th, &P.tw);
+  P.fd.resize(n);
+  for (int i = 0; i < n; ++i) {
+    FrameDev& d = P.fd[i];
+    std::memset(&d, 0, sizeof(d));
+    d.pix = f[i].pix;
+    d.mask = f[i].mask;
+    d.pitch = f[i].pitch;
+    d.h = f[i].h;
+    d.w = f[i].w;
+    d.ny = (f[i].h + p.mesh_h - 1) / p.mesh_h;
+    d.nx = (f[i].w + p.mesh_w - 1) / p.mesh_w;
+    d.node0 = P.nodes;
+    P.nodes += d.ny * d.nx;
+    d.dty = (f[i].h + P.th - 1) / P.th;
+    d.dtx = (f[i].w + P.tw - 1) / P.tw;
+    d.dtile0 = P.dtiles;
+    P.dtiles += d.dty * d.dtx;
+    d.row0 = P.rows;
+    P.rows += f[i].h;
+    d.pix0 = P.pix;
+    P.pix += (int64_t)f[i].h * f[i].w;
+  }
+  P.rec_cap = rec_cap > 0 ? rec_cap : P.pix / 32 + 4096;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
+  const size_t N = mode == kPlanFrames ? 0 : (size_t)P.nodes;
+  if (mode != kPlanDetect) {
+    P.rec_cap = 0;
+    P.rows = mode == kPlanFrames ? 0 : P.rows;
+  }
+  const int64_t npix = mode == kPlanDetect ? P.pix : 0;
+  P.o_frames = take(sizeof(FrameDev) * n);
+  P.o_mbkg = take(8 * N);
+  P.o_mrms = take(8 * N);
+  P.o_mn = take(4 * N);
+  P.o_fbkg = take(8 * N);
+  P.o_frms = take(8 * N);
+  P.o_fpass = take(4 * N);
+  for (int k = 0; k < 4; ++k) P.o_tb[k] = take(8 * N);
+  for (int k = 0; k < 4; ++k) P.o_tr[k] = take(8 * N);
+  P.o_sc0 = take(8 * 4 * N);
+  P.o_sc1 = take(8 * 4 * N);
+  P.o_flags = take(4 * (size_t)n);
+  P.o_lmap = take(2 * (size_t)npix);
+  P.o_rbase = take(4 * (size_t)(mode == kPlanDetect ? P.dtiles : 0));
+  P.o_recs = take(sizeof(Rec) * (size_t)P.rec_cap);
+  P.o_rparent = take(4 * (size_t)P.rec_cap);
+  P.o_rlabel = take(4 * (size_t)P.rec_cap);
+  P.o_bucket = take(4 * (size_t)P.rec_cap);
+  P.o_rowc = take(4 * (size_t)P.rows);
+  P.o_rows = take(4 * (size_t)P.rows);
+  P.o_rowcur = take(4 * (size_t)P.rows);
+  P.o_scanb = take(4 * (size_t)((P.rows + 1023) / 1024 + 1));
+  P.o_cnt = take(8 * 4);
+  P.total = o;
+  return P;
+}
+
+Work make_work(const Plan& P, void* ws, int32_t n) {
+  Work w;
+  std::memset(&w, 0, sizeof(w));
+  char* b = (char*)ws;
+  w.frames = (FrameDev*)(b + P.o_frames);
+  w.nframes = n;
+  w.total_nodes = P.nodes;
+  w.total_dtiles = P.dtiles;
+  w.total_rows = P.rows;
+  w.total_pix = P.pix;
+  w.m_bkg = (double*)(b + P.o_mbkg);
+  w.m_rms = (double*)(b + P.o_mrms);
+  w.m_n = (int32_t*)(b + P.o_mn);
+  w.f_bkg = (double*)(b + P.o_fbkg);
+  w.f_rms = (double*)(b + P.o_frms);
+  w.f_pass = (int32_t*)(b + P.o_fpass);
+  for (int k = 0; k < 4; ++k) {
+    w.tb[k] = (double*)(b + P.o_tb[k]);
+    w.tr[k] = (double*)(b + P.o_tr[k]);
+  }
+  w.sc0 = (double*)(b + P.o_sc0);
+  w.sc1 = (double*)(b + P.o_sc1);
+  w.frame_flags = (uint32_t*)(b + P.o_flags);
+  w.lmap = (uint16_t*)(b + P.o_lmap);
+  w.tile_rbase = (int32_t*)(b + P.o_rbase);
+  w.recs = (Rec*)(b + P.o_recs);
+  w.rparent = (int32_t*)(b + P.o_rparent);
+  w.rlabel = (int32_t*)(b + P.o_rlabel);
+  w.rec_cap = P.rec_cap;
+  w.bucket = (int32_t*)(b + P.o_bucket);
+  w.row_count = (int32_t*)(b + P.o_rowc);
+  w.row_start = (int32_t*)(b + P.o_rows);
+  w.row_cursor = (int32_t*)(b + P.o_rowcur);
+  w.scan_blocks = (int32_t*)(b + P.o_scanb);
+  w.counters = (int64_t*)(b + P.o_cnt);
+  return w;
+}
+
+#define IPP_LAUNCH(c, ...)                                                  \
+  do {                                                                      \
+    __VA_ARGS__;                                                            \
+    hipError_t e_ = hipGetLastError();                                      \
+    if (e_ != hipSuccess)                                                   \
+      return fail(c, IPP_E_DEVICE,                                          \
+                  std::string("kernel launch failed: ") +                   \
+                      hipGetErrorString(e_));                               \
+  } while (0)
+
+int grid_for(int64_t items, int per_block, int cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+ipp_status upload(IppCtx* c, const Plan& P, const Work& w,
+                  hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(w.frames, P.fd.data(),
+                                sizeof(FrameDev) * P.fd.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE,
+                std::string("descriptor upload failed: ") +
+                    hipGetErrorString(e));
+  return IPP_OK;
+}
+
+// Validates and lays out a call.  In detection mode the record capacity
+// is the largest that fits in the reserved workspace.
+ipp_status prepare(IppCtx* c, const ipp_frame* frames, int32_t n,
+                   const ipp_params* p, int mode, Plan* P) {
+  if (!c) return IPP_E_INVALID_ARG;
+  std::string m = check_params(p);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  m = check_frames(frames, n);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  *P = make_plan(frames, n, *p, 1, mode);
+  if (mode == kPlanDetect && P->total <= c->ws_bytes) {
+    const size_t per = sizeof(Rec) + 3 * sizeof(int32_t);
+    int64_t cap = (int64_t)((c->ws_bytes - P->total) / per) + 1;
+    if (cap > (1ll << 31) - 1024) cap = (1ll << 31) - 1024;
+    for (;;) {
+      Plan Q = make_plan(frames, n, *p, cap, mode);
+      if (Q.total <= c->ws_bytes || cap <= 1) { *P = Q; break; }
+      cap -= 256;
+      if (cap < 1) cap = 1;
+    }
+  }
+  if (P->rows > (1 << 20))
+    return fail(c, IPP_E_UNSUPPORTED, "more than 2^20 rows in one batch");
+  if (P->total > c->ws_bytes)
+    return fail(c, IPP_E_WORKSPACE,
+                "workspace too small: need " + std::to_string(P->total) +
+                    " bytes, have " + std::to_string(c->ws_bytes));
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE, std::string("hipSetDevice: ") +
+                                     hipGetErrorString(e));
+  return IPP_OK;
+}
+
+// ---- kernel sequences --------------------------------------------------
+ipp_status run_mesh(IppCtx* c, const Plan& P, const Work& w,
+                    const ipp_params& p, hipStream_t s) {
+  const int area = p.mesh_h * p.mesh_w;
+  if (area <= 4 * kBlock)
+    IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_stats<4>, dim3(P.nodes),
+                                     dim3(kBlock), 0, s, w, p));
+  else if (area <= 16 * kBlock)
+    IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_stats<16>, dim3(P.nodes),
+                                     dim3(kBlock), 0, s, w, p));
+  else
+    IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_stats<64>, dim3(P.nodes),
+                                     dim3(kBlock), 0, s, w, p));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_finish, dim3((int)P.fd.size()),
+                                   dim3(kBlock), 0, s, w, p));
+  return IPP_OK;
+}
+
+template <int TH, int TW>
+ipp_status run_bkg_maps(IppCtx* c, const Plan& P, const Work& w,
+                        const ipp_params& p, hipStream_t s) {
+  IPP_LAUNCH(c, hipLaunchKernelGGL((k_bkg_maps<TH, TW>), dim3(P.dtiles),
+                                   dim3(kBlock), 0, s, w, p));
+  return IPP_OK;
+}
+
+template <int TH, int TW>
+ipp_status run_tile(IppCtx* c, const Plan& P, const Work& w,
+                    const ipp_params& p, bool fused, int write_rms,
+                    hipStream_t s) {
+  const dim3 g(P.dtiles), b(kBlock);
+  if (fused && p.connectivity == 8)
+    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, true>), g, b,
+                                     0, s, w, p, write_rms));
+  else if (fused)
+    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, false>), g,
+                                     b, 0, s, w, p, write_rms));
+  else if (p.connectivity == 8)
+    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, true>), g,
+                                     b, 0, s, w, p, write_rms));
+  else
+    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, false>), g,
+                                     b, 0, s, w, p, write_rms));
+  IPP_LAUNCH(c, hipLaunchKernelGGL((k_border<TH, TW>), g, b, 0, s, w, p));
+  return IPP_OK;
+}
+
+template <int TH, int TW>
+ipp_status run_relabel(IppCtx* c, const Plan& P, const Work& w,
+                       const ipp_params& p, hipStream_t s) {
+  IPP_LAUNCH(c, hipLaunchKernelGGL((k_relabel<TH, TW>), dim3(P.dtiles),
+                                   dim3(kBlock), 0, s, w, p));
+  return IPP_OK;
+}
+
+__global__ void k_diag(Work w, int64_t* diag) {
+  if (threadIdx.x == 0) {
+    diag[0] = w.counters[0];
+    diag[1] = w.rec_cap;
+    diag[2] = w.counters[2];
+    diag[3] = w.counters[3];
+  }
+}
+
+// Detection after the tile kernel choice: fill, tiles, merge, number,
+// relabel, measure.
+ipp_status run_detect(IppCtx* c, const Plan& P, const Work& w,
+                      const ipp_params& p, ipp_sources* src, bool fused,
+                      int write_rms, int64_t* diag, hipStream_t s) {
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s,
+                                   w.counters, (int64_t)4, (int64_t)0));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_fill_i32,
+                                   dim3(grid_for(P.rows, kBlock, 4096)),
+                                   dim3(kBlock), 0, s, w.row_count,
+                                   (int64_t)P.rows, 0));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_fill_i32,
+                                   dim3(grid_for(P.rows, kBlock, 4096)),
+                                   dim3(kBlock), 0, s, w.row_cursor,
+                                   (int64_t)P.rows, 0));
+  ipp_status st;
+  if (P.th == 32) st = run_tile<32, 128>(c, P, w, p, fused, write_rms, s);
+  else if (P.th == 128) st = run_tile<128, 32>(c, P, w, p, fused, write_rms, s);
+  else st = run_tile<64, 64>(c, P, w, p, fused, write_rms, s);
+  if (st != IPP_OK) return st;
+  const int gr = grid_for(P.rec_cap, kBlock, 2048);
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_resolve, dim3(gr), dim3(kBlock), 0, s,
+                                   w, p));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_heads, dim3(gr), dim3(kBlock), 0, s, w,
+                                   p));
+  const int nb = (P.rows + 1023) / 1024;
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0,
+                                   s, w.row_count, w.scan_blocks, P.rows));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s,
+                                   w.scan_blocks, nb, w.counters + 3));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0,
+                                   s, w.row_count, w.scan_blocks,
+                                   w.row_start, P.rows));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_frame_offsets,
+                                   dim3(grid_for((int64_t)P.fd.size() + 1,
+                                                 kBlock, 4096)),
+                                   dim3(kBlock), 0, s, w, *src));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scatter, dim3(gr), dim3(kBlock), 0, s,
+                                   w, p));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_rank, dim3(gr), dim3(kBlock), 0, s, w,
+                                   p, *src));
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_reclabel, dim3(gr), dim3(kBlock), 0, s,
+                                   w));
+  if (P.th == 32) st = run_relabel<32, 128>(c, P, w, p, s);
+  else if (P.th == 128) st = run_relabel<128, 32>(c, P, w, p, s);
+  else st = run_relabel<64, 64>(c, P, w, p, s);
+  if (st != IPP_OK) return st;
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_source_stats,
+                                   dim3(grid_for(src->capacity, 4, 4096)),
+                                   dim3(kBlock), 0, s, w, *src));
+  if (diag)
+    IPP_LAUNCH(c, hipLaunchKernelGGL(k_diag, dim3(1), dim3(64), 0, s, w,
+                                     diag));
+  return IPP_OK;
+}
+
+std::string check_sources(const ipp_sources* s, bool detect) {
+  if (!s) return "sources is NULL";
+  if (s->capacity < 0) return "sources capacity < 0";
+  if (!s->frame || !s->x || !s->y || !s->flags)
+    return "sources: frame, x, y and flags are required";
+  if (detect) {
+    if (!s->n_total || !s->frame_offsets || !s->label || !s->npix ||
+        !s->xmin || !s->xmax || !s->ymin || !s->ymax || !s->peak_x ||
+        !s->peak_y || !s->peak || !s->flux_iso)
+      return "sources: every detection column is required";
+  } else {
+    if (!s->flux_ap || !s->sky || !s->area_ap || !s->area_ann)
+      return "sources: flux_ap, sky, area_ap and area_ann are required";
+  }
+  return "";
+}
+
+}  // namespace
+
+// ===================================================================== API
+extern "C" {
+
+int32_t ipp_version(void) { return IPP_API_VERSION; }
+
+const char* ipp_status_string(int32_t s) {
+  switch (s) {
+    case IPP_OK: return "ok";
+    case IPP_E_INVALID_ARG: return "invalid argument";
+    case IPP_E_UNSUPPORTED: return "unsupported";
+    case IPP_E_CAPACITY: return "capacity exceeded";
+    case IPP_E_DEVICE: return "device error";
+    case IPP_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+void ipp_params_default(ipp_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->mesh_h = p->mesh_w = 64;
+  p->filter_h = p->filter_w = 3;
+  p->clip_iters = 3;
+  p->estimator = IPP_EST_SEXTRACTOR;
+  p->clip_sigma = 3.0;
+  p->median_factor = 3.0;
+  p->mean_factor = 2.0;
+  p->min_valid = 100;
+  p->min_area = 5;
+  p->det_nsigma = 1.5;
+  p->connectivity = 8;
+  p->sky_clip_iters = 3;
+  p->sky_clip_sigma = 3.0;
+  p->r_ap = 5.0;
+  p->r_in = 8.0;
+  p->r_out = 12.0;
+  p->tile_h = p->tile_w = 0;
+  p->flags = 0;
+}
+
+ipp_status ipp_params_validate(const ipp_params* p) {
+  return check_params(p).empty() ? IPP_OK : IPP_E_INVALID_ARG;
+}
+
+ipp_status ipp_ctx_create(void** ctx, int32_t device) {
+  if (!ctx) return IPP_E_INVALID_ARG;
+  *ctx = nullptr;
+  if (device < 0) return IPP_E_INVALID_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device >= count)
+    return IPP_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return IPP_E_DEVICE;
+  IppCtx* c = new (std::nothrow) IppCtx();
+  if (!c) return IPP_E_DEVICE;
+  c->device = device;
+  *ctx = c;
+  return IPP_OK;
+}
+
+ipp_status ipp_ctx_destroy(void* ctx) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  hipSetDevice(c->device);
+  if (c->graph.exec) hipGraphExecDestroy(c->graph.exec);
+  if (c->graph.graph) hipGraphDestroy(c->graph.graph);
+  if (c->ws) hipFree(c->ws);
+  delete c;
+  return IPP_OK;
+}
+
+ipp_status ipp_ctx_reserve(void* ctx, size_t bytes) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (bytes <= c->ws_bytes) return IPP_OK;
+  hipSetDevice(c->device);
+  if (c->graph.exec) {              // graphs hold old workspace addresses
+    hipGraphExecDestroy(c->graph.exec);
+    c->graph.exec = nullptr;
+  }
+  if (c->graph.graph) {
+    hipGraphDestroy(c->graph.graph);
+    c->graph.graph = nullptr;
+  }
+  c->graph.key.clear();
+  if (c->ws) {
+    hipDeviceSynchronize();
+    hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE, std::string("hipMalloc workspace: ") +
+                                     hipGetErrorString(e));
+  c->ws = p;
+  c->ws_bytes = bytes;
+  ++c->ws_gen;
+  return IPP_OK;
+}
+
+const char* ipp_last_error(void* ctx) {
+  IppCtx* c = (IppCtx*)ctx;
+  return c ? c->err.c_str() : "null context";
+}
+
+size_t ipp_workspace_bytes(const ipp_frame* frames, int32_t n,
+                           const ipp_params* p, int64_t record_capacity) {
+  if (!check_params(p).empty() || !check_frames(frames, n).empty()) return 0;
+  if (record_capacity < 0 || record_capacity >= (1ll << 31) - 1024) return 0;
+  return make_plan(frames, n, *p, record_capacity, kPlanDetect).total;
+}
+
+ipp_status ipp_background(void* ctx, const ipp_frame* frames, int32_t n,
+                          const ipp_params* p, const ipp_maps* maps,
+                          const ipp_mesh* mesh, uint32_t* frame_flags,
+                          void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  Plan P;
+  ipp_status st = prepare(c, frames, n, p, kPlanMesh, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg || !maps[i].rms)
+      return fail(c, IPP_E_INVALID_ARG, "maps[f].bkg and .rms are required");
+    P.fd[i].bkg = maps[i].bkg;
+    P.fd[i].rms = maps[i].rms;
+    if (mesh) {
+      P.fd[i].o_bkg_raw = mesh[i].bkg_raw;
+      P.fd[i].o_rms_raw = mesh[i].rms_raw;
+      P.fd[i].o_n = mesh[i].n_used;
+      P.fd[i].o_bkg = mesh[i].bkg;
+      P.fd[i].o_rms = mesh[i].rms;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  if (frame_flags) w.frame_flags = frame_flags;
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  if ((st = run_mesh(c, P, w, *p, s)) != IPP_OK) return st;
+  if (P.th == 32) return run_bkg_maps<32, 128>(c, P, w, *p, s);
+  if (P.th == 128) return run_bkg_maps<128, 32>(c, P, w, *p, s);
+  return run_bkg_maps<64, 64>(c, P, w, *p, s);
+}
+
+ipp_status ipp_detect(void* ctx, const ipp_frame* frames, int32_t n,
+                      const ipp_params* p, const ipp_maps* maps,
+                      ipp_sources* src, int64_t* diag, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  std::string m = check_sources(src, true);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  Plan P;
+  ipp_status st = prepare(c, frames, n, p, kPlanDetect, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg || !maps[i].rms || !maps[i].labels)
+      return fail(c, IPP_E_INVALID_ARG,
+                  "maps[f].bkg, .rms and .labels are required");
+    P.fd[i].bkg = maps[i].bkg;
+    P.fd[i].rms = maps[i].rms;
+    P.fd[i].labels = maps[i].labels;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  return run_detect(c, P, w, *p, src, false, 0, diag, s);
+}
+
+ipp_status ipp_photometry(void* ctx, const ipp_frame* frames, int32_t n,
+                          const ipp_maps* maps, const ipp_params* p,
+                          ipp_sources* src, double* sky_lohi, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  std::string m = check_sources(src, false);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  Plan P;
+  ipp_status st = prepare(c, frames, n, p, kPlanFrames, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg)
+      return fail(c, IPP_E_INVALID_ARG, "maps[f].bkg is required");
+    P.fd[i].bkg = maps[i].bkg;
+  }
+  if (src->capacity == 0) return IPP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_aperture,
+                                   dim3(grid_for(src->capacity, 1, 16384)),
+                                   dim3(kBlock), 0, s, w, *p, *src,
+                                   sky_lohi));
+  return IPP_OK;
+}
+
+ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
+                             const ipp_params* p, const ipp_maps* maps,
+                             ipp_sources* src, uint32_t* frame_flags,
+                             int64_t* diag, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  std::string m = check_sources(src, true);
+  if (m.empty()) m = check_sources(src, false);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  Plan P;
+  ipp_status st = prepare(c, frames, n, p, kPlanDetect, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  const int write_rms = (p->flags & IPP_F_WRITE_RMS) ? 1 : 0;
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg || !maps[i].labels || (write_rms && !maps[i].rms))
+      return fail(c, IPP_E_INVALID_ARG,
+                  "maps[f].bkg and .labels (and .rms with "
+                  "IPP_F_WRITE_RMS) are required");
+    P.fd[i].bkg = maps[i].bkg;
+    P.fd[i].rms = maps[i].rms;
+    P.fd[i].labels = maps[i].labels;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  if (frame_flags) w.frame_flags = frame_flags;
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  if ((st = run_mesh(c, P, w, *p, s)) != IPP_OK) return st;
+  if ((st = run_detect(c, P, w, *p, src, true, write_rms, diag, s)) != IPP_OK)
+    return st;
+  IPP_LAUNCH(c, hipLaunchKernelGGL(k_aperture,
+                                   dim3(grid_for(src->capacity, 1, 16384)),
+                                   dim3(kBlock), 0, s, w, *p, *src,
+                                   (double*)nullptr));
+  return IPP_OK;
+}
+
+}  // extern "C"

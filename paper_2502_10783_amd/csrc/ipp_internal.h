@@ -1,0 +1,235 @@
+// Internal definitions shared by the HIP kernels and the host side of
+// libipp: device frame descriptors, the workspace layout, and small
+// block-level helpers for 256-thread (4 x wave64) workgroups on gfx950.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ipp.h"
+
+namespace ipp {
+
+constexpr int kBlock = 256;          // threads per workgroup everywhere
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kWaves = kBlock / kWave;
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // excluded pixel key
+constexpr int kFixedBits = 28;       // fraction bits of the exact sums
+constexpr int kMaxNcol = 8;          // mesh columns a detection tile spans
+
+// Device-side descriptor of one frame of a batch.
+struct FrameDev {
+  const float* pix;
+  const uint8_t* mask;
+  int64_t pitch;
+  int32_t h, w;
+  int32_t ny, nx;        // mesh nodes
+  int32_t node0;         // first node (= first mesh region) in batch arrays
+  int32_t dty, dtx;      // detection tile grid
+  int32_t dtile0;        // first detection tile in batch arrays
+  int32_t row0;          // first row in batch row arrays
+  int64_t pix0;          // first pixel in batch pixel arrays
+  float* bkg;            // maps (inputs in map mode, outputs otherwise)
+  float* rms;
+  int32_t* labels;
+  double* o_bkg_raw;     // optional mesh outputs
+  double* o_rms_raw;
+  int32_t* o_n;
+  double* o_bkg;
+  double* o_rms;
+};
+
+// Partial candidate: the piece of a connected component inside one
+// detection tile that touches the tile border or is large enough to keep.
+struct Rec {
+  int32_t minidx;        // first pixel in frame raster order (y*w + x)
+  int32_t npix;
+  int32_t xmin, xmax, ymin, ymax;
+  int32_t frame;
+  int32_t pad;
+};
+
+// Device pointers of one call's workspace (carved out by the host).
+struct Work {
+  FrameDev* frames;
+  int32_t nframes;
+  int32_t total_nodes;
+  int32_t total_dtiles;
+  int32_t total_rows;
+  int64_t total_pix;
+  // mesh, one entry per node of every frame
+  double* m_bkg;         // raw estimator value
+  double* m_rms;
+  int32_t* m_n;
+  double* f_bkg;         // after fill
+  double* f_rms;
+  int32_t* f_pass;       // pass at which a node became known (-1 unknown)
+  double* tb[4];         // spline tables of the background: f, fxx, fyy, fxxyy
+  double* tr[4];         // same for the rms
+  double* sc0;           // Thomas scratch
+  double* sc1;
+  uint32_t* frame_flags; // per frame
+  // detection
+  uint16_t* lmap;        // per pixel: record index within its tile + 1
+  int32_t* tile_rbase;   // per detection tile: first record
+  Rec* recs;
+  int32_t* rparent;      // union-find parent of each record
+  int32_t* rlabel;       // final frame-local label of each record (0 = none)
+  int64_t rec_cap;
+  int32_t* row_count;    // per batch row: kept candidates starting there
+  int32_t* row_start;    // exclusive scan of row_count
+  int32_t* row_cursor;
+  int32_t* bucket;       // record of each kept candidate, grouped by row
+  int32_t* scan_blocks;  // per scan block partial sums
+  int64_t* counters;     // [0] records used [1] record capacity
+                         // [2] overflow bits [3] candidates found
+};
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ uint32_t f2key(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key2f(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __uint_as_float(u);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o, kWave);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, kWave);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, kWave);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// Block-wide reductions for 256 threads.  `red` is LDS scratch of at least
+// kWaves elements of T; the result is returned to every thread.  The
+// combination order is fixed, so floating-point sums are deterministic.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  T r = (red[0] + red[1]) + (red[2] + red[3]);
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ T block_min(T v, T* red) {
+  v = wave_min(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  T a = red[0] < red[1] ? red[0] : red[1];
+  T b = red[2] < red[3] ? red[2] : red[3];
+  return a < b ? a : b;
+}
+template <typename T>
+__device__ __forceinline__ T block_max(T v, T* red) {
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  T a = red[0] > red[1] ? red[0] : red[1];
+  T b = red[2] > red[3] ? red[2] : red[3];
+  return a > b ? a : b;
+}
+
+// Exclusive scan over the 256 threads of a block (int).  `red` is LDS
+// scratch of kWaves ints.  Returns the exclusive prefix; *total gets the sum.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* red,
+                                                    int* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int u = __shfl_up(x, o, kWave);
+    if (lane >= o) x += u;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) red[w] = x;
+  __syncthreads();
+  int off = 0;
+  for (int i = 0; i < w; ++i) off += red[i];
+  *total = red[0] + red[1] + red[2] + red[3];
+  return off + x - v;
+}
+
+// Frame owning a flat index, given each frame's first index (ascending).
+__device__ __forceinline__ int find_frame(const FrameDev* fr, int nframes,
+                                          int idx, int FrameDev::*first) {
+  int lo = 0, hi = nframes - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (fr[mid].*first <= idx) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Natural-spline node coordinate along one axis: centre of region i.
+__device__ __forceinline__ double node_coord(int i, int m, int n) {
+  int a = i * m;
+  int b = min(a + m, n);
+  return 0.5 * (double)(a + b - 1);
+}
+
+// Weights (A, B, C, D) of S(t) = A f_j + B f_{j+1} + C M_j + D M_{j+1} for
+// the natural cubic spline on nodes node_coord(0..n-1), extended linearly
+// beyond the end nodes; j is returned in *j (j+1 clamped for n == 1).
+__device__ __forceinline__ void spline_weights(double t, int m, int len,
+                                               int n, int* jout,
+                                               double* w4) {
+  if (n == 1) {
+    *jout = 0;
+    w4[0] = 1.0; w4[1] = 0.0; w4[2] = 0.0; w4[3] = 0.0;
+    return;
+  }
+  // interval: largest j <= n-2 with t_j <= t (t_0 if below)
+  int j = (int)floor((t - (0.5 * (m - 1))) / (double)m);
+  j = max(0, min(j, n - 2));
+  double tj = node_coord(j, m, len);
+  double tj1 = node_coord(j + 1, m, len);
+  if (t < tj && j > 0) { --j; tj1 = tj; tj = node_coord(j, m, len); }
+  if (t > tj1 && j < n - 2) { ++j; tj = tj1; tj1 = node_coord(j + 1, m, len); }
+  double h = tj1 - tj;
+  *jout = j;
+  if (t < tj) {                 // left extension (j == 0)
+    double u = (t - tj) / h;
+    w4[0] = 1.0 - u; w4[1] = u;
+    w4[2] = -u * h * h / 3.0; w4[3] = -u * h * h / 6.0;
+  } else if (t > tj1) {         // right extension (j == n-2)
+    double u = (t - tj1) / h;
+    w4[0] = -u; w4[1] = 1.0 + u;
+    w4[2] = u * h * h / 6.0; w4[3] = u * h * h / 3.0;
+  } else {
+    double A = (tj1 - t) / h;
+    double B = (t - tj) / h;
+    w4[0] = A; w4[1] = B;
+    w4[2] = (A * A * A - A) * (h * h) / 6.0;
+    w4[3] = (B * B * B - B) * (h * h) / 6.0;
+  }
+}
+
+}  // namespace ipp

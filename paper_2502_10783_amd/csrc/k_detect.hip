@@ -1,0 +1,733 @@
+// Detection (Sec. 2.2.5): background removal and threshold, connection of
+// detected pixels into candidates, and candidate pre-analysis.
+//
+// Labelling is two-level.  k_tile_ccl labels each TH x TW tile in LDS with
+// a lock-free union-find (union by minimum index, so a tile component's
+// root is its first pixel in raster order) and emits one record per tile
+// component that touches an inner tile border or is already large enough
+// to keep.  k_border joins records across tile borders with the same
+// union-find on records in global memory, k_resolve folds every record
+// into its root, and the kept candidates are numbered 1..K in raster order
+// of their first pixel through per-row counts, a scan and a within-row
+// rank.  k_relabel writes the final label map; k_source_stats measures
+// each candidate with exact integer sums (one wavefront per candidate).
+#include "ipp_internal.h"
+#include "kernels.h"
+#include "spline_tile.h"
+
+namespace ipp {
+
+namespace {
+
+template <int TH, int TW, bool CONN8>
+struct CclLds {
+  static constexpr int NP = TH * TW;
+  static constexpr int NCMP = CONN8 ? NP / 4 : NP / 2;
+  int parent[NP];
+  int16_t cid[NP];
+  union {
+    SplineLds<TH, TW> spl;
+    struct {
+      int npix[NCMP];
+      int xmin[NCMP];
+      int xmax[NCMP];
+      int ymax[NCMP];
+      int16_t rootp[NCMP];
+      int16_t rloc[NCMP];
+    } st;
+  } u;
+  int wcnt[16 * kWaves];
+  int ired[kWaves];
+  int ncomp;
+  int nkept;
+  long long rbase;
+};
+
+__device__ __forceinline__ int lds_load(const int* a) {
+  return __atomic_load_n(a, __ATOMIC_RELAXED);
+}
+
+__device__ __forceinline__ int lfind(int* parent, int x) {
+  int px = lds_load(&parent[x]);
+  while (px != x) {
+    x = px;
+    px = lds_load(&parent[x]);
+  }
+  return x;
+}
+
+__device__ __forceinline__ void lunion(int* parent, int a, int b) {
+  while (true) {
+    a = lfind(parent, a);
+    b = lfind(parent, b);
+    if (a == b) return;
+    if (a < b) { int t = a; a = b; b = t; }
+    int old = atomicMin(&parent[a], b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+__device__ __forceinline__ int gload(const int32_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int gfind(int32_t* parent, int x) {
+  int px = gload(&parent[x]);
+  while (px != x) {
+    x = px;
+    px = gload(&parent[x]);
+  }
+  return x;
+}
+
+__device__ __forceinline__ void gunion(int32_t* parent, int a, int b) {
+  while (true) {
+    a = gfind(parent, a);
+    b = gfind(parent, b);
+    if (a == b) return;
+    if (a < b) { int t = a; a = b; b = t; }
+    int old = atomicMin(&parent[a], b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & (kWave - 1);
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------
+// Plain-path background maps: B32 = fl32(B64), R32 = fl32(R64).
+// ---------------------------------------------------------------------
+template <int TH, int TW>
+__global__ __launch_bounds__(kBlock) void k_bkg_maps(Work wk, ipp_params p) {
+  __shared__ SplineLds<TH, TW> S;
+  const int tile = blockIdx.x;
+  const int f = find_frame(wk.frames, wk.nframes, tile, &FrameDev::dtile0);
+  const FrameDev fr = wk.frames[f];
+  const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
+  const int y0 = ty * TH, x0 = tx * TW;
+  spline_prologue<TH, TW>(wk, fr, p, y0, x0, S);
+#pragma unroll 4
+  for (int k = 0; k < TH * TW / kBlock; ++k) {
+    const int q = threadIdx.x + kBlock * k;
+    const int r = q / TW, c = q % TW;
+    const int y = y0 + r, x = x0 + c;
+    if (y < fr.h && x < fr.w) {
+      double b, rr;
+      spline_pixel<TH, TW>(S, r, c, &b, &rr);
+      const int64_t o = (int64_t)y * fr.w + x;
+      fr.bkg[o] = (float)b;
+      fr.rms[o] = (float)rr;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// Tile kernel: threshold + LDS labelling + records.
+// ---------------------------------------------------------------------
+template <int TH, int TW, bool FUSED, bool CONN8>
+__global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
+                                                     int write_rms) {
+  using Lds = CclLds<TH, TW, CONN8>;
+  constexpr int NP = Lds::NP;
+  constexpr int NCMP = Lds::NCMP;
+  constexpr int PPT = NP / kBlock;            // 16
+  __shared__ Lds L;
+  const int t = threadIdx.x;
+  const int lane = t & (kWave - 1), wv = t / kWave;
+  const int tile = blockIdx.x;
+  const int f = find_frame(wk.frames, wk.nframes, tile, &FrameDev::dtile0);
+  const FrameDev fr = wk.frames[f];
+  const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
+  const int y0 = ty * TH, x0 = tx * TW;
+
+  if (FUSED) spline_prologue<TH, TW>(wk, fr, p, y0, x0, L.u.spl);
+
+  // ---- threshold: v = I - B32 > nsigma * R32 ---------------------------
+  uint32_t fgm = 0;
+#pragma unroll 4
+  for (int k = 0; k < PPT; ++k) {
+    const int q = t + kBlock * k;
+    const int r = q / TW, c = q % TW;
+    const int y = y0 + r, x = x0 + c;
+    bool det = false;
+    if (y < fr.h && x < fr.w) {
+      const float I = fr.pix[(int64_t)y * fr.pitch + x];
+      const int64_t o = (int64_t)y * fr.w + x;
+      float B32, R32;
+      if (FUSED) {
+        double b, rr;
+        spline_pixel<TH, TW>(L.u.spl, r, c, &b, &rr);
+        B32 = (float)b;
+        R32 = (float)rr;
+        fr.bkg[o] = B32;
+        if (write_rms) fr.rms[o] = R32;
+      } else {
+        B32 = fr.bkg[o];
+        R32 = fr.rms[o];
+      }
+      const double v = (double)I - (double)B32;
+      const double thr = p.det_nsigma * (double)R32;
+      det = isfinite(I) && (v > thr);
+    }
+    fgm |= (uint32_t)det << k;
+    L.parent[q] = det ? q : -1;
+  }
+  __syncthreads();
+
+  // ---- union with the already-visited neighbours -----------------------
+#pragma unroll 4
+  for (int k = 0; k < PPT; ++k) {
+    if (!((fgm >> k) & 1u)) continue;
+    const int q = t + kBlock * k;
+    const int r = q / TW, c = q % TW;
+    if (c > 0 && lds_load(&L.parent[q - 1]) >= 0) lunion(L.parent, q, q - 1);
+    if (r > 0) {
+      if (lds_load(&L.parent[q - TW]) >= 0) lunion(L.parent, q, q - TW);
+      if (CONN8) {
+        if (c > 0 && lds_load(&L.parent[q - TW - 1]) >= 0)
+          lunion(L.parent, q, q - TW - 1);
+        if (c < TW - 1 && lds_load(&L.parent[q - TW + 1]) >= 0)
+          lunion(L.parent, q, q - TW + 1);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int k = 0; k < PPT; ++k) {
+    if ((fgm >> k) & 1u) {
+      const int q = t + kBlock * k;
+      L.parent[q] = lfind(L.parent, q);
+    }
+  }
+  __syncthreads();
+
+  // ---- component ids in raster order of their roots --------------------
+  uint32_t rootm = 0;
+#pragma unroll 4
+  for (int k = 0; k < PPT; ++k) {
+    const int q = t + kBlock * k;
+    const bool isroot = ((fgm >> k) & 1u) && L.parent[q] == q;
+    rootm |= (uint32_t)isroot << k;
+    const uint64_t b = __ballot(isroot);
+    if (lane == 0) L.wcnt[k * kWaves + wv] = __popcll(b);
+  }
+  __syncthreads();
+  if (t == 0) {
+    int s = 0;
+    for (int i = 0; i < PPT * kWaves; ++i) {
+      const int v = L.wcnt[i];
+      L.wcnt[i] = s;
+      s += v;
+    }
+    L.ncomp = s;
+  }
+  __syncthreads();
+  const int ncomp = L.ncomp;
+#pragma unroll 4
+  for (int k = 0; k < PPT; ++k) {
+    const bool isroot = (rootm >> k) & 1u;
+    const uint64_t b = __ballot(isroot);
+    if (isroot) {
+      const int q = t + kBlock * k;
+      const int id = L.wcnt[k * kWaves + wv] + __popcll(b & lanemask_lt());
+      L.cid[q] = (int16_t)id;
+      L.u.st.rootp[id] = (int16_t)q;
+    }
+  }
+  for (int c = t; c < ncomp; c += kBlock) {
+    L.u.st.npix[c] = 0;
+    L.u.st.xmin[c] = TW;
+    L.u.st.xmax[c] = -1;
+    L.u.st.ymax[c] = -1;
+  }
+  __syncthreads();
+
+  // ---- per-component pixel count, bounding box, inner-border contact ----
+  const bool nb_up = y0 > 0, nb_down = y0 + TH < fr.h;
+  const bool nb_left = x0 > 0, nb_right = x0 + TW < fr.w;
+#pragma unroll 4
+  for (int k = 0; k < PPT; ++k) {
+    if (!((fgm >> k) & 1u)) continue;
+    const int q = t + kBlock * k;
+    const int r = q / TW, c = q % TW;
+    const int id = L.cid[L.parent[q]];
+    atomicAdd(&L.u.st.npix[id], 1);
+    atomicMin(&L.u.st.xmin[id], c);
+    atomicMax(&L.u.st.xmax[id], c);
+    atomicMax(&L.u.st.ymax[id], r);
+    const bool edge = (r == 0 && nb_up) || (r == TH - 1 && nb_down) ||
+                      (c == 0 && nb_left) || (c == TW - 1 && nb_right);
+    if (edge) atomicOr(&L.u.st.npix[id], 1 << 30);
+  }
+  __syncthreads();
+
+  // ---- kept components -> records ---------------------------------------
+  constexpr int CPT = NCMP / kBlock;
+  int kc = 0;
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int c = t * CPT + i;
+    if (c < ncomp) {
+      const int np = L.u.st.npix[c];
+      kc += ((np >> 30) & 1) || ((np & 0x3FFFFFFF) >= p.min_area);
+    }
+  }
+  int ktot;
+  int ex = block_exclusive_scan(kc, L.ired, &ktot);
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int c = t * CPT + i;
+    if (c < ncomp) {
+      const int np = L.u.st.npix[c];
+      const bool kept = ((np >> 30) & 1) || ((np & 0x3FFFFFFF) >= p.min_area);
+      L.u.st.rloc[c] = kept ? (int16_t)ex : (int16_t)-1;
+      ex += kept;
+    }
+  }
+  if (t == 0) {
+    long long base = 0;
+    if (ktot > 0)
+      base = (long long)atomicAdd((unsigned long long*)&wk.counters[0],
+                                  (unsigned long long)ktot);
+    if (base + ktot > wk.rec_cap)
+      atomicOr((unsigned long long*)&wk.counters[2], 1ull);
+    L.rbase = base;
+    L.nkept = ktot;
+    wk.tile_rbase[tile] = (int32_t)(base < wk.rec_cap ? base : wk.rec_cap);
+  }
+  __syncthreads();
+  const long long rbase = L.rbase;
+  for (int c = t; c < ncomp; c += kBlock) {
+    const int rl = L.u.st.rloc[c];
+    if (rl < 0) continue;
+    const long long rec = rbase + rl;
+    if (rec >= wk.rec_cap) continue;
+    const int rp = L.u.st.rootp[c];
+    const int rr = rp / TW, rc = rp % TW;
+    Rec R;
+    R.minidx = (y0 + rr) * fr.w + (x0 + rc);
+    R.npix = L.u.st.npix[c] & 0x3FFFFFFF;
+    R.xmin = x0 + L.u.st.xmin[c];
+    R.xmax = x0 + L.u.st.xmax[c];
+    R.ymin = y0 + rr;
+    R.ymax = y0 + L.u.st.ymax[c];
+    R.frame = f;
+    R.pad = 0;
+    wk.recs[rec] = R;
+    wk.rparent[rec] = (int32_t)rec;
+    wk.rlabel[rec] = 0;
+  }
+  // ---- local map: record index within the tile + 1 ----------------------
+#pragma unroll 4
+  for (int k = 0; k < PPT; ++k) {
+    const int q = t + kBlock * k;
+    const int r = q / TW, c = q % TW;
+    const int y = y0 + r, x = x0 + c;
+    if (y < fr.h && x < fr.w) {
+      uint16_t v = 0;
+      if ((fgm >> k) & 1u) {
+        const int rl = L.u.st.rloc[L.cid[L.parent[q]]];
+        if (rl >= 0 && rbase + rl < wk.rec_cap) v = (uint16_t)(rl + 1);
+      }
+      wk.lmap[fr.pix0 + (int64_t)y * fr.w + x] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// Join records across the right and bottom border of every tile.
+// ---------------------------------------------------------------------
+template <int TH, int TW>
+__global__ __launch_bounds__(kBlock) void k_border(Work wk, ipp_params p) {
+  const int tile = blockIdx.x;
+  const int f = find_frame(wk.frames, wk.nframes, tile, &FrameDev::dtile0);
+  const FrameDev fr = wk.frames[f];
+  const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
+  const int y0 = ty * TH, x0 = tx * TW;
+  const bool c8 = p.connectivity == 8;
+  const uint16_t* lm = wk.lmap + fr.pix0;
+  auto rec_of = [&](int y, int x, int l) {
+    const int tt = fr.dtile0 + (y / TH) * fr.dtx + (x / TW);
+    return wk.tile_rbase[tt] + l - 1;
+  };
+  const int t = threadIdx.x;
+  if (t < TH) {                       // right border
+    const int y = y0 + t, x = x0 + TW - 1;
+    if (y < fr.h && x + 1 < fr.w) {
+      const int a = lm[(int64_t)y * fr.w + x];
+      if (a) {
+        const int ra = rec_of(y, x, a);
+        for (int dy = c8 ? -1 : 0; dy <= (c8 ? 1 : 0); ++dy) {
+          const int yy = y + dy;
+          if (yy < 0 || yy >= fr.h) continue;
+          const int b = lm[(int64_t)yy * fr.w + x + 1];
+          if (b) gunion(wk.rparent, ra, rec_of(yy, x + 1, b));
+        }
+      }
+    }
+  } else if (t < TH + TW) {           // bottom border
+    const int y = y0 + TH - 1, x = x0 + (t - TH);
+    if (x < fr.w && y + 1 < fr.h) {
+      const int a = lm[(int64_t)y * fr.w + x];
+      if (a) {
+        const int ra = rec_of(y, x, a);
+        for (int dx = c8 ? -1 : 0; dx <= (c8 ? 1 : 0); ++dx) {
+          const int xx = x + dx;
+          if (xx < 0 || xx >= fr.w) continue;
+          const int b = lm[(int64_t)(y + 1) * fr.w + xx];
+          if (b) gunion(wk.rparent, ra, rec_of(y + 1, xx, b));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// Record-level passes (grid-stride over the records in use).
+// ---------------------------------------------------------------------
+__device__ __forceinline__ long long nrec_used(const Work& wk) {
+  const long long u = wk.counters[0];
+  return u < wk.rec_cap ? u : wk.rec_cap;
+}
+
+__global__ __launch_bounds__(kBlock) void k_resolve(Work wk, ipp_params p) {
+  const long long n = nrec_used(wk);
+  for (long long r = blockIdx.x * (long long)kBlock + threadIdx.x; r < n;
+       r += (long long)gridDim.x * kBlock) {
+    const int root = gfind(wk.rparent, (int)r);
+    if (root != r) {
+      wk.rparent[r] = root;
+      const Rec R = wk.recs[r];
+      Rec* T = &wk.recs[root];
+      atomicAdd(&T->npix, R.npix);
+      atomicMin(&T->minidx, R.minidx);
+      atomicMin(&T->xmin, R.xmin);
+      atomicMax(&T->xmax, R.xmax);
+      atomicMin(&T->ymin, R.ymin);
+      atomicMax(&T->ymax, R.ymax);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_heads(Work wk, ipp_params p) {
+  const long long n = nrec_used(wk);
+  for (long long r = blockIdx.x * (long long)kBlock + threadIdx.x; r < n;
+       r += (long long)gridDim.x * kBlock) {
+    if (wk.rparent[r] != r) continue;
+    const Rec R = wk.recs[r];
+    if (R.npix < p.min_area) continue;
+    const FrameDev& fr = wk.frames[R.frame];
+    atomicAdd(&wk.row_count[fr.row0 + R.minidx / fr.w], 1);
+  }
+}
+
+// Exclusive scan of n <= 2^20 ints in blocks of 1024.
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(const int32_t* in,
+                                                        int32_t* blocks,
+                                                        int n) {
+  __shared__ int red[kWaves];
+  const int b0 = blockIdx.x * 1024;
+  int s = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int j = b0 + threadIdx.x * 4 + i;
+    if (j < n) s += in[j];
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) blocks[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_top(int32_t* blocks,
+                                                     int nblocks,
+                                                     int64_t* total) {
+  __shared__ int red[kWaves];
+  int v[4];
+  int s = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int j = threadIdx.x * 4 + i;
+    v[i] = j < nblocks ? blocks[j] : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_exclusive_scan(s, red, &tot);
+  for (int i = 0; i < 4; ++i) {
+    const int j = threadIdx.x * 4 + i;
+    if (j < nblocks) blocks[j] = ex;
+    ex += v[i];
+  }
+  if (threadIdx.x == 0) *total = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t* in,
+                                                       const int32_t* blocks,
+                                                       int32_t* out, int n) {
+  __shared__ int red[kWaves];
+  const int b0 = blockIdx.x * 1024;
+  int v[4];
+  int s = 0;
+  for (int i = 0; i < 4; ++i) {
+    const int j = b0 + threadIdx.x * 4 + i;
+    v[i] = j < n ? in[j] : 0;
+    s += v[i];
+  }
+  int tot;
+  int ex = block_exclusive_scan(s, red, &tot) + blocks[blockIdx.x];
+  for (int i = 0; i < 4; ++i) {
+    const int j = b0 + threadIdx.x * 4 + i;
+    if (j < n) out[j] = ex;
+    ex += v[i];
+  }
+}
+
+__global__ void k_frame_offsets(Work wk, ipp_sources src) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < wk.nframes)
+    src.frame_offsets[f] = wk.row_start[wk.frames[f].row0];
+  if (f == 0) {
+    src.frame_offsets[wk.nframes] = wk.counters[3];
+    if (src.n_total) *src.n_total = wk.counters[3];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(Work wk, ipp_params p) {
+  const long long n = nrec_used(wk);
+  for (long long r = blockIdx.x * (long long)kBlock + threadIdx.x; r < n;
+       r += (long long)gridDim.x * kBlock) {
+    if (wk.rparent[r] != r) continue;
+    const Rec R = wk.recs[r];
+    if (R.npix < p.min_area) continue;
+    const FrameDev& fr = wk.frames[R.frame];
+    const int g = fr.row0 + R.minidx / fr.w;
+    const int slot = atomicAdd(&wk.row_cursor[g], 1);
+    wk.bucket[wk.row_start[g] + slot] = (int32_t)r;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank(Work wk, ipp_params p,
+                                                 ipp_sources src) {
+  const long long n = wk.counters[3];
+  for (long long e = blockIdx.x * (long long)kBlock + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kBlock) {
+    const int r = wk.bucket[e];
+    const Rec R = wk.recs[r];
+    const FrameDev& fr = wk.frames[R.frame];
+    const int g = fr.row0 + R.minidx / fr.w;
+    const int s0 = wk.row_start[g], cnt = wk.row_count[g];
+    int rank = 0;
+    for (int i = 0; i < cnt; ++i)
+      rank += wk.recs[wk.bucket[s0 + i]].minidx < R.minidx;
+    const long long out = (long long)s0 + rank;
+    const int label = (int)(out - wk.row_start[fr.row0]) + 1;
+    wk.rlabel[r] = label;
+    if (out < src.capacity) {
+      src.frame[out] = R.frame;
+      src.label[out] = label;
+      src.npix[out] = R.npix;
+      src.xmin[out] = R.xmin;
+      src.xmax[out] = R.xmax;
+      src.ymin[out] = R.ymin;
+      src.ymax[out] = R.ymax;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reclabel(Work wk) {
+  const long long n = nrec_used(wk);
+  for (long long r = blockIdx.x * (long long)kBlock + threadIdx.x; r < n;
+       r += (long long)gridDim.x * kBlock) {
+    const int root = wk.rparent[r];
+    if (root != r) wk.rlabel[r] = wk.rlabel[root];
+  }
+}
+
+template <int TH, int TW>
+__global__ __launch_bounds__(kBlock) void k_relabel(Work wk, ipp_params p) {
+  const int tile = blockIdx.x;
+  const int f = find_frame(wk.frames, wk.nframes, tile, &FrameDev::dtile0);
+  const FrameDev fr = wk.frames[f];
+  const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
+  const int y0 = ty * TH, x0 = tx * TW;
+  const int rb = wk.tile_rbase[tile];
+#pragma unroll 4
+  for (int k = 0; k < TH * TW / kBlock; ++k) {
+    const int q = threadIdx.x + kBlock * k;
+    const int y = y0 + q / TW, x = x0 + q % TW;
+    if (y < fr.h && x < fr.w) {
+      const int64_t o = (int64_t)y * fr.w + x;
+      const int l = wk.lmap[fr.pix0 + o];
+      int lab = 0;
+      if (l) {
+        const long long rec = (long long)rb + l - 1;
+        if (rec < wk.rec_cap) lab = wk.rlabel[rec];
+      }
+      fr.labels[o] = lab;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// Source table: one wavefront per candidate, exact sums.
+// ---------------------------------------------------------------------
+namespace {
+
+struct U128 {
+  uint64_t lo, hi;
+};
+
+__device__ __forceinline__ U128 add128(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo);
+  return r;
+}
+__device__ __forceinline__ U128 from_i64(int64_t v) {
+  U128 r;
+  r.lo = (uint64_t)v;
+  r.hi = v < 0 ? ~0ull : 0ull;
+  return r;
+}
+// v * m for m >= 0 small (< 2^31)
+__device__ __forceinline__ U128 mul_i64(int64_t v, int64_t m) {
+  const __int128 p = (__int128)v * (__int128)m;
+  U128 r;
+  r.lo = (uint64_t)p;
+  r.hi = (uint64_t)(p >> 64);
+  return r;
+}
+__device__ __forceinline__ U128 wave_sum128(U128 v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    U128 u;
+    u.lo = __shfl_xor(v.lo, o, kWave);
+    u.hi = __shfl_xor(v.hi, o, kWave);
+    v = add128(v, u);
+  }
+  return v;
+}
+// Correctly rounded (to nearest, ties to even) conversion to binary64.
+__device__ double to_double(U128 v) {
+  const bool neg = (int64_t)v.hi < 0;
+  unsigned __int128 u = ((unsigned __int128)v.hi << 64) | v.lo;
+  if (neg) u = (unsigned __int128)0 - u;
+  if (u == 0) return 0.0;
+  const uint64_t hi = (uint64_t)(u >> 64), lo = (uint64_t)u;
+  const int top = hi ? 127 - __clzll(hi) : 63 - __clzll(lo);
+  double r;
+  if (top < 53) {
+    r = (double)(uint64_t)u;
+  } else {
+    const int sh = top - 52;
+    uint64_t mant = (uint64_t)(u >> sh);
+    const unsigned __int128 rem = u & ((((unsigned __int128)1) << sh) - 1);
+    const unsigned __int128 half = ((unsigned __int128)1) << (sh - 1);
+    if (rem > half || (rem == half && (mant & 1))) mant += 1;
+    r = ldexp((double)mant, sh);
+  }
+  return neg ? -r : r;
+}
+
+__device__ __forceinline__ bool exact_range(float a) {
+  const float m = fabsf(a);
+  return m == 0.0f || (m >= 0.03125f && m <= 16777216.0f);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
+                                                         ipp_sources src) {
+  const int lane = threadIdx.x & (kWave - 1);
+  long long nrows = wk.counters[3];
+  if (nrows > src.capacity) nrows = src.capacity;
+  const long long wid = (blockIdx.x * (long long)kBlock + threadIdx.x) / kWave;
+  const long long nw = (long long)gridDim.x * (kBlock / kWave);
+  const double two_q = 268435456.0;                  // 2^28
+  const double dmax = 4611686018427387903.0;         // 2^62 - 1
+  for (long long row = wid; row < nrows; row += nw) {
+    const int f = src.frame[row];
+    const int label = src.label[row];
+    const int xmin = src.xmin[row], xmax = src.xmax[row];
+    const int ymin = src.ymin[row], ymax = src.ymax[row];
+    const FrameDev fr = wk.frames[f];
+    const int bw = xmax - xmin + 1;
+    const long long area = (long long)bw * (ymax - ymin + 1);
+    U128 S = {0, 0}, Sx = {0, 0}, Sy = {0, 0};
+    long long ux = 0, uy = 0;
+    double pk = -__builtin_inf();
+    int pidx = 0x7FFFFFFF;
+    uint32_t flags = 0;
+    for (long long e = lane; e < area; e += kWave) {
+      const int y = ymin + (int)(e / bw), x = xmin + (int)(e % bw);
+      const int64_t o = (int64_t)y * fr.w + x;
+      if (fr.labels[o] != label) continue;
+      const float I = fr.pix[(int64_t)y * fr.pitch + x];
+      const float B = fr.bkg[o];
+      const double v = (double)I - (double)B;
+      double s = rint(v * two_q);
+      if (!(exact_range(I) && exact_range(B))) flags |= IPP_SRC_INEXACT_SUM_RANGE;
+      if (s > dmax) { s = dmax; flags |= IPP_SRC_INEXACT_SUM_RANGE; }
+      if (s < -dmax) { s = -dmax; flags |= IPP_SRC_INEXACT_SUM_RANGE; }
+      const int64_t D = (int64_t)s;
+      S = add128(S, from_i64(D));
+      Sx = add128(Sx, mul_i64(D, x - xmin));
+      Sy = add128(Sy, mul_i64(D, y - ymin));
+      ux += x - xmin;
+      uy += y - ymin;
+      const int idx = y * fr.w + x;
+      if (v > pk || (v == pk && idx < pidx)) { pk = v; pidx = idx; }
+    }
+    S = wave_sum128(S);
+    Sx = wave_sum128(Sx);
+    Sy = wave_sum128(Sy);
+    ux = wave_sum(ux);
+    uy = wave_sum(uy);
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const double pv = __shfl_xor(pk, o, kWave);
+      const int pi = __shfl_xor(pidx, o, kWave);
+      if (pv > pk || (pv == pk && pi < pidx)) { pk = pv; pidx = pi; }
+      flags |= __shfl_xor(flags, o, kWave);
+    }
+    if (lane == 0) {
+      const double dS = to_double(S);
+      double cx, cy;
+      if ((int64_t)S.hi > 0 || ((int64_t)S.hi == 0 && S.lo > 0)) {
+        cx = (double)xmin + to_double(Sx) / dS;
+        cy = (double)ymin + to_double(Sy) / dS;
+      } else {
+        flags |= IPP_SRC_NONPOSITIVE_FLUX;
+        const double np = (double)src.npix[row];
+        cx = (double)xmin + (double)ux / np;
+        cy = (double)ymin + (double)uy / np;
+      }
+      src.flux_iso[row] = dS / two_q;
+      src.x[row] = cx;
+      src.y[row] = cy;
+      src.peak[row] = pk;
+      src.peak_x[row] = pidx % fr.w;
+      src.peak_y[row] = pidx / fr.w;
+      src.flags[row] = flags;
+    }
+  }
+}
+
+#define IPP_TILE_INST(TH, TW)                                              \
+  template __global__ void k_bkg_maps<TH, TW>(Work, ipp_params);           \
+  template __global__ void k_tile_ccl<TH, TW, true, true>(Work, ipp_params, \
+                                                          int);             \
+  template __global__ void k_tile_ccl<TH, TW, true, false>(Work,           \
+                                                           ipp_params, int); \
+  template __global__ void k_tile_ccl<TH, TW, false, true>(Work,           \
+                                                           ipp_params, int); \
+  template __global__ void k_tile_ccl<TH, TW, false, false>(Work,          \
+                                                            ipp_params, int); \
+  template __global__ void k_border<TH, TW>(Work, ipp_params);             \
+  template __global__ void k_relabel<TH, TW>(Work, ipp_params);
+
+IPP_TILE_INST(64, 64)
+IPP_TILE_INST(32, 128)
+IPP_TILE_INST(128, 32)
+
+}  // namespace ipp

@@ -1,0 +1,38 @@
+// Kernel declarations of libipp (definitions in k_*.hip).
+#pragma once
+
+#include "ipp_internal.h"
+
+namespace ipp {
+
+template <int PPT>
+__global__ void k_mesh_stats(Work wk, ipp_params p);
+__global__ void k_mesh_finish(Work wk, ipp_params p);
+
+template <int TH, int TW>
+__global__ void k_bkg_maps(Work wk, ipp_params p);
+template <int TH, int TW, bool FUSED, bool CONN8>
+__global__ void k_tile_ccl(Work wk, ipp_params p, int write_rms);
+template <int TH, int TW>
+__global__ void k_border(Work wk, ipp_params p);
+template <int TH, int TW>
+__global__ void k_relabel(Work wk, ipp_params p);
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v);
+__global__ void k_fill_i64(int64_t* a, int64_t n, int64_t v);
+__global__ void k_resolve(Work wk, ipp_params p);
+__global__ void k_heads(Work wk, ipp_params p);
+__global__ void k_scan_blocks(const int32_t* in, int32_t* blocks, int n);
+__global__ void k_scan_top(int32_t* blocks, int nblocks, int64_t* total);
+__global__ void k_scan_apply(const int32_t* in, const int32_t* blocks,
+                             int32_t* out, int n);
+__global__ void k_frame_offsets(Work wk, ipp_sources src);
+__global__ void k_scatter(Work wk, ipp_params p);
+__global__ void k_rank(Work wk, ipp_params p, ipp_sources src);
+__global__ void k_reclabel(Work wk);
+__global__ void k_source_stats(Work wk, ipp_sources src);
+
+__global__ void k_aperture(Work wk, ipp_params p, ipp_sources src,
+                           double* sky_lohi);
+
+}  // namespace ipp

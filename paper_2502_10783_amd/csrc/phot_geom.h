@@ -1,0 +1,82 @@
+// Exact circle/pixel overlap geometry in binary64 for aperture photometry.
+//
+// The signed corner integral G(x, y) = int_0^x int_0^y [s^2+t^2 <= r^2] of
+// a disk of radius r about the origin is odd in x and in y; for
+// 0 <= x, y <= r it is x*y when the corner lies in the circle and otherwise
+// y*xs + P(x) - P(xs) with xs = sqrt(r^2 - y^2) and
+// P(s) = int_0^s sqrt(r^2 - u^2) du = (s sqrt(r^2 - s^2) + r^2 asin(s/r))/2.
+// A pixel's overlap is the inclusion-exclusion of G over its corners.
+// Membership (the pixel square meets the open disk) and full containment
+// are decided by the exact predicates below, so that every pixel that a
+// rounding residue could move in or out is classified the same way on
+// every device.  dG/dx(x, y) = sign(y) min(|y|, sqrt(r^2 - x^2)) gives the
+// derivative of an overlap with respect to the disk centre.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ipp {
+
+__device__ __forceinline__ bool touches(double cx, double cy, double r,
+                                        int px, int py) {
+  const double dx = fmax(fabs((double)px - cx) - 0.5, 0.0);
+  const double dy = fmax(fabs((double)py - cy) - 0.5, 0.0);
+  return dx * dx + dy * dy < r * r;
+}
+
+__device__ __forceinline__ bool within(double cx, double cy, double r,
+                                       int px, int py) {
+  const double fx = fabs((double)px - cx) + 0.5;
+  const double fy = fabs((double)py - cy) + 0.5;
+  return fx * fx + fy * fy <= r * r;
+}
+
+__device__ __forceinline__ double prim(double s, double r) {
+  return 0.5 * (s * sqrt(fmax(r * r - s * s, 0.0)) +
+                r * r * asin(fmin(s / r, 1.0)));
+}
+
+__device__ __forceinline__ double corner_area(double x, double y, double r) {
+  if (r <= 0.0) return 0.0;
+  const double sx = x < 0.0 ? -1.0 : 1.0;
+  const double sy = y < 0.0 ? -1.0 : 1.0;
+  const double ax = fmin(fabs(x), r), ay = fmin(fabs(y), r);
+  double a;
+  if (ax * ax + ay * ay <= r * r) {
+    a = ax * ay;
+  } else {
+    const double xs = sqrt(r * r - ay * ay);
+    a = ay * xs + prim(ax, r) - prim(xs, r);
+  }
+  return sx * sy * a;
+}
+
+__device__ __forceinline__ double overlap(double cx, double cy, double r,
+                                          int px, int py) {
+  if (!touches(cx, cy, r, px, py)) return 0.0;
+  if (within(cx, cy, r, px, py)) return 1.0;
+  const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
+  const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
+  return corner_area(x1, y1, r) - corner_area(x0, y1, r) -
+         corner_area(x1, y0, r) + corner_area(x0, y0, r);
+}
+
+__device__ __forceinline__ double chord(double x, double y, double r) {
+  if (r <= 0.0 || fabs(x) >= r) return 0.0;
+  const double h = sqrt(r * r - x * x);
+  return copysign(fmin(fabs(y), h), y);
+}
+
+// (d/dcx, d/dcy) of overlap(cx, cy, r, px, py).
+__device__ __forceinline__ void overlap_grad(double cx, double cy, double r,
+                                             int px, int py, double* gx,
+                                             double* gy) {
+  const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
+  const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
+  *gx = -(chord(x1, y1, r) - chord(x0, y1, r) - chord(x1, y0, r) +
+          chord(x0, y0, r));
+  *gy = -(chord(y1, x1, r) - chord(y0, x1, r) - chord(y1, x0, r) +
+          chord(y0, x0, r));
+}
+
+}  // namespace ipp
