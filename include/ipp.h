@@ -105,7 +105,7 @@ typedef struct ipp_params {
   int32_t sky_clip_iters;        /* annulus clip passes (0..16)            */
   double sky_clip_sigma;         /* annulus clip k (> 0)                   */
   double r_ap, r_in, r_out;      /* aperture and annulus radii in px,
-                                    0 < r_ap <= 32, 0 <= r_in < r_out <= 32 */
+                                    0 < r_ap <= 16, 0 <= r_in < r_out <= 16 */
   int32_t tile_h, tile_w;        /* detection tile shape; 0 = default.
                                     Supported: 64x64, 32x128, 128x32       */
   uint32_t flags;                /* IPP_F_*                                */
@@ -185,6 +185,18 @@ ipp_status ipp_ctx_destroy(void* ctx);
 ipp_status ipp_ctx_reserve(void* ctx, size_t bytes);
 /* Message of the last failed call on ctx ("" if none); owned by ctx. */
 const char* ipp_last_error(void* ctx);
+
+/* Kernel timing: with `on` != 0 every kernel a call enqueues is bracketed
+ * by a pair of HIP events recorded on the call's stream (this also clears
+ * the totals); 0 stops recording.  ipp_ctx_profile_read waits for the
+ * recorded events and returns the number of distinct kernels; for the
+ * first `max` of them it writes the name (32 bytes each, NUL-terminated,
+ * into names[32*max]), the summed milliseconds and the launch count.
+ * All three output arrays are host memory and nullable.  Returns -1 for a
+ * NULL ctx. */
+ipp_status ipp_ctx_profile(void* ctx, int32_t on);
+int32_t ipp_ctx_profile_read(void* ctx, int32_t max, char* names,
+                             double* total_ms, int32_t* count);
 
 /* Workspace bytes the calls below need for this batch, with room for
  * `record_capacity` partial candidates (a candidate cut by detection-tile

@@ -108,6 +108,12 @@ def lib():
     L.ipp_ctx_reserve.restype = i32
     L.ipp_last_error.argtypes = [vp]
     L.ipp_last_error.restype = C.c_char_p
+    L.ipp_ctx_profile.argtypes = [vp, i32]
+    L.ipp_ctx_profile.restype = i32
+    L.ipp_ctx_profile_read.argtypes = [vp, i32, C.c_char_p,
+                                       C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32)]
+    L.ipp_ctx_profile_read.restype = i32
     L.ipp_workspace_bytes.argtypes = [C.POINTER(IppFrame), i32,
                                       C.POINTER(IppParams), i64]
     L.ipp_workspace_bytes.restype = sz

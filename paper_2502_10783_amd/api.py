@@ -145,6 +145,21 @@ class Context:
         if st != L.IPP_OK:
             raise IppError(st, self.lib.ipp_last_error(self.h).decode())
 
+    def profile(self, on: bool):
+        """Start (clearing totals) or stop per-kernel event timing."""
+        self._check(self.lib.ipp_ctx_profile(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches)} since profiling was switched on."""
+        n = self.lib.ipp_ctx_profile_read(self.h, 0, None, None, None)
+        names = C.create_string_buffer(32 * max(n, 1))
+        ms = (C.c_double * max(n, 1))()
+        cnt = (C.c_int32 * max(n, 1))()
+        self.lib.ipp_ctx_profile_read(self.h, n, names, ms, cnt)
+        raw = names.raw
+        return {raw[32 * i:32 * i + 32].split(b"\0")[0].decode():
+                (ms[i], cnt[i]) for i in range(n)}
+
     def workspace_bytes(self, frames, params: Params, record_capacity=0):
         fc = frames_c(frames)
         pc = params.to_c()

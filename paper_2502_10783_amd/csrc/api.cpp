@@ -21,7 +21,16 @@ struct IppGraph {
   uint64_t ws_gen = 0;            // workspace generation the graph saw
 };
 
+struct ProfSlot {
+  const char* name;
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
 struct IppCtx {
+  bool prof = false;
+  std::vector<ProfSlot> pool;     // event pairs (reused)
+  size_t used = 0;                // pairs recorded since the last read
+  std::vector<std::pair<std::string, std::pair<double, int>>> totals;
   int device = 0;
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -31,6 +40,45 @@ struct IppCtx {
 };
 
 namespace {
+
+ProfSlot* prof_begin(IppCtx* c, hipStream_t s, const char* name) {
+  if (!c || !c->prof) return nullptr;
+  if (c->used == c->pool.size()) {
+    ProfSlot ps;
+    if (hipEventCreate(&ps.a) != hipSuccess ||
+        hipEventCreate(&ps.b) != hipSuccess)
+      return nullptr;
+    c->pool.push_back(ps);
+  }
+  ProfSlot* ps = &c->pool[c->used++];
+  ps->name = name;
+  hipEventRecord(ps->a, s);
+  return ps;
+}
+
+void prof_end(ProfSlot* ps, hipStream_t s) {
+  if (ps) hipEventRecord(ps->b, s);
+}
+
+// Fold the recorded event pairs into per-kernel totals (waits for them).
+void prof_collect(IppCtx* c) {
+  for (size_t i = 0; i < c->used; ++i) {
+    ProfSlot& ps = c->pool[i];
+    float ms = 0.f;
+    hipEventSynchronize(ps.b);
+    if (hipEventElapsedTime(&ms, ps.a, ps.b) != hipSuccess) ms = 0.f;
+    bool found = false;
+    for (auto& t : c->totals)
+      if (t.first == ps.name) {
+        t.second.first += ms;
+        t.second.second += 1;
+        found = true;
+        break;
+      }
+    if (!found) c->totals.push_back({ps.name, {(double)ms, 1}});
+  }
+  c->used = 0;
+}
 
 constexpr int64_t kMaxDim = 32767;
 constexpr size_t kAlign = 256;
@@ -213,14 +261,18 @@ Work make_work(const Plan& P, void* ws, int32_t n) {
   return w;
 }
 
-#define IPP_LAUNCH(c, ...)                                                  \
+// Launch with error check; with profiling on, the launch is bracketed by
+// a pair of events recorded on the same stream.
+#define IPP_LAUNCH(c, s, name, ...)                                         \
   do {                                                                      \
+    ProfSlot* ps_ = prof_begin(c, s, name);                                 \
     __VA_ARGS__;                                                            \
     hipError_t e_ = hipGetLastError();                                      \
     if (e_ != hipSuccess)                                                   \
       return fail(c, IPP_E_DEVICE,                                          \
                   std::string("kernel launch failed: ") +                   \
                       hipGetErrorString(e_));                               \
+    prof_end(ps_, s);                                                       \
   } while (0)
 
 int grid_for(int64_t items, int per_block, int cap) {
@@ -281,15 +333,15 @@ ipp_status run_mesh(IppCtx* c, const Plan& P, const Work& w,
                     const ipp_params& p, hipStream_t s) {
   const int area = p.mesh_h * p.mesh_w;
   if (area <= 4 * kBlock)
-    IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_stats<4>, dim3(P.nodes),
+    IPP_LAUNCH(c, s, "k_mesh_stats", hipLaunchKernelGGL(k_mesh_stats<4>, dim3(P.nodes),
                                      dim3(kBlock), 0, s, w, p));
   else if (area <= 16 * kBlock)
-    IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_stats<16>, dim3(P.nodes),
+    IPP_LAUNCH(c, s, "k_mesh_stats", hipLaunchKernelGGL(k_mesh_stats<16>, dim3(P.nodes),
                                      dim3(kBlock), 0, s, w, p));
   else
-    IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_stats<64>, dim3(P.nodes),
+    IPP_LAUNCH(c, s, "k_mesh_stats", hipLaunchKernelGGL(k_mesh_stats<64>, dim3(P.nodes),
                                      dim3(kBlock), 0, s, w, p));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_mesh_finish, dim3((int)P.fd.size()),
+  IPP_LAUNCH(c, s, "k_mesh_finish", hipLaunchKernelGGL(k_mesh_finish, dim3((int)P.fd.size()),
                                    dim3(kBlock), 0, s, w, p));
   return IPP_OK;
 }
@@ -297,7 +349,7 @@ ipp_status run_mesh(IppCtx* c, const Plan& P, const Work& w,
 template <int TH, int TW>
 ipp_status run_bkg_maps(IppCtx* c, const Plan& P, const Work& w,
                         const ipp_params& p, hipStream_t s) {
-  IPP_LAUNCH(c, hipLaunchKernelGGL((k_bkg_maps<TH, TW>), dim3(P.dtiles),
+  IPP_LAUNCH(c, s, "k_bkg_maps", hipLaunchKernelGGL((k_bkg_maps<TH, TW>), dim3(P.dtiles),
                                    dim3(kBlock), 0, s, w, p));
   return IPP_OK;
 }
@@ -308,25 +360,25 @@ ipp_status run_tile(IppCtx* c, const Plan& P, const Work& w,
                     hipStream_t s) {
   const dim3 g(P.dtiles), b(kBlock);
   if (fused && p.connectivity == 8)
-    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, true>), g, b,
+    IPP_LAUNCH(c, s, "k_tile_ccl_fused", hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, true>), g, b,
                                      0, s, w, p, write_rms));
   else if (fused)
-    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, false>), g,
+    IPP_LAUNCH(c, s, "k_tile_ccl_fused", hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, false>), g,
                                      b, 0, s, w, p, write_rms));
   else if (p.connectivity == 8)
-    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, true>), g,
+    IPP_LAUNCH(c, s, "k_tile_ccl", hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, true>), g,
                                      b, 0, s, w, p, write_rms));
   else
-    IPP_LAUNCH(c, hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, false>), g,
+    IPP_LAUNCH(c, s, "k_tile_ccl", hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, false>), g,
                                      b, 0, s, w, p, write_rms));
-  IPP_LAUNCH(c, hipLaunchKernelGGL((k_border<TH, TW>), g, b, 0, s, w, p));
+  IPP_LAUNCH(c, s, "k_border", hipLaunchKernelGGL((k_border<TH, TW>), g, b, 0, s, w, p));
   return IPP_OK;
 }
 
 template <int TH, int TW>
 ipp_status run_relabel(IppCtx* c, const Plan& P, const Work& w,
                        const ipp_params& p, hipStream_t s) {
-  IPP_LAUNCH(c, hipLaunchKernelGGL((k_relabel<TH, TW>), dim3(P.dtiles),
+  IPP_LAUNCH(c, s, "k_relabel", hipLaunchKernelGGL((k_relabel<TH, TW>), dim3(P.dtiles),
                                    dim3(kBlock), 0, s, w, p));
   return IPP_OK;
 }
@@ -345,13 +397,13 @@ __global__ void k_diag(Work w, int64_t* diag) {
 ipp_status run_detect(IppCtx* c, const Plan& P, const Work& w,
                       const ipp_params& p, ipp_sources* src, bool fused,
                       int write_rms, int64_t* diag, hipStream_t s) {
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s,
+  IPP_LAUNCH(c, s, "k_fill_i64", hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s,
                                    w.counters, (int64_t)4, (int64_t)0));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_fill_i32,
+  IPP_LAUNCH(c, s, "k_fill_i32", hipLaunchKernelGGL(k_fill_i32,
                                    dim3(grid_for(P.rows, kBlock, 4096)),
                                    dim3(kBlock), 0, s, w.row_count,
                                    (int64_t)P.rows, 0));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_fill_i32,
+  IPP_LAUNCH(c, s, "k_fill_i32", hipLaunchKernelGGL(k_fill_i32,
                                    dim3(grid_for(P.rows, kBlock, 4096)),
                                    dim3(kBlock), 0, s, w.row_cursor,
                                    (int64_t)P.rows, 0));
@@ -361,37 +413,37 @@ ipp_status run_detect(IppCtx* c, const Plan& P, const Work& w,
   else st = run_tile<64, 64>(c, P, w, p, fused, write_rms, s);
   if (st != IPP_OK) return st;
   const int gr = grid_for(P.rec_cap, kBlock, 2048);
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_resolve, dim3(gr), dim3(kBlock), 0, s,
+  IPP_LAUNCH(c, s, "k_resolve", hipLaunchKernelGGL(k_resolve, dim3(gr), dim3(kBlock), 0, s,
                                    w, p));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_heads, dim3(gr), dim3(kBlock), 0, s, w,
+  IPP_LAUNCH(c, s, "k_heads", hipLaunchKernelGGL(k_heads, dim3(gr), dim3(kBlock), 0, s, w,
                                    p));
   const int nb = (P.rows + 1023) / 1024;
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0,
+  IPP_LAUNCH(c, s, "k_scan_blocks", hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0,
                                    s, w.row_count, w.scan_blocks, P.rows));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s,
+  IPP_LAUNCH(c, s, "k_scan_top", hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s,
                                    w.scan_blocks, nb, w.counters + 3));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0,
+  IPP_LAUNCH(c, s, "k_scan_apply", hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0,
                                    s, w.row_count, w.scan_blocks,
                                    w.row_start, P.rows));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_frame_offsets,
+  IPP_LAUNCH(c, s, "k_frame_offsets", hipLaunchKernelGGL(k_frame_offsets,
                                    dim3(grid_for((int64_t)P.fd.size() + 1,
                                                  kBlock, 4096)),
                                    dim3(kBlock), 0, s, w, *src));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_scatter, dim3(gr), dim3(kBlock), 0, s,
+  IPP_LAUNCH(c, s, "k_scatter", hipLaunchKernelGGL(k_scatter, dim3(gr), dim3(kBlock), 0, s,
                                    w, p));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_rank, dim3(gr), dim3(kBlock), 0, s, w,
+  IPP_LAUNCH(c, s, "k_rank", hipLaunchKernelGGL(k_rank, dim3(gr), dim3(kBlock), 0, s, w,
                                    p, *src));
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_reclabel, dim3(gr), dim3(kBlock), 0, s,
+  IPP_LAUNCH(c, s, "k_reclabel", hipLaunchKernelGGL(k_reclabel, dim3(gr), dim3(kBlock), 0, s,
                                    w));
   if (P.th == 32) st = run_relabel<32, 128>(c, P, w, p, s);
   else if (P.th == 128) st = run_relabel<128, 32>(c, P, w, p, s);
   else st = run_relabel<64, 64>(c, P, w, p, s);
   if (st != IPP_OK) return st;
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_source_stats,
+  IPP_LAUNCH(c, s, "k_source_stats", hipLaunchKernelGGL(k_source_stats,
                                    dim3(grid_for(src->capacity, 4, 4096)),
                                    dim3(kBlock), 0, s, w, *src));
   if (diag)
-    IPP_LAUNCH(c, hipLaunchKernelGGL(k_diag, dim3(1), dim3(64), 0, s, w,
+    IPP_LAUNCH(c, s, "k_diag", hipLaunchKernelGGL(k_diag, dim3(1), dim3(64), 0, s, w,
                                      diag));
   return IPP_OK;
 }
@@ -481,6 +533,10 @@ ipp_status ipp_ctx_destroy(void* ctx) {
   if (c->graph.exec) hipGraphExecDestroy(c->graph.exec);
   if (c->graph.graph) hipGraphDestroy(c->graph.graph);
   if (c->ws) hipFree(c->ws);
+  for (auto& ps : c->pool) {
+    hipEventDestroy(ps.a);
+    hipEventDestroy(ps.b);
+  }
   delete c;
   return IPP_OK;
 }
@@ -514,6 +570,32 @@ ipp_status ipp_ctx_reserve(void* ctx, size_t bytes) {
   c->ws_bytes = bytes;
   ++c->ws_gen;
   return IPP_OK;
+}
+
+ipp_status ipp_ctx_profile(void* ctx, int32_t on) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (c->prof) prof_collect(c);
+  c->prof = on != 0;
+  if (c->prof) c->totals.clear();
+  return IPP_OK;
+}
+
+int32_t ipp_ctx_profile_read(void* ctx, int32_t max, char* names,
+                             double* total_ms, int32_t* count) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c || max < 0) return -1;
+  prof_collect(c);
+  const int n = (int)c->totals.size();
+  for (int i = 0; i < n && i < max; ++i) {
+    if (names) {
+      std::strncpy(names + 32 * i, c->totals[i].first.c_str(), 31);
+      names[32 * i + 31] = 0;
+    }
+    if (total_ms) total_ms[i] = c->totals[i].second.first;
+    if (count) count[i] = c->totals[i].second.second;
+  }
+  return n;
 }
 
 const char* ipp_last_error(void* ctx) {
@@ -608,7 +690,7 @@ ipp_status ipp_photometry(void* ctx, const ipp_frame* frames, int32_t n,
   Work w = make_work(P, c->ws, n);
   ++c->ws_gen;
   if ((st = upload(c, P, w, s)) != IPP_OK) return st;
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_aperture,
+  IPP_LAUNCH(c, s, "k_aperture", hipLaunchKernelGGL(k_aperture,
                                    dim3(grid_for(src->capacity, 1, 16384)),
                                    dim3(kBlock), 0, s, w, *p, *src,
                                    sky_lohi));
@@ -646,7 +728,7 @@ ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
   if ((st = run_mesh(c, P, w, *p, s)) != IPP_OK) return st;
   if ((st = run_detect(c, P, w, *p, src, true, write_rms, diag, s)) != IPP_OK)
     return st;
-  IPP_LAUNCH(c, hipLaunchKernelGGL(k_aperture,
+  IPP_LAUNCH(c, s, "k_aperture", hipLaunchKernelGGL(k_aperture,
                                    dim3(grid_for(src->capacity, 1, 16384)),
                                    dim3(kBlock), 0, s, w, *p, *src,
                                    (double*)nullptr));
