@@ -448,6 +448,33 @@ ipp_status run_detect(IppCtx* c, const Plan& P, const Work& w,
   return IPP_OK;
 }
 
+// Aperture photometry: one wavefront per source.  NS bounds the annulus
+// pixel count: a pixel meeting the disk of radius r_out has its centre
+// within r_out + sqrt(2)/2, and every pixel with its centre within
+// r_in - sqrt(2)/2 lies inside the disk of radius r_in, so by the lattice
+// point bound the ring holds at most pi((r_out+sqrt2)^2 - (r_in-sqrt2)^2).
+ipp_status run_aperture(IppCtx* c, const Work& w, const ipp_params& p,
+                        ipp_sources* src, double* sky_lohi, hipStream_t s) {
+  const double ri = p.r_in > std::sqrt(2.0) ? p.r_in - std::sqrt(2.0) : 0.0;
+  const double ro = p.r_out + std::sqrt(2.0);
+  const double ring = M_PI * (ro * ro - ri * ri) + 16.0;
+  const int grid = grid_for(src->capacity, kWaves, 16384);
+  const dim3 g(grid), b(kBlock);
+  if (ring <= 256) {
+    IPP_LAUNCH(c, s, "k_aperture", hipLaunchKernelGGL((k_aperture_t<256>),
+               g, b, 0, s, w, p, *src, sky_lohi));
+  } else if (ring <= 512) {
+    IPP_LAUNCH(c, s, "k_aperture", hipLaunchKernelGGL((k_aperture_t<512>),
+               g, b, 0, s, w, p, *src, sky_lohi));
+  } else if (ring <= 1024) {
+    IPP_LAUNCH(c, s, "k_aperture", hipLaunchKernelGGL((k_aperture_t<1024>),
+               g, b, 0, s, w, p, *src, sky_lohi));
+  } else {
+    return fail(c, IPP_E_UNSUPPORTED, "aperture radii too large");
+  }
+  return IPP_OK;
+}
+
 std::string check_sources(const ipp_sources* s, bool detect) {
   if (!s) return "sources is NULL";
   if (s->capacity < 0) return "sources capacity < 0";
@@ -690,11 +717,7 @@ ipp_status ipp_photometry(void* ctx, const ipp_frame* frames, int32_t n,
   Work w = make_work(P, c->ws, n);
   ++c->ws_gen;
   if ((st = upload(c, P, w, s)) != IPP_OK) return st;
-  IPP_LAUNCH(c, s, "k_aperture", hipLaunchKernelGGL(k_aperture,
-                                   dim3(grid_for(src->capacity, 1, 16384)),
-                                   dim3(kBlock), 0, s, w, *p, *src,
-                                   sky_lohi));
-  return IPP_OK;
+  return run_aperture(c, w, *p, src, sky_lohi, s);
 }
 
 ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
@@ -728,11 +751,7 @@ ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
   if ((st = run_mesh(c, P, w, *p, s)) != IPP_OK) return st;
   if ((st = run_detect(c, P, w, *p, src, true, write_rms, diag, s)) != IPP_OK)
     return st;
-  IPP_LAUNCH(c, s, "k_aperture", hipLaunchKernelGGL(k_aperture,
-                                   dim3(grid_for(src->capacity, 1, 16384)),
-                                   dim3(kBlock), 0, s, w, *p, *src,
-                                   (double*)nullptr));
-  return IPP_OK;
+  return run_aperture(c, w, *p, src, nullptr, s);
 }
 
 }  // extern "C"

@@ -328,10 +328,12 @@ __device__ double median_small(double* v, int n) {
 
 // Second derivatives of the natural cubic spline along one mesh line:
 // values f[base + k*stride], k < n, on node_coord(k, m, len); Thomas
-// algorithm with scratch cp/dp at the same strided positions.
+// algorithm with scratch cp/dp at the same strided positions.  The loads
+// of each sweep are issued in chunks ahead of the dependent recurrence.
 __device__ void natural_line(const double* f, double* M, double* cp,
                              double* dp, int base, int stride, int n, int m,
                              int len) {
+  constexpr int CH = 8;
   M[base] = 0.0;
   M[base + (n - 1) * stride] = 0.0;
   if (n < 3) {
@@ -339,28 +341,48 @@ __device__ void natural_line(const double* f, double* M, double* cp,
     return;
   }
   double cprev = 0.0, dprev = 0.0;
-  for (int i = 1; i <= n - 2; ++i) {
-    const double t0 = node_coord(i - 1, m, len), t1 = node_coord(i, m, len);
-    const double t2 = node_coord(i + 1, m, len);
-    const double h0 = t1 - t0, h1 = t2 - t1;
-    const double f0 = f[base + (i - 1) * stride];
-    const double f1 = f[base + i * stride];
-    const double f2 = f[base + (i + 1) * stride];
-    const double a = (i > 1) ? h0 : 0.0;
-    const double b = 2.0 * (h0 + h1);
-    const double c = h1;
-    const double d = 6.0 * ((f2 - f1) / h1 - (f1 - f0) / h0);
-    const double den = b - a * cprev;
-    cprev = c / den;
-    dprev = (d - a * dprev) / den;
-    cp[base + i * stride] = cprev;
-    dp[base + i * stride] = dprev;
+  for (int i0 = 1; i0 <= n - 2; i0 += CH) {
+    double fl[CH + 2];
+#pragma unroll
+    for (int u = 0; u < CH + 2; ++u) {
+      const int i = i0 - 1 + u;
+      fl[u] = i < n ? f[base + i * stride] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i0 + u;
+      if (i > n - 2) break;
+      const double t0 = node_coord(i - 1, m, len), t1 = node_coord(i, m, len);
+      const double t2 = node_coord(i + 1, m, len);
+      const double h0 = t1 - t0, h1 = t2 - t1;
+      const double a = (i > 1) ? h0 : 0.0;
+      const double b = 2.0 * (h0 + h1);
+      const double d = 6.0 * ((fl[u + 2] - fl[u + 1]) / h1 -
+                              (fl[u + 1] - fl[u]) / h0);
+      const double den = b - a * cprev;
+      cprev = h1 / den;
+      dprev = (d - a * dprev) / den;
+      cp[base + i * stride] = cprev;
+      dp[base + i * stride] = dprev;
+    }
   }
-  double nxt = dp[base + (n - 2) * stride];
+  double nxt = dprev;                          // M[n-2]
   M[base + (n - 2) * stride] = nxt;
-  for (int i = n - 3; i >= 1; --i) {
-    nxt = dp[base + i * stride] - cp[base + i * stride] * nxt;
-    M[base + i * stride] = nxt;
+  for (int i1 = n - 3; i1 >= 1; i1 -= CH) {
+    double dl[CH], cl[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i1 - u;
+      dl[u] = i >= 1 ? dp[base + i * stride] : 0.0;
+      cl[u] = i >= 1 ? cp[base + i * stride] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int i = i1 - u;
+      if (i < 1) break;
+      nxt = dl[u] - cl[u] * nxt;
+      M[base + i * stride] = nxt;
+    }
   }
 }
 

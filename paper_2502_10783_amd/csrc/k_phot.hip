@@ -1,8 +1,17 @@
 // Aperture photometry with a local sky annulus (Sec. 2.2.5: per-object
-// aperture photometry).  One 256-thread workgroup per source: every window
-// pixel gets its exact circle/pixel overlap weights in binary64, the annulus
-// values are sorted in LDS (bitonic), and the k-sigma clipping of the sky
-// then works on contiguous ranges of the sorted values.
+// aperture photometry).
+//
+// One wavefront per source, four sources per workgroup, no workgroup
+// barriers.  The wave classifies every pixel of the source's window with
+// the exact membership predicates (cheap), accumulates the aperture pixels
+// that lie wholly inside the aperture, and compacts the rest of the work
+// into its LDS slice: the aperture pixels cut by the circle, the annulus
+// values with their weights, and the annulus pixels cut by either circle.
+// The exact overlap areas (binary64, one asin per corner) are then
+// computed over those dense task lists with every lane busy.  The annulus
+// (value, weight) pairs are sorted in registers with a bitonic network;
+// the k-sigma clipping of the sky works on contiguous ranges of the sorted
+// values and the weighted sky sum is a sum over the final range.
 #include "ipp_internal.h"
 #include "kernels.h"
 #include "phot_geom.h"
@@ -10,168 +19,296 @@
 namespace ipp {
 
 namespace {
-constexpr int kSortMax = 1024;     // annulus pixels (r_out <= 16)
-constexpr int kPixPerThread = 5;   // window pixels per thread (34 x 34)
-}  // namespace
 
-__global__ __launch_bounds__(kBlock) void k_aperture(Work wk, ipp_params p,
-                                                     ipp_sources src,
-                                                     double* sky_lohi) {
-  __shared__ double sbuf[kSortMax];
-  __shared__ double dred[kWaves];
-  __shared__ int ired[kWaves];
-  __shared__ int cnt_s;
-  const int t = threadIdx.x;
-  long long nrows = src.capacity;
-  if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
-  const double R = p.r_ap > p.r_out ? p.r_ap : p.r_out;
-  for (long long row = blockIdx.x; row < nrows; row += gridDim.x) {
-    const int f = src.frame[row];
-    const double cx = src.x[row], cy = src.y[row];
-    const bool fok = f >= 0 && f < wk.nframes;
-    const FrameDev fr = wk.frames[fok ? f : 0];
-    uint32_t flags = 0;
-    if (!fok || !(isfinite(cx) && isfinite(cy)) || fabs(cx) > 1e9 ||
-        fabs(cy) > 1e9) {
-      if (t == 0) {
-        src.flux_ap[row] = __builtin_nan("");
-        src.sky[row] = __builtin_nan("");
-        src.area_ap[row] = 0.0;
-        src.area_ann[row] = 0.0;
-        src.flags[row] |= IPP_SRC_APERTURE_OFF_EDGE | IPP_SRC_NO_SKY;
-        if (sky_lohi) { sky_lohi[2 * row] = 0.0; sky_lohi[2 * row + 1] = -1.0; }
-      }
-      continue;
-    }
-    const int xa = (int)ceil(cx - R - 0.5), xb = (int)floor(cx + R + 0.5);
-    const int ya = (int)ceil(cy - R - 0.5), yb = (int)floor(cy + R + 0.5);
-    const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
-    if (t == 0) cnt_s = 0;
-    __syncthreads();
-    double pv[kPixPerThread], pwa[kPixPerThread], pwn[kPixPerThread];
-    uint32_t okm = 0, annm = 0;
-    double a_ap = 0.0, raw = 0.0;
+constexpr int kApTasks = 320;   // aperture pixels cut by a circle, r <= 16
+
+template <int NS>
+struct ApLds {
+  double pv[NS];                // annulus values (sorted values later)
+  double pw[NS];                // annulus weights
+  int ab[NS];                   // annulus boundary tasks: slot << 16 | e
+  int apb[kApTasks];            // aperture boundary tasks: window index
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = threadIdx.x & (kWave - 1);
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Bitonic sort (ascending by v) of NS (v, w) pairs held as v[NS/64],
+// w[NS/64] per lane, element index e = lane * (NS/64) + k.  A pair moves
+// only when the pair ahead of it is strictly larger, decided identically by
+// both partners, so no pair is lost or duplicated on ties.
+template <int NS>
+__device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave],
+                                             double (&w)[NS / kWave]) {
+  constexpr int PL = NS / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
-    for (int k = 0; k < kPixPerThread; ++k) {
-      pv[k] = 0.0; pwa[k] = 0.0; pwn[k] = 0.0;
-      const int e = t + k * kBlock;
-      if (e >= npx) continue;
+  for (int kk = 2; kk <= NS; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j < PL) {
+#pragma unroll
+        for (int k = 0; k < PL; ++k) {
+          const int l = k ^ j;
+          if (l > k) {
+            const int e = lane * PL + k;
+            const bool up = (e & kk) == 0;
+            const double a = v[k], b = v[l];
+            const bool sw = up ? (a > b) : (a < b);
+            const double wa = w[k], wb = w[l];
+            v[k] = sw ? b : a;
+            v[l] = sw ? a : b;
+            w[k] = sw ? wb : wa;
+            w[l] = sw ? wa : wb;
+          }
+        }
+      } else {
+        const int lm = j / PL;                 // partner lane = lane ^ lm
+        const bool lower = (lane & lm) == 0;
+#pragma unroll
+        for (int k = 0; k < PL; ++k) {
+          const int e = lane * PL + k;
+          const bool up = (e & kk) == 0;
+          const double ov = __shfl_xor(v[k], lm, kWave);
+          const double ow = __shfl_xor(w[k], lm, kWave);
+          const double a = lower ? v[k] : ov;   // value at the lower index
+          const double b = lower ? ov : v[k];
+          const bool sw = up ? (a > b) : (a < b);
+          if (sw) { v[k] = ov; w[k] = ow; }
+        }
+      }
+    }
+  }
+}
+
+template <int NS>
+__device__ void aperture_one(const Work& wk, const ipp_params& p,
+                             ipp_sources& src, double* sky_lohi,
+                             long long row, ApLds<NS>& L) {
+  constexpr int PL = NS / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int f = src.frame[row];
+  const double cx = src.x[row], cy = src.y[row];
+  const bool fok = f >= 0 && f < wk.nframes;
+  const double R = p.r_ap > p.r_out ? p.r_ap : p.r_out;
+  if (!fok || !(isfinite(cx) && isfinite(cy)) || fabs(cx) > 1e9 ||
+      fabs(cy) > 1e9) {
+    if (lane == 0) {
+      src.flux_ap[row] = __builtin_nan("");
+      src.sky[row] = __builtin_nan("");
+      src.area_ap[row] = 0.0;
+      src.area_ann[row] = 0.0;
+      src.flags[row] |= IPP_SRC_APERTURE_OFF_EDGE | IPP_SRC_NO_SKY;
+      if (sky_lohi) { sky_lohi[2 * row] = 0.0; sky_lohi[2 * row + 1] = -1.0; }
+    }
+    return;
+  }
+  const FrameDev& fr = wk.frames[f];
+  const int xa = (int)ceil(cx - R - 0.5), xb = (int)floor(cx + R + 0.5);
+  const int ya = (int)ceil(cy - R - 0.5), yb = (int)floor(cy + R + 0.5);
+  const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
+
+  // ---- classify the window; compact the work -------------------------
+  uint32_t flags = 0;
+  double a_ap = 0.0, raw = 0.0;
+  int nann = 0, nab = 0, nap = 0;
+  for (int e0 = 0; e0 < npx; e0 += kWave) {
+    const int e = e0 + lane;
+    bool ap_cut = false, ann = false, ann_cut = false;
+    double v = 0.0;
+    if (e < npx) {
       const int px = xa + e % nwx, py = ya + e / nwx;
       const bool in_ap = touches(cx, cy, p.r_ap, px, py);
       const bool in_ann = touches(cx, cy, p.r_out, px, py) &&
                           !within(cx, cy, p.r_in, px, py);
-      if (!(in_ap || in_ann)) continue;
-      bool ok = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
-      double v = 0.0;
-      if (ok) {
-        const float I = fr.pix[(int64_t)py * fr.pitch + px];
-        ok = isfinite(I);
-        v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
-      }
-      if (!ok) {
-        if (in_ap) flags |= IPP_SRC_APERTURE_OFF_EDGE;
-        if (in_ann) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
-        continue;
-      }
-      okm |= 1u << k;
-      pv[k] = v;
-      if (in_ap) {
-        const double wa = overlap(cx, cy, p.r_ap, px, py);
-        pwa[k] = wa;
-        a_ap += wa;
-        raw += wa * v;
-      }
-      if (in_ann) {
-        pwn[k] = overlap(cx, cy, p.r_out, px, py) -
-                 overlap(cx, cy, p.r_in, px, py);
-        annm |= 1u << k;
-        const int slot = atomicAdd(&cnt_s, 1);
-        if (slot < kSortMax) sbuf[slot] = v;
-      }
-    }
-    __syncthreads();
-    int nann = cnt_s;
-    if (nann > kSortMax) nann = kSortMax;      // not reachable for r <= 16
-    int ns = 64;
-    while (ns < nann) ns <<= 1;
-    for (int i = nann + t; i < ns; i += kBlock) sbuf[i] = __builtin_inf();
-    __syncthreads();
-    // bitonic sort of sbuf[0, ns)
-    for (int kk = 2; kk <= ns; kk <<= 1) {
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int i = t; i < ns; i += kBlock) {
-          const int l = i ^ j;
-          if (l > i) {
-            const double a = sbuf[i], b = sbuf[l];
-            const bool up = (i & kk) == 0;
-            if ((a > b) == up) { sbuf[i] = b; sbuf[l] = a; }
+      if (in_ap || in_ann) {
+        bool ok = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
+        if (ok) {
+          const float I = fr.pix[(int64_t)py * fr.pitch + px];
+          ok = isfinite(I);
+          v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+        }
+        if (!ok) {
+          if (in_ap) flags |= IPP_SRC_APERTURE_OFF_EDGE;
+          if (in_ann) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
+        } else {
+          if (in_ap) {
+            if (within(cx, cy, p.r_ap, px, py)) {
+              a_ap += 1.0;
+              raw += v;
+            } else {
+              ap_cut = true;
+            }
+          }
+          if (in_ann) {
+            ann = true;
+            ann_cut = !(within(cx, cy, p.r_out, px, py) &&
+                        !touches(cx, cy, p.r_in, px, py));
           }
         }
-        __syncthreads();
       }
     }
-    // k-sigma clipping on the sorted range [a, b)
-    int a = 0, b = nann;
-    for (int it = 0; it < p.sky_clip_iters; ++it) {
-      const int n = b - a;
-      if (n == 0) break;
-      double med = (n & 1) ? sbuf[a + (n - 1) / 2]
-                           : (sbuf[a + n / 2 - 1] + sbuf[a + n / 2]) / 2.0;
-      double s1 = 0.0;
-      for (int i = a + t; i < b; i += kBlock) s1 += sbuf[i];
-      s1 = block_sum(s1, dred);
-      const double mean = s1 / (double)n;
-      double s2 = 0.0;
-      for (int i = a + t; i < b; i += kBlock) {
-        const double d = sbuf[i] - mean;
+    const uint64_t b1 = __ballot(ap_cut);
+    if (ap_cut) {
+      const int s = nap + __popcll(b1 & lanes_below());
+      if (s < kApTasks) L.apb[s] = e;
+    }
+    nap += __popcll(b1);
+    const uint64_t b2 = __ballot(ann);
+    int slot = 0;
+    if (ann) {
+      slot = nann + __popcll(b2 & lanes_below());
+      if (slot < NS) {
+        L.pv[slot] = v;
+        L.pw[slot] = 1.0;
+      }
+    }
+    nann += __popcll(b2);
+    const uint64_t b3 = __ballot(ann_cut);
+    if (ann_cut) {
+      const int s = nab + __popcll(b3 & lanes_below());
+      if (s < NS && slot < NS) L.ab[s] = (slot << 16) | e;
+    }
+    nab += __popcll(b3);
+  }
+  if (nann > NS) nann = NS;            // not reachable: NS bounds the ring
+  if (nab > NS) nab = NS;
+  if (nap > kApTasks) nap = kApTasks;  // not reachable for r_ap <= 16
+  wave_lds_sync();
+
+  // ---- exact overlaps over the dense task lists --------------------------
+  for (int j = lane; j < nap; j += kWave) {
+    const int e = L.apb[j];
+    const int px = xa + e % nwx, py = ya + e / nwx;
+    const float I = fr.pix[(int64_t)py * fr.pitch + px];
+    const double v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+    const double wa = overlap(cx, cy, p.r_ap, px, py);
+    a_ap += wa;
+    raw += wa * v;
+  }
+  for (int j = lane; j < nab; j += kWave) {
+    const int t = L.ab[j];
+    const int slot = t >> 16, e = t & 0xFFFF;
+    const int px = xa + e % nwx, py = ya + e / nwx;
+    L.pw[slot] = overlap(cx, cy, p.r_out, px, py) -
+                 overlap(cx, cy, p.r_in, px, py);
+  }
+  wave_lds_sync();
+
+  // ---- sort the annulus (value, weight) pairs ---------------------------
+  double sv[PL], sw[PL];
+#pragma unroll
+  for (int k = 0; k < PL; ++k) {
+    const int e = lane * PL + k;
+    sv[k] = e < nann ? L.pv[e] : __builtin_inf();
+    sw[k] = e < nann ? L.pw[e] : 0.0;
+  }
+  wave_bitonic<NS>(sv, sw);
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < PL; ++k) L.pv[lane * PL + k] = sv[k];
+  wave_lds_sync();
+
+  // ---- k-sigma clipping on the sorted range [a, bnd) ---------------------
+  int a = 0, bnd = nann;
+  for (int it = 0; it < p.sky_clip_iters; ++it) {
+    const int n = bnd - a;
+    if (n == 0) break;
+    const double med = (n & 1) ? L.pv[a + (n - 1) / 2]
+                               : (L.pv[a + n / 2 - 1] + L.pv[a + n / 2]) / 2.0;
+    double s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int e = lane * PL + k;
+      if (e >= a && e < bnd) s1 += sv[k];
+    }
+    const double mean = wave_sum(s1) / (double)n;
+    double s2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      const int e = lane * PL + k;
+      if (e >= a && e < bnd) {
+        const double d = sv[k] - mean;
         s2 += d * d;
       }
-      s2 = block_sum(s2, dred);
-      const double sd = sqrt(s2 / (double)n);
-      const double lo = med - p.sky_clip_sigma * sd;
-      const double hi = med + p.sky_clip_sigma * sd;
-      int cl = 0, ch = 0;
-      for (int i = a + t; i < b; i += kBlock) {
-        cl += sbuf[i] < lo;
-        ch += sbuf[i] > hi;
-      }
-      cl = block_sum(cl, ired);
-      ch = block_sum(ch, ired);
-      if (cl == 0 && ch == 0) break;
-      a += cl;
-      b -= ch;
     }
-    double vlo = 0.0, vhi = -1.0;
-    if (b > a) { vlo = sbuf[a]; vhi = sbuf[b - 1]; }
-    // weighted sky over the surviving annulus pixels
-    double num = 0.0, den = 0.0;
+    const double sd = sqrt(wave_sum(s2) / (double)n);
+    const double lo = med - p.sky_clip_sigma * sd;
+    const double hi = med + p.sky_clip_sigma * sd;
+    int cl = 0, ch = 0;
 #pragma unroll
-    for (int k = 0; k < kPixPerThread; ++k) {
-      if (((annm >> k) & 1u) && pv[k] >= vlo && pv[k] <= vhi) {
-        num += pwn[k] * pv[k];
-        den += pwn[k];
+    for (int k = 0; k < PL; ++k) {
+      const int e = lane * PL + k;
+      if (e >= a && e < bnd) {
+        cl += sv[k] < lo;
+        ch += sv[k] > hi;
       }
     }
-    num = block_sum(num, dred);
-    den = block_sum(den, dred);
-    a_ap = block_sum(a_ap, dred);
-    raw = block_sum(raw, dred);
-    for (int o = kWave / 2; o > 0; o >>= 1) flags |= __shfl_xor(flags, o, kWave);
-    if ((t & (kWave - 1)) == 0) ired[t / kWave] = (int)flags;
-    __syncthreads();
-    if (t == 0) {
-      uint32_t fl = (uint32_t)(ired[0] | ired[1] | ired[2] | ired[3]);
-      double sky = 0.0;
-      if (den > 0.0) sky = num / den; else fl |= IPP_SRC_NO_SKY;
-      src.flux_ap[row] = raw - sky * a_ap;
-      src.sky[row] = sky;
-      src.area_ap[row] = a_ap;
-      src.area_ann[row] = den;
-      src.flags[row] |= fl;
-      if (sky_lohi) { sky_lohi[2 * row] = vlo; sky_lohi[2 * row + 1] = vhi; }
-    }
-    __syncthreads();
+    cl = wave_sum(cl);
+    ch = wave_sum(ch);
+    if (cl == 0 && ch == 0) break;
+    a += cl;
+    bnd -= ch;
   }
+  double vlo = 0.0, vhi = -1.0;
+  if (bnd > a) { vlo = L.pv[a]; vhi = L.pv[bnd - 1]; }
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int k = 0; k < PL; ++k) {
+    const int e = lane * PL + k;
+    if (e >= a && e < bnd) {
+      num += sw[k] * sv[k];
+      den += sw[k];
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  a_ap = wave_sum(a_ap);
+  raw = wave_sum(raw);
+  for (int o = kWave / 2; o > 0; o >>= 1) flags |= __shfl_xor(flags, o, kWave);
+  if (lane == 0) {
+    double sky = 0.0;
+    if (den > 0.0) sky = num / den; else flags |= IPP_SRC_NO_SKY;
+    src.flux_ap[row] = raw - sky * a_ap;
+    src.sky[row] = sky;
+    src.area_ap[row] = a_ap;
+    src.area_ann[row] = den;
+    src.flags[row] |= flags;
+    if (sky_lohi) { sky_lohi[2 * row] = vlo; sky_lohi[2 * row + 1] = vhi; }
+  }
+  wave_lds_sync();                     // the slice is reused by the next row
 }
+
+}  // namespace
+
+// NS: sort size (>= the annulus pixel count bound).
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_aperture_t(Work wk, ipp_params p,
+                                                       ipp_sources src,
+                                                       double* sky_lohi) {
+  __shared__ ApLds<NS> L[kWaves];
+  long long nrows = src.capacity;
+  if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
+  const long long wid = (blockIdx.x * (long long)kBlock + threadIdx.x) / kWave;
+  const long long nw = (long long)gridDim.x * kWaves;
+  ApLds<NS>& mine = L[threadIdx.x / kWave];
+  for (long long row = wid; row < nrows; row += nw)
+    aperture_one<NS>(wk, p, src, sky_lohi, row, mine);
+}
+
+template __global__ void k_aperture_t<256>(Work, ipp_params, ipp_sources,
+                                           double*);
+template __global__ void k_aperture_t<512>(Work, ipp_params, ipp_sources,
+                                           double*);
+template __global__ void k_aperture_t<1024>(Work, ipp_params, ipp_sources,
+                                            double*);
 
 }  // namespace ipp

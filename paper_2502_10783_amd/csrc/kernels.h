@@ -32,7 +32,8 @@ __global__ void k_rank(Work wk, ipp_params p, ipp_sources src);
 __global__ void k_reclabel(Work wk);
 __global__ void k_source_stats(Work wk, ipp_sources src);
 
-__global__ void k_aperture(Work wk, ipp_params p, ipp_sources src,
-                           double* sky_lohi);
+template <int NS>
+__global__ void k_aperture_t(Work wk, ipp_params p, ipp_sources src,
+                             double* sky_lohi);
 
 }  // namespace ipp

@@ -4,7 +4,8 @@
 // a disk of radius r about the origin is odd in x and in y; for
 // 0 <= x, y <= r it is x*y when the corner lies in the circle and otherwise
 // y*xs + P(x) - P(xs) with xs = sqrt(r^2 - y^2) and
-// P(s) = int_0^s sqrt(r^2 - u^2) du = (s sqrt(r^2 - s^2) + r^2 asin(s/r))/2.
+// P(s) = int_0^s sqrt(r^2 - u^2) du = (s sqrt(r^2 - s^2) + r^2 asin(s/r))/2
+// (evaluated with one asin, see corner_area).
 // A pixel's overlap is the inclusion-exclusion of G over its corners.
 // Membership (the pixel square meets the open disk) and full containment
 // are decided by the exact predicates below, so that every pixel that a
@@ -31,22 +32,26 @@ __device__ __forceinline__ bool within(double cx, double cy, double r,
   return fx * fx + fy * fy <= r * r;
 }
 
-__device__ __forceinline__ double prim(double s, double r) {
-  return 0.5 * (s * sqrt(fmax(r * r - s * s, 0.0)) +
-                r * r * asin(fmin(s / r, 1.0)));
-}
-
+// G for a corner (x, y) outside the circle, 0 <= x, y <= r, with
+// xs = sqrt(r^2 - y^2) and hx = sqrt(r^2 - x^2):
+//   G = y xs + P(x) - P(xs)
+//     = (y xs + x hx + r^2 (asin(x/r) - asin(xs/r))) / 2
+// and, as cos(asin(xs/r)) = y/r and cos(asin(x/r)) = hx/r, the angle
+// difference is asin((x y - xs hx) / r^2): one asin per corner.
 __device__ __forceinline__ double corner_area(double x, double y, double r) {
   if (r <= 0.0) return 0.0;
   const double sx = x < 0.0 ? -1.0 : 1.0;
   const double sy = y < 0.0 ? -1.0 : 1.0;
   const double ax = fmin(fabs(x), r), ay = fmin(fabs(y), r);
+  const double r2 = r * r;
   double a;
-  if (ax * ax + ay * ay <= r * r) {
+  if (ax * ax + ay * ay <= r2) {
     a = ax * ay;
   } else {
-    const double xs = sqrt(r * r - ay * ay);
-    a = ay * xs + prim(ax, r) - prim(xs, r);
+    const double xs = sqrt(fmax(r2 - ay * ay, 0.0));
+    const double hx = sqrt(fmax(r2 - ax * ax, 0.0));
+    const double arg = fmin((ax * ay - xs * hx) / r2, 1.0);
+    a = 0.5 * ((ay * xs + ax * hx) + r2 * asin(arg));
   }
   return sx * sy * a;
 }

@@ -6,9 +6,10 @@
 // the spline restricted to an image row y is a 1-D natural spline in x
 // through the values g_i(y) with second derivatives g''_i(y), where g_i and
 // g''_i are 1-D splines in y of the node columns of (f, fyy) and
-// (fxx, fxxyy).  The tile prologue evaluates those per row for the few
-// mesh columns the tile spans, and the per-column x weights; each pixel is
-// then four multiply-adds per map.
+// (fxx, fxxyy).  The tile prologue stages the few mesh nodes the tile
+// spans in LDS, evaluates g and g'' per tile row for those mesh columns,
+// and the per-column x weights; each pixel is then four multiply-adds per
+// map.
 #pragma once
 
 #include "ipp_internal.h"
@@ -17,14 +18,18 @@ namespace ipp {
 
 template <int TH, int TW>
 struct SplineLds {
-  // mesh columns a tile can span (mesh >= 16), with one of slack
+  // mesh columns / rows a tile can span (mesh >= 16), with one of slack
   static constexpr int NC = TW / 16 + 4;
+  static constexpr int NR = TH / 16 + 4;
   double gB[TH][NC];
   double gBpp[TH][NC];
   double gR[TH][NC];
   double gRpp[TH][NC];
   double wx[TW][4];
   int cx[TW];
+  double wy[TH][4];
+  int ry[TH];
+  double node[8][NR][NC];      // tb[0..3], tr[0..3] of the spanned nodes
 };
 
 template <int TH, int TW>
@@ -34,37 +39,53 @@ __device__ __forceinline__ void spline_prologue(const Work& wk,
                                                 int x0,
                                                 SplineLds<TH, TW>& S) {
   constexpr int NC = SplineLds<TH, TW>::NC;
-  int ilo;
+  constexpr int NR = SplineLds<TH, TW>::NR;
+  int ilo, jlo;
   {
     double w4[4];
     spline_weights((double)x0, p.mesh_w, fr.w, fr.nx, &ilo, w4);
+    spline_weights((double)y0, p.mesh_h, fr.h, fr.ny, &jlo, w4);
   }
-  for (int c = threadIdx.x; c < TW; c += kBlock) {
+  for (int c = threadIdx.x; c < TW + TH; c += kBlock) {
     double w4[4];
     int j;
-    spline_weights((double)(x0 + c), p.mesh_w, fr.w, fr.nx, &j, w4);
-    S.cx[c] = j - ilo;
+    if (c < TW) {
+      spline_weights((double)(x0 + c), p.mesh_w, fr.w, fr.nx, &j, w4);
+      S.cx[c] = j - ilo;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) S.wx[c][k] = w4[k];
+      for (int k = 0; k < 4; ++k) S.wx[c][k] = w4[k];
+    } else {
+      const int r = c - TW;
+      const int y = min(y0 + r, fr.h - 1);
+      spline_weights((double)y, p.mesh_h, fr.h, fr.ny, &j, w4);
+      S.ry[r] = j - jlo;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S.wy[r][k] = w4[k];
+    }
   }
-  const int nx = fr.nx;
+  const int nx = fr.nx, ny = fr.ny;
+  for (int e = threadIdx.x; e < 8 * NR * NC; e += kBlock) {
+    const int t = e / (NR * NC), rc = e - t * (NR * NC);
+    const int r = rc / NC, c = rc - r * NC;
+    const int j = min(jlo + r, ny - 1), i = min(ilo + c, nx - 1);
+    const double* tab = t < 4 ? wk.tb[t] : wk.tr[t - 4];
+    S.node[t][r][c] = tab[fr.node0 + j * nx + i];
+  }
+  __syncthreads();
   for (int e = threadIdx.x; e < TH * NC; e += kBlock) {
     const int r = e / NC, c = e - (e / NC) * NC;
-    const int i = min(ilo + c, nx - 1);
-    const int y = min(y0 + r, fr.h - 1);
-    double w4[4];
-    int j;
-    spline_weights((double)y, p.mesh_h, fr.h, fr.ny, &j, w4);
-    const int j1 = (fr.ny == 1) ? j : j + 1;
-    const int n0 = fr.node0 + j * nx + i, n1 = fr.node0 + j1 * nx + i;
-    S.gB[r][c] = ((w4[0] * wk.tb[0][n0] + w4[1] * wk.tb[0][n1])
-                  + w4[2] * wk.tb[2][n0]) + w4[3] * wk.tb[2][n1];
-    S.gBpp[r][c] = ((w4[0] * wk.tb[1][n0] + w4[1] * wk.tb[1][n1])
-                    + w4[2] * wk.tb[3][n0]) + w4[3] * wk.tb[3][n1];
-    S.gR[r][c] = ((w4[0] * wk.tr[0][n0] + w4[1] * wk.tr[0][n1])
-                  + w4[2] * wk.tr[2][n0]) + w4[3] * wk.tr[2][n1];
-    S.gRpp[r][c] = ((w4[0] * wk.tr[1][n0] + w4[1] * wk.tr[1][n1])
-                    + w4[2] * wk.tr[3][n0]) + w4[3] * wk.tr[3][n1];
+    const int j = S.ry[r];
+    const int j1 = ny == 1 ? j : j + 1;
+    const double a0 = S.wy[r][0], a1 = S.wy[r][1];
+    const double a2 = S.wy[r][2], a3 = S.wy[r][3];
+    auto comb = [&](int tv, int tm) {
+      return ((a0 * S.node[tv][j][c] + a1 * S.node[tv][j1][c]) +
+              a2 * S.node[tm][j][c]) + a3 * S.node[tm][j1][c];
+    };
+    S.gB[r][c] = comb(0, 2);        // f with fyy
+    S.gBpp[r][c] = comb(1, 3);      // fxx with fxxyy
+    S.gR[r][c] = comb(4, 6);
+    S.gRpp[r][c] = comb(5, 7);
   }
   __syncthreads();
 }
