@@ -250,6 +250,42 @@ ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
                              ipp_sources* src, uint32_t* frame_flags,
                              int64_t* diag, void* stream);
 
+/*
+ * Backward of ipp_photometry (the annulus clip mask of the forward held
+ * fixed).  Inputs as for ipp_photometry plus sky_lohi (device
+ * double[2*rows], written by the forward) and dL_dflux (device
+ * double[rows], upstream gradient of flux_ap).  dL_dpix: HOST array of n
+ * device pointers (nullable, entries nullable), each a dense h x w float32
+ * map to which dL/dI is ADDED with float atomics (summation order, hence
+ * the last bits, may vary from run to run); dL/dB32 is its negative.
+ * dL_dxy: device double[2*rows] (nullable), overwritten with
+ * (dL/dx, dL/dy) per row.  Rows: min(capacity, *n_total).
+ */
+ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
+                                   int32_t n, const ipp_maps* maps,
+                                   const ipp_params* p,
+                                   const ipp_sources* src,
+                                   const double* sky_lohi,
+                                   const double* dL_dflux,
+                                   float* const* dL_dpix, double* dL_dxy,
+                                   void* stream);
+
+/*
+ * asinh gray-scale stretch (Sec. 2.2.6 gray-scale transformations):
+ * y[i] = b * asinh(v[i] / a), float32 arrays of n elements (device),
+ * a > 0 (softening), b (scale).
+ */
+ipp_status ipp_asinh(void* ctx, const float* v, float* y, int64_t n,
+                     double a, double b, void* stream);
+/* Backward: dv[i] = dy[i] * b / sqrt(a^2 + v[i]^2) (dv nullable; written,
+ * not accumulated); dL_dab (device double[2], nullable) =
+ * (sum dy * -b v / (a sqrt(a^2+v^2)), sum dy * asinh(v/a)), accumulated in
+ * binary64 in a fixed order (deterministic).  Needs 32 KiB of workspace
+ * when dL_dab is given. */
+ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
+                              float* dv, double* dL_dab, int64_t n, double a,
+                              double b, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,8 @@ Intelligence Era"):
   its adjoint (gradients with the sky clip mask held fixed).
 * ``stretch``    -- Sec. 2.2.6 (Gray Scale Transformation Function): an asinh
   gray-scale map and its derivatives.
+* ``refine``     -- gradient-ascent centroid refinement on the photometry
+  adjoint (this build's addition).
 
 Where the paper leaves a step open, the reading taken is stated in the
 docstring of the function that implements it.  Every floating-point value is
@@ -28,6 +30,7 @@ IEEE binary64; sums that decide results are exact (``math.fsum`` or Python
 integers) and rounded once.
 """
 from .params import Params
-from . import background, detect, photometry, stretch
+from . import background, detect, photometry, stretch, refine
 
-__all__ = ["Params", "background", "detect", "photometry", "stretch"]
+__all__ = ["Params", "background", "detect", "photometry", "stretch",
+           "refine"]

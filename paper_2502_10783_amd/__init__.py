@@ -7,6 +7,8 @@ and aperture photometry, per frame or as a fused batch.
 """
 from ._lib import lib, LIB_PATH, header_functions  # noqa: F401
 from .api import Params, Context, SourceTable, IppError  # noqa: F401
+from .autograd import ApertureFlux, AsinhStretch, refine_centroids  # noqa
 
 __all__ = ["Params", "Context", "SourceTable", "IppError", "lib",
-           "LIB_PATH", "header_functions"]
+           "LIB_PATH", "header_functions", "ApertureFlux", "AsinhStretch",
+           "refine_centroids"]

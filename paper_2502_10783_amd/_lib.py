@@ -133,6 +133,17 @@ def lib():
                                     C.POINTER(IppParams), C.POINTER(IppMaps),
                                     C.POINTER(IppSources), vp, vp, vp]
     L.ipp_process_batch.restype = i32
+    L.ipp_photometry_backward.argtypes = [vp, C.POINTER(IppFrame), i32,
+                                          C.POINTER(IppMaps),
+                                          C.POINTER(IppParams),
+                                          C.POINTER(IppSources), vp, vp,
+                                          C.POINTER(vp), vp, vp]
+    L.ipp_photometry_backward.restype = i32
+    L.ipp_asinh.argtypes = [vp, vp, vp, i64, C.c_double, C.c_double, vp]
+    L.ipp_asinh.restype = i32
+    L.ipp_asinh_backward.argtypes = [vp, vp, vp, vp, vp, i64, C.c_double,
+                                     C.c_double, vp]
+    L.ipp_asinh_backward.restype = i32
     _lib = L
     return L
 

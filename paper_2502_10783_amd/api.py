@@ -268,6 +268,57 @@ class Context:
             _ptr(lohi), _stream()))
         return lohi
 
+    def photometry_backward(self, frames, bkg, table: SourceTable,
+                            params: Params, sky_lohi, dL_dflux,
+                            dpix=None, want_dxy=True, use_count=False):
+        """Gradients of sum(dL_dflux * flux_ap): adds dL/dI into dpix
+        (list of float32 maps, or None) and returns dL/d(x, y) (rows x 2)."""
+        n = len(frames)
+        maps = (L.IppMaps * n)()
+        for i in range(n):
+            maps[i].bkg = bkg[i].data_ptr()
+        dp = None
+        if dpix is not None:
+            dp = (C.c_void_p * n)()
+            for i in range(n):
+                if dpix[i] is not None:
+                    _check_gpu_f32(dpix[i], "dpix")
+                    dp[i] = dpix[i].data_ptr()
+        dxy = None
+        if want_dxy:
+            dxy = torch.zeros((max(1, table.capacity), 2), dtype=torch.float64,
+                              device=frames[0].device)
+        g = dL_dflux.to(torch.float64).contiguous()
+        src = table.to_c(n_total=use_count)
+        pc = params.to_c()
+        self._check(self.lib.ipp_photometry_backward(
+            self.h, frames_c(frames), n, maps, C.byref(pc), C.byref(src),
+            _ptr(sky_lohi), _ptr(g), dp, _ptr(dxy), _stream()))
+        return dxy
+
+    def asinh(self, v: torch.Tensor, a: float, b: float):
+        """y = b * asinh(v / a) (float32, element-wise)."""
+        v = v.contiguous()
+        y = torch.empty_like(v)
+        self._check(self.lib.ipp_asinh(self.h, _ptr(v), _ptr(y), v.numel(),
+                                       float(a), float(b), _stream()))
+        return y
+
+    def asinh_backward(self, v, dy, a: float, b: float, want_dv=True,
+                       want_dab=True):
+        """(dL/dv, tensor([dL/da, dL/db]))."""
+        if want_dab and self.ws_bytes < (1 << 16):
+            self.reserve(1 << 16)
+        v = v.contiguous()
+        dy = dy.contiguous()
+        dv = torch.empty_like(v) if want_dv else None
+        dab = (torch.zeros(2, dtype=torch.float64, device=v.device)
+               if want_dab else None)
+        self._check(self.lib.ipp_asinh_backward(
+            self.h, _ptr(v), _ptr(dy), _ptr(dv), _ptr(dab), v.numel(),
+            float(a), float(b), _stream()))
+        return dv, dab
+
     def process_batch(self, frames, params: Params, capacity=None,
                       table: Optional[SourceTable] = None, outputs=None,
                       write_rms=False):

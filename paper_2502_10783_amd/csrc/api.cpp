@@ -754,4 +754,97 @@ ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
   return run_aperture(c, w, *p, src, nullptr, s);
 }
 
+ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
+                                   int32_t n, const ipp_maps* maps,
+                                   const ipp_params* p,
+                                   const ipp_sources* src,
+                                   const double* sky_lohi,
+                                   const double* dL_dflux,
+                                   float* const* dL_dpix, double* dL_dxy,
+                                   void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (!src || src->capacity < 0 || !src->frame || !src->x || !src->y)
+    return fail(c, IPP_E_INVALID_ARG, "sources: frame, x and y are required");
+  if (!sky_lohi || !dL_dflux)
+    return fail(c, IPP_E_INVALID_ARG, "sky_lohi and dL_dflux are required");
+  Plan P;
+  ipp_status st = prepare(c, frames, n, p, kPlanFrames, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg)
+      return fail(c, IPP_E_INVALID_ARG, "maps[f].bkg is required");
+    P.fd[i].bkg = maps[i].bkg;
+    P.fd[i].dpix = dL_dpix ? dL_dpix[i] : nullptr;
+  }
+  if (src->capacity == 0) return IPP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  const double ri = p->r_in > std::sqrt(2.0) ? p->r_in - std::sqrt(2.0) : 0.0;
+  const double ro = p->r_out + std::sqrt(2.0);
+  const double ring = M_PI * (ro * ro - ri * ri) + 16.0;
+  const dim3 g(grid_for(src->capacity, kWaves, 16384)), b(kBlock);
+  if (ring <= 256)
+    IPP_LAUNCH(c, s, "k_aperture_bwd",
+               hipLaunchKernelGGL((k_aperture_bwd_t<256>), g, b, 0, s, w, *p,
+                                  *src, sky_lohi, dL_dflux, dL_dxy));
+  else if (ring <= 512)
+    IPP_LAUNCH(c, s, "k_aperture_bwd",
+               hipLaunchKernelGGL((k_aperture_bwd_t<512>), g, b, 0, s, w, *p,
+                                  *src, sky_lohi, dL_dflux, dL_dxy));
+  else if (ring <= 1024)
+    IPP_LAUNCH(c, s, "k_aperture_bwd",
+               hipLaunchKernelGGL((k_aperture_bwd_t<1024>), g, b, 0, s, w,
+                                  *p, *src, sky_lohi, dL_dflux, dL_dxy));
+  else
+    return fail(c, IPP_E_UNSUPPORTED, "aperture radii too large");
+  return IPP_OK;
+}
+
+ipp_status ipp_asinh(void* ctx, const float* v, float* y, int64_t n,
+                     double a, double b, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!v || !y)))
+    return fail(c, IPP_E_INVALID_ARG, "v and y are required, n >= 0");
+  if (!std::isfinite(a) || a <= 0 || !std::isfinite(b))
+    return fail(c, IPP_E_INVALID_ARG, "need a > 0 and finite b");
+  if (n == 0) return IPP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  IPP_LAUNCH(c, s, "k_asinh_fwd",
+             hipLaunchKernelGGL(k_asinh_fwd, dim3(grid_for(n, 4 * kBlock,
+                                                           8192)),
+                                dim3(kBlock), 0, s, v, y, n,
+                                (float)(1.0 / a), (float)b));
+  return IPP_OK;
+}
+
+ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
+                              float* dv, double* dL_dab, int64_t n, double a,
+                              double b, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!v || !dy)))
+    return fail(c, IPP_E_INVALID_ARG, "v and dy are required, n >= 0");
+  if (!std::isfinite(a) || a <= 0 || !std::isfinite(b))
+    return fail(c, IPP_E_INVALID_ARG, "need a > 0 and finite b");
+  const int grid = grid_for(n, 4 * kBlock, 2048);
+  if (dL_dab && c->ws_bytes < (size_t)grid * 16)
+    return fail(c, IPP_E_WORKSPACE, "workspace too small for the partials");
+  hipStream_t s = (hipStream_t)stream;
+  double* part = dL_dab ? (double*)c->ws : nullptr;
+  ++c->ws_gen;
+  IPP_LAUNCH(c, s, "k_asinh_bwd",
+             hipLaunchKernelGGL(k_asinh_bwd, dim3(grid), dim3(kBlock), 0, s,
+                                v, dy, dv, n, a, b, part));
+  if (dL_dab)
+    IPP_LAUNCH(c, s, "k_asinh_bwd_final",
+               hipLaunchKernelGGL(k_asinh_bwd_final, dim3(1), dim3(kBlock), 0,
+                                  s, part, grid, dL_dab));
+  return IPP_OK;
+}
+
 }  // extern "C"

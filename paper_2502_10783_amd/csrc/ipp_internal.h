@@ -37,6 +37,7 @@ struct FrameDev {
   int32_t* o_n;
   double* o_bkg;
   double* o_rms;
+  float* dpix;           // pixel gradient (photometry backward), or null
 };
 
 // Partial candidate: the piece of a connected component inside one

@@ -311,4 +311,206 @@ template __global__ void k_aperture_t<512>(Work, ipp_params, ipp_sources,
 template __global__ void k_aperture_t<1024>(Work, ipp_params, ipp_sources,
                                             double*);
 
+// ---------------------------------------------------------------------
+// Backward of the aperture flux (the annulus clip mask held fixed: the
+// survivors are the annulus pixels whose value lies in the forward's
+// [vlo, vhi]).  With A = sum w_ap, W = sum m w_ann, sky = sum m w_ann v / W:
+//   dF/dv_i = w_ap_i - A m_i w_ann_i / W
+//   dF/dc   = sum v dw_ap/dc - sky dA/dc - A (sum m v dw_ann/dc
+//             - sky sum m dw_ann/dc) / W
+// One wavefront per source; pixel gradients are scattered with float
+// atomics (dL/dI; dL/dB32 is its negative), centre gradients written per
+// row.
+// ---------------------------------------------------------------------
+namespace {
+
+template <int NS>
+struct BwLds {
+  int apb[kApTasks];
+  double apw[kApTasks];
+  int anb[NS];
+  double anw[NS];
+};
+
+template <int NS>
+__device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
+                                 const ipp_sources& src,
+                                 const double* sky_lohi, const double* gF,
+                                 double* dxy, long long row, BwLds<NS>& L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int f = src.frame[row];
+  const double cx = src.x[row], cy = src.y[row];
+  const double g = gF[row];
+  const bool fok = f >= 0 && f < wk.nframes;
+  if (!fok || !(isfinite(cx) && isfinite(cy)) || fabs(cx) > 1e9 ||
+      fabs(cy) > 1e9 || g == 0.0) {
+    if (lane == 0 && dxy) { dxy[2 * row] = 0.0; dxy[2 * row + 1] = 0.0; }
+    return;
+  }
+  const FrameDev& fr = wk.frames[f];
+  const double vlo = sky_lohi[2 * row], vhi = sky_lohi[2 * row + 1];
+  const double R = p.r_ap > p.r_out ? p.r_ap : p.r_out;
+  const int xa = (int)ceil(cx - R - 0.5), xb = (int)floor(cx + R + 0.5);
+  const int ya = (int)ceil(cy - R - 0.5), yb = (int)floor(cy + R + 0.5);
+  const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
+
+  // pass 1: sums, with the cut pixels' weights kept in LDS
+  double A = 0.0, W = 0.0, Sv = 0.0;
+  double tvx = 0.0, tvy = 0.0, tax = 0.0, tay = 0.0;   // aperture terms
+  double svx = 0.0, svy = 0.0, swx = 0.0, swy = 0.0;   // sky terms
+  int nap = 0, nan_ = 0;
+  for (int e0 = 0; e0 < npx; e0 += kWave) {
+    const int e = e0 + lane;
+    bool ap_cut = false, an_cut = false;
+    if (e < npx) {
+      const int px = xa + e % nwx, py = ya + e / nwx;
+      const bool in_ap = touches(cx, cy, p.r_ap, px, py);
+      const bool in_ann = touches(cx, cy, p.r_out, px, py) &&
+                          !within(cx, cy, p.r_in, px, py);
+      if ((in_ap || in_ann) && px >= 0 && px < fr.w && py >= 0 &&
+          py < fr.h) {
+        const float I = fr.pix[(int64_t)py * fr.pitch + px];
+        if (isfinite(I)) {
+          const double v =
+              (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+          if (in_ap) {
+            if (within(cx, cy, p.r_ap, px, py)) A += 1.0;
+            else ap_cut = true;
+          }
+          if (in_ann && v >= vlo && v <= vhi) {
+            if (within(cx, cy, p.r_out, px, py) &&
+                !touches(cx, cy, p.r_in, px, py)) {
+              W += 1.0;
+              Sv += v;
+            } else {
+              an_cut = true;
+            }
+          }
+        }
+      }
+    }
+    const uint64_t b1 = __ballot(ap_cut);
+    if (ap_cut) {
+      const int s = nap + __popcll(b1 & lanes_below());
+      if (s < kApTasks) L.apb[s] = e;
+    }
+    nap += __popcll(b1);
+    const uint64_t b2 = __ballot(an_cut);
+    if (an_cut) {
+      const int s = nan_ + __popcll(b2 & lanes_below());
+      if (s < NS) L.anb[s] = e;
+    }
+    nan_ += __popcll(b2);
+  }
+  if (nap > kApTasks) nap = kApTasks;
+  if (nan_ > NS) nan_ = NS;
+  wave_lds_sync();
+  for (int j = lane; j < nap; j += kWave) {
+    const int e = L.apb[j];
+    const int px = xa + e % nwx, py = ya + e / nwx;
+    const double v = (double)fr.pix[(int64_t)py * fr.pitch + px] -
+                     (double)fr.bkg[(int64_t)py * fr.w + px];
+    const double w = overlap(cx, cy, p.r_ap, px, py);
+    L.apw[j] = w;
+    A += w;
+    double gx, gy;
+    overlap_grad(cx, cy, p.r_ap, px, py, &gx, &gy);
+    tvx += v * gx; tvy += v * gy;
+    tax += gx; tay += gy;
+  }
+  // interior aperture pixels have zero centre derivative; the interior
+  // annulus survivors too
+  for (int j = lane; j < nan_; j += kWave) {
+    const int e = L.anb[j];
+    const int px = xa + e % nwx, py = ya + e / nwx;
+    const double v = (double)fr.pix[(int64_t)py * fr.pitch + px] -
+                     (double)fr.bkg[(int64_t)py * fr.w + px];
+    const double w = overlap(cx, cy, p.r_out, px, py) -
+                     overlap(cx, cy, p.r_in, px, py);
+    L.anw[j] = w;
+    W += w;
+    Sv += w * v;
+    double ox, oy, ix, iy;
+    overlap_grad(cx, cy, p.r_out, px, py, &ox, &oy);
+    overlap_grad(cx, cy, p.r_in, px, py, &ix, &iy);
+    svx += v * (ox - ix); svy += v * (oy - iy);
+    swx += ox - ix; swy += oy - iy;
+  }
+  // interior aperture pixels also contribute v to nothing else; finish sums
+  A = wave_sum(A);
+  W = wave_sum(W);
+  Sv = wave_sum(Sv);
+  tvx = wave_sum(tvx); tvy = wave_sum(tvy);
+  tax = wave_sum(tax); tay = wave_sum(tay);
+  svx = wave_sum(svx); svy = wave_sum(svy);
+  swx = wave_sum(swx); swy = wave_sum(swy);
+  const double sky = W > 0.0 ? Sv / W : 0.0;
+  if (lane == 0 && dxy) {
+    double dsx = 0.0, dsy = 0.0;
+    if (W > 0.0) {
+      dsx = (svx - sky * swx) / W;
+      dsy = (svy - sky * swy) / W;
+    }
+    dxy[2 * row] = g * ((tvx - sky * tax) - A * dsx);
+    dxy[2 * row + 1] = g * ((tvy - sky * tay) - A * dsy);
+  }
+  float* dp = fr.dpix;
+  if (!dp) { wave_lds_sync(); return; }
+  const double ks = W > 0.0 ? -g * A / W : 0.0;
+  // pass 2: scatter dL/dv
+  for (int e0 = 0; e0 < npx; e0 += kWave) {
+    const int e = e0 + lane;
+    if (e >= npx) continue;
+    const int px = xa + e % nwx, py = ya + e / nwx;
+    if (px < 0 || px >= fr.w || py < 0 || py >= fr.h) continue;
+    const bool in_ap = touches(cx, cy, p.r_ap, px, py);
+    const bool in_ann = touches(cx, cy, p.r_out, px, py) &&
+                        !within(cx, cy, p.r_in, px, py);
+    if (!(in_ap || in_ann)) continue;
+    const float I = fr.pix[(int64_t)py * fr.pitch + px];
+    if (!isfinite(I)) continue;
+    const double v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+    double gd = 0.0;
+    if (in_ap && within(cx, cy, p.r_ap, px, py)) gd += g;
+    if (in_ann && v >= vlo && v <= vhi && within(cx, cy, p.r_out, px, py) &&
+        !touches(cx, cy, p.r_in, px, py))
+      gd += ks;
+    if (gd != 0.0) atomicAdd(&dp[(int64_t)py * fr.w + px], (float)gd);
+  }
+  for (int j = lane; j < nap; j += kWave) {
+    const int e = L.apb[j];
+    const int px = xa + e % nwx, py = ya + e / nwx;
+    atomicAdd(&dp[(int64_t)py * fr.w + px], (float)(g * L.apw[j]));
+  }
+  for (int j = lane; j < nan_; j += kWave) {
+    const int e = L.anb[j];
+    const int px = xa + e % nwx, py = ya + e / nwx;
+    atomicAdd(&dp[(int64_t)py * fr.w + px], (float)(ks * L.anw[j]));
+  }
+  wave_lds_sync();
+}
+
+}  // namespace
+
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_aperture_bwd_t(
+    Work wk, ipp_params p, ipp_sources src, const double* sky_lohi,
+    const double* gF, double* dxy) {
+  __shared__ BwLds<NS> L[kWaves];
+  long long nrows = src.capacity;
+  if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
+  const long long wid = (blockIdx.x * (long long)kBlock + threadIdx.x) / kWave;
+  const long long nw = (long long)gridDim.x * kWaves;
+  BwLds<NS>& mine = L[threadIdx.x / kWave];
+  for (long long row = wid; row < nrows; row += nw)
+    aperture_bwd_one<NS>(wk, p, src, sky_lohi, gF, dxy, row, mine);
+}
+
+template __global__ void k_aperture_bwd_t<256>(
+    Work, ipp_params, ipp_sources, const double*, const double*, double*);
+template __global__ void k_aperture_bwd_t<512>(
+    Work, ipp_params, ipp_sources, const double*, const double*, double*);
+template __global__ void k_aperture_bwd_t<1024>(
+    Work, ipp_params, ipp_sources, const double*, const double*, double*);
+
 }  // namespace ipp

@@ -36,4 +36,16 @@ template <int NS>
 __global__ void k_aperture_t(Work wk, ipp_params p, ipp_sources src,
                              double* sky_lohi);
 
+template <int NS>
+__global__ void k_aperture_bwd_t(Work wk, ipp_params p, ipp_sources src,
+                                 const double* sky_lohi, const double* gF,
+                                 double* dxy);
+
+__global__ void k_asinh_fwd(const float* v, float* y, int64_t n, float inv_a,
+                            float b);
+__global__ void k_asinh_bwd(const float* v, const float* dy, float* dv,
+                            int64_t n, double a, double b, double* partial);
+__global__ void k_asinh_bwd_final(const double* partial, int nb,
+                                  double* out);
+
 }  // namespace ipp

@@ -1,0 +1,180 @@
+"""GPU parity of the gradients: the photometry backward and the asinh
+stretch against the FP64 oracle adjoint (<= 1e-4 relative), finite
+differences of the oracle, torch autograd, and centroid refinement."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import photometry as oph, stretch as ost
+from oracle.refine import refine_centroids as oracle_refine
+from synth import make_frame
+
+import paper_2502_10783_amd as ipp
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ipp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def scene():
+    """A shrunken frame of the 64 x 2048^2 gradient workload: true sky as
+    the background map, centroid guesses with 0.3 px errors."""
+    img, truth, spec = make_frame("grad64", 2, scale=0.125)   # 256 x 256
+    h, w = img.shape
+    bkg = (1000.0 + 0.5 * torch.arange(w, dtype=torch.float64))[None, :]
+    bkg = bkg.expand(h, w).to(torch.float32).contiguous()
+    xg = truth["x_guess"].numpy()
+    yg = truth["y_guess"].numpy()
+    keep = (xg > 2) & (xg < w - 3) & (yg > 2) & (yg < h - 3)
+    return img, bkg, xg[keep][:24], yg[keep][:24]
+
+
+def _run_bwd(ctx, img, bkg, xs, ys, g, p):
+    n = xs.size
+    t = ipp.SourceTable(n, 1, DEV)
+    t.cols["frame"][:n] = 0
+    t.cols["x"][:n] = torch.from_numpy(xs).to(DEV)
+    t.cols["y"][:n] = torch.from_numpy(ys).to(DEV)
+    fr, bk = img.to(DEV), bkg.to(DEV)
+    lohi = ctx.photometry([fr], [bk], t, p, keep_sky=True, use_count=False)
+    dp = torch.zeros_like(fr)
+    dxy = ctx.photometry_backward([fr], [bk], t, p, lohi,
+                                  torch.from_numpy(g).to(DEV), dpix=[dp])
+    torch.cuda.synchronize()
+    return t, dp.cpu().numpy(), dxy[:n].cpu().numpy()
+
+
+@pytest.mark.parametrize("r_ap", [5.0, 2.0])
+def test_backward_matches_oracle_adjoint(ctx, scene, r_ap):
+    img, bkg, xs, ys = scene
+    p = ipp.Params(r_ap=r_ap)
+    op = oracle.Params(r_ap=r_ap)
+    g = np.random.default_rng(7).normal(size=xs.size)
+    t, dp, dxy = _run_bwd(ctx, img, bkg, xs, ys, g, p)
+    ref = oph.photometry(img.numpy(), bkg.numpy(), xs, ys, op)
+    gpix, gx, gy = oph.photometry_adjoint(img.numpy(), bkg.numpy(), xs, ys,
+                                          op, ref["sky_pixels"], g)
+    for k in range(xs.size):
+        want = np.array([gx[k], gy[k]])
+        err = np.linalg.norm(dxy[k] - want)
+        assert err <= 1e-4 * np.linalg.norm(want) + 1e-9, (k, dxy[k], want)
+    scale = np.abs(gpix).max()
+    assert np.max(np.abs(dp - gpix)) <= 1e-4 * scale
+
+
+def test_backward_matches_finite_differences(ctx, scene):
+    img, bkg, xs, ys = scene
+    p, op = ipp.Params(), oracle.Params()
+    xs, ys = xs[:6], ys[:6]
+    g = np.ones(xs.size)
+    _, _, dxy = _run_bwd(ctx, img, bkg, xs, ys, g, p)
+    I, B = img.numpy(), bkg.numpy()
+    h = 1e-3
+    for k in range(xs.size):
+        r = oph.measure(I, B, xs[k], ys[k], op)
+        keep = set(r["sky_pixels"])
+        def F(cx, cy):
+            # flux with the forward's sky mask held fixed
+            num = den = ap = raw = 0.0
+            for py in oph.window(cy, op.r_out):
+                for px in oph.window(cx, op.r_out):
+                    if not (0 <= px < I.shape[1] and 0 <= py < I.shape[0]):
+                        continue
+                    v = float(I[py, px]) - float(B[py, px])
+                    wa = oph.overlap(cx, cy, op.r_ap, px, py)
+                    ap += wa
+                    raw += wa * v
+                    if (px, py) in keep:
+                        wn = (oph.overlap(cx, cy, op.r_out, px, py)
+                              - oph.overlap(cx, cy, op.r_in, px, py))
+                        num += wn * v
+                        den += wn
+            return raw - (num / den) * ap
+        fx = (F(xs[k] + h, ys[k]) - F(xs[k] - h, ys[k])) / (2 * h)
+        fy = (F(xs[k], ys[k] + h) - F(xs[k], ys[k] - h)) / (2 * h)
+        want = np.array([fx, fy])
+        assert np.linalg.norm(dxy[k] - want) <= 2e-3 * np.linalg.norm(want) \
+            + 1e-3, (k, dxy[k], want)
+
+
+def test_asinh_forward_backward(ctx):
+    rng = np.random.default_rng(11)
+    v = rng.normal(0, 300, 100003).astype(np.float32)
+    g = rng.normal(0, 1, v.size).astype(np.float32)
+    a, b = 30.0, 1.7
+    vt, gt = torch.from_numpy(v).to(DEV), torch.from_numpy(g).to(DEV)
+    y = ctx.asinh(vt, a, b).cpu().numpy()
+    dv, dab = ctx.asinh_backward(vt, gt, a, b)
+    torch.cuda.synchronize()
+    yr = ost.asinh_forward(v, a, b)
+    dvr, dar, dbr = ost.asinh_backward(v, g, a, b)
+    np.testing.assert_allclose(y, yr, rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(dv.cpu().numpy(), dvr, rtol=2e-6, atol=1e-9)
+    dab = dab.cpu().numpy()
+    assert abs(dab[0] - dar) <= 1e-9 * np.sum(np.abs(g * v / a))
+    assert abs(dab[1] - dbr) <= 1e-9 * np.sum(np.abs(g * np.arcsinh(v / a)))
+
+
+def test_autograd_functions(ctx, scene):
+    img, bkg, xs, ys = scene
+    p, op = ipp.Params(), oracle.Params()
+    fr = img.to(DEV)[None].clone().requires_grad_(True)
+    bk = bkg.to(DEV)[None].clone().requires_grad_(True)
+    x = torch.from_numpy(xs).to(DEV).requires_grad_(True)
+    y = torch.from_numpy(ys).to(DEV).requires_grad_(True)
+    fi = torch.zeros(xs.size, dtype=torch.int32, device=DEV)
+    flux = ipp.ApertureFlux.apply(fr, bk, x, y, fi, ctx, p)
+    wts = torch.linspace(0.5, 1.5, xs.size, dtype=torch.float64, device=DEV)
+    (flux * wts).sum().backward()
+    ref = oph.photometry(img.numpy(), bkg.numpy(), xs, ys, op)
+    gpix, gx, gy = oph.photometry_adjoint(img.numpy(), bkg.numpy(), xs, ys,
+                                          op, ref["sky_pixels"],
+                                          wts.cpu().numpy())
+    np.testing.assert_allclose(flux.detach().cpu().numpy(), ref["flux"],
+                               rtol=1e-9, atol=1e-6)
+    np.testing.assert_allclose(x.grad.cpu().numpy(), gx, rtol=1e-4,
+                               atol=1e-6)
+    np.testing.assert_allclose(y.grad.cpu().numpy(), gy, rtol=1e-4,
+                               atol=1e-6)
+    scale = np.abs(gpix).max()
+    assert np.max(np.abs(fr.grad[0].cpu().numpy() - gpix)) <= 1e-4 * scale
+    assert torch.equal(bk.grad, -fr.grad)
+    # asinh stretch through autograd
+    v = (fr.detach()[0] - bk.detach()[0]).contiguous().requires_grad_(True)
+    a = torch.tensor(30.0, device=DEV, requires_grad=True)
+    b = torch.tensor(1.0, device=DEV, requires_grad=True)
+    ys_ = ipp.AsinhStretch.apply(v, a, b, ctx)
+    (ys_ * ys_).sum().backward()
+    vn = v.detach().cpu().numpy()
+    yr = ost.asinh_forward(vn, 30.0, 1.0)
+    dvr, dar, dbr = ost.asinh_backward(vn, 2 * yr, 30.0, 1.0)
+    np.testing.assert_allclose(v.grad.cpu().numpy(), dvr, rtol=1e-5,
+                               atol=1e-6)
+    assert abs(float(a.grad) - dar) <= 1e-4 * abs(dar)
+    assert abs(float(b.grad) - dbr) <= 1e-4 * abs(dbr)
+
+
+def test_refine_centroids_matches_oracle(ctx, scene):
+    img, bkg, xs, ys = scene
+    p, op = ipp.Params(), oracle.Params()
+    xs, ys = xs[:12], ys[:12]
+    fr = img.to(DEV)[None]
+    bk = bkg.to(DEV)[None]
+    x, y = ipp.refine_centroids(ctx, fr, bk, torch.from_numpy(xs).to(DEV),
+                                torch.from_numpy(ys).to(DEV),
+                                torch.zeros(xs.size, dtype=torch.int32,
+                                            device=DEV), p, steps=10)
+    torch.cuda.synchronize()
+    xr, yr = oracle_refine(img.numpy(), bkg.numpy(), xs, ys, op, steps=10)
+    np.testing.assert_allclose(x.cpu().numpy(), xr, atol=1e-6)
+    np.testing.assert_allclose(y.cpu().numpy(), yr, atol=1e-6)
