@@ -44,13 +44,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_frames(n, device):
+def make_frames(workload, n, device):
     from synth import spec_for, render
     frames = []
     for i in range(n):
-        img, _ = render(spec_for("stack16", i), "stack16", i, device)
+        img, _ = render(spec_for(workload, i), workload, i, device)
         frames.append(img)
     return frames
+
+
+WORKLOADS = {
+    "stack16": (16, "16 frames of 4096x4096 float32, 5000 Moffat stars each, "
+                    "poly+sinusoid sky, cosmic rays, dead columns"),
+    "uneven": (256, "256 float32 frames drawn from {512x512, 1024x1024, "
+                    "2048x4096, 4096x4096}, star density log-uniform "
+                    "1e-5..5e-3 per px, flat sky U(200, 5000)"),
+}
 
 
 def run_plain(ctx, frames, p, tables):
@@ -112,7 +121,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS),
+                    default="stack16")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="frames of the workload to use (0 = all)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick mesh and tile shape with ipp_autotune on a "
+                         "16-frame sample first")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle CPU baseline")
@@ -127,13 +142,22 @@ def main():
     import paper_2502_10783_amd as ipp
 
     dev = torch.device("cuda:0")
-    log("generating frames on the GPU")
-    frames = make_frames(args.frames, dev)
+    nfr, desc = WORKLOADS[args.workload]
+    if args.frames:
+        nfr = min(nfr, args.frames)
+    log(f"generating {nfr} frames of {args.workload} on the GPU")
+    frames = make_frames(args.workload, nfr, dev)
     torch.cuda.synchronize()
     mpix = sum(f.numel() for f in frames) / 1e6
     p = ipp.Params()
     ctx = ipp.Context(0)
-    cap = sum(f.numel() for f in frames) // 256 + 4096
+    tuned = None
+    if args.autotune:
+        log("autotuning on a 16-frame sample")
+        p, tms = ctx.autotune(frames[:16], p)
+        tuned = {"mesh": p.mesh_h, "tile": [p.tile_h, p.tile_w],
+                 "sample_ms": round(tms, 4)}
+    cap = sum(f.numel() for f in frames) // 64 + 4096
     table = ipp.SourceTable(cap, len(frames), dev)
     outputs = {"bkg": [torch.empty_like(f) for f in frames],
                "labels": [torch.empty(f.shape, dtype=torch.int32, device=dev)
@@ -163,17 +187,18 @@ def main():
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
 
-    log(f"timing {args.plain_steps} plain per-frame steps")
-    ptables = [ipp.SourceTable(cap // len(frames) * 2 + 4096, 1, dev)
-               for _ in frames]
-    run_plain(ctx, frames, p, ptables)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    psrc = 0
-    for _ in range(args.plain_steps):
-        psrc = run_plain(ctx, frames, p, ptables)
-    torch.cuda.synchronize()
-    ms_plain = (time.perf_counter() - t0) * 1e3 / args.plain_steps
+    ms_plain, psrc = None, 0
+    if args.plain_steps > 0:
+        log(f"timing {args.plain_steps} plain per-frame steps")
+        ptables = [ipp.SourceTable(f.numel() // 64 + 4096, 1, dev)
+                   for f in frames]
+        run_plain(ctx, frames, p, ptables)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            psrc = run_plain(ctx, frames, p, ptables)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t0) * 1e3 / args.plain_steps
 
     log("per-kernel event timing")
     ctx.profile(True)
@@ -207,7 +232,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline")
-        cpu = cpu_baseline(frames[0].cpu(), p)
+        big = max(range(len(frames)), key=lambda i: frames[i].numel())
+        cpu = cpu_baseline(frames[big].cpu(), p)
 
     value = mpix / (ms * 1e-3)
     res = {
@@ -223,19 +249,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{len(frames)} frames of 4096x4096 float32, "
-                               "5000 Moffat stars each, poly+sinusoid sky, "
-                               "cosmic rays, dead columns",
+        "config": {"workload": desc if nfr == WORKLOADS[args.workload][0]
+                   else f"first {nfr} frames of: {desc}",
+                   "name": args.workload,
                    "frames": len(frames), "mpix_per_step": round(mpix, 3),
-                   "mesh": p.mesh_h, "det_nsigma": p.det_nsigma,
+                   "mesh": p.mesh_h, "tile": [p.tile_h or 64, p.tile_w or 64],
+                   "autotuned": tuned, "det_nsigma": p.det_nsigma,
                    "min_area": p.min_area, "aperture": [p.r_ap, p.r_in,
                                                         p.r_out]},
         "sources_per_step": nsrc,
         "sources_per_s": round(nsrc / (ms * 1e-3), 1),
-        "plain": {"ms_per_step": round(ms_plain, 3),
-                  "mpix_per_s": round(mpix / (ms_plain * 1e-3), 2),
-                  "sources_per_s": round(psrc / (ms_plain * 1e-3), 1)},
-        "speedup_vs_plain": round(ms_plain / ms, 3),
+        "plain": None if ms_plain is None else {
+            "ms_per_step": round(ms_plain, 3),
+            "mpix_per_s": round(mpix / (ms_plain * 1e-3), 2),
+            "sources_per_s": round(psrc / (ms_plain * 1e-3), 1)},
+        "speedup_vs_plain": (None if ms_plain is None
+                             else round(ms_plain / ms, 3)),
         "flux_err_max": ferr,
         "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in
                        sorted(kern.items(), key=lambda kv: -kv[1]["ms_avg"])},

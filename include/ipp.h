@@ -286,6 +286,26 @@ ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
                               float* dv, double* dL_dab, int64_t n, double a,
                               double b, void* stream);
 
+/* ipp_autotune: what to tune */
+#define IPP_TUNE_MESH 1u   /* mesh size from {32, 64, 128} (changes results) */
+#define IPP_TUNE_TILE 2u   /* detection tile shape 64x64, 32x128, 128x32
+                              (results unchanged)                         */
+
+/*
+ * Autotuner of the pipeline mode (Sec. 2.1 runs fixed parameter sets from a
+ * configuration file): times ipp_process_batch on the given frames for
+ * every candidate mesh size and/or tile shape selected by `what`, keeps
+ * the fastest in *p (the other fields are untouched) and its time in
+ * *best_ms (nullable).  With cache_path (nullable) the choice is looked up
+ * first and stored afterwards in that JSON file, keyed by the device
+ * architecture, the multiset of frame shapes and a hash of the remaining
+ * parameters.  Allocates its trial outputs with hipMalloc, may grow the
+ * context workspace, synchronizes `stream`.  Not for use under capture.
+ */
+ipp_status ipp_autotune(void* ctx, const ipp_frame* frames, int32_t n,
+                        ipp_params* p, uint32_t what, const char* cache_path,
+                        double* best_ms, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

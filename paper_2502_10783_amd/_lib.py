@@ -21,6 +21,8 @@ IPP_E_WORKSPACE = -5
 
 IPP_EST_SEXTRACTOR, IPP_EST_MEDIAN, IPP_EST_MEAN, IPP_EST_MODE = 0, 1, 2, 3
 IPP_F_WRITE_RMS = 1
+IPP_TUNE_MESH = 1
+IPP_TUNE_TILE = 2
 IPP_FRAME_NO_VALID_MESH = 1
 IPP_FRAME_EMPTY_MESH = 2
 IPP_SRC_APERTURE_OFF_EDGE = 1
@@ -144,6 +146,10 @@ def lib():
     L.ipp_asinh_backward.argtypes = [vp, vp, vp, vp, vp, i64, C.c_double,
                                      C.c_double, vp]
     L.ipp_asinh_backward.restype = i32
+    L.ipp_autotune.argtypes = [vp, C.POINTER(IppFrame), i32,
+                               C.POINTER(IppParams), C.c_uint32, C.c_char_p,
+                               C.POINTER(C.c_double), vp]
+    L.ipp_autotune.restype = i32
     _lib = L
     return L
 

@@ -319,6 +319,26 @@ class Context:
             float(a), float(b), _stream()))
         return dv, dab
 
+    def autotune(self, frames, params: Params, mesh=True, tile=True,
+                 cache_path: Optional[str] = None):
+        """Fastest mesh size / tile shape for this batch on this device:
+        returns (Params, ms)."""
+        what = (L.IPP_TUNE_MESH if mesh else 0) | (L.IPP_TUNE_TILE if tile
+                                                   else 0)
+        pc = params.to_c()
+        ms = C.c_double(0.0)
+        self._check(self.lib.ipp_autotune(
+            self.h, frames_c(frames), len(frames), C.byref(pc), what,
+            cache_path.encode() if cache_path else None, C.byref(ms),
+            _stream()))
+        self.ws_bytes = max(self.ws_bytes, self.workspace_bytes(
+            frames, params))
+        out = Params(**{f.name: getattr(params, f.name)
+                        for f in fields(params)})
+        out.mesh_h, out.mesh_w = pc.mesh_h, pc.mesh_w
+        out.tile_h, out.tile_w = pc.tile_h, pc.tile_w
+        return out, ms.value
+
     def process_batch(self, frames, params: Params, capacity=None,
                       table: Optional[SourceTable] = None, outputs=None,
                       write_rms=False):

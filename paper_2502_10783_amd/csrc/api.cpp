@@ -14,11 +14,17 @@
 
 using namespace ipp;
 
+// A captured batch pipeline.  The graph bakes in the workspace layout, the
+// parameters and the table; the frame descriptors (pixel and map pointers)
+// live in the workspace and are uploaded before each launch unless the
+// workspace was not touched since the same descriptors were uploaded.
 struct IppGraph {
   std::vector<uint8_t> key;       // batch signature
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  uint64_t ws_gen = 0;            // workspace generation the graph saw
+  uint64_t ws_gen = 0;            // workspace generation of the last upload
+  std::vector<uint8_t> fd;        // descriptors of the last upload
+  uint64_t last_use = 0;
 };
 
 struct ProfSlot {
@@ -36,7 +42,10 @@ struct IppCtx {
   size_t ws_bytes = 0;
   uint64_t ws_gen = 1;            // bumped when the workspace is reused
   std::string err;
-  IppGraph graph;
+  std::vector<IppGraph> graphs;   // small LRU cache of captured batches
+  uint64_t tick = 0;
+  hipStream_t cap = nullptr;      // private stream used only for capture
+  bool use_graphs = true;
 };
 
 namespace {
@@ -78,6 +87,14 @@ void prof_collect(IppCtx* c) {
     if (!found) c->totals.push_back({ps.name, {(double)ms, 1}});
   }
   c->used = 0;
+}
+
+void drop_graphs(IppCtx* c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.graph) hipGraphDestroy(g.graph);
+  }
+  c->graphs.clear();
 }
 
 constexpr int64_t kMaxDim = 32767;
@@ -475,6 +492,17 @@ ipp_status run_aperture(IppCtx* c, const Work& w, const ipp_params& p,
   return IPP_OK;
 }
 
+// The whole fused batch sequence (also what a captured graph contains).
+ipp_status run_batch(IppCtx* c, const Plan& P, const Work& w,
+                     const ipp_params& p, ipp_sources* src, int write_rms,
+                     int64_t* diag, hipStream_t s) {
+  ipp_status st;
+  if ((st = run_mesh(c, P, w, p, s)) != IPP_OK) return st;
+  if ((st = run_detect(c, P, w, p, src, true, write_rms, diag, s)) != IPP_OK)
+    return st;
+  return run_aperture(c, w, p, src, nullptr, s);
+}
+
 std::string check_sources(const ipp_sources* s, bool detect) {
   if (!s) return "sources is NULL";
   if (s->capacity < 0) return "sources capacity < 0";
@@ -557,8 +585,8 @@ ipp_status ipp_ctx_destroy(void* ctx) {
   IppCtx* c = (IppCtx*)ctx;
   if (!c) return IPP_E_INVALID_ARG;
   hipSetDevice(c->device);
-  if (c->graph.exec) hipGraphExecDestroy(c->graph.exec);
-  if (c->graph.graph) hipGraphDestroy(c->graph.graph);
+  drop_graphs(c);
+  if (c->cap) hipStreamDestroy(c->cap);
   if (c->ws) hipFree(c->ws);
   for (auto& ps : c->pool) {
     hipEventDestroy(ps.a);
@@ -573,15 +601,7 @@ ipp_status ipp_ctx_reserve(void* ctx, size_t bytes) {
   if (!c) return IPP_E_INVALID_ARG;
   if (bytes <= c->ws_bytes) return IPP_OK;
   hipSetDevice(c->device);
-  if (c->graph.exec) {              // graphs hold old workspace addresses
-    hipGraphExecDestroy(c->graph.exec);
-    c->graph.exec = nullptr;
-  }
-  if (c->graph.graph) {
-    hipGraphDestroy(c->graph.graph);
-    c->graph.graph = nullptr;
-  }
-  c->graph.key.clear();
+  drop_graphs(c);                   // graphs hold old workspace addresses
   if (c->ws) {
     hipDeviceSynchronize();
     hipFree(c->ws);
@@ -746,12 +766,79 @@ ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
   hipStream_t s = (hipStream_t)stream;
   Work w = make_work(P, c->ws, n);
   if (frame_flags) w.frame_flags = frame_flags;
-  ++c->ws_gen;
-  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
-  if ((st = run_mesh(c, P, w, *p, s)) != IPP_OK) return st;
-  if ((st = run_detect(c, P, w, *p, src, true, write_rms, diag, s)) != IPP_OK)
-    return st;
-  return run_aperture(c, w, *p, src, nullptr, s);
+  if (c->prof || !c->use_graphs) {          // eager (kernel timing on)
+    ++c->ws_gen;
+    if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+    return run_batch(c, P, w, *p, src, write_rms, diag, s);
+  }
+  // signature: everything the captured kernels bake in
+  std::vector<uint8_t> key;
+  auto put = [&](const void* d, size_t len) {
+    const uint8_t* b = (const uint8_t*)d;
+    key.insert(key.end(), b, b + len);
+  };
+  put(&n, sizeof(n));
+  for (int i = 0; i < n; ++i) {
+    put(&frames[i].h, sizeof(int32_t));
+    put(&frames[i].w, sizeof(int32_t));
+  }
+  put(p, sizeof(*p));
+  put(src, sizeof(*src));
+  put(&w, sizeof(w));
+  put(&diag, sizeof(diag));
+  IppGraph* G = nullptr;
+  for (auto& g : c->graphs)
+    if (g.key == key) G = &g;
+  const uint8_t* fdb = (const uint8_t*)P.fd.data();
+  std::vector<uint8_t> fdv(fdb, fdb + sizeof(FrameDev) * P.fd.size());
+  if (!G) {
+    if (c->graphs.size() >= 4) {            // evict the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < c->graphs.size(); ++i)
+        if (c->graphs[i].last_use < c->graphs[lru].last_use) lru = i;
+      if (c->graphs[lru].exec) hipGraphExecDestroy(c->graphs[lru].exec);
+      if (c->graphs[lru].graph) hipGraphDestroy(c->graphs[lru].graph);
+      c->graphs.erase(c->graphs.begin() + lru);
+    }
+    if (!c->cap &&
+        hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+      return fail(c, IPP_E_DEVICE, "cannot create the capture stream");
+    IppGraph g;
+    g.key = key;
+    if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) !=
+        hipSuccess)
+      return fail(c, IPP_E_DEVICE, "hipStreamBeginCapture failed");
+    st = run_batch(c, P, w, *p, src, write_rms, diag, c->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (st != IPP_OK || e != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return st != IPP_OK ? st
+                          : fail(c, IPP_E_DEVICE, "hipStreamEndCapture failed");
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) !=
+        hipSuccess) {
+      hipGraphDestroy(graph);
+      return fail(c, IPP_E_DEVICE, "hipGraphInstantiate failed");
+    }
+    g.graph = graph;
+    g.exec = exec;
+    c->graphs.push_back(g);
+    G = &c->graphs.back();
+  }
+  G->last_use = ++c->tick;
+  if (G->ws_gen != c->ws_gen || G->fd != fdv) {
+    if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+    ++c->ws_gen;
+    G->ws_gen = c->ws_gen;
+    G->fd = fdv;
+  }
+  const hipError_t e = hipGraphLaunch(G->exec, s);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE, std::string("hipGraphLaunch: ") +
+                                     hipGetErrorString(e));
+  return IPP_OK;
 }
 
 ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
