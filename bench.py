@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle CPU baseline")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB "
+                         "(a kernel of known traffic, to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single "
@@ -149,6 +152,14 @@ def main():
     frames = make_frames(args.workload, nfr, dev)
     torch.cuda.synchronize()
     mpix = sum(f.numel() for f in frames) / 1e6
+    if args.calib_copy:
+        n = args.calib_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     p = ipp.Params()
     ctx = ipp.Context(0)
     tuned = None

@@ -166,7 +166,7 @@ std::string check_frames(const ipp_frame* f, int32_t n) {
 // Workspace layout of one call.
 struct Plan {
   std::vector<FrameDev> fd;
-  int32_t nodes = 0, dtiles = 0, rows = 0;
+  int32_t nodes = 0, dtiles = 0, rows = 0, lines[2] = {0, 0};
   int64_t pix = 0;
   int64_t rec_cap = 0;
   int th = 64, tw = 64;
@@ -195,6 +195,10 @@ Plan make_plan(const ipp_frame* f, int32_t n, const ipp_params& p,
     d.nx = (f[i].w + p.mesh_w - 1) / p.mesh_w;
     d.node0 = P.nodes;
     P.nodes += d.ny * d.nx;
+    d.line0[0] = P.lines[0];
+    P.lines[0] += 2 * (d.ny + d.nx);
+    d.line0[1] = P.lines[1];
+    P.lines[1] += 2 * d.nx;
     d.dty = (f[i].h + P.th - 1) / P.th;
     d.dtx = (f[i].w + P.tw - 1) / P.tw;
     d.dtile0 = P.dtiles;
@@ -249,6 +253,8 @@ Work make_work(const Plan& P, void* ws, int32_t n) {
   w.total_nodes = P.nodes;
   w.total_dtiles = P.dtiles;
   w.total_rows = P.rows;
+  w.total_lines[0] = P.lines[0];
+  w.total_lines[1] = P.lines[1];
   w.total_pix = P.pix;
   w.m_bkg = (double*)(b + P.o_mbkg);
   w.m_rms = (double*)(b + P.o_mrms);
@@ -358,8 +364,31 @@ ipp_status run_mesh(IppCtx* c, const Plan& P, const Work& w,
   else
     IPP_LAUNCH(c, s, "k_mesh_stats", hipLaunchKernelGGL(k_mesh_stats<64>, dim3(P.nodes),
                                      dim3(kBlock), 0, s, w, p));
-  IPP_LAUNCH(c, s, "k_mesh_finish", hipLaunchKernelGGL(k_mesh_finish, dim3((int)P.fd.size()),
-                                   dim3(kBlock), 0, s, w, p));
+  IPP_LAUNCH(c, s, "k_mesh_fill",
+             hipLaunchKernelGGL(k_mesh_fill, dim3((int)P.fd.size()),
+                                dim3(kBlock), 0, s, w, p));
+  const dim3 gn(grid_for(P.nodes, kBlock, 1 << 30));
+  const int fmax = std::max(p.filter_h, p.filter_w) / 2;
+  if (fmax <= 1)
+    IPP_LAUNCH(c, s, "k_mesh_filter",
+               hipLaunchKernelGGL((k_mesh_filter<1>), gn, dim3(kBlock), 0, s,
+                                  w, p));
+  else if (fmax == 2)
+    IPP_LAUNCH(c, s, "k_mesh_filter",
+               hipLaunchKernelGGL((k_mesh_filter<2>), gn, dim3(kBlock), 0, s,
+                                  w, p));
+  else
+    IPP_LAUNCH(c, s, "k_mesh_filter",
+               hipLaunchKernelGGL((k_mesh_filter<3>), gn, dim3(kBlock), 0, s,
+                                  w, p));
+  IPP_LAUNCH(c, s, "k_mesh_spline",
+             hipLaunchKernelGGL((k_mesh_spline<0>),
+                                dim3(grid_for(P.lines[0], 64, 1 << 30)),
+                                dim3(64), 0, s, w, p));
+  IPP_LAUNCH(c, s, "k_mesh_spline",
+             hipLaunchKernelGGL((k_mesh_spline<1>),
+                                dim3(grid_for(P.lines[1], 64, 1 << 30)),
+                                dim3(64), 0, s, w, p));
   return IPP_OK;
 }
 

@@ -38,6 +38,7 @@ struct FrameDev {
   double* o_bkg;
   double* o_rms;
   float* dpix;           // pixel gradient (photometry backward), or null
+  int32_t line0[2];      // first mesh line of each spline pass
 };
 
 // Partial candidate: the piece of a connected component inside one
@@ -57,6 +58,7 @@ struct Work {
   int32_t total_nodes;
   int32_t total_dtiles;
   int32_t total_rows;
+  int32_t total_lines[2];
   int64_t total_pix;
   // mesh, one entry per node of every frame
   double* m_bkg;         // raw estimator value

@@ -23,8 +23,8 @@ template <int TH, int TW, bool CONN8>
 struct CclLds {
   static constexpr int NP = TH * TW;
   static constexpr int NCMP = CONN8 ? NP / 4 : NP / 2;
-  int parent[NP];
-  int16_t cid[NP];
+  int parent[NP];              // union-find; after numbering a root holds
+                               // -2 - (its component id)
   union {
     SplineLds<TH, TW> spl;
     struct {
@@ -39,7 +39,6 @@ struct CclLds {
   int wcnt[16 * kWaves];
   int ired[kWaves];
   int ncomp;
-  int nkept;
   long long rbase;
 };
 
@@ -129,6 +128,15 @@ __global__ __launch_bounds__(kBlock) void k_bkg_maps(Work wk, ipp_params p) {
 
 // ---------------------------------------------------------------------
 // Tile kernel: threshold + LDS labelling + records.
+//
+// Pixel q = t + 256 k of the tile (raster order) belongs to lane t % 64 of
+// wave t / 64, so each wave instruction covers 64 consecutive pixels of a
+// row (two half rows for 32-wide tiles).  Detected pixels that are
+// horizontally contiguous within such a segment form a run; every pixel of
+// a run starts linked to the run's first pixel, and only one union per run
+// of the row above that touches it (and one across a segment split inside
+// a row) is needed.  Counts, bounding boxes and border contact are
+// accumulated once per run.
 // ---------------------------------------------------------------------
 template <int TH, int TW, bool FUSED, bool CONN8>
 __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
@@ -137,6 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   constexpr int NP = Lds::NP;
   constexpr int NCMP = Lds::NCMP;
   constexpr int PPT = NP / kBlock;            // 16
+  static_assert(TW >= 32 && kWave % TW == 0 || TW % kWave == 0,
+                "tile width must divide or be divided by the wave size");
   __shared__ Lds L;
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1), wv = t / kWave;
@@ -148,8 +158,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
 
   if (FUSED) spline_prologue<TH, TW>(wk, fr, p, y0, x0, L.u.spl);
 
-  // ---- threshold: v = I - B32 > nsigma * R32 ---------------------------
+  // lanes that start / end a row inside the wave's 64-pixel segment
+  uint64_t row_first = 1ull, row_last = 1ull << 63;
+  if (TW < kWave) {
+    for (int l = 0; l < kWave; l += TW) {
+      row_first |= 1ull << l;
+      row_last |= 1ull << (l + TW - 1);
+    }
+  }
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t upto = below | (1ull << lane);
+
+  // ---- threshold: v = I - B32 > nsigma * R32; runs ----------------------
   uint32_t fgm = 0;
+  uint64_t fgb[PPT];
 #pragma unroll 4
   for (int k = 0; k < PPT; ++k) {
     const int q = t + kBlock * k;
@@ -176,25 +198,44 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
       det = isfinite(I) && (v > thr);
     }
     fgm |= (uint32_t)det << k;
-    L.parent[q] = det ? q : -1;
+    const uint64_t m = __ballot(det);
+    fgb[k] = m;
+    const uint64_t heads = m & (~(m << 1) | row_first);
+    int par = -1;
+    if (det) {
+      const int s_lane = 63 - __clzll(heads & upto);
+      par = q - (lane - s_lane);
+    }
+    L.parent[q] = par;
   }
   __syncthreads();
 
-  // ---- union with the already-visited neighbours -----------------------
+  // ---- unions with the runs of the row above ----------------------------
 #pragma unroll 4
   for (int k = 0; k < PPT; ++k) {
     if (!((fgm >> k) & 1u)) continue;
+    const uint64_t m = fgb[k];
     const int q = t + kBlock * k;
     const int r = q / TW, c = q % TW;
-    if (c > 0 && lds_load(&L.parent[q - 1]) >= 0) lunion(L.parent, q, q - 1);
-    if (r > 0) {
-      if (lds_load(&L.parent[q - TW]) >= 0) lunion(L.parent, q, q - TW);
-      if (CONN8) {
-        if (c > 0 && lds_load(&L.parent[q - TW - 1]) >= 0)
-          lunion(L.parent, q, q - TW - 1);
-        if (c < TW - 1 && lds_load(&L.parent[q - TW + 1]) >= 0)
-          lunion(L.parent, q, q - TW + 1);
-      }
+    const bool head = !((m >> lane) & 1ull & (m << 1 >> lane) & 1ull) ||
+                      ((row_first >> lane) & 1ull);
+    const bool tail = !(((m >> 1) >> lane) & 1ull) ||
+                      ((row_last >> lane) & 1ull);
+    // a run cut by the wave boundary inside a row
+    if (head && lane == 0 && c > 0 && lds_load(&L.parent[q - 1]) >= 0)
+      lunion(L.parent, q, q - 1);
+    if (r == 0) continue;
+    const int x = q - TW;
+    const bool fx = lds_load(&L.parent[x]) >= 0;
+    const bool fxl = c > 0 && lds_load(&L.parent[x - 1]) >= 0;
+    if (CONN8) {
+      if (fx && !fxl) lunion(L.parent, q, x);
+      if (head && fxl) lunion(L.parent, q, x - 1);
+      if (tail && c < TW - 1 && !fx &&
+          lds_load(&L.parent[x + 1]) >= 0)
+        lunion(L.parent, q, x + 1);
+    } else {
+      if (fx && (head || !fxl)) lunion(L.parent, q, x);
     }
   }
   __syncthreads();
@@ -218,14 +259,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     if (lane == 0) L.wcnt[k * kWaves + wv] = __popcll(b);
   }
   __syncthreads();
-  if (t == 0) {
-    int s = 0;
-    for (int i = 0; i < PPT * kWaves; ++i) {
-      const int v = L.wcnt[i];
-      L.wcnt[i] = s;
-      s += v;
+  if (wv == 0) {                   // exclusive scan of the 64 counts
+    const int v = L.wcnt[lane];
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(x, o, kWave);
+      if (lane >= o) x += u;
     }
-    L.ncomp = s;
+    L.wcnt[lane] = x - v;
+    if (lane == kWave - 1) L.ncomp = x;
   }
   __syncthreads();
   const int ncomp = L.ncomp;
@@ -235,8 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     const uint64_t b = __ballot(isroot);
     if (isroot) {
       const int q = t + kBlock * k;
-      const int id = L.wcnt[k * kWaves + wv] + __popcll(b & lanemask_lt());
-      L.cid[q] = (int16_t)id;
+      const int id = L.wcnt[k * kWaves + wv] + __popcll(b & below);
+      L.parent[q] = -2 - id;
       L.u.st.rootp[id] = (int16_t)q;
     }
   }
@@ -247,22 +290,34 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     L.u.st.ymax[c] = -1;
   }
   __syncthreads();
+  auto comp_of = [&](int q) {
+    const int pq = L.parent[q];
+    return pq < 0 ? -2 - pq : -2 - L.parent[pq];
+  };
 
-  // ---- per-component pixel count, bounding box, inner-border contact ----
+  // ---- per-run pixel count, bounding box, inner-border contact ----------
   const bool nb_up = y0 > 0, nb_down = y0 + TH < fr.h;
   const bool nb_left = x0 > 0, nb_right = x0 + TW < fr.w;
 #pragma unroll 4
   for (int k = 0; k < PPT; ++k) {
     if (!((fgm >> k) & 1u)) continue;
+    const uint64_t m = fgb[k];
+    const bool head = !((m >> lane) & 1ull & (m << 1 >> lane) & 1ull) ||
+                      ((row_first >> lane) & 1ull);
+    if (!head) continue;
     const int q = t + kBlock * k;
     const int r = q / TW, c = q % TW;
-    const int id = L.cid[L.parent[q]];
-    atomicAdd(&L.u.st.npix[id], 1);
+    const uint64_t ends = m & (~(m >> 1) | row_last);
+    const int e_lane = __ffsll((unsigned long long)(ends & ~below)) - 1;
+    const int len = e_lane - lane + 1;
+    const int ce = c + len - 1;
+    const int id = comp_of(q);
+    atomicAdd(&L.u.st.npix[id], len);
     atomicMin(&L.u.st.xmin[id], c);
-    atomicMax(&L.u.st.xmax[id], c);
+    atomicMax(&L.u.st.xmax[id], ce);
     atomicMax(&L.u.st.ymax[id], r);
     const bool edge = (r == 0 && nb_up) || (r == TH - 1 && nb_down) ||
-                      (c == 0 && nb_left) || (c == TW - 1 && nb_right);
+                      (c == 0 && nb_left) || (ce == TW - 1 && nb_right);
     if (edge) atomicOr(&L.u.st.npix[id], 1 << 30);
   }
   __syncthreads();
@@ -298,7 +353,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     if (base + ktot > wk.rec_cap)
       atomicOr((unsigned long long*)&wk.counters[2], 1ull);
     L.rbase = base;
-    L.nkept = ktot;
     wk.tile_rbase[tile] = (int32_t)(base < wk.rec_cap ? base : wk.rec_cap);
   }
   __syncthreads();
@@ -332,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     if (y < fr.h && x < fr.w) {
       uint16_t v = 0;
       if ((fgm >> k) & 1u) {
-        const int rl = L.u.st.rloc[L.cid[L.parent[q]]];
+        const int rl = L.u.st.rloc[comp_of(q)];
         if (rl >= 0 && rbase + rl < wk.rec_cap) v = (uint16_t)(rl + 1);
       }
       wk.lmap[fr.pix0 + (int64_t)y * fr.w + x] = v;

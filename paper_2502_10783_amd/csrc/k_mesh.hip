@@ -315,15 +315,29 @@ __global__ __launch_bounds__(kBlock) void k_mesh_stats(Work wk,
 // ---------------------------------------------------------------------
 namespace {
 
-__device__ double median_small(double* v, int n) {
-  for (int i = 1; i < n; ++i) {           // insertion sort, n <= 49
-    double x = v[i];
-    int j = i - 1;
-    while (j >= 0 && v[j] > x) { v[j + 1] = v[j]; --j; }
-    v[j + 1] = x;
+// Median (Eq. 1) of the valid entries of a window held in registers: the
+// order statistics of rank (n-1)/2 and n/2 found by rank counting, fully
+// unrolled so nothing is indexed dynamically.
+template <int MAXN>
+__device__ __forceinline__ double median_window(const double (&v)[MAXN],
+                                                uint64_t valid, int n) {
+  const int k1 = (n - 1) / 2, k2 = n / 2;
+  double m1 = 0.0, m2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < MAXN; ++i) {
+    if (!((valid >> i) & 1ull)) continue;
+    int lt = 0, le = 0;
+#pragma unroll
+    for (int j = 0; j < MAXN; ++j) {
+      if ((valid >> j) & 1ull) {
+        lt += v[j] < v[i];
+        le += v[j] <= v[i];
+      }
+    }
+    if (lt <= k1 && k1 < le) m1 = v[i];
+    if (lt <= k2 && k2 < le) m2 = v[i];
   }
-  if (n & 1) return v[(n - 1) / 2];
-  return (v[n / 2 - 1] + v[n / 2]) / 2.0;
+  return (n & 1) ? m1 : (m1 + m2) / 2.0;
 }
 
 // Second derivatives of the natural cubic spline along one mesh line:
@@ -388,10 +402,9 @@ __device__ void natural_line(const double* f, double* M, double* cp,
 
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void k_mesh_finish(Work wk,
-                                                        ipp_params p) {
+// Invalid-node fill (one workgroup per frame).
+__global__ __launch_bounds__(kBlock) void k_mesh_fill(Work wk, ipp_params p) {
   __shared__ int ired[kWaves];
-  __shared__ int flag_s;
   const int f = blockIdx.x;
   const FrameDev fr = wk.frames[f];
   const int ny = fr.ny, nx = fr.nx, N = ny * nx, b0 = fr.node0;
@@ -417,7 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_mesh_finish(Work wk,
     wk.f_rms[b0 + i] = known ? wk.m_rms[b0 + i] : 0.0;
   }
   __syncthreads();
-  // Jacobi fill passes
+  // Jacobi fill passes: a node unknown before pass q takes the mean of its
+  // neighbours known before pass q (summed in raster order)
   for (int pass = 1; pass <= N; ++pass) {
     int todo = 0;
     for (int i = threadIdx.x; i < N; i += kBlock) {
@@ -450,59 +464,86 @@ __global__ __launch_bounds__(kBlock) void k_mesh_finish(Work wk,
     __syncthreads();
     if (todo == 0) break;
   }
-  // median filter -> tables[0]
+  if (threadIdx.x == 0 && wk.frame_flags) wk.frame_flags[f] = flags;
+}
+
+// Median filter (window (2F+1)^2 at most), one thread per node of the batch.
+template <int F>
+__global__ __launch_bounds__(kBlock) void k_mesh_filter(Work wk,
+                                                        ipp_params p) {
+  constexpr int S = 2 * F + 1, MAXN = S * S;
+  const int node = blockIdx.x * kBlock + threadIdx.x;
+  if (node >= wk.total_nodes) return;
+  const int f = find_frame(wk.frames, wk.nframes, node, &FrameDev::node0);
+  const FrameDev& fr = wk.frames[f];
+  const int nx = fr.nx, ny = fr.ny, b0 = fr.node0, i = node - b0;
   const int fh = p.filter_h / 2, fw = p.filter_w / 2;
-  for (int i = threadIdx.x; i < N; i += kBlock) {
-    const int j = i / nx, ii = i - j * nx;
-    double vb[49], vr[49];
-    int n = 0;
-    for (int jj = max(0, j - fh); jj <= min(ny - 1, j + fh); ++jj)
-      for (int i2 = max(0, ii - fw); i2 <= min(nx - 1, ii + fw); ++i2) {
-        vb[n] = wk.f_bkg[b0 + jj * nx + i2];
-        vr[n] = wk.f_rms[b0 + jj * nx + i2];
-        ++n;
-      }
-    const double mb = median_small(vb, n);
-    const double mr = median_small(vr, n);
-    wk.tb[0][b0 + i] = mb;
-    wk.tr[0][b0 + i] = mr;
-    if (fr.o_bkg) fr.o_bkg[i] = mb;
-    if (fr.o_rms) fr.o_rms[i] = mr;
+  const int j = i / nx, ii = i - j * nx;
+  double vb[MAXN], vr[MAXN];
+  uint64_t valid = 0;
+  int n = 0;
+#pragma unroll
+  for (int dj = -F; dj <= F; ++dj)
+#pragma unroll
+    for (int di = -F; di <= F; ++di) {
+      const int k = (dj + F) * S + (di + F);
+      const int jj = j + dj, i2 = ii + di;
+      const bool ok = dj >= -fh && dj <= fh && di >= -fw && di <= fw &&
+                      jj >= 0 && jj < ny && i2 >= 0 && i2 < nx;
+      vb[k] = ok ? wk.f_bkg[b0 + jj * nx + i2] : 0.0;
+      vr[k] = ok ? wk.f_rms[b0 + jj * nx + i2] : 0.0;
+      if (ok) { valid |= 1ull << k; ++n; }
+    }
+  const double mb = median_window<MAXN>(vb, valid, n);
+  const double mr = median_window<MAXN>(vr, valid, n);
+  wk.tb[0][node] = mb;
+  wk.tr[0][node] = mr;
+  if (fr.o_bkg) fr.o_bkg[i] = mb;
+  if (fr.o_rms) fr.o_rms[i] = mr;
+}
+
+// Natural-spline second derivatives, one thread per mesh line.  Pass 0:
+// fxx along every row and fyy along every column, of both meshes; pass 1:
+// fxxyy along every column of fxx, of both meshes.  Lines of frame f start
+// at fr.line0[pass]; per frame pass 0 has 2(ny + nx) lines, pass 1 2 nx.
+template <int PASS>
+__global__ __launch_bounds__(64) void k_mesh_spline(Work wk, ipp_params p) {
+  const int line = blockIdx.x * 64 + threadIdx.x;
+  if (line >= wk.total_lines[PASS]) return;
+  int lo = 0, hi = wk.nframes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wk.frames[mid].line0[PASS] <= line) lo = mid; else hi = mid - 1;
   }
-  __syncthreads();
-  // second derivatives: along x per row (fxx), along y per column (fyy)
-  for (int l = threadIdx.x; l < 2 * ny; l += kBlock) {
-    const int j = l % ny;
-    const double* src = (l < ny) ? wk.tb[0] : wk.tr[0];
-    double* dst = (l < ny) ? wk.tb[1] : wk.tr[1];
-    natural_line(src, dst, wk.sc0 + (l < ny ? 0 : wk.total_nodes),
-                 wk.sc1 + (l < ny ? 0 : wk.total_nodes), b0 + j * nx, 1, nx,
-                 p.mesh_w, fr.w);
-  }
-  for (int l = threadIdx.x; l < 2 * nx; l += kBlock) {
-    const int i = l % nx;
-    const double* src = (l < nx) ? wk.tb[0] : wk.tr[0];
-    double* dst = (l < nx) ? wk.tb[2] : wk.tr[2];
-    natural_line(src, dst, wk.sc0 + 2 * wk.total_nodes + (l < nx ? 0 : wk.total_nodes),
-                 wk.sc1 + 2 * wk.total_nodes + (l < nx ? 0 : wk.total_nodes),
-                 b0 + i, nx, ny, p.mesh_h, fr.h);
-  }
-  __syncthreads();
-  // fxxyy: along y of fxx
-  for (int l = threadIdx.x; l < 2 * nx; l += kBlock) {
-    const int i = l % nx;
-    const double* src = (l < nx) ? wk.tb[1] : wk.tr[1];
-    double* dst = (l < nx) ? wk.tb[3] : wk.tr[3];
-    natural_line(src, dst, wk.sc0 + (l < nx ? 0 : wk.total_nodes),
-                 wk.sc1 + (l < nx ? 0 : wk.total_nodes), b0 + i, nx, ny,
-                 p.mesh_h, fr.h);
-  }
-  if (threadIdx.x == 0) {
-    flag_s = 0;
-    if (wk.frame_flags) wk.frame_flags[f] = flags;
+  const FrameDev& fr = wk.frames[lo];
+  const int l = line - fr.line0[PASS];
+  const int ny = fr.ny, nx = fr.nx, b0 = fr.node0;
+  const size_t T = (size_t)wk.total_nodes;
+  if (PASS == 0) {
+    if (l < 2 * ny) {                 // rows: fxx
+      const int j = l % ny, m = l / ny;
+      natural_line(m ? wk.tr[0] : wk.tb[0], m ? wk.tr[1] : wk.tb[1],
+                   wk.sc0 + m * T, wk.sc1 + m * T, b0 + j * nx, 1, nx,
+                   p.mesh_w, fr.w);
+    } else {                          // columns: fyy
+      const int c = l - 2 * ny, i = c % nx, m = c / nx;
+      natural_line(m ? wk.tr[0] : wk.tb[0], m ? wk.tr[2] : wk.tb[2],
+                   wk.sc0 + (2 + m) * T, wk.sc1 + (2 + m) * T, b0 + i, nx,
+                   ny, p.mesh_h, fr.h);
+    }
+  } else {                            // columns of fxx: fxxyy
+    const int i = l % nx, m = l / nx;
+    natural_line(m ? wk.tr[1] : wk.tb[1], m ? wk.tr[3] : wk.tb[3],
+                 wk.sc0 + m * T, wk.sc1 + m * T, b0 + i, nx, ny, p.mesh_h,
+                 fr.h);
   }
 }
 
+template __global__ void k_mesh_filter<1>(Work, ipp_params);
+template __global__ void k_mesh_filter<2>(Work, ipp_params);
+template __global__ void k_mesh_filter<3>(Work, ipp_params);
+template __global__ void k_mesh_spline<0>(Work, ipp_params);
+template __global__ void k_mesh_spline<1>(Work, ipp_params);
 template __global__ void k_mesh_stats<4>(Work, ipp_params);
 template __global__ void k_mesh_stats<16>(Work, ipp_params);
 template __global__ void k_mesh_stats<64>(Work, ipp_params);

@@ -7,7 +7,11 @@ namespace ipp {
 
 template <int PPT>
 __global__ void k_mesh_stats(Work wk, ipp_params p);
-__global__ void k_mesh_finish(Work wk, ipp_params p);
+__global__ void k_mesh_fill(Work wk, ipp_params p);
+template <int F>
+__global__ void k_mesh_filter(Work wk, ipp_params p);
+template <int PASS>
+__global__ void k_mesh_spline(Work wk, ipp_params p);
 
 template <int TH, int TW>
 __global__ void k_bkg_maps(Work wk, ipp_params p);

@@ -16,16 +16,19 @@
 
 namespace ipp {
 
+// A tile of TW columns spans at most (TW-1)/16 + 2 mesh intervals for
+// meshes >= 16 px (only the last interval of a frame is shorter than the
+// mesh, and it is at least half a mesh long), so its columns use mesh
+// columns ilo .. ilo + TW/16 + 2; likewise for rows.
 template <int TH, int TW>
 struct SplineLds {
-  // mesh columns / rows a tile can span (mesh >= 16), with one of slack
-  static constexpr int NC = TW / 16 + 4;
-  static constexpr int NR = TH / 16 + 4;
+  static constexpr int NC = TW / 16 + 3;
+  static constexpr int NR = TH / 16 + 3;
   double gB[TH][NC];
   double gBpp[TH][NC];
   double gR[TH][NC];
   double gRpp[TH][NC];
-  double wx[TW][4];
+  double wx[4][TW];            // x weights, structure of arrays
   int cx[TW];
   double wy[TH][4];
   int ry[TH];
@@ -51,14 +54,14 @@ __device__ __forceinline__ void spline_prologue(const Work& wk,
     int j;
     if (c < TW) {
       spline_weights((double)(x0 + c), p.mesh_w, fr.w, fr.nx, &j, w4);
-      S.cx[c] = j - ilo;
+      S.cx[c] = min(j - ilo, NC - 2);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) S.wx[c][k] = w4[k];
+      for (int k = 0; k < 4; ++k) S.wx[k][c] = w4[k];
     } else {
       const int r = c - TW;
       const int y = min(y0 + r, fr.h - 1);
       spline_weights((double)y, p.mesh_h, fr.h, fr.ny, &j, w4);
-      S.ry[r] = j - jlo;
+      S.ry[r] = min(j - jlo, NR - 2);
 #pragma unroll
       for (int k = 0; k < 4; ++k) S.wy[r][k] = w4[k];
     }
@@ -96,8 +99,8 @@ __device__ __forceinline__ void spline_pixel(const SplineLds<TH, TW>& S,
                                              int r, int c, double* b,
                                              double* rr) {
   const int k = S.cx[c];
-  const double w0 = S.wx[c][0], w1 = S.wx[c][1];
-  const double w2 = S.wx[c][2], w3 = S.wx[c][3];
+  const double w0 = S.wx[0][c], w1 = S.wx[1][c];
+  const double w2 = S.wx[2][c], w3 = S.wx[3][c];
   *b = ((w0 * S.gB[r][k] + w1 * S.gB[r][k + 1]) + w2 * S.gBpp[r][k])
        + w3 * S.gBpp[r][k + 1];
   *rr = ((w0 * S.gR[r][k] + w1 * S.gR[r][k + 1]) + w2 * S.gRpp[r][k])
