@@ -355,15 +355,19 @@ ipp_status prepare(IppCtx* c, const ipp_frame* frames, int32_t n,
 ipp_status run_mesh(IppCtx* c, const Plan& P, const Work& w,
                     const ipp_params& p, hipStream_t s) {
   const int area = p.mesh_h * p.mesh_w;
-  if (area <= 4 * kBlock)
-    IPP_LAUNCH(c, s, "k_mesh_stats", hipLaunchKernelGGL(k_mesh_stats<4>, dim3(P.nodes),
-                                     dim3(kBlock), 0, s, w, p));
-  else if (area <= 16 * kBlock)
-    IPP_LAUNCH(c, s, "k_mesh_stats", hipLaunchKernelGGL(k_mesh_stats<16>, dim3(P.nodes),
-                                     dim3(kBlock), 0, s, w, p));
+  const dim3 gw((P.nodes + kWaves - 1) / kWaves);
+  if (area <= 16 * kWave)
+    IPP_LAUNCH(c, s, "k_mesh_stats",
+               hipLaunchKernelGGL(k_mesh_stats_w<16>, gw, dim3(kBlock), 0, s,
+                                  w, p));
+  else if (area <= 64 * kWave)
+    IPP_LAUNCH(c, s, "k_mesh_stats",
+               hipLaunchKernelGGL(k_mesh_stats_w<64>, gw, dim3(kBlock), 0, s,
+                                  w, p));
   else
-    IPP_LAUNCH(c, s, "k_mesh_stats", hipLaunchKernelGGL(k_mesh_stats<64>, dim3(P.nodes),
-                                     dim3(kBlock), 0, s, w, p));
+    IPP_LAUNCH(c, s, "k_mesh_stats",
+               hipLaunchKernelGGL(k_mesh_stats<64>, dim3(P.nodes),
+                                  dim3(kBlock), 0, s, w, p));
   IPP_LAUNCH(c, s, "k_mesh_fill",
              hipLaunchKernelGGL(k_mesh_fill, dim3((int)P.fd.size()),
                                 dim3(kBlock), 0, s, w, p));

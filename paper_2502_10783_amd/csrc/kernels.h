@@ -7,6 +7,8 @@ namespace ipp {
 
 template <int PPT>
 __global__ void k_mesh_stats(Work wk, ipp_params p);
+template <int PPL>
+__global__ void k_mesh_stats_w(Work wk, ipp_params p);
 __global__ void k_mesh_fill(Work wk, ipp_params p);
 template <int F>
 __global__ void k_mesh_filter(Work wk, ipp_params p);
