@@ -156,6 +156,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
   const int y0 = ty * TH, x0 = tx * TW;
 
+  // the tile's pixels are requested first, so that their latency overlaps
+  // the spline prologue
+  float Ipx[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int q = t + kBlock * k;
+    const int y = y0 + q / TW, x = x0 + q % TW;
+    Ipx[k] = (y < fr.h && x < fr.w) ? fr.pix[(int64_t)y * fr.pitch + x]
+                                    : 0.0f;
+  }
   if (FUSED) spline_prologue<TH, TW>(wk, fr, p, y0, x0, L.u.spl);
 
   // lanes that start / end a row inside the wave's 64-pixel segment
@@ -172,14 +182,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   // ---- threshold: v = I - B32 > nsigma * R32; runs ----------------------
   uint32_t fgm = 0;
   uint64_t fgb[PPT];
-#pragma unroll 4
+#pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int q = t + kBlock * k;
     const int r = q / TW, c = q % TW;
     const int y = y0 + r, x = x0 + c;
     bool det = false;
     if (y < fr.h && x < fr.w) {
-      const float I = fr.pix[(int64_t)y * fr.pitch + x];
+      const float I = Ipx[k];
       const int64_t o = (int64_t)y * fr.w + x;
       float B32, R32;
       if (FUSED) {
@@ -607,19 +617,44 @@ __global__ __launch_bounds__(kBlock) void k_relabel(Work wk, ipp_params p) {
   const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
   const int y0 = ty * TH, x0 = tx * TW;
   const int rb = wk.tile_rbase[tile];
+  auto label_of = [&](int l) -> int {
+    if (!l) return 0;
+    const long long rec = (long long)rb + l - 1;
+    return rec < wk.rec_cap ? wk.rlabel[rec] : 0;
+  };
+  // whole tile inside the frame and 4-pixel groups aligned: ushort4 in,
+  // int4 out, all loads of the tile issued before the first gather
+  const bool vec = y0 + TH <= fr.h && x0 + TW <= fr.w && (fr.w & 3) == 0 &&
+                   (fr.pix0 & 3) == 0 && ((uintptr_t)fr.labels & 15) == 0;
+  if (vec) {
+    constexpr int G = TH * TW / 4 / kBlock;     // groups per thread
+    ushort4 m[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int q = (threadIdx.x + kBlock * k) * 4;
+      const int64_t o = (int64_t)(y0 + q / TW) * fr.w + x0 + q % TW;
+      m[k] = *(const ushort4*)(wk.lmap + fr.pix0 + o);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int q = (threadIdx.x + kBlock * k) * 4;
+      const int64_t o = (int64_t)(y0 + q / TW) * fr.w + x0 + q % TW;
+      int4 out;
+      out.x = label_of(m[k].x);
+      out.y = label_of(m[k].y);
+      out.z = label_of(m[k].z);
+      out.w = label_of(m[k].w);
+      *(int4*)(fr.labels + o) = out;
+    }
+    return;
+  }
 #pragma unroll 4
   for (int k = 0; k < TH * TW / kBlock; ++k) {
     const int q = threadIdx.x + kBlock * k;
     const int y = y0 + q / TW, x = x0 + q % TW;
     if (y < fr.h && x < fr.w) {
       const int64_t o = (int64_t)y * fr.w + x;
-      const int l = wk.lmap[fr.pix0 + o];
-      int lab = 0;
-      if (l) {
-        const long long rec = (long long)rb + l - 1;
-        if (rec < wk.rec_cap) lab = wk.rlabel[rec];
-      }
-      fr.labels[o] = lab;
+      fr.labels[o] = label_of(wk.lmap[fr.pix0 + o]);
     }
   }
 }

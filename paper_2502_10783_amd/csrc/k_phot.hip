@@ -41,13 +41,10 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Bitonic sort (ascending by v) of NS (v, w) pairs held as v[NS/64],
-// w[NS/64] per lane, element index e = lane * (NS/64) + k.  A pair moves
-// only when the pair ahead of it is strictly larger, decided identically by
-// both partners, so no pair is lost or duplicated on ties.
+// Bitonic sort (ascending) of NS binary64 values held as v[NS/64] per
+// lane, element index e = lane * (NS/64) + k.
 template <int NS>
-__device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave],
-                                             double (&w)[NS / kWave]) {
+__device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave]) {
   constexpr int PL = NS / kWave;
   const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
@@ -62,12 +59,9 @@ __device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave],
             const int e = lane * PL + k;
             const bool up = (e & kk) == 0;
             const double a = v[k], b = v[l];
-            const bool sw = up ? (a > b) : (a < b);
-            const double wa = w[k], wb = w[l];
-            v[k] = sw ? b : a;
-            v[l] = sw ? a : b;
-            w[k] = sw ? wb : wa;
-            w[l] = sw ? wa : wb;
+            const double mn = fmin(a, b), mx = fmax(a, b);
+            v[k] = up ? mn : mx;
+            v[l] = up ? mx : mn;
           }
         }
       } else {
@@ -77,16 +71,26 @@ __device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave],
         for (int k = 0; k < PL; ++k) {
           const int e = lane * PL + k;
           const bool up = (e & kk) == 0;
-          const double ov = __shfl_xor(v[k], lm, kWave);
-          const double ow = __shfl_xor(w[k], lm, kWave);
-          const double a = lower ? v[k] : ov;   // value at the lower index
-          const double b = lower ? ov : v[k];
-          const bool sw = up ? (a > b) : (a < b);
-          if (sw) { v[k] = ov; w[k] = ow; }
+          const double o = __shfl_xor(v[k], lm, kWave);
+          v[k] = (lower == up) ? fmin(v[k], o) : fmax(v[k], o);
         }
       }
     }
   }
+}
+
+// Element e (wave-uniform) of a sorted register array.
+template <int PL>
+__device__ __forceinline__ double sorted_at(const double (&v)[PL], int e) {
+  const int ln = e / PL, k = e - (e / PL) * PL;
+  double x = v[0];
+#pragma unroll
+  for (int i = 1; i < PL; ++i)
+    if (i == k) x = v[i];
+  const uint64_t u = __double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, ln);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), ln);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 template <int NS>
@@ -120,28 +124,57 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   uint32_t flags = 0;
   double a_ap = 0.0, raw = 0.0;
   int nann = 0, nab = 0, nap = 0;
-  for (int e0 = 0; e0 < npx; e0 += kWave) {
-    const int e = e0 + lane;
-    bool ap_cut = false, ann = false, ann_cut = false;
-    double v = 0.0;
-    if (e < npx) {
-      const int px = xa + e % nwx, py = ya + e / nwx;
-      const bool in_ap = touches(cx, cy, p.r_ap, px, py);
-      const bool in_ann = touches(cx, cy, p.r_out, px, py) &&
-                          !within(cx, cy, p.r_in, px, py);
+  // squared radii as the membership predicates form them
+  const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
+  const double ro2 = p.r_out * p.r_out;
+  int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;   // window row, col
+  const int dwr = kWave / nwx, dwc = kWave - (kWave / nwx) * nwx;
+  // Chunks of kChunk rounds of 64 pixels: all loads of a chunk are issued
+  // before any is used, so their latencies overlap.
+  constexpr int kChunk = 4;
+  for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
+    float Iv[kChunk], Bv[kChunk];
+    uint32_t st[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int e = e0 + c * kWave + lane;
+      const int px = xa + wc, py = ya + wr;
+      wr += dwr; wc += dwc;
+      if (wc >= nwx) { wc -= nwx; ++wr; }
+      // nearest and farthest point of the pixel square (touches / within)
+      const double ax = fabs((double)px - cx), ay = fabs((double)py - cy);
+      const double nx = fmax(ax - 0.5, 0.0), ny = fmax(ay - 0.5, 0.0);
+      const double fx = ax + 0.5, fy = ay + 0.5;
+      const double near2 = nx * nx + ny * ny, far2 = fx * fx + fy * fy;
+      const bool live = e < npx;
+      const bool in_ap = live && near2 < ra2;
+      const bool in_ann = live && near2 < ro2 && !(far2 <= ri2);
+      const bool inside = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
+      Iv[c] = 0.f;
+      Bv[c] = 0.f;
+      if ((in_ap || in_ann) && inside) {
+        Iv[c] = fr.pix[(int64_t)py * fr.pitch + px];
+        Bv[c] = fr.bkg[(int64_t)py * fr.w + px];
+      }
+      st[c] = (uint32_t)in_ap | ((uint32_t)in_ann << 1) |
+              ((uint32_t)inside << 2) | ((uint32_t)(far2 <= ra2) << 3) |
+              ((uint32_t)!(far2 <= ro2 && !(near2 < ri2)) << 4);
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int e = e0 + c * kWave + lane;
+      const bool in_ap = st[c] & 1u, in_ann = st[c] & 2u;
+      bool ap_cut = false, ann = false, ann_cut = false;
+      double v = 0.0;
       if (in_ap || in_ann) {
-        bool ok = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
-        if (ok) {
-          const float I = fr.pix[(int64_t)py * fr.pitch + px];
-          ok = isfinite(I);
-          v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
-        }
+        const bool ok = (st[c] & 4u) && isfinite(Iv[c]);
+        v = (double)Iv[c] - (double)Bv[c];
         if (!ok) {
           if (in_ap) flags |= IPP_SRC_APERTURE_OFF_EDGE;
           if (in_ann) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
         } else {
           if (in_ap) {
-            if (within(cx, cy, p.r_ap, px, py)) {
+            if (st[c] & 8u) {
               a_ap += 1.0;
               raw += v;
             } else {
@@ -150,34 +183,33 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
           }
           if (in_ann) {
             ann = true;
-            ann_cut = !(within(cx, cy, p.r_out, px, py) &&
-                        !touches(cx, cy, p.r_in, px, py));
+            ann_cut = st[c] & 16u;
           }
         }
       }
-    }
-    const uint64_t b1 = __ballot(ap_cut);
-    if (ap_cut) {
-      const int s = nap + __popcll(b1 & lanes_below());
-      if (s < kApTasks) L.apb[s] = e;
-    }
-    nap += __popcll(b1);
-    const uint64_t b2 = __ballot(ann);
-    int slot = 0;
-    if (ann) {
-      slot = nann + __popcll(b2 & lanes_below());
-      if (slot < NS) {
-        L.pv[slot] = v;
-        L.pw[slot] = 1.0;
+      const uint64_t b1 = __ballot(ap_cut);
+      if (ap_cut) {
+        const int s = nap + __popcll(b1 & lanes_below());
+        if (s < kApTasks) L.apb[s] = e;
       }
+      nap += __popcll(b1);
+      const uint64_t b2 = __ballot(ann);
+      int slot = 0;
+      if (ann) {
+        slot = nann + __popcll(b2 & lanes_below());
+        if (slot < NS) {
+          L.pv[slot] = v;
+          L.pw[slot] = 1.0;
+        }
+      }
+      nann += __popcll(b2);
+      const uint64_t b3 = __ballot(ann_cut);
+      if (ann_cut) {
+        const int s = nab + __popcll(b3 & lanes_below());
+        if (s < NS && slot < NS) L.ab[s] = (slot << 16) | e;
+      }
+      nab += __popcll(b3);
     }
-    nann += __popcll(b2);
-    const uint64_t b3 = __ballot(ann_cut);
-    if (ann_cut) {
-      const int s = nab + __popcll(b3 & lanes_below());
-      if (s < NS && slot < NS) L.ab[s] = (slot << 16) | e;
-    }
-    nab += __popcll(b3);
   }
   if (nann > NS) nann = NS;            // not reachable: NS bounds the ring
   if (nab > NS) nab = NS;
@@ -203,27 +235,24 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   }
   wave_lds_sync();
 
-  // ---- sort the annulus (value, weight) pairs ---------------------------
-  double sv[PL], sw[PL];
+  // ---- sort the annulus values ------------------------------------------
+  double sv[PL];
 #pragma unroll
   for (int k = 0; k < PL; ++k) {
     const int e = lane * PL + k;
     sv[k] = e < nann ? L.pv[e] : __builtin_inf();
-    sw[k] = e < nann ? L.pw[e] : 0.0;
   }
-  wave_bitonic<NS>(sv, sw);
-  wave_lds_sync();
-#pragma unroll
-  for (int k = 0; k < PL; ++k) L.pv[lane * PL + k] = sv[k];
-  wave_lds_sync();
+  wave_bitonic<NS>(sv);
 
   // ---- k-sigma clipping on the sorted range [a, bnd) ---------------------
   int a = 0, bnd = nann;
   for (int it = 0; it < p.sky_clip_iters; ++it) {
     const int n = bnd - a;
     if (n == 0) break;
-    const double med = (n & 1) ? L.pv[a + (n - 1) / 2]
-                               : (L.pv[a + n / 2 - 1] + L.pv[a + n / 2]) / 2.0;
+    const double med =
+        (n & 1) ? sorted_at<PL>(sv, a + (n - 1) / 2)
+                : (sorted_at<PL>(sv, a + n / 2 - 1) +
+                   sorted_at<PL>(sv, a + n / 2)) / 2.0;
     double s1 = 0.0;
 #pragma unroll
     for (int k = 0; k < PL; ++k) {
@@ -258,15 +287,15 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     a += cl;
     bnd -= ch;
   }
+  // the survivors are the values in [vlo, vhi] (clipping is by value)
   double vlo = 0.0, vhi = -1.0;
-  if (bnd > a) { vlo = L.pv[a]; vhi = L.pv[bnd - 1]; }
+  if (bnd > a) { vlo = sorted_at<PL>(sv, a); vhi = sorted_at<PL>(sv, bnd - 1); }
   double num = 0.0, den = 0.0;
-#pragma unroll
-  for (int k = 0; k < PL; ++k) {
-    const int e = lane * PL + k;
-    if (e >= a && e < bnd) {
-      num += sw[k] * sv[k];
-      den += sw[k];
+  for (int j = lane; j < nann; j += kWave) {
+    const double v = L.pv[j], w = L.pw[j];
+    if (v >= vlo && v <= vhi) {
+      num += w * v;
+      den += w;
     }
   }
   num = wave_sum(num);

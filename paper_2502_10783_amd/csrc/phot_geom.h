@@ -5,7 +5,7 @@
 // 0 <= x, y <= r it is x*y when the corner lies in the circle and otherwise
 // y*xs + P(x) - P(xs) with xs = sqrt(r^2 - y^2) and
 // P(s) = int_0^s sqrt(r^2 - u^2) du = (s sqrt(r^2 - s^2) + r^2 asin(s/r))/2
-// (evaluated with one asin, see corner_area).
+// (evaluated with one asin, see corner_g).
 // A pixel's overlap is the inclusion-exclusion of G over its corners.
 // Membership (the pixel square meets the open disk) and full containment
 // are decided by the exact predicates below, so that every pixel that a
@@ -37,33 +37,38 @@ __device__ __forceinline__ bool within(double cx, double cy, double r,
 //   G = y xs + P(x) - P(xs)
 //     = (y xs + x hx + r^2 (asin(x/r) - asin(xs/r))) / 2
 // and, as cos(asin(xs/r)) = y/r and cos(asin(x/r)) = hx/r, the angle
-// difference is asin((x y - xs hx) / r^2): one asin per corner.
-__device__ __forceinline__ double corner_area(double x, double y, double r) {
-  if (r <= 0.0) return 0.0;
-  const double sx = x < 0.0 ? -1.0 : 1.0;
-  const double sy = y < 0.0 ? -1.0 : 1.0;
-  const double ax = fmin(fabs(x), r), ay = fmin(fabs(y), r);
-  const double r2 = r * r;
-  double a;
-  if (ax * ax + ay * ay <= r2) {
-    a = ax * ay;
-  } else {
-    const double xs = sqrt(fmax(r2 - ay * ay, 0.0));
-    const double hx = sqrt(fmax(r2 - ax * ax, 0.0));
-    const double arg = fmin((ax * ay - xs * hx) / r2, 1.0);
-    a = 0.5 * ((ay * xs + ax * hx) + r2 * asin(arg));
-  }
-  return sx * sy * a;
+// difference is asin((x y - xs hx) / r^2): one asin per corner.  The two
+// square roots depend on one coordinate each, so a pixel needs four.
+__device__ __forceinline__ double corner_g(double ax, double ay, double hx,
+                                           double xs, double r2,
+                                           double inv_r2) {
+  if (ax * ax + ay * ay <= r2) return ax * ay;
+  const double arg = fmin((ax * ay - xs * hx) * inv_r2, 1.0);
+  return 0.5 * ((ay * xs + ax * hx) + r2 * asin(arg));
 }
 
+// Overlap of the pixel square [px-1/2, px+1/2] x [py-1/2, py+1/2] with the
+// disk of radius r about (cx, cy): inclusion-exclusion of G over the
+// square's corners.
 __device__ __forceinline__ double overlap(double cx, double cy, double r,
                                           int px, int py) {
   if (!touches(cx, cy, r, px, py)) return 0.0;
   if (within(cx, cy, r, px, py)) return 1.0;
+  const double r2 = r * r, inv_r2 = 1.0 / r2;
   const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
   const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
-  return corner_area(x1, y1, r) - corner_area(x0, y1, r) -
-         corner_area(x1, y0, r) + corner_area(x0, y0, r);
+  const double ax0 = fmin(fabs(x0), r), ax1 = fmin(fabs(x1), r);
+  const double ay0 = fmin(fabs(y0), r), ay1 = fmin(fabs(y1), r);
+  const double hx0 = sqrt(fmax(r2 - ax0 * ax0, 0.0));
+  const double hx1 = sqrt(fmax(r2 - ax1 * ax1, 0.0));
+  const double xs0 = sqrt(fmax(r2 - ay0 * ay0, 0.0));
+  const double xs1 = sqrt(fmax(r2 - ay1 * ay1, 0.0));
+  const double sx0 = x0 < 0.0 ? -1.0 : 1.0, sx1 = x1 < 0.0 ? -1.0 : 1.0;
+  const double sy0 = y0 < 0.0 ? -1.0 : 1.0, sy1 = y1 < 0.0 ? -1.0 : 1.0;
+  return sx1 * sy1 * corner_g(ax1, ay1, hx1, xs1, r2, inv_r2) -
+         sx0 * sy1 * corner_g(ax0, ay1, hx0, xs1, r2, inv_r2) -
+         sx1 * sy0 * corner_g(ax1, ay0, hx1, xs0, r2, inv_r2) +
+         sx0 * sy0 * corner_g(ax0, ay0, hx0, xs0, r2, inv_r2);
 }
 
 __device__ __forceinline__ double chord(double x, double y, double r) {
