@@ -104,6 +104,52 @@ __device__ __forceinline__ T wave_sum(T v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v = v + __shfl_xor(v, o, kWave);
   return v;
 }
+
+// Lane moves inside rows of 16 lanes (DPP: no LDS round trip).  The
+// patterns used are involutions, so both lanes of a pair add the same two
+// values and every lane ends with a bit-identical sum.
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)dpp_mov<CTRL>((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u,
+                                                          lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(
+      (int)(uint32_t)(u >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ int read_lane(int v, int lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+template <typename T>
+__device__ __forceinline__ T row16_sum(T v) {
+  v = v + dpp_mov<0xB1>(v);        // quad_perm [1,0,3,2]
+  v = v + dpp_mov<0x4E>(v);        // quad_perm [2,3,0,1]
+  v = v + dpp_mov<0x141>(v);       // row_half_mirror
+  v = v + dpp_mov<0x140>(v);       // row_mirror
+  return v;
+}
+// Wave sums of binary64 and int: rows by DPP, then the four row sums,
+// combined in a fixed order; the result is wave-uniform.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) +
+         (read_lane(v, 32) + read_lane(v, 48));
+}
+__device__ __forceinline__ int wave_sum(int v) {
+  v = row16_sum(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) +
+         (read_lane(v, 32) + read_lane(v, 48));
+}
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll

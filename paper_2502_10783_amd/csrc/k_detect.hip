@@ -36,6 +36,11 @@ struct CclLds {
       int16_t rloc[NCMP];
     } st;
   } u;
+  // one bit per pixel, 64 consecutive raster pixels per word: detected,
+  // run heads, component roots
+  uint64_t fgbits[NP / 64];
+  uint64_t headbits[NP / 64];
+  uint64_t rootbits[NP / 64];
   int wcnt[16 * kWaves];
   int ired[kWaves];
   int ncomp;
@@ -89,6 +94,40 @@ __device__ __forceinline__ void gunion(int32_t* parent, int a, int b) {
     int old = atomicMin(&parent[a], b);
     if (old == a) return;
     a = old;
+  }
+}
+
+// Stores and loads through the global address space (the pointers come
+// from descriptors in memory, where the compiler would use flat accesses).
+template <typename T>
+__device__ __forceinline__ void gst(T* a, T v) {
+  *(__attribute__((address_space(1))) T*)a = v;
+}
+template <typename T>
+__device__ __forceinline__ T gld(const T* a) {
+  return *(const __attribute__((address_space(1))) T*)a;
+}
+
+// Calls fn(q, len) for every run head q of the 16-pixel slice of the tile
+// that thread t owns (segment t / 4, bits 16 (t % 4) ..).  A run is a
+// maximal horizontal stretch of detected pixels inside one 64-pixel
+// segment and one row (row_last marks the segment's last pixel of each
+// row); len is read off the bits.
+template <typename Fn>
+__device__ __forceinline__ void for_runs(const uint64_t* fgbits,
+                                         const uint64_t* headbits,
+                                         uint64_t row_last, Fn fn) {
+  const int seg = threadIdx.x >> 2, b0 = (threadIdx.x & 3) * 16;
+  uint32_t h = (uint32_t)(headbits[seg] >> b0) & 0xFFFFu;
+  // positions where a run cannot continue: undetected, or after a row end
+  const uint64_t stop = ~fgbits[seg] | (row_last << 1);
+  while (h) {
+    const int b = b0 + __builtin_ctz(h);
+    h &= h - 1;
+    const int len =
+        b == 63 ? 1
+                : 1 + __builtin_ctzll((stop >> (b + 1)) | (1ull << (63 - b)));
+    fn(seg * 64 + b, len);
   }
 }
 
@@ -163,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   for (int k = 0; k < PPT; ++k) {
     const int q = t + kBlock * k;
     const int y = y0 + q / TW, x = x0 + q % TW;
-    Ipx[k] = (y < fr.h && x < fr.w) ? fr.pix[(int64_t)y * fr.pitch + x]
+    Ipx[k] = (y < fr.h && x < fr.w) ? gld(fr.pix + (int64_t)y * fr.pitch + x)
                                     : 0.0f;
   }
   if (FUSED) spline_prologue<TH, TW>(wk, fr, p, y0, x0, L.u.spl);
@@ -197,11 +236,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
         spline_pixel<TH, TW>(L.u.spl, r, c, &b, &rr);
         B32 = (float)b;
         R32 = (float)rr;
-        fr.bkg[o] = B32;
-        if (write_rms) fr.rms[o] = R32;
+        gst(fr.bkg + o, B32);
+        if (write_rms) gst(fr.rms + o, R32);
       } else {
-        B32 = fr.bkg[o];
-        R32 = fr.rms[o];
+        B32 = gld(fr.bkg + o);
+        R32 = gld(fr.rms + o);
       }
       const double v = (double)I - (double)B32;
       const double thr = p.det_nsigma * (double)R32;
@@ -211,6 +250,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     const uint64_t m = __ballot(det);
     fgb[k] = m;
     const uint64_t heads = m & (~(m << 1) | row_first);
+    if (lane == 0) {
+      L.fgbits[wv + kWaves * k] = m;
+      L.headbits[wv + kWaves * k] = heads;
+      L.rootbits[wv + kWaves * k] = 0;
+    }
     int par = -1;
     if (det) {
       const int s_lane = 63 - __clzll(heads & upto);
@@ -220,57 +264,44 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   }
   __syncthreads();
 
-  // ---- unions with the runs of the row above ----------------------------
-#pragma unroll 4
-  for (int k = 0; k < PPT; ++k) {
-    if (!((fgm >> k) & 1u)) continue;
-    const uint64_t m = fgb[k];
-    const int q = t + kBlock * k;
+  // ---- unions with the runs of the row above (one thread per run) -------
+  auto fg_at = [&](int q) -> bool {
+    return (L.fgbits[q >> 6] >> (q & 63)) & 1ull;
+  };
+  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int len) {
     const int r = q / TW, c = q % TW;
-    const bool head = !((m >> lane) & 1ull & (m << 1 >> lane) & 1ull) ||
-                      ((row_first >> lane) & 1ull);
-    const bool tail = !(((m >> 1) >> lane) & 1ull) ||
-                      ((row_last >> lane) & 1ull);
-    // a run cut by the wave boundary inside a row
-    if (head && lane == 0 && c > 0 && lds_load(&L.parent[q - 1]) >= 0)
-      lunion(L.parent, q, q - 1);
-    if (r == 0) continue;
-    const int x = q - TW;
-    const bool fx = lds_load(&L.parent[x]) >= 0;
-    const bool fxl = c > 0 && lds_load(&L.parent[x - 1]) >= 0;
-    if (CONN8) {
-      if (fx && !fxl) lunion(L.parent, q, x);
-      if (head && fxl) lunion(L.parent, q, x - 1);
-      if (tail && c < TW - 1 && !fx &&
-          lds_load(&L.parent[x + 1]) >= 0)
-        lunion(L.parent, q, x + 1);
-    } else {
-      if (fx && (head || !fxl)) lunion(L.parent, q, x);
+    // a row run cut by a segment boundary (tiles wider than 64)
+    if ((q & 63) == 0 && c > 0 && fg_at(q - 1)) lunion(L.parent, q, q - 1);
+    if (r == 0) return;
+    const int c1 = c + len - 1;
+    const int lo = CONN8 ? max(c - 1, 0) : c;
+    const int hi = CONN8 ? min(c1 + 1, TW - 1) : c1;
+    // one union per run of the row above that meets [lo, hi]
+    int x = q - TW + (lo - c);
+    const int xe = q - TW + (hi - c);
+    while (x <= xe) {
+      const uint64_t w = L.fgbits[x >> 6] >> (x & 63);
+      if (!w) { x = ((x >> 6) + 1) << 6; continue; }
+      x += __builtin_ctzll(w);
+      if (x > xe) break;
+      lunion(L.parent, q, x);
+      const uint64_t z = ~(L.fgbits[x >> 6] >> (x & 63));
+      x = z ? x + __builtin_ctzll(z) : ((x >> 6) + 1) << 6;
     }
-  }
+  });
   __syncthreads();
-#pragma unroll 4
-  for (int k = 0; k < PPT; ++k) {
-    if ((fgm >> k) & 1u) {
-      const int q = t + kBlock * k;
-      L.parent[q] = lfind(L.parent, q);
-    }
-  }
+  // heads point at their roots; other detected pixels keep their head
+  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int) {
+    const int root = lfind(L.parent, q);
+    L.parent[q] = root;
+    if (root == q) atomicOr((unsigned long long*)&L.rootbits[q >> 6],
+                            1ull << (q & 63));
+  });
   __syncthreads();
 
   // ---- component ids in raster order of their roots --------------------
-  uint32_t rootm = 0;
-#pragma unroll 4
-  for (int k = 0; k < PPT; ++k) {
-    const int q = t + kBlock * k;
-    const bool isroot = ((fgm >> k) & 1u) && L.parent[q] == q;
-    rootm |= (uint32_t)isroot << k;
-    const uint64_t b = __ballot(isroot);
-    if (lane == 0) L.wcnt[k * kWaves + wv] = __popcll(b);
-  }
-  __syncthreads();
-  if (wv == 0) {                   // exclusive scan of the 64 counts
-    const int v = L.wcnt[lane];
+  if (wv == 0) {                   // exclusive scan of the 64 root counts
+    const int v = __popcll(L.rootbits[lane]);
     int x = v;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -282,17 +313,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   }
   __syncthreads();
   const int ncomp = L.ncomp;
-#pragma unroll 4
-  for (int k = 0; k < PPT; ++k) {
-    const bool isroot = (rootm >> k) & 1u;
-    const uint64_t b = __ballot(isroot);
-    if (isroot) {
-      const int q = t + kBlock * k;
-      const int id = L.wcnt[k * kWaves + wv] + __popcll(b & below);
-      L.parent[q] = -2 - id;
-      L.u.st.rootp[id] = (int16_t)q;
-    }
-  }
+  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int) {
+    if (L.parent[q] != q) return;
+    const uint64_t bits = L.rootbits[q >> 6];
+    const uint64_t lt = (q & 63) ? (bits & (~0ull >> (64 - (q & 63)))) : 0;
+    const int id = L.wcnt[q >> 6] + __popcll(lt);
+    L.parent[q] = -2 - id;
+    L.u.st.rootp[id] = (int16_t)q;
+  });
   for (int c = t; c < ncomp; c += kBlock) {
     L.u.st.npix[c] = 0;
     L.u.st.xmin[c] = TW;
@@ -308,20 +336,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   // ---- per-run pixel count, bounding box, inner-border contact ----------
   const bool nb_up = y0 > 0, nb_down = y0 + TH < fr.h;
   const bool nb_left = x0 > 0, nb_right = x0 + TW < fr.w;
-#pragma unroll 4
-  for (int k = 0; k < PPT; ++k) {
-    if (!((fgm >> k) & 1u)) continue;
-    const uint64_t m = fgb[k];
-    const bool head = !((m >> lane) & 1ull & (m << 1 >> lane) & 1ull) ||
-                      ((row_first >> lane) & 1ull);
-    if (!head) continue;
-    const int q = t + kBlock * k;
+  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int len) {
     const int r = q / TW, c = q % TW;
-    const uint64_t ends = m & (~(m >> 1) | row_last);
-    const int e_lane = __ffsll((unsigned long long)(ends & ~below)) - 1;
-    const int len = e_lane - lane + 1;
     const int ce = c + len - 1;
-    const int id = comp_of(q);
+    const int pq = L.parent[q];
+    const int id = pq < 0 ? -2 - pq : -2 - L.parent[pq];
+    if (pq >= 0) L.parent[q] = -2 - id;   // every head now holds its id
     atomicAdd(&L.u.st.npix[id], len);
     atomicMin(&L.u.st.xmin[id], c);
     atomicMax(&L.u.st.xmax[id], ce);
@@ -329,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     const bool edge = (r == 0 && nb_up) || (r == TH - 1 && nb_down) ||
                       (c == 0 && nb_left) || (ce == TW - 1 && nb_right);
     if (edge) atomicOr(&L.u.st.npix[id], 1 << 30);
-  }
+  });
   __syncthreads();
 
   // ---- kept components -> records ---------------------------------------
@@ -399,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
         const int rl = L.u.st.rloc[comp_of(q)];
         if (rl >= 0 && rbase + rl < wk.rec_cap) v = (uint16_t)(rl + 1);
       }
-      wk.lmap[fr.pix0 + (int64_t)y * fr.w + x] = v;
+      gst(wk.lmap + fr.pix0 + (int64_t)y * fr.w + x, v);
     }
   }
 }
