@@ -245,6 +245,21 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   wave_bitonic<NS>(sv);
 
   // ---- k-sigma clipping on the sorted range [a, bnd) ---------------------
+  // Running sums of (v - c) and (v - c)^2 over the range, c a fixed shift
+  // (the first median); each pass removes a prefix and a suffix of the
+  // range, whose sizes are ballot counts over the sorted values (the +inf
+  // padding counts as above every bound).
+  const double c0 = nann > 0 ? sorted_at<PL>(sv, (nann - 1) / 2) : 0.0;
+  double S1 = 0.0, S2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < PL; ++k) {
+    const int e = lane * PL + k;
+    const double d = e < nann ? sv[k] - c0 : 0.0;
+    S1 += d;
+    S2 += d * d;
+  }
+  S1 = wave_sum(S1);
+  S2 = wave_sum(S2);
   int a = 0, bnd = nann;
   for (int it = 0; it < p.sky_clip_iters; ++it) {
     const int n = bnd - a;
@@ -253,37 +268,30 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
         (n & 1) ? sorted_at<PL>(sv, a + (n - 1) / 2)
                 : (sorted_at<PL>(sv, a + n / 2 - 1) +
                    sorted_at<PL>(sv, a + n / 2)) / 2.0;
-    double s1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < PL; ++k) {
-      const int e = lane * PL + k;
-      if (e >= a && e < bnd) s1 += sv[k];
-    }
-    const double mean = wave_sum(s1) / (double)n;
-    double s2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < PL; ++k) {
-      const int e = lane * PL + k;
-      if (e >= a && e < bnd) {
-        const double d = sv[k] - mean;
-        s2 += d * d;
-      }
-    }
-    const double sd = sqrt(wave_sum(s2) / (double)n);
+    const double dm = S1 / (double)n;
+    const double var = S2 / (double)n - dm * dm;
+    const double sd = sqrt(var > 0.0 ? var : 0.0);
     const double lo = med - p.sky_clip_sigma * sd;
     const double hi = med + p.sky_clip_sigma * sd;
-    int cl = 0, ch = 0;
+    int nlo = 0, nhi = 0;
+#pragma unroll
+    for (int k = 0; k < PL; ++k) {
+      nlo += __popcll(__ballot(sv[k] < lo));
+      nhi += __popcll(__ballot(sv[k] > hi));
+    }
+    const int cl = max(nlo - a, 0), ch = max(nhi - (NS - bnd), 0);
+    if (cl == 0 && ch == 0) break;
+    double r1 = 0.0, r2 = 0.0;
 #pragma unroll
     for (int k = 0; k < PL; ++k) {
       const int e = lane * PL + k;
-      if (e >= a && e < bnd) {
-        cl += sv[k] < lo;
-        ch += sv[k] > hi;
-      }
+      const bool gone = (e >= a && e < a + cl) || (e >= bnd - ch && e < bnd);
+      const double d = gone ? sv[k] - c0 : 0.0;
+      r1 += d;
+      r2 += d * d;
     }
-    cl = wave_sum(cl);
-    ch = wave_sum(ch);
-    if (cl == 0 && ch == 0) break;
+    S1 -= wave_sum(r1);
+    S2 -= wave_sum(r2);
     a += cl;
     bnd -= ch;
   }
