@@ -89,6 +89,17 @@ struct Work {
 };
 
 // ---------------------------------------------------------------- helpers
+// Stores and loads through the global address space (the pointers come
+// from descriptors in memory, where the compiler would use flat accesses).
+template <typename T>
+__device__ __forceinline__ void gst(T* a, T v) {
+  *(__attribute__((address_space(1))) T*)a = v;
+}
+template <typename T>
+__device__ __forceinline__ T gld(const T* a) {
+  return *(const __attribute__((address_space(1))) T*)a;
+}
+
 __device__ __forceinline__ uint32_t f2key(float f) {
   uint32_t u = __float_as_uint(f);
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);

@@ -97,17 +97,6 @@ __device__ __forceinline__ void gunion(int32_t* parent, int a, int b) {
   }
 }
 
-// Stores and loads through the global address space (the pointers come
-// from descriptors in memory, where the compiler would use flat accesses).
-template <typename T>
-__device__ __forceinline__ void gst(T* a, T v) {
-  *(__attribute__((address_space(1))) T*)a = v;
-}
-template <typename T>
-__device__ __forceinline__ T gld(const T* a) {
-  return *(const __attribute__((address_space(1))) T*)a;
-}
-
 // Calls fn(q, len) for every run head q of the 16-pixel slice of the tile
 // that thread t owns (segment t / 4, bits 16 (t % 4) ..).  A run is a
 // maximal horizontal stretch of detected pixels inside one 64-pixel
@@ -751,7 +740,10 @@ __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
   const int lane = threadIdx.x & (kWave - 1);
   long long nrows = wk.counters[3];
   if (nrows > src.capacity) nrows = src.capacity;
-  const long long wid = (blockIdx.x * (long long)kBlock + threadIdx.x) / kWave;
+  // wave index made provably uniform, so per-row loads are scalar
+  const long long wid =
+      blockIdx.x * (long long)kWaves +
+      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const long long nw = (long long)gridDim.x * (kBlock / kWave);
   const double two_q = 268435456.0;                  // 2^28
   const double dmax = 4611686018427387903.0;         // 2^62 - 1
@@ -768,12 +760,17 @@ __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
     double pk = -__builtin_inf();
     int pidx = 0x7FFFFFFF;
     uint32_t flags = 0;
+    // bounding-box position of element e, stepped without divisions
+    int ey = lane / bw, ex = lane - (lane / bw) * bw;
+    const int dy = kWave / bw, dx = kWave - (kWave / bw) * bw;
     for (long long e = lane; e < area; e += kWave) {
-      const int y = ymin + (int)(e / bw), x = xmin + (int)(e % bw);
+      const int y = ymin + ey, x = xmin + ex;
+      ey += dy; ex += dx;
+      if (ex >= bw) { ex -= bw; ++ey; }
       const int64_t o = (int64_t)y * fr.w + x;
-      if (fr.labels[o] != label) continue;
-      const float I = fr.pix[(int64_t)y * fr.pitch + x];
-      const float B = fr.bkg[o];
+      if (gld(fr.labels + o) != label) continue;
+      const float I = gld(fr.pix + (int64_t)y * fr.pitch + x);
+      const float B = gld(fr.bkg + o);
       const double v = (double)I - (double)B;
       double s = rint(v * two_q);
       if (!(exact_range(I) && exact_range(B))) flags |= IPP_SRC_INEXACT_SUM_RANGE;

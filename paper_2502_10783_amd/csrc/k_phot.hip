@@ -115,7 +115,7 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     }
     return;
   }
-  const FrameDev& fr = wk.frames[f];
+  const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
   const int xa = (int)ceil(cx - R - 0.5), xb = (int)floor(cx + R + 0.5);
   const int ya = (int)ceil(cy - R - 0.5), yb = (int)floor(cy + R + 0.5);
   const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
@@ -150,12 +150,11 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
       const bool in_ap = live && near2 < ra2;
       const bool in_ann = live && near2 < ro2 && !(far2 <= ri2);
       const bool inside = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
-      Iv[c] = 0.f;
-      Bv[c] = 0.f;
-      if ((in_ap || in_ann) && inside) {
-        Iv[c] = fr.pix[(int64_t)py * fr.pitch + px];
-        Bv[c] = fr.bkg[(int64_t)py * fr.w + px];
-      }
+      // unconditional loads (clamped into the frame): no branches, so all
+      // of the chunk's loads are in flight together
+      const int qx = min(max(px, 0), fr.w - 1), qy = min(max(py, 0), fr.h - 1);
+      Iv[c] = gld(fr.pix + (int64_t)qy * fr.pitch + qx);
+      Bv[c] = gld(fr.bkg + (int64_t)qy * fr.w + qx);
       st[c] = (uint32_t)in_ap | ((uint32_t)in_ann << 1) |
               ((uint32_t)inside << 2) | ((uint32_t)(far2 <= ra2) << 3) |
               ((uint32_t)!(far2 <= ro2 && !(near2 < ri2)) << 4);
@@ -220,8 +219,8 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   for (int j = lane; j < nap; j += kWave) {
     const int e = L.apb[j];
     const int px = xa + e % nwx, py = ya + e / nwx;
-    const float I = fr.pix[(int64_t)py * fr.pitch + px];
-    const double v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+    const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
+    const double v = (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
     const double wa = overlap(cx, cy, p.r_ap, px, py);
     a_ap += wa;
     raw += wa * v;
@@ -334,7 +333,10 @@ __global__ __launch_bounds__(kBlock) void k_aperture_t(Work wk, ipp_params p,
   __shared__ ApLds<NS> L[kWaves];
   long long nrows = src.capacity;
   if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
-  const long long wid = (blockIdx.x * (long long)kBlock + threadIdx.x) / kWave;
+  // wave index made provably uniform, so per-row loads are scalar
+  const long long wid =
+      blockIdx.x * (long long)kWaves +
+      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const long long nw = (long long)gridDim.x * kWaves;
   ApLds<NS>& mine = L[threadIdx.x / kWave];
   for (long long row = wid; row < nrows; row += nw)
@@ -384,7 +386,7 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
     if (lane == 0 && dxy) { dxy[2 * row] = 0.0; dxy[2 * row + 1] = 0.0; }
     return;
   }
-  const FrameDev& fr = wk.frames[f];
+  const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
   const double vlo = sky_lohi[2 * row], vhi = sky_lohi[2 * row + 1];
   const double R = p.r_ap > p.r_out ? p.r_ap : p.r_out;
   const int xa = (int)ceil(cx - R - 0.5), xb = (int)floor(cx + R + 0.5);
@@ -406,10 +408,10 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
                           !within(cx, cy, p.r_in, px, py);
       if ((in_ap || in_ann) && px >= 0 && px < fr.w && py >= 0 &&
           py < fr.h) {
-        const float I = fr.pix[(int64_t)py * fr.pitch + px];
+        const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
         if (isfinite(I)) {
           const double v =
-              (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+              (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
           if (in_ap) {
             if (within(cx, cy, p.r_ap, px, py)) A += 1.0;
             else ap_cut = true;
@@ -445,8 +447,8 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   for (int j = lane; j < nap; j += kWave) {
     const int e = L.apb[j];
     const int px = xa + e % nwx, py = ya + e / nwx;
-    const double v = (double)fr.pix[(int64_t)py * fr.pitch + px] -
-                     (double)fr.bkg[(int64_t)py * fr.w + px];
+    const double v = (double)gld(fr.pix + (int64_t)py * fr.pitch + px) -
+                     (double)gld(fr.bkg + (int64_t)py * fr.w + px);
     const double w = overlap(cx, cy, p.r_ap, px, py);
     L.apw[j] = w;
     A += w;
@@ -460,8 +462,8 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   for (int j = lane; j < nan_; j += kWave) {
     const int e = L.anb[j];
     const int px = xa + e % nwx, py = ya + e / nwx;
-    const double v = (double)fr.pix[(int64_t)py * fr.pitch + px] -
-                     (double)fr.bkg[(int64_t)py * fr.w + px];
+    const double v = (double)gld(fr.pix + (int64_t)py * fr.pitch + px) -
+                     (double)gld(fr.bkg + (int64_t)py * fr.w + px);
     const double w = overlap(cx, cy, p.r_out, px, py) -
                      overlap(cx, cy, p.r_in, px, py);
     L.anw[j] = w;
@@ -504,9 +506,9 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
     const bool in_ann = touches(cx, cy, p.r_out, px, py) &&
                         !within(cx, cy, p.r_in, px, py);
     if (!(in_ap || in_ann)) continue;
-    const float I = fr.pix[(int64_t)py * fr.pitch + px];
+    const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
     if (!isfinite(I)) continue;
-    const double v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+    const double v = (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
     double gd = 0.0;
     if (in_ap && within(cx, cy, p.r_ap, px, py)) gd += g;
     if (in_ann && v >= vlo && v <= vhi && within(cx, cy, p.r_out, px, py) &&
@@ -536,7 +538,10 @@ __global__ __launch_bounds__(kBlock) void k_aperture_bwd_t(
   __shared__ BwLds<NS> L[kWaves];
   long long nrows = src.capacity;
   if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
-  const long long wid = (blockIdx.x * (long long)kBlock + threadIdx.x) / kWave;
+  // wave index made provably uniform, so per-row loads are scalar
+  const long long wid =
+      blockIdx.x * (long long)kWaves +
+      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const long long nw = (long long)gridDim.x * kWaves;
   BwLds<NS>& mine = L[threadIdx.x / kWave];
   for (long long row = wid; row < nrows; row += nw)
