@@ -24,10 +24,12 @@ constexpr int kApTasks = 320;   // aperture pixels cut by a circle, r <= 16
 
 template <int NS>
 struct ApLds {
-  double pv[NS];                // annulus values (sorted values later)
+  double pv[NS];                // annulus values
   double pw[NS];                // annulus weights
-  int ab[NS];                   // annulus boundary tasks: slot << 16 | e
-  int apb[kApTasks];            // aperture boundary tasks: window index
+  // exact-overlap tasks: kind << 28 | annulus slot << 12 | wy << 6 | wx
+  // (kind 0: cut by the aperture; 1: cut by the outer circle only; 2: by
+  // the inner circle only; 3: by both)
+  int tk[NS + kApTasks];
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -123,7 +125,7 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   // ---- classify the window; compact the work -------------------------
   uint32_t flags = 0;
   double a_ap = 0.0, raw = 0.0;
-  int nann = 0, nab = 0, nap = 0;
+  int nann = 0, ntk = 0;
   // squared radii as the membership predicates form them
   const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
   const double ro2 = p.r_out * p.r_out;
@@ -135,10 +137,12 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
     float Iv[kChunk], Bv[kChunk];
     uint32_t st[kChunk];
+    int pos[kChunk];
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
       const int e = e0 + c * kWave + lane;
       const int px = xa + wc, py = ya + wr;
+      pos[c] = (wr << 6) | wc;
       wr += dwr; wc += dwc;
       if (wc >= nwx) { wc -= nwx; ++wr; }
       // nearest and farthest point of the pixel square (touches / within)
@@ -157,11 +161,10 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
       Bv[c] = gld(fr.bkg + (int64_t)qy * fr.w + qx);
       st[c] = (uint32_t)in_ap | ((uint32_t)in_ann << 1) |
               ((uint32_t)inside << 2) | ((uint32_t)(far2 <= ra2) << 3) |
-              ((uint32_t)!(far2 <= ro2 && !(near2 < ri2)) << 4);
+              ((uint32_t)!(far2 <= ro2) << 4) | ((uint32_t)(near2 < ri2) << 5);
     }
 #pragma unroll
     for (int c = 0; c < kChunk; ++c) {
-      const int e = e0 + c * kWave + lane;
       const bool in_ap = st[c] & 1u, in_ann = st[c] & 2u;
       bool ap_cut = false, ann = false, ann_cut = false;
       double v = 0.0;
@@ -182,16 +185,16 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
           }
           if (in_ann) {
             ann = true;
-            ann_cut = st[c] & 16u;
+            ann_cut = st[c] & 48u;
           }
         }
       }
       const uint64_t b1 = __ballot(ap_cut);
       if (ap_cut) {
-        const int s = nap + __popcll(b1 & lanes_below());
-        if (s < kApTasks) L.apb[s] = e;
+        const int s = ntk + __popcll(b1 & lanes_below());
+        if (s < NS + kApTasks) L.tk[s] = pos[c];
       }
-      nap += __popcll(b1);
+      ntk += __popcll(b1);
       const uint64_t b2 = __ballot(ann);
       int slot = 0;
       if (ann) {
@@ -204,33 +207,44 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
       nann += __popcll(b2);
       const uint64_t b3 = __ballot(ann_cut);
       if (ann_cut) {
-        const int s = nab + __popcll(b3 & lanes_below());
-        if (s < NS && slot < NS) L.ab[s] = (slot << 16) | e;
+        const int s = ntk + __popcll(b3 & lanes_below());
+        const int kind = (int)((st[c] >> 4) & 3u);
+        if (s < NS + kApTasks && slot < NS)
+          L.tk[s] = (kind << 28) | (slot << 12) | pos[c];
       }
-      nab += __popcll(b3);
+      ntk += __popcll(b3);
     }
   }
   if (nann > NS) nann = NS;            // not reachable: NS bounds the ring
-  if (nab > NS) nab = NS;
-  if (nap > kApTasks) nap = kApTasks;  // not reachable for r_ap <= 16
+  if (ntk > NS + kApTasks) ntk = NS + kApTasks;  // not reachable either
   wave_lds_sync();
 
-  // ---- exact overlaps over the dense task lists --------------------------
-  for (int j = lane; j < nap; j += kWave) {
-    const int e = L.apb[j];
-    const int px = xa + e % nwx, py = ya + e / nwx;
-    const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
-    const double v = (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
-    const double wa = overlap(cx, cy, p.r_ap, px, py);
-    a_ap += wa;
-    raw += wa * v;
-  }
-  for (int j = lane; j < nab; j += kWave) {
-    const int t = L.ab[j];
-    const int slot = t >> 16, e = t & 0xFFFF;
-    const int px = xa + e % nwx, py = ya + e / nwx;
-    L.pw[slot] = overlap(cx, cy, p.r_out, px, py) -
-                 overlap(cx, cy, p.r_in, px, py);
+  // ---- exact overlaps over one dense task list ---------------------------
+  // Every lane computes one overlap per task (two only for a pixel cut by
+  // both annulus circles), whatever circle the task belongs to.
+  {
+    const double r2a = p.r_ap * p.r_ap, r2o = p.r_out * p.r_out;
+    const double r2i = p.r_in * p.r_in;
+    const double ia = 1.0 / r2a, io = 1.0 / r2o, ii = 1.0 / r2i;
+    for (int j = lane; j < ntk; j += kWave) {
+      const int t = L.tk[j];
+      const int kind = t >> 28, slot = (t >> 12) & 0x3FF;
+      const int px = xa + (t & 63), py = ya + ((t >> 6) & 63);
+      const double r = kind == 0 ? p.r_ap : (kind == 2 ? p.r_in : p.r_out);
+      const double r2 = kind == 0 ? r2a : (kind == 2 ? r2i : r2o);
+      const double ir2 = kind == 0 ? ia : (kind == 2 ? ii : io);
+      double w = overlap_pre(cx, cy, r, r2, ir2, px, py);
+      const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
+      const double v = (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
+      if (kind == 0) {
+        a_ap += w;
+        raw += w * v;
+      } else {
+        if (kind == 3) w -= overlap_pre(cx, cy, p.r_in, r2i, ii, px, py);
+        else if (kind == 2) w = 1.0 - w;
+        L.pw[slot] = w;
+      }
+    }
   }
   wave_lds_sync();
 

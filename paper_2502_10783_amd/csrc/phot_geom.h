@@ -50,11 +50,12 @@ __device__ __forceinline__ double corner_g(double ax, double ay, double hx,
 // Overlap of the pixel square [px-1/2, px+1/2] x [py-1/2, py+1/2] with the
 // disk of radius r about (cx, cy): inclusion-exclusion of G over the
 // square's corners.
-__device__ __forceinline__ double overlap(double cx, double cy, double r,
-                                          int px, int py) {
+// r2 = r * r and inv_r2 = 1 / r2, passed in so a caller can precompute them.
+__device__ __forceinline__ double overlap_pre(double cx, double cy, double r,
+                                              double r2, double inv_r2,
+                                              int px, int py) {
   if (!touches(cx, cy, r, px, py)) return 0.0;
   if (within(cx, cy, r, px, py)) return 1.0;
-  const double r2 = r * r, inv_r2 = 1.0 / r2;
   const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
   const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
   const double ax0 = fmin(fabs(x0), r), ax1 = fmin(fabs(x1), r);
@@ -69,6 +70,12 @@ __device__ __forceinline__ double overlap(double cx, double cy, double r,
          sx0 * sy1 * corner_g(ax0, ay1, hx0, xs1, r2, inv_r2) -
          sx1 * sy0 * corner_g(ax1, ay0, hx1, xs0, r2, inv_r2) +
          sx0 * sy0 * corner_g(ax0, ay0, hx0, xs0, r2, inv_r2);
+}
+
+__device__ __forceinline__ double overlap(double cx, double cy, double r,
+                                          int px, int py) {
+  const double r2 = r * r;
+  return overlap_pre(cx, cy, r, r2, 1.0 / r2, px, py);
 }
 
 __device__ __forceinline__ double chord(double x, double y, double r) {
