@@ -489,13 +489,26 @@ __device__ __forceinline__ uint32_t byte_flag(uint32_t m, int i) {
   return (uint32_t)(-(int)((m >> (8 * i)) & 0xFFu) >> 31);
 }
 
-// Key of a pixel value; `bad` is all ones for an excluded pixel.  Non-finite
-// values also map to the sentinel, and -0 is folded onto +0.
-__device__ __forceinline__ uint32_t pix_key(float v, uint32_t bad) {
+// Pixel value as held in registers: -0 folded onto +0, and the canonical
+// quiet NaN for an excluded pixel (`bad` all ones) or a non-finite value.
+constexpr uint32_t kNanBits = 0x7FC00000u;
+constexpr uint32_t kBadKey = 0xFFC00000u;   // its key: above every finite key
+__device__ __forceinline__ float pix_val(float v, uint32_t bad) {
   const uint32_t u = __float_as_uint(v + 0.0f);
   const uint32_t nf = (uint32_t)((int)(0x7F7FFFFFu - (u & 0x7FFFFFFFu)) >> 31);
-  const uint32_t sg = (uint32_t)((int)u >> 31);
-  return (u ^ (sg | 0x80000000u)) | nf | bad;
+  const uint32_t m = nf | bad;
+  return __uint_as_float((m & kNanBits) | (~m & u));
+}
+__device__ __forceinline__ uint32_t pix_key(float v, uint32_t bad) {
+  return f2key(pix_val(v, bad));
+}
+
+// Float bounds of a key interval [lo, hi] of pixel keys: v >= flo && v <= fhi
+// holds exactly for the finite values whose key lies in [lo, hi] (no value
+// is -0, so the key of -0 as an upper bound excludes +0).
+__device__ __forceinline__ float key_lo_f(uint32_t lo) { return key2f(lo); }
+__device__ __forceinline__ float key_hi_f(uint32_t hi) {
+  return hi == 0x7FFFFFFFu ? -__uint_as_float(1u) : key2f(hi);
 }
 
 // Loads a th x tw region (row-major, four consecutive columns per group,
@@ -504,7 +517,7 @@ __device__ __forceinline__ uint32_t pix_key(float v, uint32_t bad) {
 // groups are 16-byte aligned float4s.  The scalar form converts every four
 // groups before loading more, to bound the values in flight.
 template <int PPL, bool VEC, bool MASK>
-__device__ __forceinline__ void load_region(uint32_t (&key)[PPL],
+__device__ __forceinline__ void load_region(float (&key)[PPL],
                                             const float* base,
                                             const uint8_t* mbase,
                                             int64_t pitch, int th, int tw) {
@@ -520,10 +533,10 @@ __device__ __forceinline__ void load_region(uint32_t (&key)[PPL],
       const float4 v = *(const float4*)(base + o + 4 * c);
       uint32_t mk = 0;
       if (MASK) mk = *(const uint32_t*)(mbase + o + 4 * c);
-      key[4 * k + 0] = pix_key(v.x, out | byte_flag(mk, 0));
-      key[4 * k + 1] = pix_key(v.y, out | byte_flag(mk, 1));
-      key[4 * k + 2] = pix_key(v.z, out | byte_flag(mk, 2));
-      key[4 * k + 3] = pix_key(v.w, out | byte_flag(mk, 3));
+      key[4 * k + 0] = pix_val(v.x, out | byte_flag(mk, 0));
+      key[4 * k + 1] = pix_val(v.y, out | byte_flag(mk, 1));
+      key[4 * k + 2] = pix_val(v.z, out | byte_flag(mk, 2));
+      key[4 * k + 3] = pix_val(v.w, out | byte_flag(mk, 3));
     } else {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -531,7 +544,7 @@ __device__ __forceinline__ void load_region(uint32_t (&key)[PPL],
         const int64_t oj = o + min(cc, tw - 1);
         uint32_t mk = 0;
         if (MASK) mk = mbase[oj];
-        key[4 * k + j] = pix_key(base[oj], out | byte_flag(mk, 0) |
+        key[4 * k + j] = pix_val(base[oj], out | byte_flag(mk, 0) |
                                                (uint32_t)((tw - 1 - cc) >> 31));
       }
       if ((k & 3) == 3) __builtin_amdgcn_sched_barrier(0);
@@ -544,6 +557,10 @@ __device__ __forceinline__ void load_region(uint32_t (&key)[PPL],
 // An opaque copy of a key: stops the compiler from reusing per-pixel
 // values of an earlier pass (which would keep a second PPL registers alive).
 __device__ __forceinline__ uint32_t fresh(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ float fresh(float v) {
   asm volatile("" : "+v"(v));
   return v;
 }
@@ -615,17 +632,18 @@ __device__ __forceinline__ int wave_find(const uint32_t* h, int base, int rr,
 // keys of within-range ranks w0 and w1 are returned.
 template <int PPL>
 __device__ __forceinline__ void wave_gather_select(
-    const uint32_t (&key)[PPL], uint32_t lo, uint32_t hi, int cnt, int w0,
+    const float (&val)[PPL], uint32_t lo, uint32_t hi, int cnt, int w0,
     int w1, WaveLds& L, uint32_t* k0, uint32_t* k1) {
   const int lane = lane_id();
+  const float flo = key_lo_f(lo), fhi = key_hi_f(hi);
   if (lane == 0) L.nlist = 0;
   wsync();
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const uint32_t v = fresh(key[k]);
-    if (v >= lo && v <= hi) {
+    const float v = val[k];
+    if (v >= flo && v <= fhi) {
       const uint32_t slot = atomicAdd(&L.nlist, 1u);
-      if (slot < (uint32_t)kWGather) L.list[slot] = v;
+      if (slot < (uint32_t)kWGather) L.list[slot] = f2key(fresh(v));
     }
   }
   wsync();
@@ -648,7 +666,7 @@ __device__ __forceinline__ void wave_gather_select(
 // Key of rank r inside level-1 bin [lo, hi] (base keys below it, cnt in
 // it), narrowing with 1024-bin histograms until a gather suffices.
 template <int PPL>
-__device__ __forceinline__ uint32_t wave_narrow(const uint32_t (&key)[PPL],
+__device__ __forceinline__ uint32_t wave_narrow(const float (&key)[PPL],
                                                 int r, uint32_t lo,
                                                 uint32_t hi, int base, int cnt,
                                                 WaveLds& L) {
@@ -669,7 +687,7 @@ __device__ __forceinline__ uint32_t wave_narrow(const uint32_t (&key)[PPL],
     wsync();
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
-      const uint32_t v = fresh(key[k]);
+      const uint32_t v = f2key(fresh(key[k]));
       const bool in = v >= lo && v <= hi;
       const uint32_t b = in ? (v - lo) >> sh : 0u;
       atomicAdd(&L.h2[b >> 1], (uint32_t)in << ((b & 1) << 4));
@@ -713,7 +731,7 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
   // ---- load the region as keys (sentinel: excluded pixel) ------------
   // Branch-free: rows past the region re-read its last row and are turned
   // into sentinels arithmetically, so no per-element lane masks stay live.
-  uint32_t key[PPL];
+  float key[PPL];
   const float* base = fr.pix + (int64_t)y0 * fr.pitch + x0;
   const uint8_t* mbase = fr.mask ? fr.mask + (int64_t)y0 * fr.pitch + x0
                                  : nullptr;
@@ -734,22 +752,9 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
     const int64_t o = (int64_t)r * fr.pitch + c;
     smp = pix_key(base[o], mbase ? byte_flag(mbase[o], 0) : 0u);
   }
-  uint32_t kmin = kSentinel, kmax1 = 0;
-  int nloc = 0;
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const uint32_t v = key[k];
-    kmin = min(kmin, v);                 // the sentinel is the largest key
-    kmax1 = max(kmax1, v + 1u);          // and wraps to 0 here
-    nloc += (int)min(~v, 1u);
-  }
-  const int n0 = uni(wave_sum(nloc));
-  kmin = uni(wave_min(kmin));
-  const uint32_t kmax = uni(wave_max(kmax1)) - 1u;
-
   double out_bkg = __builtin_nan(""), out_rms = __builtin_nan("");
   int out_n = 0;
-  if (n0 > 0) {
+  {
     // ---- sample quartiles: histogram range and moment shift ----------
 #pragma unroll
     for (int kk = 2; kk <= kWave; kk <<= 1) {
@@ -763,23 +768,28 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
         smp = (lower == up) ? mn : mx;
       }
     }
-    const int ns = __popcll(__ballot(smp != kSentinel));
+    const int ns = __popcll(__ballot(smp < kBadKey));
+    // end bins reach over every finite key
     Bins B;
-    B.kmin = kmin;
-    B.kmax = kmax;
-    B.klo = kmin;
-    B.khi = kmax;
-    float c0f = key2f(ns > 0 ? (uint32_t)rl((int)smp, ns / 2) : kmin);
+    B.kmin = 0;
+    B.kmax = kBadKey - 1;
+    B.klo = 0;
+    B.khi = kBadKey - 1;
+    float c0f = 0.0f;
+    if (ns > 0) {
+      c0f = key2f((uint32_t)rl((int)smp, ns / 2));
+      B.klo = (uint32_t)rl((int)smp, 0);
+      B.khi = (uint32_t)rl((int)smp, ns - 1);
+    }
     if (ns >= 16) {
       const double a = (double)key2f((uint32_t)rl((int)smp, ns / 4));
       const double b = (double)key2f((uint32_t)rl((int)smp, (3 * ns) / 4));
       const double iqr = b - a;
       if (iqr > 0.0) {
-        const uint32_t klo = key_ceil(a - 4.0 * iqr);
-        const uint32_t khi = key_floor(b + 4.0 * iqr);
-        B.klo = klo > kmin ? klo : kmin;
-        B.khi = khi < kmax ? khi : kmax;
-        if (B.klo > B.khi) { B.klo = kmin; B.khi = kmax; }
+        B.klo = key_ceil(a - 4.0 * iqr);
+        B.khi = key_floor(b + 4.0 * iqr);
+        if (B.khi >= kBadKey) B.khi = kBadKey - 1;
+        if (B.klo > B.khi) B.klo = B.khi;
       }
     }
     {
@@ -795,18 +805,24 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
     for (int i = 0; i < kWBins / 2 / kWave; ++i) L.h[lane + i * kWave] = 0;
     wsync();
     double s1 = 0.0, s2 = 0.0;
+    int n0 = 0;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
-      // branch-free: sentinels land in the top bin and are taken out below
-      const uint32_t v = fresh(key[k]);
+      // branch-free: excluded pixels land in the top bin and are taken out
+      // below
+      const float fv = fresh(key[k]);
+      const uint32_t v = f2key(fv);
       uint32_t b = 1 + ((v - B.klo) >> B.sh);
       b = v > B.khi ? kWBins - 1 : b;
       b = v < B.klo ? 0 : b;
       atomicAdd(&L.h[b >> 1], 1u << ((b & 1) << 4));
-      const double d = (double)(v <= kmax ? key2f(v) : c0f) - c0;
+      const bool ok = fv == fv;
+      n0 += __popcll(__builtin_amdgcn_ballot_w64(ok));
+      const double d = (double)(ok ? fv : c0f) - c0;
       s1 += d;
       s2 = fma(d, d, s2);
     }
+    n0 = uni(n0);
     s1 = uni(wave_sum(s1));
     s2 = uni(wave_sum(s2));
     wsync();
@@ -844,7 +860,7 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
     int below = 0, nS = n0;
     double med = 0, mean = 0, sd = 0;
     bool have = false;
-    for (int it = 0; it <= p.clip_iters; ++it) {
+    for (int it = 0; n0 > 0 && it <= p.clip_iters; ++it) {
       const int r0 = below + (nS - 1) / 2, r1 = below + nS / 2;
       uint32_t k0, k1;
       select(r0, r1, &k0, &k1);
@@ -861,22 +877,25 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
       uint32_t nlo = key_ceil(lo), nhi = key_floor(hi);
       nlo = nlo > klo ? nlo : klo;
       nhi = nhi < khi ? nhi : khi;
+      // float bounds of the key interval (a NaN value fails both tests)
+      const float flo = key_lo_f(nlo), fhi = key_hi_f(nhi);
       int cin = 0, cb = 0;
       double t1 = 0.0, t2 = 0.0;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        const uint32_t v = fresh(key[k]);
-        const bool in = v >= nlo && v <= nhi;
-        cin += in;
-        cb += v < nlo;
-        const double d = (double)(in ? key2f(v) : c0f) - c0;
+        const float v = key[k];
+        const bool in = v >= flo && v <= fhi;
+        cin += __popcll(__builtin_amdgcn_ballot_w64(v >= flo) &
+                        __builtin_amdgcn_ballot_w64(v <= fhi));
+        cb += __popcll(__builtin_amdgcn_ballot_w64(v < flo));
+        const double d = (double)(in ? v : c0f) - c0;
         t1 += d;
         t2 = fma(d, d, t2);
       }
       // summed before the exit test, so that the per-pixel terms are not
       // deferred past it and kept alive
-      cin = uni(wave_sum(cin));
-      cb = uni(wave_sum(cb));
+      cin = uni(cin);
+      cb = uni(cb);
       t1 = uni(wave_sum(t1));
       t2 = uni(wave_sum(t2));
       if (cin == nS) break;          // nothing rejected: data stabilised

@@ -218,3 +218,41 @@ def test_edge_cases(ctx):
     n = out["table"].count()
     assert n > 3
     assert int(out["labels"][0].max()) == n
+
+
+def _mesh_variant_cases():
+    img, _, _ = make_frame("single", 2, scale=0.5)             # 512 x 512
+    rng = np.random.default_rng(7)
+    mask = rng.random(img.shape) < 0.1
+    mask[64:128, 0:128] = True                   # fully masked regions
+    quant = torch.round(img / 4.0) * 4.0          # many equal values
+    return [
+        ("mask", img, mask, (32, 32)),
+        ("mesh128", img, None, (128, 128)),
+        ("mesh48x80", img, None, (48, 80)),
+        ("mesh20x30", img, None, (20, 30)),
+        ("quantised", quant, None, (64, 64)),
+    ]
+
+
+@pytest.mark.parametrize("case", _mesh_variant_cases(),
+                         ids=lambda c: c[0])
+def test_mesh_variants(ctx, case):
+    """Masks, large and non-square regions, and heavily tied values, which
+    take the other register layouts and the narrowing path of the region
+    selection."""
+    name, img, mask, (mh, mw) = case
+    p, op = _params(mesh_h=mh, mesh_w=mw)
+    masks = None
+    if mask is not None:
+        masks = [torch.from_numpy(mask.astype(np.uint8)).to(DEV)]
+    out = ctx.background([img.to(DEV)], p, mesh=True, masks=masks)
+    torch.cuda.synchronize()
+    ref = obg.background(img.numpy(), op, mask)
+    assert np.array_equal(out["n_used"][0].cpu().numpy(), ref["n_used"]), name
+    np.testing.assert_allclose(out["bkg_raw"][0].cpu().numpy(),
+                               ref["bkg_raw"], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(out["rms_raw"][0].cpu().numpy(),
+                               ref["rms_raw"], rtol=1e-11, atol=0)
+    B = out["bkg"][0].cpu().numpy()
+    assert np.max(np.abs(B - ref["B64"]) / np.abs(ref["B64"])) <= 1e-6, name
