@@ -186,13 +186,17 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
 
   // the tile's pixels are requested first, so that their latency overlaps
   // the spline prologue
-  float Ipx[PPT];
+  float Ipx[PPT], Bv[FUSED ? 1 : PPT], Rv[FUSED ? 1 : PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int q = t + kBlock * k;
     const int y = y0 + q / TW, x = x0 + q % TW;
-    Ipx[k] = (y < fr.h && x < fr.w) ? gld(fr.pix + (int64_t)y * fr.pitch + x)
-                                    : 0.0f;
+    const bool in = y < fr.h && x < fr.w;
+    Ipx[k] = in ? gld(fr.pix + (int64_t)y * fr.pitch + x) : 0.0f;
+    if (!FUSED) {
+      Bv[k] = in ? gld(fr.bkg + (int64_t)y * fr.w + x) : 0.0f;
+      Rv[k] = in ? gld(fr.rms + (int64_t)y * fr.w + x) : 0.0f;
+    }
   }
   if (FUSED) spline_prologue<TH, TW>(wk, fr, p, y0, x0, L.u.spl);
 
@@ -208,6 +212,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   const uint64_t upto = below | (1ull << lane);
 
   // ---- threshold: v = I - B32 > nsigma * R32; runs ----------------------
+  // Every prefetched pixel is consumed here, before the loop, so that the
+  // loop's stores are never waited on together with a pending load.
+  uint32_t finm = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) finm |= (uint32_t)isfinite(Ipx[k]) << k;
   uint32_t fgm = 0;
   uint64_t fgb[PPT];
 #pragma unroll
@@ -218,25 +227,25 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     bool det = false;
     if (y < fr.h && x < fr.w) {
       const float I = Ipx[k];
-      const int64_t o = (int64_t)y * fr.w + x;
       float B32, R32;
       if (FUSED) {
         double b, rr;
         spline_pixel<TH, TW>(L.u.spl, r, c, &b, &rr);
         B32 = (float)b;
         R32 = (float)rr;
+        const int64_t o = (int64_t)y * fr.w + x;
         gst(fr.bkg + o, B32);
         if (write_rms) gst(fr.rms + o, R32);
       } else {
-        B32 = gld(fr.bkg + o);
-        R32 = gld(fr.rms + o);
+        B32 = Bv[k];
+        R32 = Rv[k];
       }
       const double v = (double)I - (double)B32;
       const double thr = p.det_nsigma * (double)R32;
-      det = isfinite(I) && (v > thr);
+      det = ((finm >> k) & 1u) && (v > thr);
     }
     fgm |= (uint32_t)det << k;
-    const uint64_t m = __ballot(det);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(det);
     fgb[k] = m;
     const uint64_t heads = m & (~(m << 1) | row_first);
     if (lane == 0) {

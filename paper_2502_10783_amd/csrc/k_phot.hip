@@ -43,6 +43,21 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Value of lane (lane ^ LM): DPP moves inside rows of 16 lanes for LM of
+// 1, 2, 4 and 8 (no LDS round trip), the LDS permute beyond.
+template <int LM>
+__device__ __forceinline__ double xor_lane(double v) {
+  if (LM == 1) return dpp_mov<0xB1>(v);          // quad_perm [1,0,3,2]
+  if (LM == 2) return dpp_mov<0x4E>(v);          // quad_perm [2,3,0,1]
+  if (LM == 8) return dpp_mov<0x128>(v);         // row_ror:8
+  if (LM == 4) {
+    const double up = dpp_mov<0x104>(v);         // row_shl:4 (lane + 4)
+    const double dn = dpp_mov<0x114>(v);         // row_shr:4 (lane - 4)
+    return (threadIdx.x & 4) ? dn : up;
+  }
+  return __shfl_xor(v, LM, kWave);
+}
+
 // Bitonic sort (ascending) of NS binary64 values held as v[NS/64] per
 // lane, element index e = lane * (NS/64) + k.
 template <int NS>
@@ -73,7 +88,15 @@ __device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave]) {
         for (int k = 0; k < PL; ++k) {
           const int e = lane * PL + k;
           const bool up = (e & kk) == 0;
-          const double o = __shfl_xor(v[k], lm, kWave);
+          double o;
+          switch (lm) {
+            case 1: o = xor_lane<1>(v[k]); break;
+            case 2: o = xor_lane<2>(v[k]); break;
+            case 4: o = xor_lane<4>(v[k]); break;
+            case 8: o = xor_lane<8>(v[k]); break;
+            case 16: o = xor_lane<16>(v[k]); break;
+            default: o = xor_lane<32>(v[k]); break;
+          }
           v[k] = (lower == up) ? fmin(v[k], o) : fmax(v[k], o);
         }
       }

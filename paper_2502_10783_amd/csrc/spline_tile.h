@@ -101,10 +101,11 @@ __device__ __forceinline__ void spline_pixel(const SplineLds<TH, TW>& S,
   const int k = S.cx[c];
   const double w0 = S.wx[0][c], w1 = S.wx[1][c];
   const double w2 = S.wx[2][c], w3 = S.wx[3][c];
-  *b = ((w0 * S.gB[r][k] + w1 * S.gB[r][k + 1]) + w2 * S.gBpp[r][k])
-       + w3 * S.gBpp[r][k + 1];
-  *rr = ((w0 * S.gR[r][k] + w1 * S.gR[r][k + 1]) + w2 * S.gRpp[r][k])
-        + w3 * S.gRpp[r][k + 1];
+  // fused multiply-adds: four FP64 operations per map
+  *b = fma(w3, S.gBpp[r][k + 1],
+           fma(w2, S.gBpp[r][k], fma(w1, S.gB[r][k + 1], w0 * S.gB[r][k])));
+  *rr = fma(w3, S.gRpp[r][k + 1],
+            fma(w2, S.gRpp[r][k], fma(w1, S.gR[r][k + 1], w0 * S.gR[r][k])));
 }
 
 }  // namespace ipp
