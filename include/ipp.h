@@ -113,9 +113,9 @@ typedef struct ipp_params {
 } ipp_params;
 
 /* One input frame: h rows of w float32 pixels, row stride `pitch`
- * elements (pitch >= w).  `mask` (nullable) is h x w bytes with the same
- * pitch; a nonzero byte excludes the pixel from the background statistics.
- * Frames up to 32767 x 32767 pixels. */
+ * elements (w <= pitch <= 2^24).  `mask` (nullable) is h x w bytes with the
+ * same pitch; a nonzero byte excludes the pixel from the background
+ * statistics.  Frames up to 32767 x 32767 pixels. */
 typedef struct ipp_frame {
   const float* pix;
   const uint8_t* mask;

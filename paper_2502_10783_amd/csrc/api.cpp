@@ -159,6 +159,8 @@ std::string check_frames(const ipp_frame* f, int32_t n) {
       return "frame " + std::to_string(i) + ": size must be 1..32767";
     if (f[i].pitch < f[i].w)
       return "frame " + std::to_string(i) + ": pitch < w";
+    if (f[i].pitch > (1 << 24))
+      return "frame " + std::to_string(i) + ": pitch must be at most 2^24";
   }
   return "";
 }

@@ -49,6 +49,9 @@ template <int LM>
 __device__ __forceinline__ double xor_lane(double v) {
   if (LM == 1) return dpp_mov<0xB1>(v);          // quad_perm [1,0,3,2]
   if (LM == 2) return dpp_mov<0x4E>(v);          // quad_perm [2,3,0,1]
+  if (LM == 3) return dpp_mov<0x1B>(v);          // quad_perm [3,2,1,0]
+  if (LM == 7) return dpp_mov<0x141>(v);         // row_half_mirror
+  if (LM == 15) return dpp_mov<0x140>(v);        // row_mirror
   if (LM == 8) return dpp_mov<0x128>(v);         // row_ror:8
   if (LM == 4) {
     const double up = dpp_mov<0x104>(v);         // row_shl:4 (lane + 4)
@@ -58,50 +61,60 @@ __device__ __forceinline__ double xor_lane(double v) {
   return __shfl_xor(v, LM, kWave);
 }
 
+// Ascending compare-exchange of every element with the element at lane ^
+// LM, register k (FLIP: register PL - 1 - k); the lower lane keeps the
+// minimum.
+template <int PL, int LM, bool FLIP>
+__device__ __forceinline__ void exch_lanes(double (&v)[PL], bool lower) {
+  double o[PL];
+#pragma unroll
+  for (int k = 0; k < PL; ++k) o[k] = xor_lane<LM>(v[FLIP ? PL - 1 - k : k]);
+#pragma unroll
+  for (int k = 0; k < PL; ++k)
+    v[k] = lower ? fmin(v[k], o[k]) : fmax(v[k], o[k]);
+}
+
+// Ascending compare-exchange of registers k and k ^ D inside each lane.
+template <int PL, int D>
+__device__ __forceinline__ void exch_regs(double (&v)[PL]) {
+#pragma unroll
+  for (int k = 0; k < PL; ++k) {
+    const int l = k ^ D;
+    if (l > k) {
+      const double a = v[k], b = v[l];
+      v[k] = fmin(a, b);
+      v[l] = fmax(a, b);
+    }
+  }
+}
+
+// Half-cleaners J, J/2, .., 1 of a bitonic merge.
+template <int PL, int J>
+__device__ __forceinline__ void half_cleaners(double (&v)[PL], int lane) {
+  if constexpr (J >= 1) {
+    if constexpr (J < PL) exch_regs<PL, J>(v);
+    else exch_lanes<PL, J / PL, false>(v, (lane & (J / PL)) == 0);
+    half_cleaners<PL, J / 2>(v, lane);
+  }
+}
+
+// Merges of block sizes KK, 2 KK, .., NS: each starts with a flip (e
+// against e ^ (KK - 1)), so that every compare-exchange is ascending.
+template <int PL, int NS, int KK>
+__device__ __forceinline__ void bitonic_merges(double (&v)[PL], int lane) {
+  if constexpr (KK <= NS) {
+    if constexpr (KK <= PL) exch_regs<PL, KK - 1>(v);
+    else exch_lanes<PL, KK / PL - 1, true>(v, (lane & (KK / 2 / PL)) == 0);
+    half_cleaners<PL, KK / 4>(v, lane);
+    bitonic_merges<PL, NS, KK * 2>(v, lane);
+  }
+}
+
 // Bitonic sort (ascending) of NS binary64 values held as v[NS/64] per
 // lane, element index e = lane * (NS/64) + k.
 template <int NS>
 __device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave]) {
-  constexpr int PL = NS / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int kk = 2; kk <= NS; kk <<= 1) {
-#pragma unroll
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      if (j < PL) {
-#pragma unroll
-        for (int k = 0; k < PL; ++k) {
-          const int l = k ^ j;
-          if (l > k) {
-            const int e = lane * PL + k;
-            const bool up = (e & kk) == 0;
-            const double a = v[k], b = v[l];
-            const double mn = fmin(a, b), mx = fmax(a, b);
-            v[k] = up ? mn : mx;
-            v[l] = up ? mx : mn;
-          }
-        }
-      } else {
-        const int lm = j / PL;                 // partner lane = lane ^ lm
-        const bool lower = (lane & lm) == 0;
-#pragma unroll
-        for (int k = 0; k < PL; ++k) {
-          const int e = lane * PL + k;
-          const bool up = (e & kk) == 0;
-          double o;
-          switch (lm) {
-            case 1: o = xor_lane<1>(v[k]); break;
-            case 2: o = xor_lane<2>(v[k]); break;
-            case 4: o = xor_lane<4>(v[k]); break;
-            case 8: o = xor_lane<8>(v[k]); break;
-            case 16: o = xor_lane<16>(v[k]); break;
-            default: o = xor_lane<32>(v[k]); break;
-          }
-          v[k] = (lower == up) ? fmin(v[k], o) : fmax(v[k], o);
-        }
-      }
-    }
-  }
+  bitonic_merges<NS / kWave, NS, 2>(v, threadIdx.x & (kWave - 1));
 }
 
 // Element e (wave-uniform) of a sorted register array.
@@ -141,8 +154,11 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     return;
   }
   const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
-  const int xa = (int)ceil(cx - R - 0.5), xb = (int)floor(cx + R + 0.5);
-  const int ya = (int)ceil(cy - R - 0.5), yb = (int)floor(cy + R + 0.5);
+  // window bounds: wave-uniform values, kept in scalar registers
+  const int xa = __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5));
+  const int xb = __builtin_amdgcn_readfirstlane((int)floor(cx + R + 0.5));
+  const int ya = __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5));
+  const int yb = __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5));
   const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
 
   // ---- classify the window; compact the work -------------------------
@@ -154,6 +170,12 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   const double ro2 = p.r_out * p.r_out;
   int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;   // window row, col
   const int dwr = kWave / nwx, dwc = kWave - (kWave / nwx) * nwx;
+  // row base of the window's first in-frame row (wave-uniform); loads take
+  // 32-bit offsets from it (pitch <= 2^24, at most 35 rows)
+  const int ry0 = min(max(ya, 0), fr.h - 1);
+  const float* wpix = fr.pix + (int64_t)ry0 * fr.pitch;
+  const float* wbkg = fr.bkg + (int64_t)ry0 * fr.w;
+  const uint32_t pitch32 = (uint32_t)fr.pitch, w32 = (uint32_t)fr.w;
   // Chunks of kChunk rounds of 64 pixels: all loads of a chunk are issued
   // before any is used, so their latencies overlap.
   constexpr int kChunk = 4;
@@ -179,9 +201,10 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
       const bool inside = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
       // unconditional loads (clamped into the frame): no branches, so all
       // of the chunk's loads are in flight together
-      const int qx = min(max(px, 0), fr.w - 1), qy = min(max(py, 0), fr.h - 1);
-      Iv[c] = gld(fr.pix + (int64_t)qy * fr.pitch + qx);
-      Bv[c] = gld(fr.bkg + (int64_t)qy * fr.w + qx);
+      const uint32_t qx = (uint32_t)min(max(px, 0), fr.w - 1);
+      const uint32_t qr = (uint32_t)(min(max(py, 0), fr.h - 1) - ry0);
+      Iv[c] = gld(wpix + (qr * pitch32 + qx));
+      Bv[c] = gld(wbkg + (qr * w32 + qx));
       st[c] = (uint32_t)in_ap | ((uint32_t)in_ann << 1) |
               ((uint32_t)inside << 2) | ((uint32_t)(far2 <= ra2) << 3) |
               ((uint32_t)!(far2 <= ro2) << 4) | ((uint32_t)(near2 < ri2) << 5);
@@ -257,8 +280,10 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
       const double r2 = kind == 0 ? r2a : (kind == 2 ? r2i : r2o);
       const double ir2 = kind == 0 ? ia : (kind == 2 ? ii : io);
       double w = overlap_pre(cx, cy, r, r2, ir2, px, py);
-      const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
-      const double v = (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
+      const uint32_t qr = (uint32_t)(py - ry0);
+      const float I = gld(wpix + (qr * pitch32 + (uint32_t)px));
+      const double v =
+          (double)I - (double)gld(wbkg + (qr * w32 + (uint32_t)px));
       if (kind == 0) {
         a_ap += w;
         raw += w * v;
@@ -426,8 +451,11 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
   const double vlo = sky_lohi[2 * row], vhi = sky_lohi[2 * row + 1];
   const double R = p.r_ap > p.r_out ? p.r_ap : p.r_out;
-  const int xa = (int)ceil(cx - R - 0.5), xb = (int)floor(cx + R + 0.5);
-  const int ya = (int)ceil(cy - R - 0.5), yb = (int)floor(cy + R + 0.5);
+  // window bounds: wave-uniform values, kept in scalar registers
+  const int xa = __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5));
+  const int xb = __builtin_amdgcn_readfirstlane((int)floor(cx + R + 0.5));
+  const int ya = __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5));
+  const int yb = __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5));
   const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
 
   // pass 1: sums, with the cut pixels' weights kept in LDS
