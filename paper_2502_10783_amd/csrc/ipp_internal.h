@@ -116,6 +116,16 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Wave ballot of a predicate, and the number of set bits of a mask below
+// the calling lane (two mbcnt instructions).
+__device__ __forceinline__ uint64_t ballot(bool b) {
+  return __builtin_amdgcn_ballot_w64(b);
+}
+__device__ __forceinline__ int lanes_before(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi(
+      (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Lane moves inside rows of 16 lanes (DPP: no LDS round trip).  The
 // patterns used are involutions, so both lanes of a pair add the same two
 // values and every lane ends with a bit-identical sum.

@@ -38,10 +38,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-__device__ __forceinline__ uint64_t lanes_below() {
-  const int lane = threadIdx.x & (kWave - 1);
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
 
 // Value of lane (lane ^ LM): DPP moves inside rows of 16 lanes for LM of
 // 1, 2, 4 and 8 (no LDS round trip), the LDS permute beyond.
@@ -235,25 +231,25 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
           }
         }
       }
-      const uint64_t b1 = __ballot(ap_cut);
+      const uint64_t b1 = ballot(ap_cut);
       if (ap_cut) {
-        const int s = ntk + __popcll(b1 & lanes_below());
+        const int s = ntk + lanes_before(b1);
         if (s < NS + kApTasks) L.tk[s] = pos[c];
       }
       ntk += __popcll(b1);
-      const uint64_t b2 = __ballot(ann);
+      const uint64_t b2 = ballot(ann);
       int slot = 0;
       if (ann) {
-        slot = nann + __popcll(b2 & lanes_below());
+        slot = nann + lanes_before(b2);
         if (slot < NS) {
           L.pv[slot] = v;
           L.pw[slot] = 1.0;
         }
       }
       nann += __popcll(b2);
-      const uint64_t b3 = __ballot(ann_cut);
+      const uint64_t b3 = ballot(ann_cut);
       if (ann_cut) {
-        const int s = ntk + __popcll(b3 & lanes_below());
+        const int s = ntk + lanes_before(b3);
         const int kind = (int)((st[c] >> 4) & 3u);
         if (s < NS + kApTasks && slot < NS)
           L.tk[s] = (kind << 28) | (slot << 12) | pos[c];
@@ -337,8 +333,8 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     int nlo = 0, nhi = 0;
 #pragma unroll
     for (int k = 0; k < PL; ++k) {
-      nlo += __popcll(__ballot(sv[k] < lo));
-      nhi += __popcll(__ballot(sv[k] > hi));
+      nlo += __popcll(ballot(sv[k] < lo));
+      nhi += __popcll(ballot(sv[k] > hi));
     }
     const int cl = max(nlo - a, 0), ch = max(nhi - (NS - bnd), 0);
     if (cl == 0 && ch == 0) break;
@@ -493,15 +489,15 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
         }
       }
     }
-    const uint64_t b1 = __ballot(ap_cut);
+    const uint64_t b1 = ballot(ap_cut);
     if (ap_cut) {
-      const int s = nap + __popcll(b1 & lanes_below());
+      const int s = nap + lanes_before(b1);
       if (s < kApTasks) L.apb[s] = e;
     }
     nap += __popcll(b1);
-    const uint64_t b2 = __ballot(an_cut);
+    const uint64_t b2 = ballot(an_cut);
     if (an_cut) {
-      const int s = nan_ + __popcll(b2 & lanes_below());
+      const int s = nan_ + lanes_before(b2);
       if (s < NS) L.anb[s] = e;
     }
     nan_ += __popcll(b2);
