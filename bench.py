@@ -48,6 +48,32 @@ def aperture_flops_per_source(p):
     return 60.0 * 8.0 * (p.r_ap + p.r_in + p.r_out)
 
 
+# HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE, scaled by a copy kernel of known size), keyed by kernel with
+# a hash of the sources they were measured on: reported only while the
+# sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stack16.json")
+
+
+def measured_traffic(kernel, workload):
+    import hashlib
+    if workload != "stack16" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE)).get(kernel)
+    if not t:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        path = os.path.join(ROOT, "paper_2502_10783_amd", "csrc", f)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    if h.hexdigest()[:16] != t["source_sha256_16"]:
+        return None
+    return {"read_bytes": t["read_bytes"], "write_bytes": t["write_bytes"],
+            "total_bytes": t["read_bytes"] + t["write_bytes"]}
+
+
 def roofline(kern, dom, npx, nsrc, p):
     """Roofline entry of the dominant kernel from its event-timed average
     launch duration and its algorithmic bytes or flops per launch."""
@@ -254,10 +280,14 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms_avg"])
     npx = sum(f.numel() for f in frames)
     roof = roofline(kern, dom, npx, nsrc, p)
+    roof["traffic"] = measured_traffic(dom, args.workload)
     # the largest per-pixel (HBM-bound) kernel, reported beside it
     hb = [k for k in kern if k in ALGO_BYTES_PER_PX]
-    roof_hbm = (roofline(kern, max(hb, key=lambda k: kern[k]["ms_avg"]),
-                         npx, nsrc, p) if hb else None)
+    roof_hbm = None
+    if hb:
+        hk = max(hb, key=lambda k: kern[k]["ms_avg"])
+        roof_hbm = roofline(kern, hk, npx, nsrc, p)
+        roof_hbm["traffic"] = measured_traffic(hk, args.workload)
 
     log("flux check against the oracle")
     rows = table.rows()
