@@ -132,13 +132,14 @@ def run_plain(ctx, frames, p, tables):
     return n
 
 
-def cpu_baseline(frame_cpu, params):
-    """The FP64 oracle on a 1024 x 1024 crop of one frame, one thread."""
+def cpu_baseline(frame_cpu, params, side=2048):
+    """The FP64 oracle on a side x side crop of one frame, one thread (about
+    10-20 s of CPU work)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     import oracle
     from oracle import background as obg, detect as odt, photometry as oph
-    crop = frame_cpu[:1024, :1024].numpy()
+    crop = frame_cpu[:side, :side].numpy()
     op = oracle.Params()
     with threadpool_limits(1):
         t0 = time.perf_counter()
@@ -152,7 +153,7 @@ def cpu_baseline(frame_cpu, params):
             "kind": "oracle",
             "sources_per_s": round(det["n"] / dt, 2),
             "seconds": round(dt, 2),
-            "sample": (f"one 1024x1024 crop of a 4096x4096 frame of the "
+            "sample": (f"one {side}x{side} crop of a 4096x4096 frame of the "
                        f"workload: background, detection and photometry of "
                        f"its {det['n']} sources, single thread")}
 
