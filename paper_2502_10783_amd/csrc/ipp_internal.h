@@ -73,7 +73,7 @@ struct Work {
   double* sc1;
   uint32_t* frame_flags; // per frame
   // detection
-  uint16_t* lmap;        // per pixel: record index within its tile + 1
+  uint8_t* tmap;         // per detection tile: its run map (kTmap*)
   int32_t* tile_rbase;   // per detection tile: first record
   Rec* recs;
   int32_t* rparent;      // union-find parent of each record
@@ -87,6 +87,16 @@ struct Work {
   int64_t* counters;     // [0] records used [1] record capacity
                          // [2] overflow bits [3] candidates found
 };
+
+// Run map of one detection tile (4096 pixels, 64 segments of 64 raster
+// pixels), kTmapBytes bytes per tile: detected bits, run-head bits, the
+// exclusive prefix of head counts per segment, and per run (raster order
+// of heads) its record index within the tile + 1 (0: not kept).
+constexpr int kTmapFg = 0;              // uint64_t[64]
+constexpr int kTmapHead = 512;          // uint64_t[64]
+constexpr int kTmapSeg = 1024;          // uint16_t[64]
+constexpr int kTmapRun = 1152;          // uint16_t[2048]
+constexpr int kTmapBytes = 1152 + 4096;
 
 // ---------------------------------------------------------------- helpers
 // Stores and loads through the global address space (the pointers come

@@ -405,21 +405,48 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     wk.rparent[rec] = (int32_t)rec;
     wk.rlabel[rec] = 0;
   }
-  // ---- local map: record index within the tile + 1 ----------------------
-#pragma unroll 4
-  for (int k = 0; k < PPT; ++k) {
-    const int q = t + kBlock * k;
-    const int r = q / TW, c = q % TW;
-    const int y = y0 + r, x = x0 + c;
-    if (y < fr.h && x < fr.w) {
-      uint16_t v = 0;
-      if ((fgm >> k) & 1u) {
-        const int rl = L.u.st.rloc[comp_of(q)];
-        if (rl >= 0 && rbase + rl < wk.rec_cap) v = (uint16_t)(rl + 1);
-      }
-      gst(wk.lmap + fr.pix0 + (int64_t)y * fr.w + x, v);
-    }
+  // ---- run map of the tile: detected / head bits, per-segment run offset,
+  // per run its record index + 1 --------------------------------------------
+  uint8_t* tm = wk.tmap + (size_t)tile * kTmapBytes;
+  if (t < 64) {
+    gst((uint64_t*)(tm + kTmapFg) + t, L.fgbits[t]);
+  } else if (t < 128) {
+    gst((uint64_t*)(tm + kTmapHead) + (t - 64), L.headbits[t - 64]);
   }
+  if (wv == 0) {                   // exclusive scan of the heads per segment
+    const int v = __popcll(L.headbits[lane]);
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(x, o, kWave);
+      if (lane >= o) x += u;
+    }
+    L.wcnt[lane] = x - v;
+    gst((uint16_t*)(tm + kTmapSeg) + lane, (uint16_t)(x - v));
+  }
+  __syncthreads();
+  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int) {
+    const int seg = q >> 6, b = q & 63;
+    const uint64_t before = b ? (L.headbits[seg] & (~0ull >> (64 - b))) : 0;
+    const int ri = L.wcnt[seg] + __popcll(before);
+    const int rl = L.u.st.rloc[-2 - L.parent[q]];
+    const uint16_t v =
+        (rl >= 0 && rbase + rl < wk.rec_cap) ? (uint16_t)(rl + 1) : 0;
+    gst((uint16_t*)(tm + kTmapRun) + ri, v);
+  });
+}
+
+// Record index within its tile + 1 of tile-local pixel q (0: background
+// or not kept), from the tile's run map.
+__device__ __forceinline__ int tmap_local(const uint8_t* tm, int q) {
+  const int seg = q >> 6, b = q & 63;
+  const uint64_t fg = gld((const uint64_t*)(tm + kTmapFg) + seg);
+  if (!((fg >> b) & 1ull)) return 0;
+  const uint64_t hd = gld((const uint64_t*)(tm + kTmapHead) + seg);
+  const uint64_t upto = b == 63 ? ~0ull : ((2ull << b) - 1);
+  const int ri = (int)gld((const uint16_t*)(tm + kTmapSeg) + seg) +
+                 __popcll(hd & upto) - 1;
+  return gld((const uint16_t*)(tm + kTmapRun) + ri);
 }
 
 // ---------------------------------------------------------------------
@@ -433,22 +460,28 @@ __global__ __launch_bounds__(kBlock) void k_border(Work wk, ipp_params p) {
   const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
   const int y0 = ty * TH, x0 = tx * TW;
   const bool c8 = p.connectivity == 8;
-  const uint16_t* lm = wk.lmap + fr.pix0;
+  auto tile_of = [&](int y, int x) {
+    return fr.dtile0 + (y / TH) * fr.dtx + (x / TW);
+  };
+  // record index + 1 within its tile of frame pixel (y, x), or 0
+  auto local_of = [&](int y, int x) {
+    const uint8_t* tm = wk.tmap + (size_t)tile_of(y, x) * kTmapBytes;
+    return tmap_local(tm, (y % TH) * TW + (x % TW));
+  };
   auto rec_of = [&](int y, int x, int l) {
-    const int tt = fr.dtile0 + (y / TH) * fr.dtx + (x / TW);
-    return wk.tile_rbase[tt] + l - 1;
+    return wk.tile_rbase[tile_of(y, x)] + l - 1;
   };
   const int t = threadIdx.x;
   if (t < TH) {                       // right border
     const int y = y0 + t, x = x0 + TW - 1;
     if (y < fr.h && x + 1 < fr.w) {
-      const int a = lm[(int64_t)y * fr.w + x];
+      const int a = local_of(y, x);
       if (a) {
         const int ra = rec_of(y, x, a);
         for (int dy = c8 ? -1 : 0; dy <= (c8 ? 1 : 0); ++dy) {
           const int yy = y + dy;
           if (yy < 0 || yy >= fr.h) continue;
-          const int b = lm[(int64_t)yy * fr.w + x + 1];
+          const int b = local_of(yy, x + 1);
           if (b) gunion(wk.rparent, ra, rec_of(yy, x + 1, b));
         }
       }
@@ -456,13 +489,13 @@ __global__ __launch_bounds__(kBlock) void k_border(Work wk, ipp_params p) {
   } else if (t < TH + TW) {           // bottom border
     const int y = y0 + TH - 1, x = x0 + (t - TH);
     if (x < fr.w && y + 1 < fr.h) {
-      const int a = lm[(int64_t)y * fr.w + x];
+      const int a = local_of(y, x);
       if (a) {
         const int ra = rec_of(y, x, a);
         for (int dx = c8 ? -1 : 0; dx <= (c8 ? 1 : 0); ++dx) {
           const int xx = x + dx;
           if (xx < 0 || xx >= fr.w) continue;
-          const int b = lm[(int64_t)(y + 1) * fr.w + xx];
+          const int b = local_of(y + 1, xx);
           if (b) gunion(wk.rparent, ra, rec_of(y + 1, xx, b));
         }
       }
@@ -629,50 +662,66 @@ __global__ __launch_bounds__(kBlock) void k_reclabel(Work wk) {
 
 template <int TH, int TW>
 __global__ __launch_bounds__(kBlock) void k_relabel(Work wk, ipp_params p) {
+  __shared__ uint64_t fgs[64], hds[64];
+  __shared__ int segs[64];
+  __shared__ int runlab[2048];         // label of every run of the tile
   const int tile = blockIdx.x;
   const int f = find_frame(wk.frames, wk.nframes, tile, &FrameDev::dtile0);
   const FrameDev fr = wk.frames[f];
   const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
   const int y0 = ty * TH, x0 = tx * TW;
   const int rb = wk.tile_rbase[tile];
-  auto label_of = [&](int l) -> int {
-    if (!l) return 0;
+  const uint8_t* tm = wk.tmap + (size_t)tile * kTmapBytes;
+  const int t = threadIdx.x;
+  if (t < 64) {
+    fgs[t] = gld((const uint64_t*)(tm + kTmapFg) + t);
+    hds[t] = gld((const uint64_t*)(tm + kTmapHead) + t);
+    segs[t] = gld((const uint16_t*)(tm + kTmapSeg) + t);
+  }
+  __syncthreads();
+  // every run's label first (one gather per run), then pixels from LDS
+  const uint16_t* runrec = (const uint16_t*)(tm + kTmapRun);
+  const int nruns = segs[63] + __popcll(hds[63]);
+  for (int r = t; r < nruns; r += kBlock) {
+    const int l = gld(runrec + r);
     const long long rec = (long long)rb + l - 1;
-    return rec < wk.rec_cap ? wk.rlabel[rec] : 0;
+    runlab[r] = (l && rec < wk.rec_cap) ? gld(wk.rlabel + rec) : 0;
+  }
+  __syncthreads();
+  // label of detected tile pixel q: that of its run
+  auto label_at = [&](int q) -> int {
+    const int seg = q >> 6, b = q & 63;
+    const uint64_t upto = b == 63 ? ~0ull : ((2ull << b) - 1);
+    return runlab[segs[seg] + __popcll(hds[seg] & upto) - 1];
   };
-  // whole tile inside the frame and 4-pixel groups aligned: ushort4 in,
-  // int4 out, all loads of the tile issued before the first gather
+  // whole tile inside the frame and 4-pixel groups aligned: int4 stores
   const bool vec = y0 + TH <= fr.h && x0 + TW <= fr.w && (fr.w & 3) == 0 &&
-                   (fr.pix0 & 3) == 0 && ((uintptr_t)fr.labels & 15) == 0;
+                   ((uintptr_t)fr.labels & 15) == 0;
   if (vec) {
-    constexpr int G = TH * TW / 4 / kBlock;     // groups per thread
-    ushort4 m[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int q = (threadIdx.x + kBlock * k) * 4;
+    for (int k = 0; k < TH * TW / 4 / kBlock; ++k) {
+      const int q = (t + kBlock * k) * 4;
       const int64_t o = (int64_t)(y0 + q / TW) * fr.w + x0 + q % TW;
-      m[k] = *(const ushort4*)(wk.lmap + fr.pix0 + o);
-    }
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int q = (threadIdx.x + kBlock * k) * 4;
-      const int64_t o = (int64_t)(y0 + q / TW) * fr.w + x0 + q % TW;
-      int4 out;
-      out.x = label_of(m[k].x);
-      out.y = label_of(m[k].y);
-      out.z = label_of(m[k].z);
-      out.w = label_of(m[k].w);
-      *(int4*)(fr.labels + o) = out;
+      const uint32_t d = (uint32_t)(fgs[q >> 6] >> (q & 63)) & 0xFu;
+      typedef int v4i __attribute__((ext_vector_type(4)));
+      v4i out = {0, 0, 0, 0};
+      if (d) {
+        if (d & 1u) out.x = label_at(q);
+        if (d & 2u) out.y = label_at(q + 1);
+        if (d & 4u) out.z = label_at(q + 2);
+        if (d & 8u) out.w = label_at(q + 3);
+      }
+      gst((v4i*)(fr.labels + o), out);
     }
     return;
   }
 #pragma unroll 4
   for (int k = 0; k < TH * TW / kBlock; ++k) {
-    const int q = threadIdx.x + kBlock * k;
+    const int q = t + kBlock * k;
     const int y = y0 + q / TW, x = x0 + q % TW;
     if (y < fr.h && x < fr.w) {
-      const int64_t o = (int64_t)y * fr.w + x;
-      fr.labels[o] = label_of(wk.lmap[fr.pix0 + o]);
+      const bool det = (fgs[q >> 6] >> (q & 63)) & 1ull;
+      gst(fr.labels + (int64_t)y * fr.w + x, det ? label_at(q) : 0);
     }
   }
 }
