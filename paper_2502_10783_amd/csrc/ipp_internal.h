@@ -109,6 +109,15 @@ template <typename T>
 __device__ __forceinline__ T gld(const T* a) {
   return *(const __attribute__((address_space(1))) T*)a;
 }
+// A wave-uniform pointer moved to scalar registers, so that loads can take
+// it as their scalar base.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t u = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
 
 __device__ __forceinline__ uint32_t f2key(float f) {
   uint32_t u = __float_as_uint(f);

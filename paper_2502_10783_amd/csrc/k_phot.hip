@@ -7,11 +7,13 @@
 // that lie wholly inside the aperture, and compacts the rest of the work
 // into its LDS slice: the aperture pixels cut by the circle, the annulus
 // values with their weights, and the annulus pixels cut by either circle.
-// The exact overlap areas (binary64, one asin per corner) are then
+// The exact overlap areas (binary64; one atan2 per circle and pixel) are then
 // computed over those dense task lists with every lane busy.  The annulus
 // (value, weight) pairs are sorted in registers with a bitonic network;
 // the k-sigma clipping of the sky works on contiguous ranges of the sorted
 // values and the weighted sky sum is a sum over the final range.
+#include <type_traits>
+
 #include "ipp_internal.h"
 #include "kernels.h"
 #include "phot_geom.h"
@@ -158,105 +160,131 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
 
   // ---- classify the window; compact the work -------------------------
-  uint32_t flags = 0;
+  // Per pixel: the exact membership predicates, the value I - B and a place
+  // in one of the compacted lists.  The count of pixels wholly inside the
+  // aperture and the off-edge flags are wave-uniform (ballots).
+  uint32_t flags = 0;                  // wave-uniform
+  int nfull = 0;                       // pixels wholly inside the aperture
   double a_ap = 0.0, raw = 0.0;
   int nann = 0, ntk = 0;
   // squared radii as the membership predicates form them
   const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
   const double ro2 = p.r_out * p.r_out;
-  int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;   // window row, col
   const int dwr = kWave / nwx, dwc = kWave - (kWave / nwx) * nwx;
-  // row base of the window's first in-frame row (wave-uniform); loads take
-  // 32-bit offsets from it (pitch <= 2^24, at most 35 rows)
+  // Row base of the window's first in-frame row (wave-uniform); loads take
+  // 32-bit byte offsets from it (pitch <= 2^24, at most 35 rows).
   const int ry0 = min(max(ya, 0), fr.h - 1);
-  const float* wpix = fr.pix + (int64_t)ry0 * fr.pitch;
-  const float* wbkg = fr.bkg + (int64_t)ry0 * fr.w;
-  const uint32_t pitch32 = (uint32_t)fr.pitch, w32 = (uint32_t)fr.w;
-  // Chunks of kChunk rounds of 64 pixels: all loads of a chunk are issued
-  // before any is used, so their latencies overlap.
-  constexpr int kChunk = 4;
-  for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
-    float Iv[kChunk], Bv[kChunk];
-    uint32_t st[kChunk];
-    int pos[kChunk];
+  const char* wpix =
+      uniform_ptr((const char*)(fr.pix + (int64_t)ry0 * fr.pitch));
+  const char* wbkg = uniform_ptr((const char*)(fr.bkg + (int64_t)ry0 * fr.w));
+  const uint32_t pitchB = (uint32_t)fr.pitch * 4u, wB = (uint32_t)fr.w * 4u;
+  // A window wholly inside the frame needs neither clamping nor an inside
+  // test: its offsets advance by constant steps.
+  const bool interior = xa >= 0 && ya >= 0 && xb < fr.w && yb < fr.h;
+
+  auto classify = [&](auto edge_tag) {
+    constexpr bool EDGE = decltype(edge_tag)::value;
+    int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;  // window row, col
+    uint32_t offp = (uint32_t)wr * pitchB + (uint32_t)(xa + wc) * 4u;
+    uint32_t offb = (uint32_t)wr * wB + (uint32_t)(xa + wc) * 4u;
+    const uint32_t stepP = (uint32_t)dwr * pitchB + (uint32_t)dwc * 4u;
+    const uint32_t stepB = (uint32_t)dwr * wB + (uint32_t)dwc * 4u;
+    const uint32_t wrapP = pitchB - (uint32_t)nwx * 4u;
+    const uint32_t wrapB = wB - (uint32_t)nwx * 4u;
+    // Chunks of kChunk rounds of 64 pixels: all loads of a chunk are issued
+    // before any is used, so their latencies overlap.
+    constexpr int kChunk = 4;
+    for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
+      float Iv[kChunk], Bv[kChunk];
+      uint32_t st[kChunk];
+      int pos[kChunk];
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
-      const int e = e0 + c * kWave + lane;
-      const int px = xa + wc, py = ya + wr;
-      pos[c] = (wr << 6) | wc;
-      wr += dwr; wc += dwc;
-      if (wc >= nwx) { wc -= nwx; ++wr; }
-      // nearest and farthest point of the pixel square (touches / within)
-      const double ax = fabs((double)px - cx), ay = fabs((double)py - cy);
-      const double nx = fmax(ax - 0.5, 0.0), ny = fmax(ay - 0.5, 0.0);
-      const double fx = ax + 0.5, fy = ay + 0.5;
-      const double near2 = nx * nx + ny * ny, far2 = fx * fx + fy * fy;
-      const bool live = e < npx;
-      const bool in_ap = live && near2 < ra2;
-      const bool in_ann = live && near2 < ro2 && !(far2 <= ri2);
-      const bool inside = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
-      // unconditional loads (clamped into the frame): no branches, so all
-      // of the chunk's loads are in flight together
-      const uint32_t qx = (uint32_t)min(max(px, 0), fr.w - 1);
-      const uint32_t qr = (uint32_t)(min(max(py, 0), fr.h - 1) - ry0);
-      Iv[c] = gld(wpix + (qr * pitch32 + qx));
-      Bv[c] = gld(wbkg + (qr * w32 + qx));
-      st[c] = (uint32_t)in_ap | ((uint32_t)in_ann << 1) |
-              ((uint32_t)inside << 2) | ((uint32_t)(far2 <= ra2) << 3) |
-              ((uint32_t)!(far2 <= ro2) << 4) | ((uint32_t)(near2 < ri2) << 5);
-    }
-#pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
-      const bool in_ap = st[c] & 1u, in_ann = st[c] & 2u;
-      bool ap_cut = false, ann = false, ann_cut = false;
-      double v = 0.0;
-      if (in_ap || in_ann) {
-        const bool ok = (st[c] & 4u) && isfinite(Iv[c]);
-        v = (double)Iv[c] - (double)Bv[c];
-        if (!ok) {
-          if (in_ap) flags |= IPP_SRC_APERTURE_OFF_EDGE;
-          if (in_ann) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
+      for (int c = 0; c < kChunk; ++c) {
+        if (e0 + c * kWave >= npx) break;            // wave-uniform
+        const int e = e0 + c * kWave + lane;
+        const int px = xa + wc, py = ya + wr;
+        const bool live = e < npx;
+        pos[c] = (wr << 6) | wc;
+        // nearest and farthest point of the pixel square (touches / within)
+        const double ax = fabs((double)px - cx), ay = fabs((double)py - cy);
+        const double nx = fmax(ax - 0.5, 0.0), ny = fmax(ay - 0.5, 0.0);
+        const double fx = ax + 0.5, fy = ay + 0.5;
+        const double near2 = nx * nx + ny * ny, far2 = fx * fx + fy * fy;
+        // (bitwise logic: no branches)
+        const bool in_ap = live & (near2 < ra2);
+        const bool in_ann = live & (near2 < ro2) & !(far2 <= ri2);
+        bool inside = true;
+        if constexpr (EDGE) {
+          // loads clamped into the frame: every lane loads, no branches
+          inside = (px >= 0) & (px < fr.w) & (py >= 0) & (py < fr.h);
+          const uint32_t qx = (uint32_t)min(max(px, 0), fr.w - 1);
+          const uint32_t qr = (uint32_t)(min(max(py, 0), fr.h - 1) - ry0);
+          Iv[c] = gld((const float*)(wpix + (qr * pitchB + qx * 4u)));
+          Bv[c] = gld((const float*)(wbkg + (qr * wB + qx * 4u)));
         } else {
-          if (in_ap) {
-            if (st[c] & 8u) {
-              a_ap += 1.0;
-              raw += v;
-            } else {
-              ap_cut = true;
-            }
-          }
-          if (in_ann) {
-            ann = true;
-            ann_cut = st[c] & 48u;
-          }
+          // a lane past the window end loads the window's first pixel
+          Iv[c] = gld((const float*)(wpix + (live ? offp : 0u)));
+          Bv[c] = gld((const float*)(wbkg + (live ? offb : 0u)));
+        }
+        st[c] = (uint32_t)in_ap | ((uint32_t)in_ann << 1) |
+                ((uint32_t)inside << 2) | ((uint32_t)(far2 <= ra2) << 3) |
+                ((uint32_t)!(far2 <= ro2) << 4) |
+                ((uint32_t)(near2 < ri2) << 5);
+        wr += dwr;
+        wc += dwc;
+        offp += stepP;
+        offb += stepB;
+        if (wc >= nwx) {
+          wc -= nwx;
+          ++wr;
+          offp += wrapP;
+          offb += wrapB;
         }
       }
-      const uint64_t b1 = ballot(ap_cut);
-      if (ap_cut) {
-        const int s = ntk + lanes_before(b1);
-        if (s < NS + kApTasks) L.tk[s] = pos[c];
-      }
-      ntk += __popcll(b1);
-      const uint64_t b2 = ballot(ann);
-      int slot = 0;
-      if (ann) {
-        slot = nann + lanes_before(b2);
-        if (slot < NS) {
-          L.pv[slot] = v;
-          L.pw[slot] = 1.0;
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (e0 + c * kWave >= npx) break;            // wave-uniform
+        const bool in_ap = st[c] & 1u, in_ann = st[c] & 2u;
+        const bool ok = ((st[c] & 4u) != 0) & isfinite(Iv[c]);
+        const double v = (double)Iv[c] - (double)Bv[c];
+        if (ballot(in_ap & !ok)) flags |= IPP_SRC_APERTURE_OFF_EDGE;
+        if (ballot(in_ann & !ok)) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
+        const bool whole = (st[c] & 8u) != 0;
+        const bool full = in_ap & ok & whole;
+        const bool ap_cut = in_ap & ok & !whole;
+        const bool ann = in_ann & ok;
+        const bool ann_cut = ann & ((st[c] & 48u) != 0);
+        nfull += __popcll(ballot(full));
+        if (full) raw += v;
+        const uint64_t b1 = ballot(ap_cut);
+        if (ap_cut) {
+          const int s = ntk + lanes_before(b1);
+          if (s < NS + kApTasks) L.tk[s] = pos[c];
         }
+        ntk += __popcll(b1);
+        const uint64_t b2 = ballot(ann);
+        int slot = 0;
+        if (ann) {
+          slot = nann + lanes_before(b2);
+          if (slot < NS) {
+            L.pv[slot] = v;
+            L.pw[slot] = 1.0;
+          }
+        }
+        nann += __popcll(b2);
+        const uint64_t b3 = ballot(ann_cut);
+        if (ann_cut) {
+          const int s = ntk + lanes_before(b3);
+          const int kind = (int)((st[c] >> 4) & 3u);
+          if (s < NS + kApTasks && slot < NS)
+            L.tk[s] = (kind << 28) | (slot << 12) | pos[c];
+        }
+        ntk += __popcll(b3);
       }
-      nann += __popcll(b2);
-      const uint64_t b3 = ballot(ann_cut);
-      if (ann_cut) {
-        const int s = ntk + lanes_before(b3);
-        const int kind = (int)((st[c] >> 4) & 3u);
-        if (s < NS + kApTasks && slot < NS)
-          L.tk[s] = (kind << 28) | (slot << 12) | pos[c];
-      }
-      ntk += __popcll(b3);
     }
-  }
+  };
+  if (interior) classify(std::false_type{});
+  else classify(std::true_type{});
   if (nann > NS) nann = NS;            // not reachable: NS bounds the ring
   if (ntk > NS + kApTasks) ntk = NS + kApTasks;  // not reachable either
   wave_lds_sync();
@@ -267,24 +295,24 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   {
     const double r2a = p.r_ap * p.r_ap, r2o = p.r_out * p.r_out;
     const double r2i = p.r_in * p.r_in;
-    const double ia = 1.0 / r2a, io = 1.0 / r2o, ii = 1.0 / r2i;
     for (int j = lane; j < ntk; j += kWave) {
       const int t = L.tk[j];
       const int kind = t >> 28, slot = (t >> 12) & 0x3FF;
       const int px = xa + (t & 63), py = ya + ((t >> 6) & 63);
       const double r = kind == 0 ? p.r_ap : (kind == 2 ? p.r_in : p.r_out);
       const double r2 = kind == 0 ? r2a : (kind == 2 ? r2i : r2o);
-      const double ir2 = kind == 0 ? ia : (kind == 2 ? ii : io);
-      double w = overlap_pre(cx, cy, r, r2, ir2, px, py);
+      double w = overlap_pre(cx, cy, r, r2, px, py);
       const uint32_t qr = (uint32_t)(py - ry0);
-      const float I = gld(wpix + (qr * pitch32 + (uint32_t)px));
+      const float I =
+          gld((const float*)(wpix + (qr * pitchB + (uint32_t)px * 4u)));
       const double v =
-          (double)I - (double)gld(wbkg + (qr * w32 + (uint32_t)px));
+          (double)I -
+          (double)gld((const float*)(wbkg + (qr * wB + (uint32_t)px * 4u)));
       if (kind == 0) {
         a_ap += w;
         raw += w * v;
       } else {
-        if (kind == 3) w -= overlap_pre(cx, cy, p.r_in, r2i, ii, px, py);
+        if (kind == 3) w -= overlap_pre(cx, cy, p.r_in, r2i, px, py);
         else if (kind == 2) w = 1.0 - w;
         L.pw[slot] = w;
       }
@@ -365,9 +393,8 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   }
   num = wave_sum(num);
   den = wave_sum(den);
-  a_ap = wave_sum(a_ap);
+  a_ap = (double)nfull + wave_sum(a_ap);
   raw = wave_sum(raw);
-  for (int o = kWave / 2; o > 0; o >>= 1) flags |= __shfl_xor(flags, o, kWave);
   if (lane == 0) {
     double sky = 0.0;
     if (den > 0.0) sky = num / den; else flags |= IPP_SRC_NO_SKY;
@@ -385,7 +412,9 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
 
 // NS: sort size (>= the annulus pixel count bound).
 template <int NS>
-__global__ __launch_bounds__(kBlock) void k_aperture_t(Work wk, ipp_params p,
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_aperture_t(
+    Work wk, ipp_params p,
                                                        ipp_sources src,
                                                        double* sky_lohi) {
   __shared__ ApLds<NS> L[kWaves];

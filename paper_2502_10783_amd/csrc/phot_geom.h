@@ -5,8 +5,10 @@
 // 0 <= x, y <= r it is x*y when the corner lies in the circle and otherwise
 // y*xs + P(x) - P(xs) with xs = sqrt(r^2 - y^2) and
 // P(s) = int_0^s sqrt(r^2 - u^2) du = (s sqrt(r^2 - s^2) + r^2 asin(s/r))/2
-// (evaluated with one asin, see corner_g).
-// A pixel's overlap is the inclusion-exclusion of G over its corners.
+// (its angle term evaluated with atan2, see corner_g).
+// A pixel's overlap is the inclusion-exclusion of G over its corners; for
+// r >= 3/4 the four angle terms are summed as one rotation and recovered by
+// a single atan2 (see corner_rot).
 // Membership (the pixel square meets the open disk) and full containment
 // are decided by the exact predicates below, so that every pixel that a
 // rounding residue could move in or out is classified the same way on
@@ -35,25 +37,53 @@ __device__ __forceinline__ bool within(double cx, double cy, double r,
 // G for a corner (x, y) outside the circle, 0 <= x, y <= r, with
 // xs = sqrt(r^2 - y^2) and hx = sqrt(r^2 - x^2):
 //   G = y xs + P(x) - P(xs)
-//     = (y xs + x hx + r^2 (asin(x/r) - asin(xs/r))) / 2
-// and, as cos(asin(xs/r)) = y/r and cos(asin(x/r)) = hx/r, the angle
-// difference is asin((x y - xs hx) / r^2): one asin per corner.  The two
-// square roots depend on one coordinate each, so a pixel needs four.
+//     = (y xs + x hx + r^2 (asin(x/r) - asin(xs/r))) / 2.
+// With a = asin(x/r) and b = asin(y/r) the angle asin(x/r) - asin(xs/r) is
+// a + b - pi/2, whose direction (cos, sin) is proportional to
+// (hx y + x xs, x y - xs hx): the cosine is a sum of non-negative products,
+// so atan2 of the pair is accurate up to the right angle, where asin of the
+// sine alone would lose half its digits.  The two square roots depend on
+// one coordinate each, so a pixel needs four.
 __device__ __forceinline__ double corner_g(double ax, double ay, double hx,
-                                           double xs, double r2,
-                                           double inv_r2) {
+                                           double xs, double r2) {
   if (ax * ax + ay * ay <= r2) return ax * ay;
-  const double arg = fmin((ax * ay - xs * hx) * inv_r2, 1.0);
-  return 0.5 * ((ay * xs + ax * hx) + r2 * asin(arg));
+  const double c = hx * ay + ax * xs;
+  const double s = ax * ay - xs * hx;
+  return 0.5 * ((ay * xs + ax * hx) + r2 * atan2(s, c));
+}
+
+// The same corner as a rotation: corner_rot adds the corner's non-angular
+// part to lin and turns (re, im) by the corner's signed angle; a corner in
+// the circle has no angle term.  After all four corners the summed angle is
+// the arc of the circle that lies inside the pixel, and lin plus r^2/2 times
+// that angle is the overlap.  The factors are left unnormalised (length
+// r^2 each); atan2 does not depend on the length.
+__device__ __forceinline__ void corner_rot(double ax, double ay, double hx,
+                                           double xs, double sig, double r2,
+                                           double& lin, double& re,
+                                           double& im) {
+  const bool out = ax * ax + ay * ay > r2;
+  const double c = hx * ay + ax * xs;
+  const double s = sig * (ax * ay - xs * hx);
+  lin = fma(sig, out ? 0.5 * (ay * xs + ax * hx) : ax * ay, lin);
+  const double cc = out ? c : 1.0, ss = out ? s : 0.0;
+  const double nre = re * cc - im * ss;
+  im = fma(re, ss, im * cc);
+  re = nre;
 }
 
 // Overlap of the pixel square [px-1/2, px+1/2] x [py-1/2, py+1/2] with the
 // disk of radius r about (cx, cy): inclusion-exclusion of G over the
 // square's corners.
-// r2 = r * r and inv_r2 = 1 / r2, passed in so a caller can precompute them.
+// r2 = r * r, passed in so that a caller can precompute it.
+// The arc of a circle inside a unit square is below half the circle once
+// 2r exceeds the square's diagonal (an arc of half the circle or more holds
+// two antipodal points), so for r >= 3/4 the summed corner angle lies in
+// [0, pi) and one atan2 of the composed rotation returns it; smaller
+// circles, whose arc inside one pixel can reach the whole circle, take one
+// atan2 per corner.
 __device__ __forceinline__ double overlap_pre(double cx, double cy, double r,
-                                              double r2, double inv_r2,
-                                              int px, int py) {
+                                              double r2, int px, int py) {
   if (!touches(cx, cy, r, px, py)) return 0.0;
   if (within(cx, cy, r, px, py)) return 1.0;
   const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
@@ -66,16 +96,23 @@ __device__ __forceinline__ double overlap_pre(double cx, double cy, double r,
   const double xs1 = sqrt(fmax(r2 - ay1 * ay1, 0.0));
   const double sx0 = x0 < 0.0 ? -1.0 : 1.0, sx1 = x1 < 0.0 ? -1.0 : 1.0;
   const double sy0 = y0 < 0.0 ? -1.0 : 1.0, sy1 = y1 < 0.0 ? -1.0 : 1.0;
-  return sx1 * sy1 * corner_g(ax1, ay1, hx1, xs1, r2, inv_r2) -
-         sx0 * sy1 * corner_g(ax0, ay1, hx0, xs1, r2, inv_r2) -
-         sx1 * sy0 * corner_g(ax1, ay0, hx1, xs0, r2, inv_r2) +
-         sx0 * sy0 * corner_g(ax0, ay0, hx0, xs0, r2, inv_r2);
+  if (r >= 0.75) {
+    double lin = 0.0, re = 1.0, im = 0.0;
+    corner_rot(ax1, ay1, hx1, xs1, sx1 * sy1, r2, lin, re, im);
+    corner_rot(ax0, ay1, hx0, xs1, -(sx0 * sy1), r2, lin, re, im);
+    corner_rot(ax1, ay0, hx1, xs0, -(sx1 * sy0), r2, lin, re, im);
+    corner_rot(ax0, ay0, hx0, xs0, sx0 * sy0, r2, lin, re, im);
+    return fma(0.5 * r2, atan2(im, re), lin);
+  }
+  return sx1 * sy1 * corner_g(ax1, ay1, hx1, xs1, r2) -
+         sx0 * sy1 * corner_g(ax0, ay1, hx0, xs1, r2) -
+         sx1 * sy0 * corner_g(ax1, ay0, hx1, xs0, r2) +
+         sx0 * sy0 * corner_g(ax0, ay0, hx0, xs0, r2);
 }
 
 __device__ __forceinline__ double overlap(double cx, double cy, double r,
                                           int px, int py) {
-  const double r2 = r * r;
-  return overlap_pre(cx, cy, r, r2, 1.0 / r2, px, py);
+  return overlap_pre(cx, cy, r, r * r, px, py);
 }
 
 __device__ __forceinline__ double chord(double x, double y, double r) {
