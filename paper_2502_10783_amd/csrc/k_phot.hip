@@ -31,7 +31,12 @@ struct ApLds {
   // exact-overlap tasks: kind << 28 | annulus slot << 12 | wy << 6 | wx
   // (kind 0: cut by the aperture; 1: cut by the outer circle only; 2: by
   // the inner circle only; 3: by both)
-  int tk[NS + kApTasks];
+  // the task list is consumed before the annulus values are sorted; the
+  // sort's transposes and the sorted values then use the same space
+  union {
+    int tk[NS + kApTasks];
+    double xs[NS + kWave];
+  };
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -41,92 +46,154 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 
-// Value of lane (lane ^ LM): DPP moves inside rows of 16 lanes for LM of
-// 1, 2, 4 and 8 (no LDS round trip), the LDS permute beyond.
-template <int LM>
-__device__ __forceinline__ double xor_lane(double v) {
-  if (LM == 1) return dpp_mov<0xB1>(v);          // quad_perm [1,0,3,2]
-  if (LM == 2) return dpp_mov<0x4E>(v);          // quad_perm [2,3,0,1]
-  if (LM == 3) return dpp_mov<0x1B>(v);          // quad_perm [3,2,1,0]
-  if (LM == 7) return dpp_mov<0x141>(v);         // row_half_mirror
-  if (LM == 15) return dpp_mov<0x140>(v);        // row_mirror
-  if (LM == 8) return dpp_mov<0x128>(v);         // row_ror:8
-  if (LM == 4) {
-    const double up = dpp_mov<0x104>(v);         // row_shl:4 (lane + 4)
-    const double dn = dpp_mov<0x114>(v);         // row_shr:4 (lane - 4)
-    return (threadIdx.x & 4) ? dn : up;
+// ---- bitonic sort of the annulus values -------------------------------
+// NS = 2^(P+6) binary64 values, 2^P per lane.  In layout S a lane's
+// registers hold the elements whose index bits [S, S+P) give the register
+// number, and the lane number supplies the other six bits (layout 0:
+// e = lane * 2^P + k).  Every compare-exchange of the network is then
+// between two registers of one lane; the network changes layout through
+// LDS, one write and one read per register.  Blocks that the network sorts
+// in descending order are negated for the length of their merge, so that
+// every compare-exchange is ascending.
+
+// v_min_f64 / v_max_f64 as single instructions: the values are never NaN,
+// so the canonicalising moves the compiler adds around fmin/fmax are not
+// needed.
+__device__ __forceinline__ double min64(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double max64(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Element index of register 0 of this lane in layout S.
+template <int P, int S>
+__device__ __forceinline__ int lay_base(int lane) {
+  return (lane & ((1 << S) - 1)) | ((lane >> S) << (S + P));
+}
+
+// LDS address of element e in a transpose from layout A to layout B:
+// e + MUL * (e >> Q).  The element index is a disjoint sum of a lane part
+// and a register part, so the address is a per-lane base plus a constant
+// per register (an instruction offset).  Q and MUL are chosen so that the
+// 32 lanes of a half-wave meet 32 different 8-byte bank slots on both
+// sides of every transpose the network uses (at worst two lanes share
+// one); every address is below NS + 64.
+template <int P, int A, int B>
+struct SortPad {
+  static constexpr int S = A + B;          // the other layout, if one is 0
+  static constexpr bool Z = A == 0 || B == 0;
+  static constexpr int Q =
+      Z ? (S <= P ? P : (S >= 5 ? 5 : (P == 2 && S == 3 ? 3 : 6)))
+        : (B == 1 ? P + 1 : (P == 2 && B == 3 ? 4 : 5));
+  static constexpr int MUL = Z ? 1 : 2;
+  static __device__ __forceinline__ int at(int e) { return e + MUL * (e >> Q); }
+};
+
+template <int P, int A, int B>
+__device__ __forceinline__ void relayout(double (&v)[1 << P], double* xs,
+                                         int lane) {
+  using Pad = SortPad<P, A, B>;
+  const int wb = Pad::at(lay_base<P, A>(lane));
+  const int rb = Pad::at(lay_base<P, B>(lane));
+#pragma unroll
+  for (int k = 0; k < (1 << P); ++k) xs[wb + Pad::at(k << A)] = v[k];
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < (1 << P); ++k) v[k] = xs[rb + Pad::at(k << B)];
+  wave_lds_sync();
+}
+
+// Negate the elements whose index bit M is set (layout S).
+template <int P, int M, int S>
+__device__ __forceinline__ void negate_bit(double (&v)[1 << P], int lane) {
+  if constexpr (M >= S && M < S + P) {
+#pragma unroll
+    for (int k = 0; k < (1 << P); ++k)
+      if (k & (1 << (M - S))) v[k] = -v[k];
+  } else {
+    constexpr int LB = M < S ? M : M - P;   // the lane bit holding bit M
+    const int sg = ((lane >> LB) & 1) << 31;
+#pragma unroll
+    for (int k = 0; k < (1 << P); ++k)
+      v[k] = __hiloint2double(__double2hiint(v[k]) ^ sg, __double2loint(v[k]));
   }
-  return __shfl_xor(v, LM, kWave);
 }
 
-// Ascending compare-exchange of every element with the element at lane ^
-// LM, register k (FLIP: register PL - 1 - k); the lower lane keeps the
-// minimum.
-template <int PL, int LM, bool FLIP>
-__device__ __forceinline__ void exch_lanes(double (&v)[PL], bool lower) {
-  double o[PL];
+// Ascending compare-exchange of registers k and k + 2^B (bit B of k clear).
+template <int P, int B>
+__device__ __forceinline__ void cx_regs(double (&v)[1 << P]) {
 #pragma unroll
-  for (int k = 0; k < PL; ++k) o[k] = xor_lane<LM>(v[FLIP ? PL - 1 - k : k]);
-#pragma unroll
-  for (int k = 0; k < PL; ++k)
-    v[k] = lower ? fmin(v[k], o[k]) : fmax(v[k], o[k]);
-}
-
-// Ascending compare-exchange of registers k and k ^ D inside each lane.
-template <int PL, int D>
-__device__ __forceinline__ void exch_regs(double (&v)[PL]) {
-#pragma unroll
-  for (int k = 0; k < PL; ++k) {
-    const int l = k ^ D;
-    if (l > k) {
+  for (int k = 0; k < (1 << P); ++k) {
+    if (!(k & (1 << B))) {
+      const int l = k | (1 << B);
       const double a = v[k], b = v[l];
-      v[k] = fmin(a, b);
-      v[l] = fmax(a, b);
+      v[k] = min64(a, b);
+      v[l] = max64(a, b);
     }
   }
 }
 
-// Half-cleaners J, J/2, .., 1 of a bitonic merge.
-template <int PL, int J>
-__device__ __forceinline__ void half_cleaners(double (&v)[PL], int lane) {
-  if constexpr (J >= 1) {
-    if constexpr (J < PL) exch_regs<PL, J>(v);
-    else exch_lanes<PL, J / PL, false>(v, (lane & (J / PL)) == 0);
-    half_cleaners<PL, J / 2>(v, lane);
+template <int P, int M, int S>
+__device__ __forceinline__ void bitonic_merge_from(double (&v)[1 << P],
+                                                   double* xs, int lane);
+
+// Stages J, J-1, .., 0 of the merge of blocks of 2^M elements, entered in
+// layout S; a stage on bit J outside the layout's register bits first
+// moves to the layout whose register bits end at J.
+template <int P, int M, int J, int S>
+__device__ __forceinline__ void bitonic_stages(double (&v)[1 << P],
+                                               double* xs, int lane) {
+  constexpr int N = P + 6;
+  if constexpr (J < 0) {
+    if constexpr (M < N) negate_bit<P, M, S>(v, lane);
+    bitonic_merge_from<P, M + 1, S>(v, xs, lane);
+  } else if constexpr (J >= S && J < S + P) {
+    cx_regs<P, J - S>(v);
+    bitonic_stages<P, M, J - 1, S>(v, xs, lane);
+  } else {
+    constexpr int S2 = J - P + 1 > 0 ? J - P + 1 : 0;
+    relayout<P, S, S2>(v, xs, lane);
+    cx_regs<P, J - S2>(v);
+    bitonic_stages<P, M, J - 1, S2>(v, xs, lane);
   }
 }
 
-// Merges of block sizes KK, 2 KK, .., NS: each starts with a flip (e
-// against e ^ (KK - 1)), so that every compare-exchange is ascending.
-template <int PL, int NS, int KK>
-__device__ __forceinline__ void bitonic_merges(double (&v)[PL], int lane) {
-  if constexpr (KK <= NS) {
-    if constexpr (KK <= PL) exch_regs<PL, KK - 1>(v);
-    else exch_lanes<PL, KK / PL - 1, true>(v, (lane & (KK / 2 / PL)) == 0);
-    half_cleaners<PL, KK / 4>(v, lane);
-    bitonic_merges<PL, NS, KK * 2>(v, lane);
+template <int P, int M, int S>
+__device__ __forceinline__ void bitonic_merge_from(double (&v)[1 << P],
+                                                   double* xs, int lane) {
+  constexpr int N = P + 6;
+  if constexpr (M <= N) {
+    // blocks with bit M set are sorted descending (the last merge, M = N,
+    // sorts the whole array ascending)
+    if constexpr (M < N) negate_bit<P, M, S>(v, lane);
+    bitonic_stages<P, M, M - 1, S>(v, xs, lane);
+  } else {
+    static_assert(S == 0, "the network ends in layout 0");
   }
 }
 
-// Bitonic sort (ascending) of NS binary64 values held as v[NS/64] per
-// lane, element index e = lane * (NS/64) + k.
-template <int NS>
-__device__ __forceinline__ void wave_bitonic(double (&v)[NS / kWave]) {
-  bitonic_merges<NS / kWave, NS, 2>(v, threadIdx.x & (kWave - 1));
-}
-
-// Element e (wave-uniform) of a sorted register array.
-template <int PL>
-__device__ __forceinline__ double sorted_at(const double (&v)[PL], int e) {
-  const int ln = e / PL, k = e - (e / PL) * PL;
-  double x = v[0];
+// Ascending sort of v (layout 0); the sorted array is also left in xs at
+// sorted_addr(e), for wave-uniform reads.
+template <int P>
+__device__ __forceinline__ void wave_sort(double (&v)[1 << P], double* xs,
+                                          int lane) {
+  bitonic_merge_from<P, 1, 0>(v, xs, lane);
 #pragma unroll
-  for (int i = 1; i < PL; ++i)
-    if (i == k) x = v[i];
-  const uint64_t u = __double_as_longlong(x);
-  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, ln);
-  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), ln);
-  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  for (int k = 0; k < (1 << P); ++k) {
+    const int e = (lane << P) | k;
+    xs[e + (e >> P)] = v[k];
+  }
+  wave_lds_sync();
+}
+
+template <int P>
+__device__ __forceinline__ double sorted_at(const double* xs, int e) {
+  return xs[e + (e >> P)];
 }
 
 template <int NS>
@@ -134,6 +201,8 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
                              ipp_sources& src, double* sky_lohi,
                              long long row, ApLds<NS>& L) {
   constexpr int PL = NS / kWave;
+  constexpr int P = PL == 4 ? 2 : (PL == 8 ? 3 : 4);
+  static_assert((1 << P) == PL, "NS is 256, 512 or 1024");
   const int lane = threadIdx.x & (kWave - 1);
   const int f = src.frame[row];
   const double cx = src.x[row], cy = src.y[row];
@@ -327,14 +396,14 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     const int e = lane * PL + k;
     sv[k] = e < nann ? L.pv[e] : __builtin_inf();
   }
-  wave_bitonic<NS>(sv);
+  wave_sort<P>(sv, L.xs, lane);
 
   // ---- k-sigma clipping on the sorted range [a, bnd) ---------------------
   // Running sums of (v - c) and (v - c)^2 over the range, c a fixed shift
   // (the first median); each pass removes a prefix and a suffix of the
   // range, whose sizes are ballot counts over the sorted values (the +inf
   // padding counts as above every bound).
-  const double c0 = nann > 0 ? sorted_at<PL>(sv, (nann - 1) / 2) : 0.0;
+  const double c0 = nann > 0 ? sorted_at<P>(L.xs, (nann - 1) / 2) : 0.0;
   double S1 = 0.0, S2 = 0.0;
 #pragma unroll
   for (int k = 0; k < PL; ++k) {
@@ -350,9 +419,9 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     const int n = bnd - a;
     if (n == 0) break;
     const double med =
-        (n & 1) ? sorted_at<PL>(sv, a + (n - 1) / 2)
-                : (sorted_at<PL>(sv, a + n / 2 - 1) +
-                   sorted_at<PL>(sv, a + n / 2)) / 2.0;
+        (n & 1) ? sorted_at<P>(L.xs, a + (n - 1) / 2)
+                : (sorted_at<P>(L.xs, a + n / 2 - 1) +
+                   sorted_at<P>(L.xs, a + n / 2)) / 2.0;
     const double dm = S1 / (double)n;
     const double var = S2 / (double)n - dm * dm;
     const double sd = sqrt(var > 0.0 ? var : 0.0);
@@ -382,7 +451,7 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   }
   // the survivors are the values in [vlo, vhi] (clipping is by value)
   double vlo = 0.0, vhi = -1.0;
-  if (bnd > a) { vlo = sorted_at<PL>(sv, a); vhi = sorted_at<PL>(sv, bnd - 1); }
+  if (bnd > a) { vlo = sorted_at<P>(L.xs, a); vhi = sorted_at<P>(L.xs, bnd - 1); }
   double num = 0.0, den = 0.0;
   for (int j = lane; j < nann; j += kWave) {
     const double v = L.pv[j], w = L.pw[j];

@@ -1,0 +1,95 @@
+"""GPU parity of aperture photometry over the radius range the ABI accepts.
+
+The kernel evaluates a pixel's overlap with one atan2 of the composed corner
+rotations for r >= 3/4 and with one atan2 per corner below that, sizes its
+annulus sort by the ring bound (256, 512 or 1024 slots) and loads windows
+inside the frame from a scalar base and windows over an edge with clamped
+loads.  Each radius set below drives a different combination; the centres
+include integer and half-integer positions, where the circle passes through
+pixel corners, and positions near and past the frame edges.
+
+Bars as in the other photometry tests: fluxes <= 1e-5 of the flux's
+condition scale, aperture areas to 1e-12 relative, flags exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import photometry as oph
+from synth import make_frame
+
+import paper_2502_10783_amd as ipp
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+# (r_ap, r_in, r_out)
+RADII = [
+    (0.3, 0.0, 0.6),        # every circle below 3/4; r_in = 0
+    (0.74, 0.75, 0.76),     # both sides of the 3/4 switch
+    (1.0, 2.0, 3.5),
+    (5.0, 8.0, 12.0),       # the default (512-slot sort)
+    (16.0, 3.0, 6.0),       # widest aperture, 256-slot sort
+    (2.5, 0.0, 16.0),       # full disk as annulus: 1024-slot sort
+]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ipp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def scene():
+    img, _, _ = make_frame("single", 4, scale=0.125)          # 128 x 128
+    img = img.contiguous()
+    rng = np.random.default_rng(11)
+    h, w = img.shape
+    # a smooth stand-in background, so that values are I - B as in use
+    yy, xx = np.mgrid[0:h, 0:w]
+    bkg = (np.float32(100.0) + np.float32(0.01) * xx.astype(np.float32)
+           - np.float32(0.02) * yy.astype(np.float32)).astype(np.float32)
+    xs = list(rng.uniform(20.0, w - 21.0, 14))
+    ys = list(rng.uniform(20.0, h - 21.0, 14))
+    # corners and centres of pixels, near and past the frame edges
+    special = [(40.0, 50.0), (40.5, 50.5), (63.5, 64.0), (0.2, 60.3),
+               (w - 1.3, 5.0), (3.0, h - 0.6), (-0.4, 30.0), (70.0, h + 0.3)]
+    xs += [p[0] for p in special]
+    ys += [p[1] for p in special]
+    return img, torch.from_numpy(bkg), np.array(xs), np.array(ys)
+
+
+def _flux_scale(ph):
+    raw = ph["flux"] + ph["sky"] * ph["area_ap"]
+    return np.abs(raw) + ph["area_ap"] * np.abs(ph["sky"]) + 1e-30
+
+
+@pytest.mark.parametrize("radii", RADII, ids=lambda r: "%g-%g-%g" % r)
+def test_photometry_radii(ctx, scene, radii):
+    img, bkg, xs, ys = scene
+    r_ap, r_in, r_out = radii
+    p = ipp.Params(r_ap=r_ap, r_in=r_in, r_out=r_out)
+    op = oracle.Params(r_ap=r_ap, r_in=r_in, r_out=r_out)
+    k = xs.size
+    table = ipp.SourceTable(k, 1, DEV)
+    table.cols["frame"][:k] = 0
+    table.cols["x"][:k] = torch.from_numpy(xs).to(DEV)
+    table.cols["y"][:k] = torch.from_numpy(ys).to(DEV)
+    ctx.photometry([img.to(DEV)], [bkg.to(DEV)], table, p, use_count=False)
+    torch.cuda.synchronize()
+    got = {c: table.cols[c][:k].cpu().numpy()
+           for c in ("flux_ap", "sky", "area_ap", "area_ann", "flags")}
+    ph = oph.photometry(img.numpy(), bkg.numpy(), xs, ys, op)
+    assert np.array_equal(got["flags"], ph["flags"].astype(np.int32))
+    ok = np.isfinite(ph["flux"])
+    assert np.array_equal(np.isfinite(got["flux_ap"]), ok)
+    np.testing.assert_allclose(got["area_ap"], ph["area_ap"], rtol=1e-12,
+                               atol=1e-13)
+    np.testing.assert_allclose(got["area_ann"], ph["area_ann"], rtol=1e-9,
+                               atol=1e-12)
+    err = np.abs(got["flux_ap"][ok] - ph["flux"][ok]) / _flux_scale(ph)[ok]
+    assert err.max() <= 1e-5, err.max()
