@@ -184,18 +184,39 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
   const int y0 = ty * TH, x0 = tx * TW;
 
+  // Pixel q = t + 256 k of the tile lies in tile column c = t % TW for
+  // every k (TW divides 256) and in tile row t / TW + (256 / TW) k.  A wave
+  // instruction covers one row (TW >= 64) or two (TW = 32): the row of the
+  // wave's first lane is wave-uniform, so loads and stores take a scalar
+  // row pointer and a per-lane 32-bit byte offset fixed for the whole loop.
+  constexpr int RSTEP = kBlock / TW;
+  const int c = t % TW;
+  const int rw = __builtin_amdgcn_readfirstlane((wv * kWave) / TW);
+  const int dr = (wv * kWave + lane) / TW - (wv * kWave) / TW;  // 0 or 1
+  const int x = x0 + c;
+  const bool xin = x < fr.w;
+  const bool interior = y0 + TH <= fr.h && x0 + TW <= fr.w;
+  const uint32_t offI = (uint32_t)dr * ((uint32_t)fr.pitch * 4u) +
+                        (uint32_t)x * 4u;
+  const uint32_t offB = (uint32_t)dr * ((uint32_t)fr.w * 4u) +
+                        (uint32_t)x * 4u;
+  const char* prow = uniform_ptr(
+      (const char*)(fr.pix + (int64_t)(y0 + rw) * fr.pitch));
+  const int64_t pstep = (int64_t)RSTEP * fr.pitch * 4;
+
   // the tile's pixels are requested first, so that their latency overlaps
   // the spline prologue
   float Ipx[PPT], Bv[FUSED ? 1 : PPT], Rv[FUSED ? 1 : PPT];
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int q = t + kBlock * k;
-    const int y = y0 + q / TW, x = x0 + q % TW;
-    const bool in = y < fr.h && x < fr.w;
-    Ipx[k] = in ? gld(fr.pix + (int64_t)y * fr.pitch + x) : 0.0f;
+    const int y = y0 + rw + dr + RSTEP * k;
+    const bool in = interior || (xin && y < fr.h);
+    const char* pk = uniform_ptr(prow + pstep * k);
+    Ipx[k] = in ? gld((const float*)(pk + offI)) : 0.0f;
     if (!FUSED) {
-      Bv[k] = in ? gld(fr.bkg + (int64_t)y * fr.w + x) : 0.0f;
-      Rv[k] = in ? gld(fr.rms + (int64_t)y * fr.w + x) : 0.0f;
+      const int64_t o = (int64_t)y * fr.w + x;
+      Bv[k] = in ? gld(fr.bkg + o) : 0.0f;
+      Rv[k] = in ? gld(fr.rms + o) : 0.0f;
     }
   }
   if (FUSED) spline_prologue<TH, TW>(wk, fr, p, y0, x0, L.u.spl);
@@ -208,8 +229,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
       row_last |= 1ull << (l + TW - 1);
     }
   }
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t upto = below | (1ull << lane);
 
   // ---- threshold: v = I - B32 > nsigma * R32; runs ----------------------
   // Every prefetched pixel is consumed here, before the loop, so that the
@@ -217,25 +236,30 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   uint32_t finm = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) finm |= (uint32_t)isfinite(Ipx[k]) << k;
-  uint32_t fgm = 0;
-  uint64_t fgb[PPT];
+  SplineX sx;
+  if (FUSED) sx = spline_x<TH, TW>(L.u.spl, c);
+  char* brow = FUSED ? uniform_ptr((char*)(fr.bkg + (int64_t)(y0 + rw) * fr.w))
+                     : nullptr;
+  char* rrow = FUSED ? uniform_ptr((char*)(fr.rms + (int64_t)(y0 + rw) * fr.w))
+                     : nullptr;
+  const int64_t bstep = (int64_t)RSTEP * fr.w * 4;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int q = t + kBlock * k;
-    const int r = q / TW, c = q % TW;
-    const int y = y0 + r, x = x0 + c;
+    const int r = rw + dr + RSTEP * k;
+    const bool in = interior || (xin && y0 + r < fr.h);
     bool det = false;
-    if (y < fr.h && x < fr.w) {
+    if (in) {
       const float I = Ipx[k];
       float B32, R32;
       if (FUSED) {
         double b, rr;
-        spline_pixel<TH, TW>(L.u.spl, r, c, &b, &rr);
+        spline_at<TH, TW>(L.u.spl, sx, r, &b, &rr);
         B32 = (float)b;
         R32 = (float)rr;
-        const int64_t o = (int64_t)y * fr.w + x;
-        gst(fr.bkg + o, B32);
-        if (write_rms) gst(fr.rms + o, R32);
+        gst((float*)(uniform_ptr(brow + bstep * k) + offB), B32);
+        if (write_rms)
+          gst((float*)(uniform_ptr(rrow + bstep * k) + offB), R32);
       } else {
         B32 = Bv[k];
         R32 = Rv[k];
@@ -244,21 +268,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
       const double thr = p.det_nsigma * (double)R32;
       det = ((finm >> k) & 1u) && (v > thr);
     }
-    fgm |= (uint32_t)det << k;
     const uint64_t m = __builtin_amdgcn_ballot_w64(det);
-    fgb[k] = m;
     const uint64_t heads = m & (~(m << 1) | row_first);
     if (lane == 0) {
       L.fgbits[wv + kWaves * k] = m;
       L.headbits[wv + kWaves * k] = heads;
       L.rootbits[wv + kWaves * k] = 0;
     }
-    int par = -1;
-    if (det) {
-      const int s_lane = 63 - __clzll(heads & upto);
-      par = q - (lane - s_lane);
-    }
-    L.parent[q] = par;
+    // a run head starts as its own root; the other pixels of a run are
+    // found from the head bits when needed
+    if ((heads >> lane) & 1ull) L.parent[q] = q;
   }
   __syncthreads();
 
@@ -266,10 +285,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   auto fg_at = [&](int q) -> bool {
     return (L.fgbits[q >> 6] >> (q & 63)) & 1ull;
   };
+  // head of the run holding detected pixel q (runs lie inside a segment)
+  auto head_of = [&](int q) -> int {
+    const int b = q & 63;
+    const uint64_t hb =
+        L.headbits[q >> 6] & (b == 63 ? ~0ull : ((2ull << b) - 1));
+    return (q - b) + 63 - __clzll(hb);
+  };
   for_runs(L.fgbits, L.headbits, row_last, [&](int q, int len) {
     const int r = q / TW, c = q % TW;
     // a row run cut by a segment boundary (tiles wider than 64)
-    if ((q & 63) == 0 && c > 0 && fg_at(q - 1)) lunion(L.parent, q, q - 1);
+    if ((q & 63) == 0 && c > 0 && fg_at(q - 1))
+      lunion(L.parent, q, head_of(q - 1));
     if (r == 0) return;
     const int c1 = c + len - 1;
     const int lo = CONN8 ? max(c - 1, 0) : c;
@@ -282,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
       if (!w) { x = ((x >> 6) + 1) << 6; continue; }
       x += __builtin_ctzll(w);
       if (x > xe) break;
-      lunion(L.parent, q, x);
+      lunion(L.parent, q, head_of(x));
       const uint64_t z = ~(L.fgbits[x >> 6] >> (x & 63));
       x = z ? x + __builtin_ctzll(z) : ((x >> 6) + 1) << 6;
     }
@@ -326,10 +353,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
     L.u.st.ymax[c] = -1;
   }
   __syncthreads();
-  auto comp_of = [&](int q) {
-    const int pq = L.parent[q];
-    return pq < 0 ? -2 - pq : -2 - L.parent[pq];
-  };
 
   // ---- per-run pixel count, bounding box, inner-border contact ----------
   const bool nb_up = y0 > 0, nb_down = y0 + TH < fr.h;

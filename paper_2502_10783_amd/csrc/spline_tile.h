@@ -93,19 +93,46 @@ __device__ __forceinline__ void spline_prologue(const Work& wk,
   __syncthreads();
 }
 
-// Background and rms (binary64) of tile pixel (r, c) after the prologue.
+// The x part of a tile column's spline evaluation: its mesh interval and
+// four weights, the same for every row.
+struct SplineX {
+  int k;
+  double w0, w1, w2, w3;
+};
+
+template <int TH, int TW>
+__device__ __forceinline__ SplineX spline_x(const SplineLds<TH, TW>& S,
+                                            int c) {
+  SplineX x;
+  x.k = S.cx[c];
+  x.w0 = S.wx[0][c];
+  x.w1 = S.wx[1][c];
+  x.w2 = S.wx[2][c];
+  x.w3 = S.wx[3][c];
+  return x;
+}
+
+// Background and rms (binary64) of tile pixel (r, c) after the prologue,
+// from the column's x part.
+template <int TH, int TW>
+__device__ __forceinline__ void spline_at(const SplineLds<TH, TW>& S,
+                                          const SplineX& x, int r, double* b,
+                                          double* rr) {
+  const int k = x.k;
+  // fused multiply-adds: four FP64 operations per map
+  *b = fma(x.w3, S.gBpp[r][k + 1],
+           fma(x.w2, S.gBpp[r][k],
+               fma(x.w1, S.gB[r][k + 1], x.w0 * S.gB[r][k])));
+  *rr = fma(x.w3, S.gRpp[r][k + 1],
+            fma(x.w2, S.gRpp[r][k],
+                fma(x.w1, S.gR[r][k + 1], x.w0 * S.gR[r][k])));
+}
+
 template <int TH, int TW>
 __device__ __forceinline__ void spline_pixel(const SplineLds<TH, TW>& S,
                                              int r, int c, double* b,
                                              double* rr) {
-  const int k = S.cx[c];
-  const double w0 = S.wx[0][c], w1 = S.wx[1][c];
-  const double w2 = S.wx[2][c], w3 = S.wx[3][c];
-  // fused multiply-adds: four FP64 operations per map
-  *b = fma(w3, S.gBpp[r][k + 1],
-           fma(w2, S.gBpp[r][k], fma(w1, S.gB[r][k + 1], w0 * S.gB[r][k])));
-  *rr = fma(w3, S.gRpp[r][k + 1],
-            fma(w2, S.gRpp[r][k], fma(w1, S.gR[r][k + 1], w0 * S.gR[r][k])));
+  spline_at<TH, TW>(S, spline_x<TH, TW>(S, c), r, b, rr);
 }
 
 }  // namespace ipp
