@@ -411,19 +411,19 @@ template <int TH, int TW>
 ipp_status run_tile(IppCtx* c, const Plan& P, const Work& w,
                     const ipp_params& p, bool fused, int write_rms,
                     hipStream_t s) {
-  const dim3 g(P.dtiles), b(kBlock);
+  const dim3 g(P.dtiles), b(kBlock), bt(kTileThreads);
   if (fused && p.connectivity == 8)
-    IPP_LAUNCH(c, s, "k_tile_ccl_fused", hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, true>), g, b,
+    IPP_LAUNCH(c, s, "k_tile_ccl_fused", hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, true, kTileThreads>), g, bt,
                                      0, s, w, p, write_rms));
   else if (fused)
-    IPP_LAUNCH(c, s, "k_tile_ccl_fused", hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, false>), g,
-                                     b, 0, s, w, p, write_rms));
+    IPP_LAUNCH(c, s, "k_tile_ccl_fused", hipLaunchKernelGGL((k_tile_ccl<TH, TW, true, false, kTileThreads>), g,
+                                     bt, 0, s, w, p, write_rms));
   else if (p.connectivity == 8)
-    IPP_LAUNCH(c, s, "k_tile_ccl", hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, true>), g,
-                                     b, 0, s, w, p, write_rms));
+    IPP_LAUNCH(c, s, "k_tile_ccl", hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, true, kTileThreads>), g,
+                                     bt, 0, s, w, p, write_rms));
   else
-    IPP_LAUNCH(c, s, "k_tile_ccl", hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, false>), g,
-                                     b, 0, s, w, p, write_rms));
+    IPP_LAUNCH(c, s, "k_tile_ccl", hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, false, kTileThreads>), g,
+                                     bt, 0, s, w, p, write_rms));
   IPP_LAUNCH(c, s, "k_border", hipLaunchKernelGGL((k_border<TH, TW>), g, b, 0, s, w, p));
   return IPP_OK;
 }

@@ -245,8 +245,10 @@ __device__ __forceinline__ T block_max(T v, T* red) {
   return a > b ? a : b;
 }
 
-// Exclusive scan over the 256 threads of a block (int).  `red` is LDS
-// scratch of kWaves ints.  Returns the exclusive prefix; *total gets the sum.
+// Exclusive scan over the threads of a block of NW waves (int).  `red` is
+// LDS scratch of NW ints.  Returns the exclusive prefix; *total gets the
+// sum.
+template <int NW = kWaves>
 __device__ __forceinline__ int block_exclusive_scan(int v, int* red,
                                                     int* total) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -260,9 +262,13 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* red,
   __syncthreads();
   if (lane == kWave - 1) red[w] = x;
   __syncthreads();
-  int off = 0;
-  for (int i = 0; i < w; ++i) off += red[i];
-  *total = red[0] + red[1] + red[2] + red[3];
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    off += i < w ? red[i] : 0;
+    tot += red[i];
+  }
+  *total = tot;
   return off + x - v;
 }
 

@@ -22,28 +22,32 @@ namespace {
 template <int TH, int TW, bool CONN8>
 struct CclLds {
   static constexpr int NP = TH * TW;
+  static constexpr int NSEG = NP / 64;         // 64-pixel segments
+  static constexpr int NRUN = NP / 2;          // runs: at most every other pixel
   static constexpr int NCMP = CONN8 ? NP / 4 : NP / 2;
-  int parent[NP];              // union-find; after numbering a root holds
-                               // -2 - (its component id)
   union {
-    SplineLds<TH, TW> spl;
+    SplineLds<TH, TW> spl;                     // until the threshold is taken
     struct {
+      int parent[NRUN];        // union-find over runs; after numbering a
+                               // root holds -2 - (its component id)
+      uint16_t rq[NRUN];       // head pixel of each run
       int npix[NCMP];
       int xmin[NCMP];
       int xmax[NCMP];
       int ymax[NCMP];
       int16_t rootp[NCMP];
       int16_t rloc[NCMP];
-    } st;
+    } cc;
   } u;
   // one bit per pixel, 64 consecutive raster pixels per word: detected,
-  // run heads, component roots
-  uint64_t fgbits[NP / 64];
-  uint64_t headbits[NP / 64];
-  uint64_t rootbits[NP / 64];
-  int wcnt[16 * kWaves];
-  int ired[kWaves];
-  int ncomp;
+  // run heads; one bit per run: component roots
+  uint64_t fgbits[NSEG];
+  uint64_t headbits[NSEG];
+  uint64_t rootbits[NRUN / 64];
+  int scnt[NSEG];              // runs before each segment
+  int rcnt[NRUN / 64];         // roots before each word of rootbits
+  int ired[16];
+  int nrun, ncomp;
   long long rbase;
 };
 
@@ -97,34 +101,6 @@ __device__ __forceinline__ void gunion(int32_t* parent, int a, int b) {
   }
 }
 
-// Calls fn(q, len) for every run head q of the 16-pixel slice of the tile
-// that thread t owns (segment t / 4, bits 16 (t % 4) ..).  A run is a
-// maximal horizontal stretch of detected pixels inside one 64-pixel
-// segment and one row (row_last marks the segment's last pixel of each
-// row); len is read off the bits.
-template <typename Fn>
-__device__ __forceinline__ void for_runs(const uint64_t* fgbits,
-                                         const uint64_t* headbits,
-                                         uint64_t row_last, Fn fn) {
-  const int seg = threadIdx.x >> 2, b0 = (threadIdx.x & 3) * 16;
-  uint32_t h = (uint32_t)(headbits[seg] >> b0) & 0xFFFFu;
-  // positions where a run cannot continue: undetected, or after a row end
-  const uint64_t stop = ~fgbits[seg] | (row_last << 1);
-  while (h) {
-    const int b = b0 + __builtin_ctz(h);
-    h &= h - 1;
-    const int len =
-        b == 63 ? 1
-                : 1 + __builtin_ctzll((stop >> (b + 1)) | (1ull << (63 - b)));
-    fn(seg * 64 + b, len);
-  }
-}
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const int lane = threadIdx.x & (kWave - 1);
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------
@@ -157,24 +133,30 @@ __global__ __launch_bounds__(kBlock) void k_bkg_maps(Work wk, ipp_params p) {
 // ---------------------------------------------------------------------
 // Tile kernel: threshold + LDS labelling + records.
 //
-// Pixel q = t + 256 k of the tile (raster order) belongs to lane t % 64 of
-// wave t / 64, so each wave instruction covers 64 consecutive pixels of a
-// row (two half rows for 32-wide tiles).  Detected pixels that are
-// horizontally contiguous within such a segment form a run; every pixel of
-// a run starts linked to the run's first pixel, and only one union per run
-// of the row above that touches it (and one across a segment split inside
-// a row) is needed.  Counts, bounding boxes and border contact are
-// accumulated once per run.
+// NT threads per tile.  Pixel q = t + NT k of the tile (raster order)
+// belongs to lane t % 64 of wave t / 64, so each wave instruction covers 64
+// consecutive pixels of a row (two half rows for 32-wide tiles).  Detected
+// pixels that are horizontally contiguous within such a segment form a
+// run.  Runs are numbered in raster order of their first pixel (the head)
+// and listed; the union-find works on run numbers, with one union per run
+// of the row above that touches a run (and one across a segment split
+// inside a row), and counts, bounding boxes and border contact are
+// accumulated once per run.  Every pass over runs walks the dense list.
 // ---------------------------------------------------------------------
-template <int TH, int TW, bool FUSED, bool CONN8>
-__global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
-                                                     int write_rms) {
+template <int TH, int TW, bool FUSED, bool CONN8, int NT>
+__global__ __launch_bounds__(NT) void k_tile_ccl(Work wk, ipp_params p,
+                                                 int write_rms) {
   using Lds = CclLds<TH, TW, CONN8>;
   constexpr int NP = Lds::NP;
+  constexpr int NSEG = Lds::NSEG;
+  constexpr int NRUN = Lds::NRUN;
   constexpr int NCMP = Lds::NCMP;
-  constexpr int PPT = NP / kBlock;            // 16
-  static_assert(TW >= 32 && kWave % TW == 0 || TW % kWave == 0,
+  constexpr int NW = NT / kWave;              // waves per tile
+  constexpr int PPT = NP / NT;                // pixels per thread
+  static_assert((TW >= 32 && kWave % TW == 0) || TW % kWave == 0,
                 "tile width must divide or be divided by the wave size");
+  static_assert(NSEG == kWave && NT % TW == 0 && PPT <= 16 && NW <= 16,
+                "4096-pixel tiles, 256 or 512 threads");
   __shared__ Lds L;
   const int t = threadIdx.x;
   const int lane = t & (kWave - 1), wv = t / kWave;
@@ -184,12 +166,12 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
   const int y0 = ty * TH, x0 = tx * TW;
 
-  // Pixel q = t + 256 k of the tile lies in tile column c = t % TW for
-  // every k (TW divides 256) and in tile row t / TW + (256 / TW) k.  A wave
-  // instruction covers one row (TW >= 64) or two (TW = 32): the row of the
-  // wave's first lane is wave-uniform, so loads and stores take a scalar
-  // row pointer and a per-lane 32-bit byte offset fixed for the whole loop.
-  constexpr int RSTEP = kBlock / TW;
+  // Pixel q = t + NT k lies in tile column c = t % TW for every k (TW
+  // divides NT) and in tile row t / TW + (NT / TW) k.  A wave instruction
+  // covers one row (TW >= 64) or two (TW = 32): the row of the wave's first
+  // lane is wave-uniform, so loads and stores take a scalar row pointer and
+  // a per-lane 32-bit byte offset fixed for the whole loop.
+  constexpr int RSTEP = NT / TW;
   const int c = t % TW;
   const int rw = __builtin_amdgcn_readfirstlane((wv * kWave) / TW);
   const int dr = (wv * kWave + lane) / TW - (wv * kWave) / TW;  // 0 or 1
@@ -219,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
       Rv[k] = in ? gld(fr.rms + o) : 0.0f;
     }
   }
-  if (FUSED) spline_prologue<TH, TW>(wk, fr, p, y0, x0, L.u.spl);
+  if (FUSED) spline_prologue<TH, TW, NT>(wk, fr, p, y0, x0, L.u.spl);
 
   // lanes that start / end a row inside the wave's 64-pixel segment
   uint64_t row_first = 1ull, row_last = 1ull << 63;
@@ -245,7 +227,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   const int64_t bstep = (int64_t)RSTEP * fr.w * 4;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const int q = t + kBlock * k;
     const int r = rw + dr + RSTEP * k;
     const bool in = interior || (xin && y0 + r < fr.h);
     bool det = false;
@@ -269,36 +250,74 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
       det = ((finm >> k) & 1u) && (v > thr);
     }
     const uint64_t m = __builtin_amdgcn_ballot_w64(det);
-    const uint64_t heads = m & (~(m << 1) | row_first);
     if (lane == 0) {
-      L.fgbits[wv + kWaves * k] = m;
-      L.headbits[wv + kWaves * k] = heads;
-      L.rootbits[wv + kWaves * k] = 0;
+      L.fgbits[wv + NW * k] = m;
+      L.headbits[wv + NW * k] = m & (~(m << 1) | row_first);
     }
-    // a run head starts as its own root; the other pixels of a run are
-    // found from the head bits when needed
-    if ((heads >> lane) & 1ull) L.parent[q] = q;
   }
   __syncthreads();
 
-  // ---- unions with the runs of the row above (one thread per run) -------
+  // ---- runs, numbered in raster order of their heads ---------------------
+  if (wv == 0) {                   // exclusive scan of the 64 head counts
+    const int v = __popcll(L.headbits[lane]);
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int u = __shfl_up(x, o, kWave);
+      if (lane >= o) x += u;
+    }
+    L.scnt[lane] = x - v;
+    if (lane == kWave - 1) L.nrun = x;
+  }
+  if (t < NRUN / 64) L.rootbits[t] = 0;
+  __syncthreads();
+  const int nrun = L.nrun;
+  int* parent = L.u.cc.parent;
+  uint16_t* rq = L.u.cc.rq;
+  {
+    // thread t lists the heads among PPT bits of segment t / (64 / PPT)
+    constexpr int TPS = kWave / PPT;
+    const int seg = t / TPS, b0 = (t % TPS) * PPT;
+    const uint64_t hw = L.headbits[seg];
+    uint32_t h = (uint32_t)(hw >> b0) & ((1u << PPT) - 1u);
+    int j = L.scnt[seg] + (b0 ? __popcll(hw & (~0ull >> (64 - b0))) : 0);
+    while (h) {
+      const int b = b0 + __builtin_ctz(h);
+      h &= h - 1;
+      rq[j] = (uint16_t)(seg * kWave + b);
+      parent[j] = j;
+      ++j;
+    }
+  }
+  __syncthreads();
+
   auto fg_at = [&](int q) -> bool {
     return (L.fgbits[q >> 6] >> (q & 63)) & 1ull;
   };
-  // head of the run holding detected pixel q (runs lie inside a segment)
-  auto head_of = [&](int q) -> int {
+  // length of the run whose head is q
+  auto run_len = [&](int q) -> int {
+    const int b = q & 63;
+    const uint64_t stop = ~L.fgbits[q >> 6] | (row_last << 1);
+    return b == 63 ? 1
+                   : 1 + __builtin_ctzll((stop >> (b + 1)) | (1ull << (63 - b)));
+  };
+  // number of the run holding detected pixel q (runs lie inside a segment)
+  auto run_of = [&](int q) -> int {
     const int b = q & 63;
     const uint64_t hb =
         L.headbits[q >> 6] & (b == 63 ? ~0ull : ((2ull << b) - 1));
-    return (q - b) + 63 - __clzll(hb);
+    return L.scnt[q >> 6] + __popcll(hb) - 1;
   };
-  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int len) {
+
+  // ---- unions with the runs of the row above ----------------------------
+  for (int j = t; j < nrun; j += NT) {
+    const int q = rq[j];
     const int r = q / TW, c = q % TW;
-    // a row run cut by a segment boundary (tiles wider than 64)
-    if ((q & 63) == 0 && c > 0 && fg_at(q - 1))
-      lunion(L.parent, q, head_of(q - 1));
-    if (r == 0) return;
-    const int c1 = c + len - 1;
+    // a row run cut by a segment boundary (tiles wider than 64): the run
+    // holding q - 1 is the previous run
+    if ((q & 63) == 0 && c > 0 && fg_at(q - 1)) lunion(parent, j, j - 1);
+    if (r == 0) continue;
+    const int c1 = c + run_len(q) - 1;
     const int lo = CONN8 ? max(c - 1, 0) : c;
     const int hi = CONN8 ? min(c1 + 1, TW - 1) : c1;
     // one union per run of the row above that meets [lo, hi]
@@ -309,90 +328,92 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
       if (!w) { x = ((x >> 6) + 1) << 6; continue; }
       x += __builtin_ctzll(w);
       if (x > xe) break;
-      lunion(L.parent, q, head_of(x));
+      lunion(parent, j, run_of(x));
       const uint64_t z = ~(L.fgbits[x >> 6] >> (x & 63));
       x = z ? x + __builtin_ctzll(z) : ((x >> 6) + 1) << 6;
     }
-  });
+  }
   __syncthreads();
-  // heads point at their roots; other detected pixels keep their head
-  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int) {
-    const int root = lfind(L.parent, q);
-    L.parent[q] = root;
-    if (root == q) atomicOr((unsigned long long*)&L.rootbits[q >> 6],
-                            1ull << (q & 63));
-  });
+  // every run points at its root
+  for (int j = t; j < nrun; j += NT) {
+    const int root = lfind(parent, j);
+    parent[j] = root;
+    if (root == j) atomicOr((unsigned long long*)&L.rootbits[j >> 6],
+                            1ull << (j & 63));
+  }
   __syncthreads();
 
   // ---- component ids in raster order of their roots --------------------
-  if (wv == 0) {                   // exclusive scan of the 64 root counts
-    const int v = __popcll(L.rootbits[lane]);
+  if (wv == 0) {                   // exclusive scan of the root counts
+    const int v = lane < NRUN / 64 ? __popcll(L.rootbits[lane]) : 0;
     int x = v;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const int u = __shfl_up(x, o, kWave);
       if (lane >= o) x += u;
     }
-    L.wcnt[lane] = x - v;
+    if (lane < NRUN / 64) L.rcnt[lane] = x - v;
     if (lane == kWave - 1) L.ncomp = x;
   }
   __syncthreads();
   const int ncomp = L.ncomp;
-  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int) {
-    if (L.parent[q] != q) return;
-    const uint64_t bits = L.rootbits[q >> 6];
-    const uint64_t lt = (q & 63) ? (bits & (~0ull >> (64 - (q & 63)))) : 0;
-    const int id = L.wcnt[q >> 6] + __popcll(lt);
-    L.parent[q] = -2 - id;
-    L.u.st.rootp[id] = (int16_t)q;
-  });
-  for (int c = t; c < ncomp; c += kBlock) {
-    L.u.st.npix[c] = 0;
-    L.u.st.xmin[c] = TW;
-    L.u.st.xmax[c] = -1;
-    L.u.st.ymax[c] = -1;
+  for (int j = t; j < nrun; j += NT) {
+    if (parent[j] != j) continue;
+    const uint64_t bits = L.rootbits[j >> 6];
+    const uint64_t lt = (j & 63) ? (bits & (~0ull >> (64 - (j & 63)))) : 0;
+    const int id = L.rcnt[j >> 6] + __popcll(lt);
+    parent[j] = -2 - id;
+    L.u.cc.rootp[id] = (int16_t)rq[j];
+  }
+  for (int c = t; c < ncomp; c += NT) {
+    L.u.cc.npix[c] = 0;
+    L.u.cc.xmin[c] = TW;
+    L.u.cc.xmax[c] = -1;
+    L.u.cc.ymax[c] = -1;
   }
   __syncthreads();
 
   // ---- per-run pixel count, bounding box, inner-border contact ----------
   const bool nb_up = y0 > 0, nb_down = y0 + TH < fr.h;
   const bool nb_left = x0 > 0, nb_right = x0 + TW < fr.w;
-  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int len) {
+  for (int j = t; j < nrun; j += NT) {
+    const int q = rq[j];
     const int r = q / TW, c = q % TW;
+    const int len = run_len(q);
     const int ce = c + len - 1;
-    const int pq = L.parent[q];
-    const int id = pq < 0 ? -2 - pq : -2 - L.parent[pq];
-    if (pq >= 0) L.parent[q] = -2 - id;   // every head now holds its id
-    atomicAdd(&L.u.st.npix[id], len);
-    atomicMin(&L.u.st.xmin[id], c);
-    atomicMax(&L.u.st.xmax[id], ce);
-    atomicMax(&L.u.st.ymax[id], r);
+    const int pj = parent[j];
+    const int id = pj < 0 ? -2 - pj : -2 - parent[pj];
+    if (pj >= 0) parent[j] = -2 - id;   // every run now holds its id
+    atomicAdd(&L.u.cc.npix[id], len);
+    atomicMin(&L.u.cc.xmin[id], c);
+    atomicMax(&L.u.cc.xmax[id], ce);
+    atomicMax(&L.u.cc.ymax[id], r);
     const bool edge = (r == 0 && nb_up) || (r == TH - 1 && nb_down) ||
                       (c == 0 && nb_left) || (ce == TW - 1 && nb_right);
-    if (edge) atomicOr(&L.u.st.npix[id], 1 << 30);
-  });
+    if (edge) atomicOr(&L.u.cc.npix[id], 1 << 30);
+  }
   __syncthreads();
 
   // ---- kept components -> records ---------------------------------------
-  constexpr int CPT = NCMP / kBlock;
+  constexpr int CPT = NCMP / NT;
   int kc = 0;
 #pragma unroll
   for (int i = 0; i < CPT; ++i) {
     const int c = t * CPT + i;
     if (c < ncomp) {
-      const int np = L.u.st.npix[c];
+      const int np = L.u.cc.npix[c];
       kc += ((np >> 30) & 1) || ((np & 0x3FFFFFFF) >= p.min_area);
     }
   }
   int ktot;
-  int ex = block_exclusive_scan(kc, L.ired, &ktot);
+  int ex = block_exclusive_scan<NW>(kc, L.ired, &ktot);
 #pragma unroll
   for (int i = 0; i < CPT; ++i) {
     const int c = t * CPT + i;
     if (c < ncomp) {
-      const int np = L.u.st.npix[c];
+      const int np = L.u.cc.npix[c];
       const bool kept = ((np >> 30) & 1) || ((np & 0x3FFFFFFF) >= p.min_area);
-      L.u.st.rloc[c] = kept ? (int16_t)ex : (int16_t)-1;
+      L.u.cc.rloc[c] = kept ? (int16_t)ex : (int16_t)-1;
       ex += kept;
     }
   }
@@ -408,55 +429,42 @@ __global__ __launch_bounds__(kBlock) void k_tile_ccl(Work wk, ipp_params p,
   }
   __syncthreads();
   const long long rbase = L.rbase;
-  for (int c = t; c < ncomp; c += kBlock) {
-    const int rl = L.u.st.rloc[c];
+  for (int c = t; c < ncomp; c += NT) {
+    const int rl = L.u.cc.rloc[c];
     if (rl < 0) continue;
     const long long rec = rbase + rl;
     if (rec >= wk.rec_cap) continue;
-    const int rp = L.u.st.rootp[c];
+    const int rp = L.u.cc.rootp[c];
     const int rr = rp / TW, rc = rp % TW;
     Rec R;
     R.minidx = (y0 + rr) * fr.w + (x0 + rc);
-    R.npix = L.u.st.npix[c] & 0x3FFFFFFF;
-    R.xmin = x0 + L.u.st.xmin[c];
-    R.xmax = x0 + L.u.st.xmax[c];
+    R.npix = L.u.cc.npix[c] & 0x3FFFFFFF;
+    R.xmin = x0 + L.u.cc.xmin[c];
+    R.xmax = x0 + L.u.cc.xmax[c];
     R.ymin = y0 + rr;
-    R.ymax = y0 + L.u.st.ymax[c];
+    R.ymax = y0 + L.u.cc.ymax[c];
     R.frame = f;
     R.pad = 0;
     wk.recs[rec] = R;
     wk.rparent[rec] = (int32_t)rec;
     wk.rlabel[rec] = 0;
   }
-  // ---- run map of the tile: detected / head bits, per-segment run offset,
-  // per run its record index + 1 --------------------------------------------
+  // ---- run map of the tile: detected / head bits, runs before each
+  // segment, per run its record index + 1 ----------------------------------
   uint8_t* tm = wk.tmap + (size_t)tile * kTmapBytes;
   if (t < 64) {
     gst((uint64_t*)(tm + kTmapFg) + t, L.fgbits[t]);
   } else if (t < 128) {
     gst((uint64_t*)(tm + kTmapHead) + (t - 64), L.headbits[t - 64]);
+  } else if (t < 192) {
+    gst((uint16_t*)(tm + kTmapSeg) + (t - 128), (uint16_t)L.scnt[t - 128]);
   }
-  if (wv == 0) {                   // exclusive scan of the heads per segment
-    const int v = __popcll(L.headbits[lane]);
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int u = __shfl_up(x, o, kWave);
-      if (lane >= o) x += u;
-    }
-    L.wcnt[lane] = x - v;
-    gst((uint16_t*)(tm + kTmapSeg) + lane, (uint16_t)(x - v));
-  }
-  __syncthreads();
-  for_runs(L.fgbits, L.headbits, row_last, [&](int q, int) {
-    const int seg = q >> 6, b = q & 63;
-    const uint64_t before = b ? (L.headbits[seg] & (~0ull >> (64 - b))) : 0;
-    const int ri = L.wcnt[seg] + __popcll(before);
-    const int rl = L.u.st.rloc[-2 - L.parent[q]];
+  for (int j = t; j < nrun; j += NT) {
+    const int rl = L.u.cc.rloc[-2 - parent[j]];
     const uint16_t v =
         (rl >= 0 && rbase + rl < wk.rec_cap) ? (uint16_t)(rl + 1) : 0;
-    gst((uint16_t*)(tm + kTmapRun) + ri, v);
-  });
+    gst((uint16_t*)(tm + kTmapRun) + j, v);
+  }
 }
 
 // Record index within its tile + 1 of tile-local pixel q (0: background
@@ -902,13 +910,13 @@ __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
 
 #define IPP_TILE_INST(TH, TW)                                              \
   template __global__ void k_bkg_maps<TH, TW>(Work, ipp_params);           \
-  template __global__ void k_tile_ccl<TH, TW, true, true>(Work, ipp_params, \
+  template __global__ void k_tile_ccl<TH, TW, true, true, kTileThreads>(Work, ipp_params, \
                                                           int);             \
-  template __global__ void k_tile_ccl<TH, TW, true, false>(Work,           \
+  template __global__ void k_tile_ccl<TH, TW, true, false, kTileThreads>(Work,           \
                                                            ipp_params, int); \
-  template __global__ void k_tile_ccl<TH, TW, false, true>(Work,           \
+  template __global__ void k_tile_ccl<TH, TW, false, true, kTileThreads>(Work,           \
                                                            ipp_params, int); \
-  template __global__ void k_tile_ccl<TH, TW, false, false>(Work,          \
+  template __global__ void k_tile_ccl<TH, TW, false, false, kTileThreads>(Work,          \
                                                             ipp_params, int); \
   template __global__ void k_border<TH, TW>(Work, ipp_params);             \
   template __global__ void k_relabel<TH, TW>(Work, ipp_params);

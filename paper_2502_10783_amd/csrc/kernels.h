@@ -17,7 +17,9 @@ __global__ void k_mesh_spline(Work wk, ipp_params p);
 
 template <int TH, int TW>
 __global__ void k_bkg_maps(Work wk, ipp_params p);
-template <int TH, int TW, bool FUSED, bool CONN8>
+// threads per detection tile (4096 pixels: 8 per thread)
+constexpr int kTileThreads = 512;
+template <int TH, int TW, bool FUSED, bool CONN8, int NT>
 __global__ void k_tile_ccl(Work wk, ipp_params p, int write_rms);
 template <int TH, int TW>
 __global__ void k_border(Work wk, ipp_params p);

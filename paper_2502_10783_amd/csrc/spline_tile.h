@@ -35,7 +35,7 @@ struct SplineLds {
   double node[8][NR][NC];      // tb[0..3], tr[0..3] of the spanned nodes
 };
 
-template <int TH, int TW>
+template <int TH, int TW, int NT = kBlock>
 __device__ __forceinline__ void spline_prologue(const Work& wk,
                                                 const FrameDev& fr,
                                                 const ipp_params& p, int y0,
@@ -49,7 +49,7 @@ __device__ __forceinline__ void spline_prologue(const Work& wk,
     spline_weights((double)x0, p.mesh_w, fr.w, fr.nx, &ilo, w4);
     spline_weights((double)y0, p.mesh_h, fr.h, fr.ny, &jlo, w4);
   }
-  for (int c = threadIdx.x; c < TW + TH; c += kBlock) {
+  for (int c = threadIdx.x; c < TW + TH; c += NT) {
     double w4[4];
     int j;
     if (c < TW) {
@@ -67,7 +67,7 @@ __device__ __forceinline__ void spline_prologue(const Work& wk,
     }
   }
   const int nx = fr.nx, ny = fr.ny;
-  for (int e = threadIdx.x; e < 8 * NR * NC; e += kBlock) {
+  for (int e = threadIdx.x; e < 8 * NR * NC; e += NT) {
     const int t = e / (NR * NC), rc = e - t * (NR * NC);
     const int r = rc / NC, c = rc - r * NC;
     const int j = min(jlo + r, ny - 1), i = min(ilo + c, nx - 1);
@@ -75,7 +75,7 @@ __device__ __forceinline__ void spline_prologue(const Work& wk,
     S.node[t][r][c] = tab[fr.node0 + j * nx + i];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TH * NC; e += kBlock) {
+  for (int e = threadIdx.x; e < TH * NC; e += NT) {
     const int r = e / NC, c = e - (e / NC) * NC;
     const int j = S.ry[r];
     const int j1 = ny == 1 ? j : j + 1;
