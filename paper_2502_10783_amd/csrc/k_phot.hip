@@ -23,6 +23,7 @@ namespace ipp {
 namespace {
 
 constexpr int kApTasks = 320;   // aperture pixels cut by a circle, r <= 16
+constexpr int kEdges = 36;      // pixel edges per axis of a window, r <= 16
 
 template <int NS>
 struct ApLds {
@@ -34,7 +35,12 @@ struct ApLds {
   // the task list is consumed before the annulus values are sorted; the
   // sort's transposes and the sorted values then use the same space
   union {
-    int tk[NS + kApTasks];
+    struct {
+      int tk[NS + kApTasks];
+      // square roots at the window's column and row edges for the
+      // aperture, outer and inner circle: [circle][axis][edge]
+      double sq[3 * 2 * kEdges];
+    };
     double xs[NS + kWave];
   };
 };
@@ -199,7 +205,8 @@ __device__ __forceinline__ double sorted_at(const double* xs, int e) {
 template <int NS>
 __device__ void aperture_one(const Work& wk, const ipp_params& p,
                              ipp_sources& src, double* sky_lohi,
-                             long long row, ApLds<NS>& L) {
+                             long long row, ApLds<NS>& L,
+                             const double* atan_lds) {
   constexpr int PL = NS / kWave;
   constexpr int P = PL == 4 ? 2 : (PL == 8 ? 3 : 4);
   static_assert((1 << P) == PL, "NS is 256, 512 or 1024");
@@ -361,16 +368,49 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   // ---- exact overlaps over one dense task list ---------------------------
   // Every lane computes one overlap per task (two only for a pixel cut by
   // both annulus circles), whatever circle the task belongs to.
+  // The square roots depend on one pixel edge and one circle each: they
+  // are taken once per window edge (the window spans at most 34 pixels).
   {
     const double r2a = p.r_ap * p.r_ap, r2o = p.r_out * p.r_out;
     const double r2i = p.r_in * p.r_in;
+    for (int e = lane; e < 6 * kEdges; e += kWave) {
+      const int c = e / (2 * kEdges), j = e % kEdges;
+      const bool col = (e / kEdges) % 2 == 0;
+      const double r = c == 0 ? p.r_ap : (c == 1 ? p.r_out : p.r_in);
+      const double r2 = c == 0 ? r2a : (c == 1 ? r2o : r2i);
+      const double q = col ? ((double)(xa + j) - 0.5) - cx
+                           : ((double)(ya + j) - 0.5) - cy;
+      L.sq[e] = edge_root(q, r, r2);
+    }
+  }
+  wave_lds_sync();
+  {
+    const double r2a = p.r_ap * p.r_ap, r2o = p.r_out * p.r_out;
+    const double r2i = p.r_in * p.r_in;
+    // overlap of a task pixel with circle c (0 aperture, 1 outer, 2 inner)
+    auto overlap_c = [&](int c, double r, double r2, int wx, int wy,
+                         const double* coef) {
+      const int px = xa + wx, py = ya + wy;
+      if (!touches(cx, cy, r, px, py)) return 0.0;
+      if (within(cx, cy, r, px, py)) return 1.0;
+      const double* sq = L.sq + c * 2 * kEdges;
+      return overlap_cut(cx, cy, r, r2, px, py, sq[wx], sq[wx + 1],
+                         sq[kEdges + wy], sq[kEdges + wy + 1], coef);
+    };
     for (int j = lane; j < ntk; j += kWave) {
+      // the series coefficients are read where they are used (an offset the
+      // compiler cannot hoist keeps them out of registers across the loop)
+      int co = 0;
+      asm volatile("" : "+s"(co));
+      const double* coef = atan_lds + co;
       const int t = L.tk[j];
       const int kind = t >> 28, slot = (t >> 12) & 0x3FF;
-      const int px = xa + (t & 63), py = ya + ((t >> 6) & 63);
+      const int wx = t & 63, wy = (t >> 6) & 63;
+      const int px = xa + wx, py = ya + wy;
+      const int c = kind == 0 ? 0 : (kind == 2 ? 2 : 1);
       const double r = kind == 0 ? p.r_ap : (kind == 2 ? p.r_in : p.r_out);
       const double r2 = kind == 0 ? r2a : (kind == 2 ? r2i : r2o);
-      double w = overlap_pre(cx, cy, r, r2, px, py);
+      double w = overlap_c(c, r, r2, wx, wy, coef);
       const uint32_t qr = (uint32_t)(py - ry0);
       const float I =
           gld((const float*)(wpix + (qr * pitchB + (uint32_t)px * 4u)));
@@ -381,7 +421,7 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
         a_ap += w;
         raw += w * v;
       } else {
-        if (kind == 3) w -= overlap_pre(cx, cy, p.r_in, r2i, px, py);
+        if (kind == 3) w -= overlap_c(2, p.r_in, r2i, wx, wy, coef);
         else if (kind == 2) w = 1.0 - w;
         L.pw[slot] = w;
       }
@@ -487,6 +527,9 @@ __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_aperture_t(
                                                        ipp_sources src,
                                                        double* sky_lohi) {
   __shared__ ApLds<NS> L[kWaves];
+  __shared__ double atan_lds[kAtanTerms];
+  if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
+  __syncthreads();
   long long nrows = src.capacity;
   if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
   // wave index made provably uniform, so per-row loads are scalar
@@ -496,7 +539,7 @@ __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_aperture_t(
   const long long nw = (long long)gridDim.x * kWaves;
   ApLds<NS>& mine = L[threadIdx.x / kWave];
   for (long long row = wid; row < nrows; row += nw)
-    aperture_one<NS>(wk, p, src, sky_lohi, row, mine);
+    aperture_one<NS>(wk, p, src, sky_lohi, row, mine, atan_lds);
 }
 
 template __global__ void k_aperture_t<256>(Work, ipp_params, ipp_sources,

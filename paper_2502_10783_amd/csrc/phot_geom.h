@@ -72,28 +72,48 @@ __device__ __forceinline__ void corner_rot(double ax, double ay, double hx,
   re = nre;
 }
 
+// Coefficients of the Maclaurin series of atan through the power 33:
+// (-1)^k / (2k + 1), k = 0..16.
+constexpr int kAtanTerms = 17;
+__device__ __forceinline__ double atan_coef(int k) {
+  return (k & 1 ? -1.0 : 1.0) / (double)(2 * k + 1);
+}
+
+// Angle in [0, pi) of the rotation (re, im).  With a coefficient table
+// (atan_coef, in LDS) and |im| <= 0.3 re: the series of atan(im / re), whose
+// first term left out is below 2e-20 relative; otherwise atan2.
+__device__ __forceinline__ double rotor_angle(double re, double im,
+                                              const double* coef) {
+  if (coef && fabs(im) <= 0.3 * re) {
+    const double t = im / re, t2 = t * t;
+    double s = coef[kAtanTerms - 1];
+#pragma unroll
+    for (int k = kAtanTerms - 2; k >= 0; --k) s = fma(s, t2, coef[k]);
+    return t * s;
+  }
+  return atan2(im, re);
+}
+
 // Overlap of the pixel square [px-1/2, px+1/2] x [py-1/2, py+1/2] with the
-// disk of radius r about (cx, cy): inclusion-exclusion of G over the
-// square's corners.
-// r2 = r * r, passed in so that a caller can precompute it.
+// disk of radius r about (cx, cy), for a square that meets the disk and is
+// not inside it: inclusion-exclusion of G over the square's corners, given
+// the four square roots hx0/hx1 = sqrt(r^2 - min(|x|, r)^2) at the left /
+// right edge and xs0/xs1 likewise at the bottom / top edge.
 // The arc of a circle inside a unit square is below half the circle once
 // 2r exceeds the square's diagonal (an arc of half the circle or more holds
 // two antipodal points), so for r >= 3/4 the summed corner angle lies in
-// [0, pi) and one atan2 of the composed rotation returns it; smaller
+// [0, pi) and one angle of the composed rotation returns it; smaller
 // circles, whose arc inside one pixel can reach the whole circle, take one
 // atan2 per corner.
-__device__ __forceinline__ double overlap_pre(double cx, double cy, double r,
-                                              double r2, int px, int py) {
-  if (!touches(cx, cy, r, px, py)) return 0.0;
-  if (within(cx, cy, r, px, py)) return 1.0;
+__device__ __forceinline__ double overlap_cut(double cx, double cy, double r,
+                                              double r2, int px, int py,
+                                              double hx0, double hx1,
+                                              double xs0, double xs1,
+                                              const double* coef = nullptr) {
   const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
   const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
   const double ax0 = fmin(fabs(x0), r), ax1 = fmin(fabs(x1), r);
   const double ay0 = fmin(fabs(y0), r), ay1 = fmin(fabs(y1), r);
-  const double hx0 = sqrt(fmax(r2 - ax0 * ax0, 0.0));
-  const double hx1 = sqrt(fmax(r2 - ax1 * ax1, 0.0));
-  const double xs0 = sqrt(fmax(r2 - ay0 * ay0, 0.0));
-  const double xs1 = sqrt(fmax(r2 - ay1 * ay1, 0.0));
   const double sx0 = x0 < 0.0 ? -1.0 : 1.0, sx1 = x1 < 0.0 ? -1.0 : 1.0;
   const double sy0 = y0 < 0.0 ? -1.0 : 1.0, sy1 = y1 < 0.0 ? -1.0 : 1.0;
   if (r >= 0.75) {
@@ -102,12 +122,31 @@ __device__ __forceinline__ double overlap_pre(double cx, double cy, double r,
     corner_rot(ax0, ay1, hx0, xs1, -(sx0 * sy1), r2, lin, re, im);
     corner_rot(ax1, ay0, hx1, xs0, -(sx1 * sy0), r2, lin, re, im);
     corner_rot(ax0, ay0, hx0, xs0, sx0 * sy0, r2, lin, re, im);
-    return fma(0.5 * r2, atan2(im, re), lin);
+    return fma(0.5 * r2, rotor_angle(re, im, coef), lin);
   }
   return sx1 * sy1 * corner_g(ax1, ay1, hx1, xs1, r2) -
          sx0 * sy1 * corner_g(ax0, ay1, hx0, xs1, r2) -
          sx1 * sy0 * corner_g(ax1, ay0, hx1, xs0, r2) +
          sx0 * sy0 * corner_g(ax0, ay0, hx0, xs0, r2);
+}
+
+// Square root term of one pixel edge at offset q from the centre.
+__device__ __forceinline__ double edge_root(double q, double r, double r2) {
+  const double a = fmin(fabs(q), r);
+  return sqrt(fmax(r2 - a * a, 0.0));
+}
+
+// Overlap of pixel (px, py) with the disk of radius r about (cx, cy).
+// r2 = r * r, passed in so that a caller can precompute it.
+__device__ __forceinline__ double overlap_pre(double cx, double cy, double r,
+                                              double r2, int px, int py) {
+  if (!touches(cx, cy, r, px, py)) return 0.0;
+  if (within(cx, cy, r, px, py)) return 1.0;
+  const double hx0 = edge_root(((double)px - 0.5) - cx, r, r2);
+  const double hx1 = edge_root(((double)px + 0.5) - cx, r, r2);
+  const double xs0 = edge_root(((double)py - 0.5) - cy, r, r2);
+  const double xs1 = edge_root(((double)py + 0.5) - cy, r, r2);
+  return overlap_cut(cx, cy, r, r2, px, py, hx0, hx1, xs0, xs1);
 }
 
 __device__ __forceinline__ double overlap(double cx, double cy, double r,
