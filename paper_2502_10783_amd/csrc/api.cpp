@@ -424,7 +424,8 @@ ipp_status run_tile(IppCtx* c, const Plan& P, const Work& w,
   else
     IPP_LAUNCH(c, s, "k_tile_ccl", hipLaunchKernelGGL((k_tile_ccl<TH, TW, false, false, kTileThreads>), g,
                                      bt, 0, s, w, p, write_rms));
-  IPP_LAUNCH(c, s, "k_border", hipLaunchKernelGGL((k_border<TH, TW>), g, b, 0, s, w, p));
+  IPP_LAUNCH(c, s, "k_border", hipLaunchKernelGGL((k_border<TH, TW>), g,
+                                   dim3(border_threads<TH, TW>()), 0, s, w, p));
   return IPP_OK;
 }
 

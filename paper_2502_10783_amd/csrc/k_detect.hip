@@ -484,7 +484,8 @@ __device__ __forceinline__ int tmap_local(const uint8_t* tm, int q) {
 // Join records across the right and bottom border of every tile.
 // ---------------------------------------------------------------------
 template <int TH, int TW>
-__global__ __launch_bounds__(kBlock) void k_border(Work wk, ipp_params p) {
+__global__ __launch_bounds__((border_threads<TH, TW>())) void k_border(
+    Work wk, ipp_params p) {
   const int tile = blockIdx.x;
   const int f = find_frame(wk.frames, wk.nframes, tile, &FrameDev::dtile0);
   const FrameDev fr = wk.frames[f];

@@ -21,6 +21,10 @@ __global__ void k_bkg_maps(Work wk, ipp_params p);
 constexpr int kTileThreads = 512;
 template <int TH, int TW, bool FUSED, bool CONN8, int NT>
 __global__ void k_tile_ccl(Work wk, ipp_params p, int write_rms);
+// threads of k_border: one per right-border and bottom-border pixel of a
+// tile, in whole waves
+template <int TH, int TW>
+constexpr int border_threads() { return (TH + TW + 63) / 64 * 64; }
 template <int TH, int TW>
 __global__ void k_border(Work wk, ipp_params p);
 template <int TH, int TW>
