@@ -787,14 +787,50 @@ __device__ __forceinline__ U128 mul_i64(int64_t v, int64_t m) {
   r.hi = (uint64_t)(p >> 64);
   return r;
 }
+// Wave reductions: rows of 16 lanes by DPP moves (involutions, so both
+// lanes of a pair combine the same two values), then the four row results
+// in a fixed order.  Integer sums are exact, so any order gives the same
+// result.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t u) {
+  const uint32_t lo = (uint32_t)dpp_mov<CTRL>((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)dpp_mov<CTRL>((int)(uint32_t)(u >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t u, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u,
+                                                          lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(
+      (int)(uint32_t)(u >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL>
+__device__ __forceinline__ U128 dpp128(U128 v) {
+  U128 r;
+  r.lo = dpp_u64<CTRL>(v.lo);
+  r.hi = dpp_u64<CTRL>(v.hi);
+  return r;
+}
 __device__ __forceinline__ U128 wave_sum128(U128 v) {
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    U128 u;
-    u.lo = __shfl_xor(v.lo, o, kWave);
-    u.hi = __shfl_xor(v.hi, o, kWave);
-    v = add128(v, u);
+  v = add128(v, dpp128<0xB1>(v));      // quad_perm [1,0,3,2]
+  v = add128(v, dpp128<0x4E>(v));      // quad_perm [2,3,0,1]
+  v = add128(v, dpp128<0x141>(v));     // row_half_mirror
+  v = add128(v, dpp128<0x140>(v));     // row_mirror
+  U128 r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i].lo = read_lane_u64(v.lo, 16 * i);
+    r[i].hi = read_lane_u64(v.hi, 16 * i);
   }
-  return v;
+  return add128(add128(r[0], r[1]), add128(r[2], r[3]));
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t u) {
+  u += dpp_u64<0xB1>(u);
+  u += dpp_u64<0x4E>(u);
+  u += dpp_u64<0x141>(u);
+  u += dpp_u64<0x140>(u);
+  return (read_lane_u64(u, 0) + read_lane_u64(u, 16)) +
+         (read_lane_u64(u, 32) + read_lane_u64(u, 48));
 }
 // Correctly rounded (to nearest, ties to even) conversion to binary64.
 __device__ double to_double(U128 v) {
@@ -858,34 +894,63 @@ __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
       ey += dy; ex += dx;
       if (ex >= bw) { ex -= bw; ++ey; }
       const int64_t o = (int64_t)y * fr.w + x;
-      if (gld(fr.labels + o) != label) continue;
+      // the label and the two values are loaded together; a pixel of
+      // another label contributes zeros
+      const bool mem = gld(fr.labels + o) == label;
       const float I = gld(fr.pix + (int64_t)y * fr.pitch + x);
       const float B = gld(fr.bkg + o);
       const double v = (double)I - (double)B;
       double s = rint(v * two_q);
-      if (!(exact_range(I) && exact_range(B))) flags |= IPP_SRC_INEXACT_SUM_RANGE;
-      if (s > dmax) { s = dmax; flags |= IPP_SRC_INEXACT_SUM_RANGE; }
-      if (s < -dmax) { s = -dmax; flags |= IPP_SRC_INEXACT_SUM_RANGE; }
-      const int64_t D = (int64_t)s;
+      bool inexact = !(exact_range(I) && exact_range(B));
+      if (s > dmax) { s = dmax; inexact = true; }
+      if (s < -dmax) { s = -dmax; inexact = true; }
+      if (mem && inexact) flags |= IPP_SRC_INEXACT_SUM_RANGE;
+      const int64_t D = mem ? (int64_t)s : 0;
       S = add128(S, from_i64(D));
       Sx = add128(Sx, mul_i64(D, x - xmin));
       Sy = add128(Sy, mul_i64(D, y - ymin));
-      ux += x - xmin;
-      uy += y - ymin;
+      ux += mem ? x - xmin : 0;
+      uy += mem ? y - ymin : 0;
       const int idx = y * fr.w + x;
-      if (v > pk || (v == pk && idx < pidx)) { pk = v; pidx = idx; }
+      if (mem && (v > pk || (v == pk && idx < pidx))) { pk = v; pidx = idx; }
     }
     S = wave_sum128(S);
     Sx = wave_sum128(Sx);
     Sy = wave_sum128(Sy);
-    ux = wave_sum(ux);
-    uy = wave_sum(uy);
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-      const double pv = __shfl_xor(pk, o, kWave);
-      const int pi = __shfl_xor(pidx, o, kWave);
+    ux = (long long)wave_sum_u64((uint64_t)ux);
+    uy = (long long)wave_sum_u64((uint64_t)uy);
+    // peak: largest value, ties to the smallest index (associative, so the
+    // reduction order does not matter)
+    auto take = [&](double pv, int pi) {
       if (pv > pk || (pv == pk && pi < pidx)) { pk = pv; pidx = pi; }
-      flags |= __shfl_xor(flags, o, kWave);
+    };
+    {
+      double pv; int pi;
+      pv = dpp_mov<0xB1>(pk); pi = dpp_mov<0xB1>(pidx); take(pv, pi);
+      pv = dpp_mov<0x4E>(pk); pi = dpp_mov<0x4E>(pidx); take(pv, pi);
+      pv = dpp_mov<0x141>(pk); pi = dpp_mov<0x141>(pidx); take(pv, pi);
+      pv = dpp_mov<0x140>(pk); pi = dpp_mov<0x140>(pidx); take(pv, pi);
+      double pr[4];
+      int ir[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        pr[i] = read_lane(pk, 16 * i);
+        ir[i] = read_lane(pidx, 16 * i);
+      }
+      pk = pr[0];
+      pidx = ir[0];
+      take(pr[1], ir[1]);
+      take(pr[2], ir[2]);
+      take(pr[3], ir[3]);
     }
+    flags = (uint32_t)dpp_mov<0xB1>((int)flags) | flags;
+    flags = (uint32_t)dpp_mov<0x4E>((int)flags) | flags;
+    flags = (uint32_t)dpp_mov<0x141>((int)flags) | flags;
+    flags = (uint32_t)dpp_mov<0x140>((int)flags) | flags;
+    flags = ((uint32_t)read_lane((int)flags, 0) |
+             (uint32_t)read_lane((int)flags, 16)) |
+            ((uint32_t)read_lane((int)flags, 32) |
+             (uint32_t)read_lane((int)flags, 48));
     if (lane == 0) {
       const double dS = to_double(S);
       double cx, cy;
