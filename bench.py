@@ -132,9 +132,9 @@ def run_plain(ctx, frames, p, tables):
     return n
 
 
-def cpu_baseline(frame_cpu, params, side=2048):
+def cpu_baseline(frame_cpu, params, side=2896):
     """The FP64 oracle on a side x side crop of one frame, one thread (about
-    10-20 s of CPU work)."""
+    10-30 s of CPU work)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     import oracle
