@@ -811,27 +811,6 @@ __device__ __forceinline__ U128 dpp128(U128 v) {
   r.hi = dpp_u64<CTRL>(v.hi);
   return r;
 }
-__device__ __forceinline__ U128 wave_sum128(U128 v) {
-  v = add128(v, dpp128<0xB1>(v));      // quad_perm [1,0,3,2]
-  v = add128(v, dpp128<0x4E>(v));      // quad_perm [2,3,0,1]
-  v = add128(v, dpp128<0x141>(v));     // row_half_mirror
-  v = add128(v, dpp128<0x140>(v));     // row_mirror
-  U128 r[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    r[i].lo = read_lane_u64(v.lo, 16 * i);
-    r[i].hi = read_lane_u64(v.hi, 16 * i);
-  }
-  return add128(add128(r[0], r[1]), add128(r[2], r[3]));
-}
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t u) {
-  u += dpp_u64<0xB1>(u);
-  u += dpp_u64<0x4E>(u);
-  u += dpp_u64<0x141>(u);
-  u += dpp_u64<0x140>(u);
-  return (read_lane_u64(u, 0) + read_lane_u64(u, 16)) +
-         (read_lane_u64(u, 32) + read_lane_u64(u, 48));
-}
 // Correctly rounded (to nearest, ties to even) conversion to binary64.
 __device__ double to_double(U128 v) {
   const bool neg = (int64_t)v.hi < 0;
@@ -861,6 +840,148 @@ __device__ __forceinline__ bool exact_range(float a) {
 
 }  // namespace
 
+// Sums of one lane's pixels of a candidate: D = v * 2^28 rounded to an
+// integer, and its first moments about the bounding-box corner.
+struct StatAcc {
+  U128 S, Sx, Sy;
+  uint64_t ux, uy;
+  double pk;
+  int pidx;
+  uint32_t flags;
+};
+
+__device__ __forceinline__ void stat_init(StatAcc& a) {
+  a.S = {0, 0};
+  a.Sx = {0, 0};
+  a.Sy = {0, 0};
+  a.ux = 0;
+  a.uy = 0;
+  a.pk = -__builtin_inf();
+  a.pidx = 0x7FFFFFFF;
+  a.flags = 0;
+}
+
+// Pixel (x, y) of frame fr for the candidate with the given label and
+// bounding-box corner (xmin, ymin).  The label and the two values are
+// loaded together; a pixel of another label contributes zeros.
+__device__ __forceinline__ void stat_pixel(StatAcc& a, const FrameDev& fr,
+                                           int label, int x, int y,
+                                           int xmin, int ymin) {
+  const double two_q = 268435456.0;                  // 2^28
+  const double dmax = 4611686018427387903.0;         // 2^62 - 1
+  const int64_t o = (int64_t)y * fr.w + x;
+  const bool mem = gld(fr.labels + o) == label;
+  const float I = gld(fr.pix + (int64_t)y * fr.pitch + x);
+  const float B = gld(fr.bkg + o);
+  const double v = (double)I - (double)B;
+  double s = rint(v * two_q);
+  bool inexact = !(exact_range(I) && exact_range(B));
+  if (s > dmax) { s = dmax; inexact = true; }
+  if (s < -dmax) { s = -dmax; inexact = true; }
+  if (mem && inexact) a.flags |= IPP_SRC_INEXACT_SUM_RANGE;
+  const int64_t D = mem ? (int64_t)s : 0;
+  a.S = add128(a.S, from_i64(D));
+  a.Sx = add128(a.Sx, mul_i64(D, x - xmin));
+  a.Sy = add128(a.Sy, mul_i64(D, y - ymin));
+  a.ux += mem ? (uint64_t)(x - xmin) : 0;
+  a.uy += mem ? (uint64_t)(y - ymin) : 0;
+  const int idx = y * fr.w + x;
+  if (mem && (v > a.pk || (v == a.pk && idx < a.pidx))) {
+    a.pk = v;
+    a.pidx = idx;
+  }
+}
+
+// Peak: largest value, ties to the smallest index (associative, so any
+// reduction order gives the same pair).
+__device__ __forceinline__ void stat_take(StatAcc& a, double pv, int pi) {
+  if (pv > a.pk || (pv == a.pk && pi < a.pidx)) {
+    a.pk = pv;
+    a.pidx = pi;
+  }
+}
+
+template <int CTRL>
+__device__ __forceinline__ void stat_dpp_step(StatAcc& a) {
+  a.S = add128(a.S, dpp128<CTRL>(a.S));
+  a.Sx = add128(a.Sx, dpp128<CTRL>(a.Sx));
+  a.Sy = add128(a.Sy, dpp128<CTRL>(a.Sy));
+  a.ux += dpp_u64<CTRL>(a.ux);
+  a.uy += dpp_u64<CTRL>(a.uy);
+  const double pv = dpp_mov<CTRL>(a.pk);
+  const int pi = dpp_mov<CTRL>(a.pidx);
+  stat_take(a, pv, pi);
+  a.flags |= (uint32_t)dpp_mov<CTRL>((int)a.flags);
+}
+
+// Every lane of each row of 16 lanes ends with that row's totals.
+__device__ __forceinline__ void stat_row16(StatAcc& a) {
+  stat_dpp_step<0xB1>(a);          // quad_perm [1,0,3,2]
+  stat_dpp_step<0x4E>(a);          // quad_perm [2,3,0,1]
+  stat_dpp_step<0x141>(a);         // row_half_mirror
+  stat_dpp_step<0x140>(a);         // row_mirror
+}
+
+// Totals of the whole wave (after stat_row16), wave-uniform.
+__device__ __forceinline__ void stat_rows_combine(StatAcc& a) {
+  StatAcc r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i].S.lo = read_lane_u64(a.S.lo, 16 * i);
+    r[i].S.hi = read_lane_u64(a.S.hi, 16 * i);
+    r[i].Sx.lo = read_lane_u64(a.Sx.lo, 16 * i);
+    r[i].Sx.hi = read_lane_u64(a.Sx.hi, 16 * i);
+    r[i].Sy.lo = read_lane_u64(a.Sy.lo, 16 * i);
+    r[i].Sy.hi = read_lane_u64(a.Sy.hi, 16 * i);
+    r[i].ux = read_lane_u64(a.ux, 16 * i);
+    r[i].uy = read_lane_u64(a.uy, 16 * i);
+    r[i].pk = read_lane(a.pk, 16 * i);
+    r[i].pidx = read_lane(a.pidx, 16 * i);
+    r[i].flags = (uint32_t)read_lane((int)a.flags, 16 * i);
+  }
+  a = r[0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i) {
+    a.S = add128(a.S, r[i].S);
+    a.Sx = add128(a.Sx, r[i].Sx);
+    a.Sy = add128(a.Sy, r[i].Sy);
+    a.ux += r[i].ux;
+    a.uy += r[i].uy;
+    stat_take(a, r[i].pk, r[i].pidx);
+    a.flags |= r[i].flags;
+  }
+}
+
+// Table row of a candidate from its totals.
+__device__ __forceinline__ void stat_finish(const StatAcc& a,
+                                            ipp_sources& src, long long row,
+                                            int xmin, int ymin, int fw) {
+  const double two_q = 268435456.0;
+  uint32_t flags = a.flags;
+  const double dS = to_double(a.S);
+  double cx, cy;
+  if ((int64_t)a.S.hi > 0 || ((int64_t)a.S.hi == 0 && a.S.lo > 0)) {
+    cx = (double)xmin + to_double(a.Sx) / dS;
+    cy = (double)ymin + to_double(a.Sy) / dS;
+  } else {
+    flags |= IPP_SRC_NONPOSITIVE_FLUX;
+    const double np = (double)src.npix[row];
+    cx = (double)xmin + (double)(long long)a.ux / np;
+    cy = (double)ymin + (double)(long long)a.uy / np;
+  }
+  src.flux_iso[row] = dS / two_q;
+  src.x[row] = cx;
+  src.y[row] = cy;
+  src.peak[row] = a.pk;
+  src.peak_x[row] = a.pidx % fw;
+  src.peak_y[row] = a.pidx / fw;
+  src.flags[row] = flags;
+}
+
+// One wavefront measures four consecutive table rows: those whose bounding
+// box holds at most 16 pixels together, one row of 16 lanes per candidate
+// (one pixel per lane, DPP reductions inside the row), then each larger one
+// over the whole wave.
 __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
                                                          ipp_sources src) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -871,105 +992,67 @@ __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
       blockIdx.x * (long long)kWaves +
       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const long long nw = (long long)gridDim.x * (kBlock / kWave);
-  const double two_q = 268435456.0;                  // 2^28
-  const double dmax = 4611686018427387903.0;         // 2^62 - 1
-  for (long long row = wid; row < nrows; row += nw) {
-    const int f = src.frame[row];
-    const int label = src.label[row];
-    const int xmin = src.xmin[row], xmax = src.xmax[row];
-    const int ymin = src.ymin[row], ymax = src.ymax[row];
-    const FrameDev fr = wk.frames[f];
-    const int bw = xmax - xmin + 1;
-    const long long area = (long long)bw * (ymax - ymin + 1);
-    U128 S = {0, 0}, Sx = {0, 0}, Sy = {0, 0};
-    long long ux = 0, uy = 0;
-    double pk = -__builtin_inf();
-    int pidx = 0x7FFFFFFF;
-    uint32_t flags = 0;
-    // bounding-box position of element e, stepped without divisions
-    int ey = lane / bw, ex = lane - (lane / bw) * bw;
-    const int dy = kWave / bw, dx = kWave - (kWave / bw) * bw;
-    for (long long e = lane; e < area; e += kWave) {
-      const int y = ymin + ey, x = xmin + ex;
-      ey += dy; ex += dx;
-      if (ex >= bw) { ex -= bw; ++ey; }
-      const int64_t o = (int64_t)y * fr.w + x;
-      // the label and the two values are loaded together; a pixel of
-      // another label contributes zeros
-      const bool mem = gld(fr.labels + o) == label;
-      const float I = gld(fr.pix + (int64_t)y * fr.pitch + x);
-      const float B = gld(fr.bkg + o);
-      const double v = (double)I - (double)B;
-      double s = rint(v * two_q);
-      bool inexact = !(exact_range(I) && exact_range(B));
-      if (s > dmax) { s = dmax; inexact = true; }
-      if (s < -dmax) { s = -dmax; inexact = true; }
-      if (mem && inexact) flags |= IPP_SRC_INEXACT_SUM_RANGE;
-      const int64_t D = mem ? (int64_t)s : 0;
-      S = add128(S, from_i64(D));
-      Sx = add128(Sx, mul_i64(D, x - xmin));
-      Sy = add128(Sy, mul_i64(D, y - ymin));
-      ux += mem ? x - xmin : 0;
-      uy += mem ? y - ymin : 0;
-      const int idx = y * fr.w + x;
-      if (mem && (v > pk || (v == pk && idx < pidx))) { pk = v; pidx = idx; }
+  const long long nquads = (nrows + 3) >> 2;
+  for (long long qd = wid; qd < nquads; qd += nw) {
+    const long long r0 = qd * 4;
+    const int seg = lane >> 4, sl = lane & 15;
+    const long long rowp = r0 + seg;
+    const bool have = rowp < nrows;
+    int pxmin = 0, pymin = 0, pbw = 1, parea = 0;
+    if (have) {
+      pxmin = src.xmin[rowp];
+      pymin = src.ymin[rowp];
+      pbw = src.xmax[rowp] - pxmin + 1;
+      parea = pbw * (src.ymax[rowp] - pymin + 1);
     }
-    S = wave_sum128(S);
-    Sx = wave_sum128(Sx);
-    Sy = wave_sum128(Sy);
-    ux = (long long)wave_sum_u64((uint64_t)ux);
-    uy = (long long)wave_sum_u64((uint64_t)uy);
-    // peak: largest value, ties to the smallest index (associative, so the
-    // reduction order does not matter)
-    auto take = [&](double pv, int pi) {
-      if (pv > pk || (pv == pk && pi < pidx)) { pk = pv; pidx = pi; }
-    };
-    {
-      double pv; int pi;
-      pv = dpp_mov<0xB1>(pk); pi = dpp_mov<0xB1>(pidx); take(pv, pi);
-      pv = dpp_mov<0x4E>(pk); pi = dpp_mov<0x4E>(pidx); take(pv, pi);
-      pv = dpp_mov<0x141>(pk); pi = dpp_mov<0x141>(pidx); take(pv, pi);
-      pv = dpp_mov<0x140>(pk); pi = dpp_mov<0x140>(pidx); take(pv, pi);
-      double pr[4];
-      int ir[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        pr[i] = read_lane(pk, 16 * i);
-        ir[i] = read_lane(pidx, 16 * i);
+    const bool small = have && parea <= 16;
+    const uint64_t smask = __builtin_amdgcn_ballot_w64(small);
+    if (smask) {
+      // ---- the small candidates, 16 lanes each -------------------------
+      StatAcc a;
+      stat_init(a);
+      int fw = 1;
+      if (small) {
+        const int f = src.frame[rowp];
+        const FrameDev fr = wk.frames[f];
+        fw = fr.w;
+        if (sl < parea) {
+          // small integers: the correctly rounded quotient floors exactly
+          const int ey = (int)((float)sl / (float)pbw);
+          const int ex = sl - ey * pbw;
+          stat_pixel(a, fr, src.label[rowp], pxmin + ex, pymin + ey, pxmin,
+                     pymin);
+        }
       }
-      pk = pr[0];
-      pidx = ir[0];
-      take(pr[1], ir[1]);
-      take(pr[2], ir[2]);
-      take(pr[3], ir[3]);
+      stat_row16(a);
+      if (small && sl == 0) stat_finish(a, src, rowp, pxmin, pymin, fw);
     }
-    flags = (uint32_t)dpp_mov<0xB1>((int)flags) | flags;
-    flags = (uint32_t)dpp_mov<0x4E>((int)flags) | flags;
-    flags = (uint32_t)dpp_mov<0x141>((int)flags) | flags;
-    flags = (uint32_t)dpp_mov<0x140>((int)flags) | flags;
-    flags = ((uint32_t)read_lane((int)flags, 0) |
-             (uint32_t)read_lane((int)flags, 16)) |
-            ((uint32_t)read_lane((int)flags, 32) |
-             (uint32_t)read_lane((int)flags, 48));
-    if (lane == 0) {
-      const double dS = to_double(S);
-      double cx, cy;
-      if ((int64_t)S.hi > 0 || ((int64_t)S.hi == 0 && S.lo > 0)) {
-        cx = (double)xmin + to_double(Sx) / dS;
-        cy = (double)ymin + to_double(Sy) / dS;
-      } else {
-        flags |= IPP_SRC_NONPOSITIVE_FLUX;
-        const double np = (double)src.npix[row];
-        cx = (double)xmin + (double)ux / np;
-        cy = (double)ymin + (double)uy / np;
+    // ---- each larger candidate over the whole wave -----------------------
+    for (int k = 0; k < 4; ++k) {
+      const long long row = r0 + k;
+      if (row >= nrows) break;
+      if ((smask >> (16 * k)) & 1ull) continue;
+      const int f = src.frame[row];
+      const int label = src.label[row];
+      const int xmin = src.xmin[row], xmax = src.xmax[row];
+      const int ymin = src.ymin[row], ymax = src.ymax[row];
+      const FrameDev fr = wk.frames[f];
+      const int bw = xmax - xmin + 1;
+      const long long area = (long long)bw * (ymax - ymin + 1);
+      StatAcc a;
+      stat_init(a);
+      // bounding-box position of element e, stepped without divisions
+      int ey = lane / bw, ex = lane - (lane / bw) * bw;
+      const int dy = kWave / bw, dx = kWave - (kWave / bw) * bw;
+      for (long long e = lane; e < area; e += kWave) {
+        const int y = ymin + ey, x = xmin + ex;
+        ey += dy; ex += dx;
+        if (ex >= bw) { ex -= bw; ++ey; }
+        stat_pixel(a, fr, label, x, y, xmin, ymin);
       }
-      src.flux_iso[row] = dS / two_q;
-      src.x[row] = cx;
-      src.y[row] = cy;
-      src.peak[row] = pk;
-      src.peak_x[row] = pidx % fr.w;
-      src.peak_y[row] = pidx / fr.w;
-      src.flags[row] = flags;
+      stat_row16(a);
+      stat_rows_combine(a);
+      if (lane == 0) stat_finish(a, src, row, xmin, ymin, fr.w);
     }
   }
 }

@@ -413,13 +413,15 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
       const double r = kind == 0 ? p.r_ap : (kind == 2 ? p.r_in : p.r_out);
       const double r2 = kind == 0 ? r2a : (kind == 2 ? r2i : r2o);
       double w = overlap_c(c, r, r2, wx, wy, coef);
-      const uint32_t qr = (uint32_t)(py - ry0);
-      const float I =
-          gld((const float*)(wpix + (qr * pitchB + (uint32_t)px * 4u)));
-      const double v =
-          (double)I -
-          (double)gld((const float*)(wbkg + (qr * wB + (uint32_t)px * 4u)));
       if (kind == 0) {
+        // only the aperture needs the value here (annulus values are in
+        // the value list already)
+        const uint32_t qr = (uint32_t)(py - ry0);
+        const float I =
+            gld((const float*)(wpix + (qr * pitchB + (uint32_t)px * 4u)));
+        const double v =
+            (double)I -
+            (double)gld((const float*)(wbkg + (qr * wB + (uint32_t)px * 4u)));
         a_ap += w;
         raw += w * v;
       } else {
