@@ -174,13 +174,116 @@ def flux_error_sample(frame_cpu, bkg_cpu, table_rows, params, k=64):
                         / scale))
 
 
+GRAD_DESC = ("64 frames of 2048x2048 float32, 2000 Gaussian stars each, "
+             "centroid guesses = truth + N(0, 0.3^2) px per axis")
+
+
+def run_grad(args):
+    """The differentiable part: forward + backward of the aperture flux for
+    every centroid guess of the 64-frame stack (one refinement step, Sec.
+    2.2.5 photometry with its adjoint), and the asinh stretch forward +
+    backward over the stack (Sec. 2.2.6 gray-scale map)."""
+    import torch
+    import paper_2502_10783_amd as ipp
+    from synth import spec_for, render
+
+    dev = torch.device("cuda:0")
+    n = args.frames or 64
+    log(f"generating {n} frames of grad64 on the GPU")
+    rend = [render(spec_for("grad64", i), "grad64", i, dev) for i in range(n)]
+    frames = [r[0] for r in rend]
+    xg = torch.cat([r[1]["x_guess"] for r in rend]).to(torch.float64)
+    yg = torch.cat([r[1]["y_guess"] for r in rend]).to(torch.float64)
+    fi = torch.cat([torch.full((r[1]["x_guess"].numel(),), k,
+                               dtype=torch.int32, device=dev)
+                    for k, r in enumerate(rend)])
+    s = xg.numel()
+    p = ipp.Params()
+    ctx = ipp.Context(0)
+    out = ctx.process_batch(frames, p)
+    bkg = out["bkg"]
+    t = ipp.SourceTable(s, n, dev)
+    t.cols["frame"][:s] = fi
+    t.cols["x"][:s] = xg
+    t.cols["y"][:s] = yg
+    g = torch.ones(s, dtype=torch.float64, device=dev)
+
+    def step():
+        lohi = ctx.photometry(frames, bkg, t, p, keep_sky=True,
+                              use_count=False)
+        return ctx.photometry_backward(frames, bkg, t, p, lohi, g)
+
+    v = torch.stack(frames) - torch.stack(bkg)
+    dy = torch.ones_like(v)
+    a, b = 30.0, 1.0
+
+    def timed(fn, k):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    log(f"timing {args.steps} forward+backward photometry steps")
+    ms = timed(step, args.steps)
+    ms_fwd = timed(lambda: ctx.asinh(v, a, b), args.steps)
+    ms_bwd = timed(lambda: ctx.asinh_backward(v, dy, a, b), args.steps)
+    ctx.profile(True)
+    for _ in range(3):
+        step()
+        ctx.asinh(v, a, b)
+        ctx.asinh_backward(v, dy, a, b)
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    npx = v.numel()
+    res = {
+        "metric": "sources/s, aperture flux forward + backward (one "
+                  "refinement step)",
+        "value": round(s / (ms * 1e-3), 1),
+        "unit": "sources/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": GRAD_DESC if n == 64 else
+                   f"first {n} frames of: {GRAD_DESC}", "name": "grad64",
+                   "frames": n, "sources": s,
+                   "aperture": [p.r_ap, p.r_in, p.r_out]},
+        "asinh": {
+            "forward_ms": round(ms_fwd, 4),
+            "forward_GBps": round(8 * npx / (ms_fwd * 1e-3) / 1e9, 1),
+            "backward_ms": round(ms_bwd, 4),
+            "backward_GBps": round(12 * npx / (ms_bwd * 1e-3) / 1e9, 1),
+            "backward_frac_of_hbm": round(
+                12 * npx / (ms_bwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_px": {"forward": 8, "backward": 12}},
+        "kernels_ms": {k: round(v0 / v1, 4) for k, (v0, v1) in
+                       sorted(prof.items(), key=lambda kv: -kv[1][0])},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS),
-                    default="stack16")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["grad64"],
+                    default="stack16",
+                    help="grad64: the forward + backward of the aperture "
+                         "flux and of the asinh stretch (its own metric)")
     ap.add_argument("--frames", type=int, default=0,
                     help="frames of the workload to use (0 = all)")
     ap.add_argument("--autotune", action="store_true",
@@ -198,6 +301,10 @@ def main():
               "MI355X and has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "grad64":
+        run_grad(args)
+        return
 
     import torch
     import paper_2502_10783_amd as ipp
