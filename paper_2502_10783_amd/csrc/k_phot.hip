@@ -568,17 +568,106 @@ namespace {
 
 template <int NS>
 struct BwLds {
-  int apb[kApTasks];
-  double apw[kApTasks];
-  int anb[NS];
-  double anw[NS];
+  // cut pixels: kind << 28 | wy << 6 | wx (kind 0: aperture, 1: annulus
+  // survivor), and their weights
+  int tk[NS + kApTasks];
+  double tw[NS + kApTasks];
+  double sq[3 * 2 * kEdges];     // edge square roots, as in the forward
 };
+
+// Per pixel of a source window, round by round (64 pixels): its window
+// position, the exact membership distances and its two values.  Windows
+// inside the frame load through 32-bit offsets advanced by constant steps;
+// others through offsets clamped into the frame.
+struct WinWalk {
+  int xa, ya, nwx, npx, ry0;
+  bool interior;
+  const char* wpix;
+  const char* wbkg;
+  uint32_t pitchB, wB, stepP, stepB, wrapP, wrapB;
+  int w, h, dwr, dwc;
+  int wr, wc;
+  uint32_t offp, offb;
+
+  __device__ void init(const FrameDev& fr, int xa_, int xb, int ya_, int yb,
+                       int lane) {
+    xa = xa_;
+    ya = ya_;
+    nwx = xb - xa + 1;
+    npx = nwx * (yb - ya + 1);
+    w = fr.w;
+    h = fr.h;
+    ry0 = min(max(ya, 0), fr.h - 1);
+    wpix = uniform_ptr((const char*)(fr.pix + (int64_t)ry0 * fr.pitch));
+    wbkg = uniform_ptr((const char*)(fr.bkg + (int64_t)ry0 * fr.w));
+    pitchB = (uint32_t)fr.pitch * 4u;
+    wB = (uint32_t)fr.w * 4u;
+    interior = xa >= 0 && ya >= 0 && xb < fr.w && yb < fr.h;
+    dwr = kWave / nwx;
+    dwc = kWave - dwr * nwx;
+    stepP = (uint32_t)dwr * pitchB + (uint32_t)dwc * 4u;
+    stepB = (uint32_t)dwr * wB + (uint32_t)dwc * 4u;
+    wrapP = pitchB - (uint32_t)nwx * 4u;
+    wrapB = wB - (uint32_t)nwx * 4u;
+    wr = lane / nwx;
+    wc = lane - wr * nwx;
+    offp = (uint32_t)wr * pitchB + (uint32_t)(xa + wc) * 4u;
+    offb = (uint32_t)wr * wB + (uint32_t)(xa + wc) * 4u;
+  }
+  // values of the current pixel; inside: the pixel lies in the frame
+  __device__ void load(bool live, float* I, float* B, bool* inside) const {
+    const int px = xa + wc, py = ya + wr;
+    if (interior) {
+      *inside = true;
+      *I = gld((const float*)(wpix + (live ? offp : 0u)));
+      *B = gld((const float*)(wbkg + (live ? offb : 0u)));
+    } else {
+      *inside = (px >= 0) & (px < w) & (py >= 0) & (py < h);
+      const uint32_t qx = (uint32_t)min(max(px, 0), w - 1);
+      const uint32_t qr = (uint32_t)(min(max(py, 0), h - 1) - ry0);
+      *I = gld((const float*)(wpix + (qr * pitchB + qx * 4u)));
+      *B = gld((const float*)(wbkg + (qr * wB + qx * 4u)));
+    }
+  }
+  __device__ void advance() {
+    wr += dwr;
+    wc += dwc;
+    offp += stepP;
+    offb += stepB;
+    if (wc >= nwx) {
+      wc -= nwx;
+      ++wr;
+      offp += wrapP;
+      offb += wrapB;
+    }
+  }
+  // value of window pixel (wx, wy) (in the frame)
+  __device__ double value_at(int wx, int wy) const {
+    const uint32_t qr = (uint32_t)(ya + wy - ry0);
+    const uint32_t qx = (uint32_t)(xa + wx);
+    return (double)gld((const float*)(wpix + (qr * pitchB + qx * 4u))) -
+           (double)gld((const float*)(wbkg + (qr * wB + qx * 4u)));
+  }
+};
+
+// Nearest and farthest squared distance of window pixel (px, py) from the
+// centre (the membership predicates compare them with r^2).
+__device__ __forceinline__ void pixel_dist2(double cx, double cy, int px,
+                                            int py, double* near2,
+                                            double* far2) {
+  const double ax = fabs((double)px - cx), ay = fabs((double)py - cy);
+  const double nx = fmax(ax - 0.5, 0.0), ny = fmax(ay - 0.5, 0.0);
+  const double fx = ax + 0.5, fy = ay + 0.5;
+  *near2 = nx * nx + ny * ny;
+  *far2 = fx * fx + fy * fy;
+}
 
 template <int NS>
 __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
                                  const ipp_sources& src,
                                  const double* sky_lohi, const double* gF,
-                                 double* dxy, long long row, BwLds<NS>& L) {
+                                 double* dxy, long long row, BwLds<NS>& L,
+                                 const double* atan_lds) {
   const int lane = threadIdx.x & (kWave - 1);
   const int f = src.frame[row];
   const double cx = src.x[row], cy = src.y[row];
@@ -597,140 +686,153 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   const int xb = __builtin_amdgcn_readfirstlane((int)floor(cx + R + 0.5));
   const int ya = __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5));
   const int yb = __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5));
-  const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
+  const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
+  const double ro2 = p.r_out * p.r_out;
 
-  // pass 1: sums, with the cut pixels' weights kept in LDS
-  double A = 0.0, W = 0.0, Sv = 0.0;
-  double tvx = 0.0, tvy = 0.0, tax = 0.0, tay = 0.0;   // aperture terms
-  double svx = 0.0, svy = 0.0, swx = 0.0, swy = 0.0;   // sky terms
-  int nap = 0, nan_ = 0;
-  for (int e0 = 0; e0 < npx; e0 += kWave) {
-    const int e = e0 + lane;
-    bool ap_cut = false, an_cut = false;
-    if (e < npx) {
-      const int px = xa + e % nwx, py = ya + e / nwx;
-      const bool in_ap = touches(cx, cy, p.r_ap, px, py);
-      const bool in_ann = touches(cx, cy, p.r_out, px, py) &&
-                          !within(cx, cy, p.r_in, px, py);
-      if ((in_ap || in_ann) && px >= 0 && px < fr.w && py >= 0 &&
-          py < fr.h) {
-        const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
-        if (isfinite(I)) {
-          const double v =
-              (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
-          if (in_ap) {
-            if (within(cx, cy, p.r_ap, px, py)) A += 1.0;
-            else ap_cut = true;
-          }
-          if (in_ann && v >= vlo && v <= vhi) {
-            if (within(cx, cy, p.r_out, px, py) &&
-                !touches(cx, cy, p.r_in, px, py)) {
-              W += 1.0;
-              Sv += v;
-            } else {
-              an_cut = true;
-            }
-          }
-        }
-      }
+  // ---- pass 1: whole pixels summed, cut pixels listed ------------------
+  // (aperture members: the square meets the disk; annulus survivors: it
+  // meets the outer disk, is not inside the inner one, and its value lies
+  // in the forward's [vlo, vhi])
+  WinWalk W0;
+  W0.init(fr, xa, xb, ya, yb, lane);
+  double A = 0.0, Wt = 0.0, Sv = 0.0;
+  int ntk = 0;
+  for (int e0 = 0; e0 < W0.npx; e0 += kWave) {
+    const bool live = e0 + lane < W0.npx;
+    const int px = xa + W0.wc, py = ya + W0.wr;
+    const int pos = (W0.wr << 6) | W0.wc;
+    float I, B;
+    bool inside;
+    W0.load(live, &I, &B, &inside);
+    double near2, far2;
+    pixel_dist2(cx, cy, px, py, &near2, &far2);
+    W0.advance();
+    const bool ok = live & inside & isfinite(I);
+    const double v = (double)I - (double)B;
+    const bool in_ap = ok & (near2 < ra2);
+    const bool in_ann = ok & (near2 < ro2) & !(far2 <= ri2) & (v >= vlo) &
+                        (v <= vhi);
+    const bool ap_whole = in_ap & (far2 <= ra2);
+    const bool ann_whole = in_ann & (far2 <= ro2) & !(near2 < ri2);
+    A += ap_whole ? 1.0 : 0.0;
+    if (ann_whole) {
+      Wt += 1.0;
+      Sv += v;
     }
+    const bool ap_cut = in_ap & !ap_whole, ann_cut = in_ann & !ann_whole;
     const uint64_t b1 = ballot(ap_cut);
     if (ap_cut) {
-      const int s = nap + lanes_before(b1);
-      if (s < kApTasks) L.apb[s] = e;
+      const int s = ntk + lanes_before(b1);
+      if (s < NS + kApTasks) L.tk[s] = pos;
     }
-    nap += __popcll(b1);
-    const uint64_t b2 = ballot(an_cut);
-    if (an_cut) {
-      const int s = nan_ + lanes_before(b2);
-      if (s < NS) L.anb[s] = e;
+    ntk += __popcll(b1);
+    const uint64_t b2 = ballot(ann_cut);
+    if (ann_cut) {
+      const int s = ntk + lanes_before(b2);
+      if (s < NS + kApTasks) L.tk[s] = (1 << 28) | pos;
     }
-    nan_ += __popcll(b2);
+    ntk += __popcll(b2);
   }
-  if (nap > kApTasks) nap = kApTasks;
-  if (nan_ > NS) nan_ = NS;
+  if (ntk > NS + kApTasks) ntk = NS + kApTasks;   // not reachable
+  // edge square roots of the window for the three circles
+  for (int e = lane; e < 6 * kEdges; e += kWave) {
+    const int c = e / (2 * kEdges), j = e % kEdges;
+    const bool col = (e / kEdges) % 2 == 0;
+    const double r = c == 0 ? p.r_ap : (c == 1 ? p.r_out : p.r_in);
+    const double r2 = c == 0 ? ra2 : (c == 1 ? ro2 : ri2);
+    const double q = col ? ((double)(xa + j) - 0.5) - cx
+                         : ((double)(ya + j) - 0.5) - cy;
+    L.sq[e] = edge_root(q, r, r2);
+  }
   wave_lds_sync();
-  for (int j = lane; j < nap; j += kWave) {
-    const int e = L.apb[j];
-    const int px = xa + e % nwx, py = ya + e / nwx;
-    const double v = (double)gld(fr.pix + (int64_t)py * fr.pitch + px) -
-                     (double)gld(fr.bkg + (int64_t)py * fr.w + px);
-    const double w = overlap(cx, cy, p.r_ap, px, py);
-    L.apw[j] = w;
-    A += w;
-    double gx, gy;
-    overlap_grad(cx, cy, p.r_ap, px, py, &gx, &gy);
-    tvx += v * gx; tvy += v * gy;
-    tax += gx; tay += gy;
+
+  // ---- pass 2: the cut pixels' weights and centre derivatives ----------
+  double tvx = 0.0, tvy = 0.0, tax = 0.0, tay = 0.0;   // aperture terms
+  double svx = 0.0, svy = 0.0, swx = 0.0, swy = 0.0;   // sky terms
+  for (int j = lane; j < ntk; j += kWave) {
+    int co = 0;
+    asm volatile("" : "+s"(co));
+    const double* coef = atan_lds + co;
+    const int t = L.tk[j];
+    const int wx = t & 63, wy = (t >> 6) & 63;
+    const int px = xa + wx, py = ya + wy;
+    const double v = W0.value_at(wx, wy);
+    // overlap and its centre derivative for circle c
+    auto circle = [&](int c, double r, double r2, double* gx, double* gy) {
+      const double* sq = L.sq + c * 2 * kEdges;
+      const double hx0 = sq[wx], hx1 = sq[wx + 1];
+      const double xs0 = sq[kEdges + wy], xs1 = sq[kEdges + wy + 1];
+      overlap_grad_roots(cx, cy, px, py, hx0, hx1, xs0, xs1, gx, gy);
+      if (!touches(cx, cy, r, px, py)) return 0.0;
+      if (within(cx, cy, r, px, py)) return 1.0;
+      return overlap_cut(cx, cy, r, r2, px, py, hx0, hx1, xs0, xs1, coef);
+    };
+    double w, gx, gy;
+    if ((t >> 28) == 0) {
+      w = circle(0, p.r_ap, ra2, &gx, &gy);
+      A += w;
+      tvx += v * gx; tvy += v * gy;
+      tax += gx; tay += gy;
+    } else {
+      double ix, iy;
+      w = circle(1, p.r_out, ro2, &gx, &gy) -
+          circle(2, p.r_in, ri2, &ix, &iy);
+      gx -= ix;
+      gy -= iy;
+      Wt += w;
+      Sv += w * v;
+      svx += v * gx; svy += v * gy;
+      swx += gx; swy += gy;
+    }
+    L.tw[j] = w;
   }
-  // interior aperture pixels have zero centre derivative; the interior
-  // annulus survivors too
-  for (int j = lane; j < nan_; j += kWave) {
-    const int e = L.anb[j];
-    const int px = xa + e % nwx, py = ya + e / nwx;
-    const double v = (double)gld(fr.pix + (int64_t)py * fr.pitch + px) -
-                     (double)gld(fr.bkg + (int64_t)py * fr.w + px);
-    const double w = overlap(cx, cy, p.r_out, px, py) -
-                     overlap(cx, cy, p.r_in, px, py);
-    L.anw[j] = w;
-    W += w;
-    Sv += w * v;
-    double ox, oy, ix, iy;
-    overlap_grad(cx, cy, p.r_out, px, py, &ox, &oy);
-    overlap_grad(cx, cy, p.r_in, px, py, &ix, &iy);
-    svx += v * (ox - ix); svy += v * (oy - iy);
-    swx += ox - ix; swy += oy - iy;
-  }
-  // interior aperture pixels also contribute v to nothing else; finish sums
   A = wave_sum(A);
-  W = wave_sum(W);
+  Wt = wave_sum(Wt);
   Sv = wave_sum(Sv);
   tvx = wave_sum(tvx); tvy = wave_sum(tvy);
   tax = wave_sum(tax); tay = wave_sum(tay);
   svx = wave_sum(svx); svy = wave_sum(svy);
   swx = wave_sum(swx); swy = wave_sum(swy);
-  const double sky = W > 0.0 ? Sv / W : 0.0;
+  const double sky = Wt > 0.0 ? Sv / Wt : 0.0;
   if (lane == 0 && dxy) {
     double dsx = 0.0, dsy = 0.0;
-    if (W > 0.0) {
-      dsx = (svx - sky * swx) / W;
-      dsy = (svy - sky * swy) / W;
+    if (Wt > 0.0) {
+      dsx = (svx - sky * swx) / Wt;
+      dsy = (svy - sky * swy) / Wt;
     }
     dxy[2 * row] = g * ((tvx - sky * tax) - A * dsx);
     dxy[2 * row + 1] = g * ((tvy - sky * tay) - A * dsy);
   }
   float* dp = fr.dpix;
   if (!dp) { wave_lds_sync(); return; }
-  const double ks = W > 0.0 ? -g * A / W : 0.0;
-  // pass 2: scatter dL/dv
-  for (int e0 = 0; e0 < npx; e0 += kWave) {
-    const int e = e0 + lane;
-    if (e >= npx) continue;
-    const int px = xa + e % nwx, py = ya + e / nwx;
-    if (px < 0 || px >= fr.w || py < 0 || py >= fr.h) continue;
-    const bool in_ap = touches(cx, cy, p.r_ap, px, py);
-    const bool in_ann = touches(cx, cy, p.r_out, px, py) &&
-                        !within(cx, cy, p.r_in, px, py);
-    if (!(in_ap || in_ann)) continue;
-    const float I = gld(fr.pix + (int64_t)py * fr.pitch + px);
-    if (!isfinite(I)) continue;
-    const double v = (double)I - (double)gld(fr.bkg + (int64_t)py * fr.w + px);
-    double gd = 0.0;
-    if (in_ap && within(cx, cy, p.r_ap, px, py)) gd += g;
-    if (in_ann && v >= vlo && v <= vhi && within(cx, cy, p.r_out, px, py) &&
-        !touches(cx, cy, p.r_in, px, py))
-      gd += ks;
+
+  // ---- pass 3: scatter dL/dv (whole pixels, then the cut ones) ---------
+  const double ks = Wt > 0.0 ? -g * A / Wt : 0.0;
+  WinWalk W1;
+  W1.init(fr, xa, xb, ya, yb, lane);
+  for (int e0 = 0; e0 < W1.npx; e0 += kWave) {
+    const bool live = e0 + lane < W1.npx;
+    const int px = xa + W1.wc, py = ya + W1.wr;
+    float I, B;
+    bool inside;
+    W1.load(live, &I, &B, &inside);
+    double near2, far2;
+    pixel_dist2(cx, cy, px, py, &near2, &far2);
+    W1.advance();
+    const bool ok = live & inside & isfinite(I);
+    const double v = (double)I - (double)B;
+    const bool ap_whole = ok & (near2 < ra2) & (far2 <= ra2);
+    const bool ann_whole = ok & (near2 < ro2) & !(far2 <= ri2) &
+                           (v >= vlo) & (v <= vhi) & (far2 <= ro2) &
+                           !(near2 < ri2);
+    const double gd = (ap_whole ? g : 0.0) + (ann_whole ? ks : 0.0);
     if (gd != 0.0) atomicAdd(&dp[(int64_t)py * fr.w + px], (float)gd);
   }
-  for (int j = lane; j < nap; j += kWave) {
-    const int e = L.apb[j];
-    const int px = xa + e % nwx, py = ya + e / nwx;
-    atomicAdd(&dp[(int64_t)py * fr.w + px], (float)(g * L.apw[j]));
-  }
-  for (int j = lane; j < nan_; j += kWave) {
-    const int e = L.anb[j];
-    const int px = xa + e % nwx, py = ya + e / nwx;
-    atomicAdd(&dp[(int64_t)py * fr.w + px], (float)(ks * L.anw[j]));
+  for (int j = lane; j < ntk; j += kWave) {
+    const int t = L.tk[j];
+    const int px = xa + (t & 63), py = ya + ((t >> 6) & 63);
+    const double k = (t >> 28) == 0 ? g : ks;
+    atomicAdd(&dp[(int64_t)py * fr.w + px], (float)(k * L.tw[j]));
   }
   wave_lds_sync();
 }
@@ -738,10 +840,14 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
 }  // namespace
 
 template <int NS>
-__global__ __launch_bounds__(kBlock) void k_aperture_bwd_t(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_aperture_bwd_t(
     Work wk, ipp_params p, ipp_sources src, const double* sky_lohi,
     const double* gF, double* dxy) {
   __shared__ BwLds<NS> L[kWaves];
+  __shared__ double atan_lds[kAtanTerms];
+  if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
+  __syncthreads();
   long long nrows = src.capacity;
   if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
   // wave index made provably uniform, so per-row loads are scalar
@@ -751,7 +857,8 @@ __global__ __launch_bounds__(kBlock) void k_aperture_bwd_t(
   const long long nw = (long long)gridDim.x * kWaves;
   BwLds<NS>& mine = L[threadIdx.x / kWave];
   for (long long row = wid; row < nrows; row += nw)
-    aperture_bwd_one<NS>(wk, p, src, sky_lohi, gF, dxy, row, mine);
+    aperture_bwd_one<NS>(wk, p, src, sky_lohi, gF, dxy, row, mine,
+                         atan_lds);
 }
 
 template __global__ void k_aperture_bwd_t<256>(

@@ -160,6 +160,21 @@ __device__ __forceinline__ double chord(double x, double y, double r) {
   return copysign(fmin(fabs(y), h), y);
 }
 
+// (d/dcx, d/dcy) of the overlap of pixel (px, py) with the disk of radius
+// r about (cx, cy), from the pixel's four edge roots (as for overlap_cut):
+// the chord at an edge x is sign(y) min(|y|, sqrt(r^2 - x^2)).
+__device__ __forceinline__ void overlap_grad_roots(double cx, double cy,
+                                                   int px, int py,
+                                                   double hx0, double hx1,
+                                                   double xs0, double xs1,
+                                                   double* gx, double* gy) {
+  const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
+  const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
+  auto ch = [](double h, double y) { return copysign(fmin(fabs(y), h), y); };
+  *gx = -(ch(hx1, y1) - ch(hx0, y1) - ch(hx1, y0) + ch(hx0, y0));
+  *gy = -(ch(xs1, x1) - ch(xs0, x1) - ch(xs1, x0) + ch(xs0, x0));
+}
+
 // (d/dcx, d/dcy) of overlap(cx, cy, r, px, py).
 __device__ __forceinline__ void overlap_grad(double cx, double cy, double r,
                                              int px, int py, double* gx,
