@@ -260,6 +260,26 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   // test: its offsets advance by constant steps.
   const bool interior = xa >= 0 && ya >= 0 && xb < fr.w && yb < fr.h;
 
+  // Squared nearest and farthest offsets of every window column and row
+  // from the centre (the pixel's distances are sums of one of each: the
+  // same two rounded squares and the same addition as computing them per
+  // pixel).  They occupy the edge-root table, which is filled only after
+  // the classification.
+  double2* colT = (double2*)L.sq;              // [kEdges]
+  double2* rowT = colT + kEdges;               // [kEdges]
+  for (int e = lane; e < 2 * kEdges; e += kWave) {
+    const bool col = e < kEdges;
+    const int j = col ? e : e - kEdges;
+    const double a = col ? fabs((double)(xa + j) - cx)
+                         : fabs((double)(ya + j) - cy);
+    const double n = fmax(a - 0.5, 0.0), fo = a + 0.5;
+    double2 t;
+    t.x = n * n;
+    t.y = fo * fo;
+    (col ? colT : rowT)[j] = t;
+  }
+  wave_lds_sync();
+
   auto classify = [&](auto edge_tag) {
     constexpr bool EDGE = decltype(edge_tag)::value;
     int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;  // window row, col
@@ -284,10 +304,9 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
         const bool live = e < npx;
         pos[c] = (wr << 6) | wc;
         // nearest and farthest point of the pixel square (touches / within)
-        const double ax = fabs((double)px - cx), ay = fabs((double)py - cy);
-        const double nx = fmax(ax - 0.5, 0.0), ny = fmax(ay - 0.5, 0.0);
-        const double fx = ax + 0.5, fy = ay + 0.5;
-        const double near2 = nx * nx + ny * ny, far2 = fx * fx + fy * fy;
+        // (a lane past the window end reads a valid row of the table)
+        const double2 tc = colT[wc], tr = rowT[min(wr, kEdges - 1)];
+        const double near2 = tc.x + tr.x, far2 = tc.y + tr.y;
         // (bitwise logic: no branches)
         const bool in_ap = live & (near2 < ra2);
         const bool in_ann = live & (near2 < ro2) & !(far2 <= ri2);
