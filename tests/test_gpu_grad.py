@@ -125,6 +125,31 @@ def test_asinh_forward_backward(ctx):
     assert abs(dab[1] - dbr) <= 1e-9 * np.sum(np.abs(g * np.arcsinh(v / a)))
 
 
+def test_asinh_unaligned_and_ragged(ctx):
+    """Element counts that leave a tail after the groups of four, and
+    arrays that do not start on a 16-byte boundary (the element loop then
+    takes one element at a time)."""
+    rng = np.random.default_rng(12)
+    a, b = 17.0, 0.8
+    for n, off in ((4099, 0), (4101, 1), (9, 3), (1, 0)):
+        base = rng.normal(0, 500, n + off).astype(np.float32)
+        gb = rng.normal(0, 1, n + off).astype(np.float32)
+        vt = torch.from_numpy(base).to(DEV)[off:]
+        gt = torch.from_numpy(gb).to(DEV)[off:]
+        v, g = base[off:], gb[off:]
+        y = ctx.asinh(vt, a, b).cpu().numpy()
+        dv, dab = ctx.asinh_backward(vt, gt, a, b)
+        torch.cuda.synchronize()
+        yr = ost.asinh_forward(v, a, b)
+        dvr, dar, dbr = ost.asinh_backward(v, g, a, b)
+        np.testing.assert_allclose(y, yr, rtol=2e-6, atol=1e-6)
+        np.testing.assert_allclose(dv.cpu().numpy(), dvr, rtol=2e-6,
+                                   atol=1e-9)
+        dab = dab.cpu().numpy()
+        assert abs(dab[0] - dar) <= 1e-9 * np.sum(np.abs(g * v / a)) + 1e-300
+        assert abs(dab[1] - dbr) <= 1e-9 * np.sum(np.abs(g * np.arcsinh(v / a)))
+
+
 def test_autograd_functions(ctx, scene):
     img, bkg, xs, ys = scene
     p, op = ipp.Params(), oracle.Params()

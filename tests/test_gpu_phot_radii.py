@@ -93,3 +93,37 @@ def test_photometry_radii(ctx, scene, radii):
                                atol=1e-12)
     err = np.abs(got["flux_ap"][ok] - ph["flux"][ok]) / _flux_scale(ph)[ok]
     assert err.max() <= 1e-5, err.max()
+
+
+@pytest.mark.parametrize("radii", [RADII[0], RADII[3], RADII[5]],
+                         ids=lambda r: "%g-%g-%g" % r)
+def test_backward_radii(ctx, scene, radii):
+    """The flux adjoint over the same radius sets and centres (windows over
+    the frame edge included) against the oracle's adjoint: centre gradient
+    and pixel gradient to 1e-4."""
+    img, bkg, xs, ys = scene
+    r_ap, r_in, r_out = radii
+    p = ipp.Params(r_ap=r_ap, r_in=r_in, r_out=r_out)
+    op = oracle.Params(r_ap=r_ap, r_in=r_in, r_out=r_out)
+    k = xs.size
+    g = np.random.default_rng(5).normal(size=k)
+    t = ipp.SourceTable(k, 1, DEV)
+    t.cols["frame"][:k] = 0
+    t.cols["x"][:k] = torch.from_numpy(xs).to(DEV)
+    t.cols["y"][:k] = torch.from_numpy(ys).to(DEV)
+    fr, bk = img.to(DEV), bkg.to(DEV)
+    lohi = ctx.photometry([fr], [bk], t, p, keep_sky=True, use_count=False)
+    dp = torch.zeros_like(fr)
+    dxy = ctx.photometry_backward([fr], [bk], t, p, lohi,
+                                  torch.from_numpy(g).to(DEV), dpix=[dp])
+    torch.cuda.synchronize()
+    dxy = dxy[:k].cpu().numpy()
+    ref = oph.photometry(img.numpy(), bkg.numpy(), xs, ys, op)
+    gpix, gx, gy = oph.photometry_adjoint(img.numpy(), bkg.numpy(), xs, ys,
+                                          op, ref["sky_pixels"], g)
+    for j in range(k):
+        want = np.array([gx[j], gy[j]])
+        err = np.linalg.norm(dxy[j] - want)
+        assert err <= 1e-4 * np.linalg.norm(want) + 1e-9, (j, dxy[j], want)
+    scale = np.abs(gpix).max()
+    assert np.max(np.abs(dp.cpu().numpy() - gpix)) <= 1e-4 * scale
