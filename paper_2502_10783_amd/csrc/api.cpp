@@ -174,7 +174,8 @@ struct Plan {
   int th = 64, tw = 64;
   // byte offsets
   size_t o_frames, o_mbkg, o_mrms, o_mn, o_fbkg, o_frms, o_fpass, o_tb[4],
-      o_tr[4], o_sc0, o_sc1, o_flags, o_tmap, o_rbase, o_recs, o_rparent,
+      o_tr[4], o_sc0, o_sc1, o_flags, o_tmap, o_tedge, o_rbase, o_recs,
+      o_rparent,
       o_rlabel, o_bucket, o_rowc, o_rows, o_rowcur, o_scanb, o_cnt, total;
 };
 
@@ -233,6 +234,8 @@ Plan make_plan(const ipp_frame* f, int32_t n, const ipp_params& p,
   P.o_flags = take(4 * (size_t)n);
   P.o_tmap = take((size_t)kTmapBytes *
                   (size_t)(mode == kPlanDetect ? P.dtiles : 0));
+  P.o_tedge = take(4 * (size_t)kEdgeInts *
+                   (size_t)(mode == kPlanDetect ? P.dtiles : 0));
   P.o_rbase = take(4 * (size_t)(mode == kPlanDetect ? P.dtiles : 0));
   P.o_recs = take(sizeof(Rec) * (size_t)P.rec_cap);
   P.o_rparent = take(4 * (size_t)P.rec_cap);
@@ -273,6 +276,7 @@ Work make_work(const Plan& P, void* ws, int32_t n) {
   w.sc1 = (double*)(b + P.o_sc1);
   w.frame_flags = (uint32_t*)(b + P.o_flags);
   w.tmap = (uint8_t*)(b + P.o_tmap);
+  w.tedge = (int32_t*)(b + P.o_tedge);
   w.tile_rbase = (int32_t*)(b + P.o_rbase);
   w.recs = (Rec*)(b + P.o_recs);
   w.rparent = (int32_t*)(b + P.o_rparent);

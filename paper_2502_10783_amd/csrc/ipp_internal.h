@@ -74,6 +74,7 @@ struct Work {
   uint32_t* frame_flags; // per frame
   // detection
   uint8_t* tmap;         // per detection tile: its run map (kTmap*)
+  int32_t* tedge;        // per detection tile: record of each edge pixel
   int32_t* tile_rbase;   // per detection tile: first record
   Rec* recs;
   int32_t* rparent;      // union-find parent of each record
@@ -97,6 +98,12 @@ constexpr int kTmapHead = 512;          // uint64_t[64]
 constexpr int kTmapSeg = 1024;          // uint16_t[64]
 constexpr int kTmapRun = 1152;          // uint16_t[2048]
 constexpr int kTmapBytes = 1152 + 4096;
+
+// Edge records of one detection tile, kEdgeInts int32 per tile: the record
+// index of every pixel on the tile's border (-1: none), top row [0, TW),
+// bottom row [TW, 2TW), left column [2TW, 2TW+TH), right column
+// [2TW+TH, 2TW+2TH).
+constexpr int kEdgeInts = 320;          // 2 (TH + TW) for 32x128 tiles
 
 // ---------------------------------------------------------------- helpers
 // Stores and loads through the global address space (the pointers come

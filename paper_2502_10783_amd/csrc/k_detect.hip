@@ -465,19 +465,22 @@ __global__ __launch_bounds__(NT) void k_tile_ccl(Work wk, ipp_params p,
         (rl >= 0 && rbase + rl < wk.rec_cap) ? (uint16_t)(rl + 1) : 0;
     gst((uint16_t*)(tm + kTmapRun) + j, v);
   }
-}
-
-// Record index within its tile + 1 of tile-local pixel q (0: background
-// or not kept), from the tile's run map.
-__device__ __forceinline__ int tmap_local(const uint8_t* tm, int q) {
-  const int seg = q >> 6, b = q & 63;
-  const uint64_t fg = gld((const uint64_t*)(tm + kTmapFg) + seg);
-  if (!((fg >> b) & 1ull)) return 0;
-  const uint64_t hd = gld((const uint64_t*)(tm + kTmapHead) + seg);
-  const uint64_t upto = b == 63 ? ~0ull : ((2ull << b) - 1);
-  const int ri = (int)gld((const uint16_t*)(tm + kTmapSeg) + seg) +
-                 __popcll(hd & upto) - 1;
-  return gld((const uint16_t*)(tm + kTmapRun) + ri);
+  // ---- edge records: the record of every pixel on the tile's border -----
+  static_assert(2 * (TH + TW) <= kEdgeInts, "edge records of a tile");
+  int32_t* te = wk.tedge + (size_t)tile * kEdgeInts;
+  for (int e = t; e < 2 * (TH + TW); e += NT) {
+    int q;
+    if (e < TW) q = e;                                   // top row
+    else if (e < 2 * TW) q = (TH - 1) * TW + (e - TW);   // bottom row
+    else if (e < 2 * TW + TH) q = (e - 2 * TW) * TW;     // left column
+    else q = (e - 2 * TW - TH) * TW + TW - 1;            // right column
+    int32_t rec = -1;
+    if (fg_at(q)) {
+      const int rl = L.u.cc.rloc[-2 - parent[run_of(q)]];
+      if (rl >= 0 && rbase + rl < wk.rec_cap) rec = (int32_t)(rbase + rl);
+    }
+    gst(te + e, rec);
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -492,43 +495,40 @@ __global__ __launch_bounds__((border_threads<TH, TW>())) void k_border(
   const int lt = tile - fr.dtile0, ty = lt / fr.dtx, tx = lt - ty * fr.dtx;
   const int y0 = ty * TH, x0 = tx * TW;
   const bool c8 = p.connectivity == 8;
-  auto tile_of = [&](int y, int x) {
-    return fr.dtile0 + (y / TH) * fr.dtx + (x / TW);
-  };
-  // record index + 1 within its tile of frame pixel (y, x), or 0
-  auto local_of = [&](int y, int x) {
-    const uint8_t* tm = wk.tmap + (size_t)tile_of(y, x) * kTmapBytes;
-    return tmap_local(tm, (y % TH) * TW + (x % TW));
-  };
-  auto rec_of = [&](int y, int x, int l) {
-    return wk.tile_rbase[tile_of(y, x)] + l - 1;
+  // record of frame pixel (y, x) on the border of its tile (-1: none),
+  // from that tile's edge records
+  auto edge_rec = [&](int y, int x) {
+    const int tl = fr.dtile0 + (y / TH) * fr.dtx + (x / TW);
+    const int ly = y % TH, lx = x % TW;
+    const int idx = lx == 0 ? 2 * TW + ly
+                  : lx == TW - 1 ? 2 * TW + TH + ly
+                  : ly == 0 ? lx : TW + lx;
+    return gld(wk.tedge + (size_t)tl * kEdgeInts + idx);
   };
   const int t = threadIdx.x;
   if (t < TH) {                       // right border
     const int y = y0 + t, x = x0 + TW - 1;
     if (y < fr.h && x + 1 < fr.w) {
-      const int a = local_of(y, x);
-      if (a) {
-        const int ra = rec_of(y, x, a);
+      const int ra = edge_rec(y, x);
+      if (ra >= 0) {
         for (int dy = c8 ? -1 : 0; dy <= (c8 ? 1 : 0); ++dy) {
           const int yy = y + dy;
           if (yy < 0 || yy >= fr.h) continue;
-          const int b = local_of(yy, x + 1);
-          if (b) gunion(wk.rparent, ra, rec_of(yy, x + 1, b));
+          const int rb = edge_rec(yy, x + 1);
+          if (rb >= 0) gunion(wk.rparent, ra, rb);
         }
       }
     }
   } else if (t < TH + TW) {           // bottom border
     const int y = y0 + TH - 1, x = x0 + (t - TH);
     if (x < fr.w && y + 1 < fr.h) {
-      const int a = local_of(y, x);
-      if (a) {
-        const int ra = rec_of(y, x, a);
+      const int ra = edge_rec(y, x);
+      if (ra >= 0) {
         for (int dx = c8 ? -1 : 0; dx <= (c8 ? 1 : 0); ++dx) {
           const int xx = x + dx;
           if (xx < 0 || xx >= fr.w) continue;
-          const int b = local_of(y + 1, xx);
-          if (b) gunion(wk.rparent, ra, rec_of(y + 1, xx, b));
+          const int rb = edge_rec(y + 1, xx);
+          if (rb >= 0) gunion(wk.rparent, ra, rb);
         }
       }
     }
