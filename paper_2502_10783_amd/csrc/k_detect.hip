@@ -705,6 +705,12 @@ __global__ __launch_bounds__(kBlock) void k_relabel(Work wk, ipp_params p) {
   const int rb = wk.tile_rbase[tile];
   const uint8_t* tm = wk.tmap + (size_t)tile * kTmapBytes;
   const int t = threadIdx.x;
+  // the run entries of runs 8t .. 8t+7 are requested with the header (the
+  // 2048 possible runs fill 256 x 16 bytes), so only the label gathers wait
+  // on the run count
+  static_assert(kBlock * 8 >= 2048, "one 16-byte group of runs per thread");
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u rr = gld((const v4u*)(tm + kTmapRun) + t);
   if (t < 64) {
     fgs[t] = gld((const uint64_t*)(tm + kTmapFg) + t);
     hds[t] = gld((const uint64_t*)(tm + kTmapHead) + t);
@@ -712,10 +718,12 @@ __global__ __launch_bounds__(kBlock) void k_relabel(Work wk, ipp_params p) {
   }
   __syncthreads();
   // every run's label first (one gather per run), then pixels from LDS
-  const uint16_t* runrec = (const uint16_t*)(tm + kTmapRun);
   const int nruns = segs[63] + __popcll(hds[63]);
-  for (int r = t; r < nruns; r += kBlock) {
-    const int l = gld(runrec + r);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int r = 8 * t + i;
+    if (r >= nruns) break;
+    const int l = (int)((rr[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
     const long long rec = (long long)rb + l - 1;
     runlab[r] = (l && rec < wk.rec_cap) ? gld(wk.rlabel + rec) : 0;
   }
