@@ -291,7 +291,7 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     const uint32_t wrapB = wB - (uint32_t)nwx * 4u;
     // Chunks of kChunk rounds of 64 pixels: all loads of a chunk are issued
     // before any is used, so their latencies overlap.
-    constexpr int kChunk = 4;
+    constexpr int kChunk = 8;
     for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
       float Iv[kChunk], Bv[kChunk];
       uint32_t st[kChunk];
