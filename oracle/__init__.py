@@ -21,6 +21,8 @@ Intelligence Era"):
   its adjoint (gradients with the sky clip mask held fixed).
 * ``stretch``    -- Sec. 2.2.6 (Gray Scale Transformation Function): an asinh
   gray-scale map and its derivatives.
+* ``gray``       -- Sec. 2.2.6: the zscale display range, linear /
+  logarithmic / exponential / power-law maps and histogram equalization.
 * ``refine``     -- gradient-ascent centroid refinement on the photometry
   adjoint (this build's addition).
 
@@ -30,7 +32,7 @@ IEEE binary64; sums that decide results are exact (``math.fsum`` or Python
 integers) and rounded once.
 """
 from .params import Params
-from . import background, detect, photometry, stretch, refine
+from . import background, detect, photometry, stretch, refine, gray
 
 __all__ = ["Params", "background", "detect", "photometry", "stretch",
-           "refine"]
+           "refine", "gray"]

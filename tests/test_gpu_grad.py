@@ -128,10 +128,11 @@ def test_asinh_forward_backward(ctx):
 def test_asinh_unaligned_and_ragged(ctx):
     """Element counts that leave a tail after the groups of four, and
     arrays that do not start on a 16-byte boundary (the element loop then
-    takes one element at a time)."""
+    takes one element at a time), and the empty array (parameter gradients
+    exactly zero)."""
     rng = np.random.default_rng(12)
     a, b = 17.0, 0.8
-    for n, off in ((4099, 0), (4101, 1), (9, 3), (1, 0)):
+    for n, off in ((4099, 0), (4101, 1), (9, 3), (1, 0), (0, 0)):
         base = rng.normal(0, 500, n + off).astype(np.float32)
         gb = rng.normal(0, 1, n + off).astype(np.float32)
         vt = torch.from_numpy(base).to(DEV)[off:]
