@@ -286,6 +286,65 @@ ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
                               float* dv, double* dL_dab, int64_t n, double a,
                               double b, void* stream);
 
+/*
+ * Gray-scale transformations (Sec. 2.2.6): the zscale display range, point
+ * maps and histogram equalization.  Frames as elsewhere (mask ignored);
+ * outputs out[f] are device float32 h x w arrays with row pitch w.
+ */
+#define IPP_MAP_LINEAR 0  /* y = x                                         */
+#define IPP_MAP_LOG 1     /* y = ln(1 + a x) / ln(1 + a), a > 0            */
+#define IPP_MAP_EXP 2     /* y = (a^x - 1) / (a - 1), a > 0, a != 1        */
+#define IPP_MAP_POWER 3   /* y = x^a, a > 0                                */
+#define IPP_ZSCALE_MAX_SAMPLES 1000
+#define IPP_EQ_MAX_BINS 4096
+
+/* Workspace bytes the gray-scale calls need for n frames and nbins
+ * histogram bins (ipp_zscale and ipp_gray_map: nbins 0).  Host-only;
+ * 0 for invalid arguments. */
+size_t ipp_gray_workspace_bytes(int32_t n, int32_t nbins);
+
+/*
+ * zscale display range of each frame (the SAOimage DS9 / IRAF estimate):
+ * the finite pixels on the grid of rows and columns 0, s, 2s, ... (s the
+ * smallest step giving at most nsamples points, nsamples in
+ * [1, IPP_ZSCALE_MAX_SAMPLES]) are sorted; a straight line is fitted to
+ * them against their index with up to 5 fits, rejecting samples beyond
+ * 2.5 standard deviations of the residuals and widening each rejection by
+ * floor(n/100)/2 samples on either side; while at least half the samples
+ * (and 5) remain, the line through the median with its slope divided by
+ * contrast (> 0; 0 keeps the slope) gives the range, clamped to the
+ * sample's extremes, else the extremes are the range.  z1z2: device
+ * double[2n] (z1, z2 per frame; (0, 0) without finite samples).  info:
+ * device double[4n], nullable: samples, samples kept, fits, fitted slope.
+ */
+ipp_status ipp_zscale(void* ctx, const ipp_frame* frames, int32_t n,
+                      int32_t nsamples, double contrast, double* z1z2,
+                      double* info, void* stream);
+
+/*
+ * Point map of every frame: x = (v - lo) / (hi - lo) clipped to [0, 1]
+ * (for hi <= lo, 0 where v <= lo and 1 elsewhere), then the IPP_MAP_*
+ * function of x with parameter a; non-finite v gives NaN.  lohi: device
+ * double[2n] (lo, hi per frame, e.g. the output of ipp_zscale).
+ */
+ipp_status ipp_gray_map(void* ctx, const ipp_frame* frames, int32_t n,
+                        int32_t kind, double a, const double* lohi,
+                        float* const* out, void* stream);
+
+/*
+ * Histogram equalization of every frame over nbins (2..IPP_EQ_MAX_BINS)
+ * equal bins spanning its finite values [lo, hi]: a value's bin is
+ * floor(((v - lo) / (hi - lo)) nbins) (binary64; the top value in the last
+ * bin), cdf_k = pixels in bins 0..k over the finite pixels, and y is the
+ * linear interpolation of (lo + (k + 1/2)(hi - lo)/nbins, cdf_k) at v, held
+ * at the end values outside the first and last centre.  A constant frame
+ * maps to 1, non-finite pixels to NaN.  counts: device uint32[n * nbins],
+ * nullable: the histograms (cleared and written by the call).
+ */
+ipp_status ipp_equalize(void* ctx, const ipp_frame* frames, int32_t n,
+                        int32_t nbins, float* const* out, uint32_t* counts,
+                        void* stream);
+
 /* ipp_autotune: what to tune */
 #define IPP_TUNE_MESH 1u   /* mesh size from {32, 64, 128} (changes results) */
 #define IPP_TUNE_TILE 2u   /* detection tile shape 64x64, 32x128, 128x32

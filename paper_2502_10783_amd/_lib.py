@@ -23,6 +23,7 @@ IPP_EST_SEXTRACTOR, IPP_EST_MEDIAN, IPP_EST_MEAN, IPP_EST_MODE = 0, 1, 2, 3
 IPP_F_WRITE_RMS = 1
 IPP_TUNE_MESH = 1
 IPP_TUNE_TILE = 2
+IPP_MAP_LINEAR, IPP_MAP_LOG, IPP_MAP_EXP, IPP_MAP_POWER = 0, 1, 2, 3
 IPP_FRAME_NO_VALID_MESH = 1
 IPP_FRAME_EMPTY_MESH = 2
 IPP_SRC_APERTURE_OFF_EDGE = 1
@@ -150,6 +151,17 @@ def lib():
                                C.POINTER(IppParams), C.c_uint32, C.c_char_p,
                                C.POINTER(C.c_double), vp]
     L.ipp_autotune.restype = i32
+    L.ipp_gray_workspace_bytes.argtypes = [i32, i32]
+    L.ipp_gray_workspace_bytes.restype = sz
+    L.ipp_zscale.argtypes = [vp, C.POINTER(IppFrame), i32, i32, C.c_double,
+                             vp, vp, vp]
+    L.ipp_zscale.restype = i32
+    L.ipp_gray_map.argtypes = [vp, C.POINTER(IppFrame), i32, i32, C.c_double,
+                               vp, C.POINTER(vp), vp]
+    L.ipp_gray_map.restype = i32
+    L.ipp_equalize.argtypes = [vp, C.POINTER(IppFrame), i32, i32,
+                               C.POINTER(vp), vp, vp]
+    L.ipp_equalize.restype = i32
     _lib = L
     return L
 

@@ -319,6 +319,61 @@ class Context:
             float(a), float(b), _stream()))
         return dv, dab
 
+    # ------------------------------------------------ gray scale (2.2.6)
+    def _gray_reserve(self, n, nbins=0):
+        need = self.lib.ipp_gray_workspace_bytes(n, nbins)
+        if need == 0:
+            raise IppError(L.IPP_E_INVALID_ARG, "ipp_gray_workspace_bytes")
+        if need > self.ws_bytes:
+            self.reserve(need)
+
+    def zscale(self, frames, nsamples=1000, contrast=0.25, info=False):
+        """zscale display range per frame: tensor [n, 2] (z1, z2), and with
+        info=True also [n, 4] (samples, kept, fits, slope)."""
+        n = len(frames)
+        self._gray_reserve(n)
+        dev = frames[0].device
+        z = torch.zeros((n, 2), dtype=torch.float64, device=dev)
+        inf = (torch.zeros((n, 4), dtype=torch.float64, device=dev)
+               if info else None)
+        self._check(self.lib.ipp_zscale(
+            self.h, frames_c(frames), n, int(nsamples), float(contrast),
+            _ptr(z), _ptr(inf), _stream()))
+        return (z, inf) if info else z
+
+    def gray_map(self, frames, kind: int, lohi: torch.Tensor, a=1000.0,
+                 out=None):
+        """Point map (IPP_MAP_*) of each frame over lohi[f] = (lo, hi)."""
+        n = len(frames)
+        self._gray_reserve(n)
+        if lohi.dtype != torch.float64 or not lohi.is_contiguous():
+            raise ValueError("lohi must be a contiguous float64 tensor")
+        if out is None:
+            out = [torch.empty(f.shape, dtype=torch.float32, device=f.device)
+                   for f in frames]
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in out])
+        self._check(self.lib.ipp_gray_map(
+            self.h, frames_c(frames), n, int(kind), float(a), _ptr(lohi),
+            ptrs, _stream()))
+        return out
+
+    def equalize(self, frames, nbins=4096, counts=False, out=None):
+        """Histogram equalization of each frame (and, with counts=True, the
+        histograms as an int32 tensor [n, nbins] holding uint32 counts)."""
+        n = len(frames)
+        self._gray_reserve(n, nbins)
+        dev = frames[0].device
+        if out is None:
+            out = [torch.empty(f.shape, dtype=torch.float32, device=dev)
+                   for f in frames]
+        cnt = (torch.empty((n, nbins), dtype=torch.int32, device=dev)
+               if counts else None)
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in out])
+        self._check(self.lib.ipp_equalize(
+            self.h, frames_c(frames), n, int(nbins), ptrs, _ptr(cnt),
+            _stream()))
+        return (out, cnt) if counts else out
+
     def autotune(self, frames, params: Params, mesh=True, tile=True,
                  cache_path: Optional[str] = None):
         """Fastest mesh size / tile shape for this batch on this device:

@@ -561,6 +561,90 @@ std::string check_sources(const ipp_sources* s, bool detect) {
   return "";
 }
 
+// ---------------------------------------------------------------------
+// Gray-scale calls (Sec. 2.2.6): descriptors and workspace layout.
+// ---------------------------------------------------------------------
+struct GrayPlan {
+  std::vector<GrayFrame> fr;
+  int rows = 0;
+  size_t o_frames = 0, o_mm = 0, o_counts = 0, o_cdf = 0, total = 0;
+};
+
+// Smallest step s >= 1 with ceil(h/s) * ceil(w/s) <= nsamples.
+int zscale_step(int h, int w, int nsamples) {
+  int s = (int)std::floor(std::sqrt((double)h * (double)w / nsamples)) - 1;
+  if (s < 1) s = 1;
+  auto pts = [&](int k) {
+    return (int64_t)((h + k - 1) / k) * (int64_t)((w + k - 1) / k);
+  };
+  while (s > 1 && pts(s - 1) <= nsamples) --s;
+  while (pts(s) > nsamples) ++s;
+  return s;
+}
+
+size_t gray_layout(int32_t n, int32_t nbins, GrayPlan* G) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
+  G->o_frames = take(sizeof(GrayFrame) * (size_t)n);
+  G->o_mm = take(sizeof(uint32_t) * 2 * (size_t)n);
+  G->o_counts = take(sizeof(uint32_t) * (size_t)n * (size_t)nbins);
+  G->o_cdf = take(sizeof(double) * (size_t)n * (size_t)nbins);
+  G->total = o;
+  return o;
+}
+
+// Validates the frames and outputs, fills the descriptors and uploads them
+// into the workspace.
+ipp_status gray_prepare(IppCtx* c, const ipp_frame* frames, int32_t n,
+                        int32_t nsamples, int32_t nbins, float* const* out,
+                        bool need_out, GrayPlan* G, hipStream_t s) {
+  if (!c) return IPP_E_INVALID_ARG;
+  std::string m = check_frames(frames, n);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  if (need_out) {
+    if (!out) return fail(c, IPP_E_INVALID_ARG, "out is NULL");
+    for (int i = 0; i < n; ++i)
+      if (!out[i])
+        return fail(c, IPP_E_INVALID_ARG,
+                    "out[" + std::to_string(i) + "] is NULL");
+  }
+  gray_layout(n, nbins, G);
+  if (G->total > c->ws_bytes)
+    return fail(c, IPP_E_WORKSPACE,
+                "workspace too small: need " + std::to_string(G->total) +
+                    " bytes, have " + std::to_string(c->ws_bytes));
+  G->fr.resize(n);
+  int64_t rows = 0;
+  for (int i = 0; i < n; ++i) {
+    GrayFrame& g = G->fr[i];
+    g.pix = frames[i].pix;
+    g.pitch = frames[i].pitch;
+    g.h = frames[i].h;
+    g.w = frames[i].w;
+    g.s = nsamples > 0 ? zscale_step(g.h, g.w, nsamples) : 1;
+    g.sy = (g.h + g.s - 1) / g.s;
+    g.sx = (g.w + g.s - 1) / g.s;
+    g.row0 = (int32_t)rows;
+    g.out = out ? out[i] : nullptr;
+    rows += g.h;
+    if (nsamples > 0 && (int64_t)g.sy * g.sx > kZMax)
+      return fail(c, IPP_E_INVALID_ARG, "zscale sample grid too large");
+  }
+  if (rows > (1 << 30))
+    return fail(c, IPP_E_UNSUPPORTED, "more than 2^30 rows in one batch");
+  G->rows = (int)rows;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((char*)c->ws + G->o_frames, G->fr.data(),
+                       sizeof(GrayFrame) * G->fr.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE, std::string("descriptor upload failed: ") +
+                                     hipGetErrorString(e));
+  ++c->ws_gen;
+  return IPP_OK;
+}
+
 }  // namespace
 
 // ===================================================================== API
@@ -972,6 +1056,109 @@ ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
     IPP_LAUNCH(c, s, "k_asinh_bwd_final",
                hipLaunchKernelGGL(k_asinh_bwd_final, dim3(1), dim3(kBlock), 0,
                                   s, part, grid, dL_dab));
+  return IPP_OK;
+}
+
+size_t ipp_gray_workspace_bytes(int32_t n, int32_t nbins) {
+  if (n < 1 || n > 65536 || nbins < 0 || nbins == 1 || nbins > kMaxBins)
+    return 0;
+  GrayPlan G;
+  return gray_layout(n, nbins, &G);
+}
+
+ipp_status ipp_zscale(void* ctx, const ipp_frame* frames, int32_t n,
+                      int32_t nsamples, double contrast, double* z1z2,
+                      double* info, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (nsamples < 1 || nsamples > IPP_ZSCALE_MAX_SAMPLES)
+    return fail(c, IPP_E_INVALID_ARG, "nsamples must be in [1, 1000]");
+  if (!std::isfinite(contrast) || contrast < 0)
+    return fail(c, IPP_E_INVALID_ARG, "contrast must be finite and >= 0");
+  if (!z1z2) return fail(c, IPP_E_INVALID_ARG, "z1z2 is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  GrayPlan G;
+  ipp_status st = gray_prepare(c, frames, n, nsamples, 0, nullptr, false,
+                               &G, s);
+  if (st != IPP_OK) return st;
+  const GrayFrame* fr = (const GrayFrame*)((char*)c->ws + G.o_frames);
+  IPP_LAUNCH(c, s, "k_zscale",
+             hipLaunchKernelGGL(k_zscale, dim3(n), dim3(kBlock), 0, s, fr,
+                                contrast, 2.5, 5, z1z2, info));
+  return IPP_OK;
+}
+
+ipp_status ipp_gray_map(void* ctx, const ipp_frame* frames, int32_t n,
+                        int32_t kind, double a, const double* lohi,
+                        float* const* out, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (kind < IPP_MAP_LINEAR || kind > IPP_MAP_POWER)
+    return fail(c, IPP_E_INVALID_ARG, "unknown map kind");
+  if (kind != IPP_MAP_LINEAR &&
+      (!std::isfinite(a) || a <= 0 || (kind == IPP_MAP_EXP && a == 1.0)))
+    return fail(c, IPP_E_INVALID_ARG,
+                "the map needs a finite a > 0 (and a != 1 for exp)");
+  if (!lohi) return fail(c, IPP_E_INVALID_ARG, "lohi is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  GrayPlan G;
+  ipp_status st = gray_prepare(c, frames, n, 0, 0, out, true, &G, s);
+  if (st != IPP_OK) return st;
+  float cc = 1.0f, lna = 0.0f;
+  if (kind == IPP_MAP_LOG) cc = (float)(1.0 / std::log1p(a));
+  if (kind == IPP_MAP_EXP) {
+    cc = (float)(1.0 / (a - 1.0));
+    lna = (float)std::log(a);
+  }
+  const GrayFrame* fr = (const GrayFrame*)((char*)c->ws + G.o_frames);
+  IPP_LAUNCH(c, s, "k_gray_map",
+             hipLaunchKernelGGL(k_gray_map, dim3(grid_for(G.rows, 1, 4096)),
+                                dim3(kBlock), 0, s, fr, n, G.rows, kind,
+                                (float)a, cc, lna, lohi));
+  return IPP_OK;
+}
+
+ipp_status ipp_equalize(void* ctx, const ipp_frame* frames, int32_t n,
+                        int32_t nbins, float* const* out, uint32_t* counts,
+                        void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (nbins < 2 || nbins > IPP_EQ_MAX_BINS)
+    return fail(c, IPP_E_INVALID_ARG, "nbins must be in [2, 4096]");
+  hipStream_t s = (hipStream_t)stream;
+  GrayPlan G;
+  ipp_status st = gray_prepare(c, frames, n, 0, nbins, out, true, &G, s);
+  if (st != IPP_OK) return st;
+  char* b = (char*)c->ws;
+  const GrayFrame* fr = (const GrayFrame*)(b + G.o_frames);
+  uint32_t* mm = (uint32_t*)(b + G.o_mm);
+  uint32_t* cnt = counts ? counts : (uint32_t*)(b + G.o_counts);
+  double* cdf = (double*)(b + G.o_cdf);
+  const int64_t nc = (int64_t)n * nbins;
+  // fill kernels, not memsets: the call may be captured into a graph
+  IPP_LAUNCH(c, s, "k_fill_i32",
+             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s,
+                                (int32_t*)mm, (int64_t)n, (int32_t)-1));
+  IPP_LAUNCH(c, s, "k_fill_i32",
+             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kBlock), 0, s,
+                                (int32_t*)mm + n, (int64_t)n, 0));
+  IPP_LAUNCH(c, s, "k_fill_i32",
+             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nc, kBlock, 4096)),
+                                dim3(kBlock), 0, s, (int32_t*)cnt, nc, 0));
+  const int gr = grid_for(G.rows, 16, 4096);
+  IPP_LAUNCH(c, s, "k_eq_minmax",
+             hipLaunchKernelGGL(k_eq_minmax, dim3(gr), dim3(kBlock), 0, s, fr,
+                                n, G.rows, mm));
+  IPP_LAUNCH(c, s, "k_eq_hist",
+             hipLaunchKernelGGL(k_eq_hist, dim3(gr), dim3(kBlock), 0, s, fr,
+                                n, G.rows, nbins, mm, cnt));
+  IPP_LAUNCH(c, s, "k_eq_cdf",
+             hipLaunchKernelGGL(k_eq_cdf, dim3(n), dim3(kBlock), 0, s, cnt,
+                                nbins, cdf));
+  IPP_LAUNCH(c, s, "k_eq_map",
+             hipLaunchKernelGGL(k_eq_map, dim3(grid_for(G.rows, 1, 4096)),
+                                dim3(kBlock), 0, s, fr, n, G.rows, nbins, mm,
+                                cdf));
   return IPP_OK;
 }
 

@@ -41,6 +41,19 @@ struct FrameDev {
   int32_t line0[2];      // first mesh line of each spline pass
 };
 
+// Frame of the gray-scale calls: input, output and the zscale sample grid.
+struct GrayFrame {
+  const float* pix;
+  int64_t pitch;
+  int32_t h, w;
+  int32_t s;             // zscale sample step
+  int32_t sy, sx;        // sample grid rows, columns (sy * sx <= kZMax)
+  int32_t row0;          // first row of the frame among the batch's rows
+  float* out;            // h x w, row pitch w (nullable where unused)
+};
+constexpr int kZMax = 1024;       // zscale sample capacity
+constexpr int kMaxBins = 4096;    // histogram equalization bins
+
 // Partial candidate: the piece of a connected component inside one
 // detection tile that touches the tile border or is large enough to keep.
 struct Rec {

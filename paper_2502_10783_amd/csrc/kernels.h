@@ -60,4 +60,19 @@ __global__ void k_asinh_bwd(const float* v, const float* dy, float* dv,
 __global__ void k_asinh_bwd_final(const double* partial, int nb,
                                   double* out);
 
+__global__ void k_zscale(const GrayFrame* frames, double contrast,
+                         double krej, int max_iter, double* z1z2,
+                         double* info);
+__global__ void k_gray_map(const GrayFrame* frames, int nframes,
+                           int total_rows, int kind, float a, float c,
+                           float lna, const double* lohi);
+__global__ void k_eq_minmax(const GrayFrame* frames, int nframes,
+                            int total_rows, uint32_t* mm);
+__global__ void k_eq_hist(const GrayFrame* frames, int nframes,
+                          int total_rows, int nbins, const uint32_t* mm,
+                          uint32_t* counts);
+__global__ void k_eq_cdf(const uint32_t* counts, int nbins, double* cdf);
+__global__ void k_eq_map(const GrayFrame* frames, int nframes, int total_rows,
+                         int nbins, const uint32_t* mm, const double* cdf);
+
 }  // namespace ipp

@@ -91,3 +91,21 @@ def test_null_context_rejected(lib):
                                  None, None, None) == L.IPP_E_INVALID_ARG
     assert lib.ipp_ctx_destroy(None) == L.IPP_E_INVALID_ARG
     assert lib.ipp_ctx_create(None, 0) == L.IPP_E_INVALID_ARG
+
+
+def test_gray_workspace_and_argument_checks(lib):
+    assert lib.ipp_gray_workspace_bytes(0, 0) == 0
+    assert lib.ipp_gray_workspace_bytes(2, 1) == 0
+    assert lib.ipp_gray_workspace_bytes(2, 4097) == 0
+    n0 = lib.ipp_gray_workspace_bytes(16, 0)
+    n1 = lib.ipp_gray_workspace_bytes(16, 4096)
+    assert n0 > 0 and n1 >= n0 + 16 * 4096 * (4 + 8)
+    f = _frames([(64, 64)])
+    z = C.c_void_p(1)
+    assert lib.ipp_zscale(None, f, 1, 1000, 0.25, z, None,
+                          None) == L.IPP_E_INVALID_ARG
+    outs = (C.c_void_p * 1)(1)
+    assert lib.ipp_gray_map(None, f, 1, L.IPP_MAP_LOG, 1000.0, z, outs,
+                            None) == L.IPP_E_INVALID_ARG
+    assert lib.ipp_equalize(None, f, 1, 4096, outs, None,
+                            None) == L.IPP_E_INVALID_ARG
