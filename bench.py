@@ -275,15 +275,111 @@ def run_grad(args):
     print(json.dumps(res), flush=True)
 
 
+def run_gray(args):
+    """Gray-scale transformations of the 16-frame stack (Sec. 2.2.6): the
+    zscale range of every frame and a logarithmic map over it, and histogram
+    equalization (4096 bins)."""
+    import torch
+    import paper_2502_10783_amd as ipp
+
+    dev = torch.device("cuda:0")
+    nfr, desc = WORKLOADS["stack16"]
+    if args.frames:
+        nfr = min(nfr, args.frames)
+    log(f"generating {nfr} frames of stack16 on the GPU")
+    frames = make_frames("stack16", nfr, dev)
+    ctx = ipp.Context(0)
+    out_map = [torch.empty_like(f) for f in frames]
+    out_eq = [torch.empty_like(f) for f in frames]
+
+    def zmap():
+        z = ctx.zscale(frames)
+        ctx.gray_map(frames, ipp.IPP_MAP_LOG, z, 1000.0, out=out_map)
+
+    def equalize():
+        ctx.equalize(frames, nbins=4096, out=out_eq)
+
+    def timed(fn, k):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    log(f"timing {args.steps} steps of each")
+    ms_map = timed(zmap, args.steps)
+    ms_eq = timed(equalize, args.steps)
+    ctx.profile(True)
+    for _ in range(3):
+        zmap()
+        equalize()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kern = {k: v0 / v1 for k, (v0, v1) in prof.items()}
+    npx = sum(f.numel() for f in frames)
+    # algorithmic bytes per pixel of each pass
+    per_px = {"k_gray_map": 8, "k_eq_map": 8, "k_eq_hist": 4,
+              "k_eq_minmax": 4}
+
+    def hbm(k):
+        gbs = per_px[k] * npx / (kern[k] * 1e-3) / 1e9
+        return {"kernel": k, "bound": "hbm", "achieved": round(gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "algo_bytes_per_launch": per_px[k] * npx,
+                "ms_per_launch": round(kern[k], 4)}
+
+    dom = max(per_px, key=lambda k: kern.get(k, 0.0))
+    res = {
+        "metric": "Mpix/s, zscale range + logarithmic map of every frame",
+        "value": round(npx / 1e6 / (ms_map * 1e-3), 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_map, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc if nfr == WORKLOADS["stack16"][0] else
+                   f"first {nfr} frames of: {desc}", "name": "gray16",
+                   "frames": nfr, "map": "log", "a": 1000.0,
+                   "zscale_samples": 1000, "contrast": 0.25,
+                   "equalize_bins": 4096},
+        "map_GBps": round(8 * npx / (ms_map * 1e-3) / 1e9, 1),
+        "equalize": {"ms_per_step": round(ms_eq, 4),
+                     "mpix_per_s": round(npx / 1e6 / (ms_eq * 1e-3), 1),
+                     "GBps_at_16B_per_px": round(
+                         16 * npx / (ms_eq * 1e-3) / 1e9, 1)},
+        "roofline": hbm(dom),
+        "roofline_map": hbm("k_gray_map"),
+        "kernels_ms": {k: round(v, 4) for k, v in
+                       sorted(kern.items(), key=lambda kv: -kv[1])},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["grad64"],
+    ap.add_argument("--workload",
+                    choices=sorted(WORKLOADS) + ["grad64", "gray16"],
                     default="stack16",
                     help="grad64: the forward + backward of the aperture "
-                         "flux and of the asinh stretch (its own metric)")
+                         "flux and of the asinh stretch; gray16: zscale, "
+                         "point map and histogram equalization of the "
+                         "16-frame stack (each its own metric)")
     ap.add_argument("--frames", type=int, default=0,
                     help="frames of the workload to use (0 = all)")
     ap.add_argument("--autotune", action="store_true",
@@ -304,6 +400,9 @@ def main():
 
     if args.workload == "grad64":
         run_grad(args)
+        return
+    if args.workload == "gray16":
+        run_gray(args)
         return
 
     import torch

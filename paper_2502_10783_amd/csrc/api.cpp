@@ -1156,7 +1156,7 @@ ipp_status ipp_equalize(void* ctx, const ipp_frame* frames, int32_t n,
              hipLaunchKernelGGL(k_eq_cdf, dim3(n), dim3(kBlock), 0, s, cnt,
                                 nbins, cdf));
   IPP_LAUNCH(c, s, "k_eq_map",
-             hipLaunchKernelGGL(k_eq_map, dim3(grid_for(G.rows, 1, 4096)),
+             hipLaunchKernelGGL(k_eq_map, dim3(grid_for(G.rows, 32, 2048)),
                                 dim3(kBlock), 0, s, fr, n, G.rows, nbins, mm,
                                 cdf));
   return IPP_OK;

@@ -414,40 +414,53 @@ __global__ __launch_bounds__(kBlock) void k_eq_cdf(const uint32_t* counts,
   }
 }
 
-// y = the interpolation of (centre_k, cdf_k) at v, held at the ends.
+// y = the interpolation of (centre_k, cdf_k) at v, held at the ends.  Each
+// block maps a contiguous range of rows; the cdf of the frame being mapped
+// is staged in LDS in binary32 (values in [0, 1]: 6e-8 absolute).  The
+// position of v among the centres, t = (v - lo) / w - 1/2, is taken in
+// binary64 (v - lo exactly); the interpolation is continuous, so the
+// interval a value on a centre falls in does not change y.
 __global__ __launch_bounds__(kBlock) void k_eq_map(const GrayFrame* frames,
                                                    int nframes,
                                                    int total_rows, int nbins,
                                                    const uint32_t* mm,
                                                    const double* cdf) {
-  for (int row = blockIdx.x; row < total_rows; row += gridDim.x) {
-    const int f = gray_frame_of(frames, nframes, row);
+  __shared__ float T[kMaxBins];
+  int r0, r1;
+  block_rows(total_rows, &r0, &r1);
+  if (r0 >= r1) return;
+  int f = -1;
+  double lo = 0.0, inv_w = 0.0;
+  bool span = false;
+  for (int row = r0; row < r1; ++row) {
+    int nf = f < 0 ? gray_frame_of(frames, nframes, row) : f;
+    while (nf + 1 < nframes && frames[nf + 1].row0 <= row) ++nf;
+    if (nf != f) {
+      // a new frame: its value range and cdf
+      f = nf;
+      const uint32_t kl = mm[f], kh = mm[nframes + f];
+      const double l = kl <= kh ? (double)key2f(kl) : 0.0;
+      const double h = kl <= kh ? (double)key2f(kh) : 0.0;
+      lo = l;
+      span = h > l;
+      inv_w = span ? (double)nbins / (h - l) : 0.0;
+      __syncthreads();
+      if (span)
+        for (int k = threadIdx.x; k < nbins; k += kBlock)
+          T[k] = (float)cdf[(size_t)f * nbins + k];
+      __syncthreads();
+    }
     const GrayFrame F = frames[f];
-    const uint32_t kl = mm[f], kh = mm[nframes + f];
-    const bool any = kl <= kh;
-    const double lo = any ? (double)key2f(kl) : 0.0;
-    const double hi = any ? (double)key2f(kh) : 0.0;
-    const double w = (hi - lo) / (double)nbins;
-    const double inv_w = w > 0.0 ? 1.0 / w : 0.0;
-    const double* C = cdf + (size_t)f * nbins;
-    auto centre = [&](int k) { return lo + ((double)k + 0.5) * w; };
     auto eq = [&](float vf) -> float {
       if (!isfinite(vf)) return __builtin_nanf("");
-      if (!(hi > lo)) return 1.0f;
-      const double v = (double)vf;
-      // interval [centre_j, centre_{j+1}) holding v: an arithmetic guess,
-      // corrected against the centres as the interpolation defines them
-      int j = (int)floor((v - lo) * inv_w - 0.5);
-      j = min(max(j, -1), nbins - 1);
-      for (int it = 0; it < 2; ++it)
-        if (j + 1 < nbins && centre(j + 1) <= v) ++j;
-      for (int it = 0; it < 2; ++it)
-        if (j >= 0 && centre(j) > v) --j;
-      if (j < 0) return (float)C[0];
-      if (j >= nbins - 1) return (float)C[nbins - 1];
-      const double c0 = centre(j), c1 = centre(j + 1);
-      const double y0 = C[j], y1 = C[j + 1];
-      return (float)(y0 + (y1 - y0) * ((v - c0) / (c1 - c0)));
+      if (!span) return 1.0f;
+      const double t = ((double)vf - lo) * inv_w - 0.5;
+      if (t < 0.0) return T[0];
+      const int j = (int)t;
+      if (j >= nbins - 1) return T[nbins - 1];
+      const float fr = (float)(t - (double)j);
+      const float y0 = T[j];
+      return y0 + (T[j + 1] - y0) * fr;
     };
     row_elements(F, row - F.row0, row_vec(F),
                  [&](const float* in, float* out, int x, bool four) {
