@@ -52,14 +52,16 @@ def aperture_flops_per_source(p):
 # WRITE_SIZE, scaled by a copy kernel of known size), keyed by kernel with
 # a hash of the sources they were measured on: reported only while the
 # sources are unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stack16.json")
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
 
 
 def measured_traffic(kernel, workload):
     import hashlib
-    if workload != "stack16" or not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(workload)
+    if not os.path.exists(path):
         return None
-    t = json.load(open(TRAFFIC_FILE)).get(kernel)
+    t = json.load(open(path)).get(kernel)
     if not t:
         return None
     h = hashlib.sha256()
@@ -275,6 +277,19 @@ def run_grad(args):
     print(json.dumps(res), flush=True)
 
 
+def calibration_copy(mib, dev):
+    """One device-to-device copy of `mib` MiB: a kernel of known traffic
+    that scales the HBM byte counters of a profiled run."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def run_gray(args):
     """Gray-scale transformations of the 16-frame stack (Sec. 2.2.6): the
     zscale range of every frame and a logarithmic map over it, and histogram
@@ -288,6 +303,8 @@ def run_gray(args):
         nfr = min(nfr, args.frames)
     log(f"generating {nfr} frames of stack16 on the GPU")
     frames = make_frames("stack16", nfr, dev)
+    if args.calib_copy:
+        calibration_copy(args.calib_copy, dev)
     ctx = ipp.Context(0)
     out_map = [torch.empty_like(f) for f in frames]
     out_eq = [torch.empty_like(f) for f in frames]
@@ -360,8 +377,10 @@ def run_gray(args):
                      "mpix_per_s": round(npx / 1e6 / (ms_eq * 1e-3), 1),
                      "GBps_at_16B_per_px": round(
                          16 * npx / (ms_eq * 1e-3) / 1e9, 1)},
-        "roofline": hbm(dom),
-        "roofline_map": hbm("k_gray_map"),
+        "roofline": dict(hbm(dom), traffic=measured_traffic(dom, "gray16")),
+        "roofline_map": dict(hbm("k_gray_map"),
+                             traffic=measured_traffic("k_gray_map",
+                                                      "gray16")),
         "kernels_ms": {k: round(v, 4) for k, v in
                        sorted(kern.items(), key=lambda kv: -kv[1])},
     }
@@ -417,13 +436,7 @@ def main():
     torch.cuda.synchronize()
     mpix = sum(f.numel() for f in frames) / 1e6
     if args.calib_copy:
-        n = args.calib_copy * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calibration_copy(args.calib_copy, dev)
     p = ipp.Params()
     ctx = ipp.Context(0)
     tuned = None
