@@ -87,6 +87,9 @@ __device__ __forceinline__ float map_pixel(float v, double lo, double inv,
   }
 }
 
+// Row y of frame F: fn(v, out_row, x) with v a float4 of columns x..x+3
+// (aligned rows) or a float of column x.  Two groups per thread are loaded
+// before either is used, so that both loads are in flight together.
 template <typename Fn>
 __device__ __forceinline__ void row_elements(const GrayFrame& F, int y,
                                              bool vec, Fn fn) {
@@ -95,10 +98,17 @@ __device__ __forceinline__ void row_elements(const GrayFrame& F, int y,
   int x0 = 0;
   if (vec) {
     const int n4 = F.w >> 2;
-    for (int i = threadIdx.x; i < n4; i += kBlock) fn(in, out, 4 * i, true);
+    const float4* in4 = (const float4*)in;
+    int i = threadIdx.x;
+    for (; i + kBlock < n4; i += 2 * kBlock) {
+      const float4 a = in4[i], b = in4[i + kBlock];
+      fn(a, out, 4 * i);
+      fn(b, out, 4 * (i + kBlock));
+    }
+    if (i < n4) fn(in4[i], out, 4 * i);
     x0 = n4 << 2;
   }
-  for (int x = x0 + threadIdx.x; x < F.w; x += kBlock) fn(in, out, x, false);
+  for (int x = x0 + threadIdx.x; x < F.w; x += kBlock) fn(in[x], out, x);
 }
 
 __device__ __forceinline__ bool row_vec(const GrayFrame& F) {
@@ -260,20 +270,18 @@ __global__ __launch_bounds__(kBlock) void k_gray_map(
     const double lo = lohi[2 * f], hi = lohi[2 * f + 1];
     const bool step = !(hi > lo);
     const double inv = step ? 0.0 : 1.0 / (hi - lo);
-    row_elements(F, y, row_vec(F),
-                 [&](const float* in, float* out, int x, bool four) {
-                   if (four) {
-                     const float4 v = *(const float4*)(in + x);
-                     float4 o;
-                     o.x = map_pixel(v.x, lo, inv, step, m);
-                     o.y = map_pixel(v.y, lo, inv, step, m);
-                     o.z = map_pixel(v.z, lo, inv, step, m);
-                     o.w = map_pixel(v.w, lo, inv, step, m);
-                     *(float4*)(out + x) = o;
-                   } else {
-                     out[x] = map_pixel(in[x], lo, inv, step, m);
-                   }
-                 });
+    row_elements(F, y, row_vec(F), [&](auto v, float* out, int x) {
+      if constexpr (sizeof(v) == sizeof(float4)) {
+        float4 o;
+        o.x = map_pixel(v.x, lo, inv, step, m);
+        o.y = map_pixel(v.y, lo, inv, step, m);
+        o.z = map_pixel(v.z, lo, inv, step, m);
+        o.w = map_pixel(v.w, lo, inv, step, m);
+        *(float4*)(out + x) = o;
+      } else {
+        out[x] = map_pixel(v, lo, inv, step, m);
+      }
+    });
   }
 }
 
@@ -306,22 +314,20 @@ __global__ __launch_bounds__(kBlock) void k_eq_minmax(const GrayFrame* frames,
       ++f;
     }
     const GrayFrame F = frames[f];
-    row_elements(F, row - F.row0, row_vec(F),
-                 [&](const float* in, float*, int x, bool four) {
-                   auto take = [&](float v) {
-                     if (isfinite(v)) {
-                       const uint32_t k = f2key(v + 0.0f);
-                       kmin = min(kmin, k);
-                       kmax = max(kmax, k);
-                     }
-                   };
-                   if (four) {
-                     const float4 v = *(const float4*)(in + x);
-                     take(v.x); take(v.y); take(v.z); take(v.w);
-                   } else {
-                     take(in[x]);
-                   }
-                 });
+    auto take = [&](float v) {
+      if (isfinite(v)) {
+        const uint32_t k = f2key(v + 0.0f);
+        kmin = min(kmin, k);
+        kmax = max(kmax, k);
+      }
+    };
+    row_elements(F, row - F.row0, row_vec(F), [&](auto v, float*, int) {
+      if constexpr (sizeof(v) == sizeof(float4)) {
+        take(v.x); take(v.y); take(v.z); take(v.w);
+      } else {
+        take(v);
+      }
+    });
   }
   const uint32_t bmin = block_min(kmin, red);
   const uint32_t bmax = block_max(kmax, red);
@@ -376,12 +382,19 @@ __global__ __launch_bounds__(kBlock) void k_eq_hist(const GrayFrame* frames,
     }
     __syncthreads();
   };
+  int64_t held = 0;                        // pixels counted since a flush
   for (int row = r0; row < r1; ++row) {
     while (f + 1 < nframes && frames[f + 1].row0 <= row) {
       flush(f);
+      held = 0;
       ++f;
     }
     const GrayFrame F = frames[f];
+    if (held + F.w > (int64_t)1 << 31) {     // keep the 32-bit counters exact
+      flush(f);
+      held = 0;
+    }
+    held += F.w;
     const uint32_t kl = mm[f], kh = mm[nframes + f];
     if (kl > kh) continue;                 // no finite value in the frame
     const double lo = (double)key2f(kl), hi = (double)key2f(kh);
@@ -394,22 +407,20 @@ __global__ __launch_bounds__(kBlock) void k_eq_hist(const GrayFrame* frames,
     auto add = [&](int k, uint32_t c) {
       if (k >= 0) atomicAdd(&h[2 * k + rep], c);
     };
-    row_elements(F, row - F.row0, row_vec(F),
-                 [&](const float* in, float*, int x, bool four) {
-                   if (four) {
-                     const float4 v = *(const float4*)(in + x);
-                     const int k0 = bin(v.x), k1 = bin(v.y);
-                     const int k2 = bin(v.z), k3 = bin(v.w);
-                     // runs of equal bins among the four
-                     uint32_t c = 1;
-                     if (k1 == k0) ++c; else { add(k0, c); c = 1; }
-                     if (k2 == k1) ++c; else { add(k1, c); c = 1; }
-                     if (k3 == k2) ++c; else { add(k2, c); c = 1; }
-                     add(k3, c);
-                   } else {
-                     add(bin(in[x]), 1u);
-                   }
-                 });
+    row_elements(F, row - F.row0, row_vec(F), [&](auto v, float*, int) {
+      if constexpr (sizeof(v) == sizeof(float4)) {
+        const int k0 = bin(v.x), k1 = bin(v.y);
+        const int k2 = bin(v.z), k3 = bin(v.w);
+        // runs of equal bins among the four
+        uint32_t c = 1;
+        if (k1 == k0) ++c; else { add(k0, c); c = 1; }
+        if (k2 == k1) ++c; else { add(k1, c); c = 1; }
+        if (k3 == k2) ++c; else { add(k2, c); c = 1; }
+        add(k3, c);
+      } else {
+        add(bin(v), 1u);
+      }
+    });
   }
   flush(f);
 }
@@ -486,17 +497,15 @@ __global__ __launch_bounds__(kBlock) void k_eq_map(const GrayFrame* frames,
       const float y0 = T[j];
       return y0 + (T[j + 1] - y0) * fr;
     };
-    row_elements(F, row - F.row0, row_vec(F),
-                 [&](const float* in, float* out, int x, bool four) {
-                   if (four) {
-                     const float4 v = *(const float4*)(in + x);
-                     float4 o;
-                     o.x = eq(v.x); o.y = eq(v.y); o.z = eq(v.z); o.w = eq(v.w);
-                     *(float4*)(out + x) = o;
-                   } else {
-                     out[x] = eq(in[x]);
-                   }
-                 });
+    row_elements(F, row - F.row0, row_vec(F), [&](auto v, float* out, int x) {
+      if constexpr (sizeof(v) == sizeof(float4)) {
+        float4 o;
+        o.x = eq(v.x); o.y = eq(v.y); o.z = eq(v.z); o.w = eq(v.w);
+        *(float4*)(out + x) = o;
+      } else {
+        out[x] = eq(v);
+      }
+    });
   }
 }
 
