@@ -872,15 +872,27 @@ __device__ __forceinline__ void stat_init(StatAcc& a) {
 // Pixel (x, y) of frame fr for the candidate with the given label and
 // bounding-box corner (xmin, ymin).  The label and the two values are
 // loaded together; a pixel of another label contributes zeros.
-__device__ __forceinline__ void stat_pixel(StatAcc& a, const FrameDev& fr,
-                                           int label, int x, int y,
-                                           int xmin, int ymin) {
+// The label, value and background of one bounding-box pixel.
+struct PixIn {
+  int lab;
+  float I, B;
+};
+__device__ __forceinline__ PixIn stat_load(const FrameDev& fr, int x, int y) {
+  const int64_t o = (int64_t)y * fr.w + x;
+  PixIn q;
+  q.lab = gld(fr.labels + o);
+  q.I = gld(fr.pix + (int64_t)y * fr.pitch + x);
+  q.B = gld(fr.bkg + o);
+  return q;
+}
+
+__device__ __forceinline__ void stat_acc(StatAcc& a, const FrameDev& fr,
+                                         const PixIn& q, int label, int x,
+                                         int y, int xmin, int ymin) {
   const double two_q = 268435456.0;                  // 2^28
   const double dmax = 4611686018427387903.0;         // 2^62 - 1
-  const int64_t o = (int64_t)y * fr.w + x;
-  const bool mem = gld(fr.labels + o) == label;
-  const float I = gld(fr.pix + (int64_t)y * fr.pitch + x);
-  const float B = gld(fr.bkg + o);
+  const bool mem = q.lab == label;
+  const float I = q.I, B = q.B;
   const double v = (double)I - (double)B;
   double s = rint(v * two_q);
   bool inexact = !(exact_range(I) && exact_range(B));
@@ -898,6 +910,12 @@ __device__ __forceinline__ void stat_pixel(StatAcc& a, const FrameDev& fr,
     a.pk = v;
     a.pidx = idx;
   }
+}
+
+__device__ __forceinline__ void stat_pixel(StatAcc& a, const FrameDev& fr,
+                                           int label, int x, int y,
+                                           int xmin, int ymin) {
+  stat_acc(a, fr, stat_load(fr, x, y), label, x, y, xmin, ymin);
 }
 
 // Peak: largest value, ties to the smallest index (associative, so any
@@ -1049,14 +1067,23 @@ __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
       const long long area = (long long)bw * (ymax - ymin + 1);
       StatAcc a;
       stat_init(a);
-      // bounding-box position of element e, stepped without divisions
+      // bounding-box position of element e, stepped without divisions;
+      // two elements per lane and step, both loaded before either is used
       int ey = lane / bw, ex = lane - (lane / bw) * bw;
       const int dy = kWave / bw, dx = kWave - (kWave / bw) * bw;
-      for (long long e = lane; e < area; e += kWave) {
-        const int y = ymin + ey, x = xmin + ex;
+      for (long long e = lane; e < area; e += 2 * kWave) {
+        const int y0 = ymin + ey, x0 = xmin + ex;
         ey += dy; ex += dx;
         if (ex >= bw) { ex -= bw; ++ey; }
-        stat_pixel(a, fr, label, x, y, xmin, ymin);
+        const int y1 = ymin + ey, x1 = xmin + ex;
+        ey += dy; ex += dx;
+        if (ex >= bw) { ex -= bw; ++ey; }
+        const bool two = e + kWave < area;
+        const PixIn q0 = stat_load(fr, x0, y0);
+        PixIn q1 = {0, 0.0f, 0.0f};
+        if (two) q1 = stat_load(fr, x1, y1);
+        stat_acc(a, fr, q0, label, x0, y0, xmin, ymin);
+        if (two) stat_acc(a, fr, q1, label, x1, y1, xmin, ymin);
       }
       stat_row16(a);
       stat_rows_combine(a);
