@@ -716,16 +716,31 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   W0.init(fr, xa, xb, ya, yb, lane);
   double A = 0.0, Wt = 0.0, Sv = 0.0;
   int ntk = 0;
-  for (int e0 = 0; e0 < W0.npx; e0 += kWave) {
+  // chunks of kBChunk rounds of 64 pixels: the loads of a chunk are all
+  // issued before any is used
+  constexpr int kBChunk = 4;
+  for (int e00 = 0; e00 < W0.npx; e00 += kBChunk * kWave) {
+  float Iv[kBChunk], Bv[kBChunk];
+  bool insv[kBChunk];
+  int posv[kBChunk];
+#pragma unroll
+  for (int c = 0; c < kBChunk; ++c) {
+    if (e00 + c * kWave >= W0.npx) break;          // wave-uniform
+    posv[c] = (W0.wr << 6) | W0.wc;
+    W0.load(e00 + c * kWave + lane < W0.npx, &Iv[c], &Bv[c], &insv[c]);
+    W0.advance();
+  }
+#pragma unroll
+  for (int c = 0; c < kBChunk; ++c) {
+    const int e0 = e00 + c * kWave;
+    if (e0 >= W0.npx) break;                       // wave-uniform
     const bool live = e0 + lane < W0.npx;
-    const int px = xa + W0.wc, py = ya + W0.wr;
-    const int pos = (W0.wr << 6) | W0.wc;
-    float I, B;
-    bool inside;
-    W0.load(live, &I, &B, &inside);
+    const int pos = posv[c];
+    const int px = xa + (pos & 63), py = ya + (pos >> 6);
+    const float I = Iv[c], B = Bv[c];
+    const bool inside = insv[c];
     double near2, far2;
     pixel_dist2(cx, cy, px, py, &near2, &far2);
-    W0.advance();
     const bool ok = live & inside & isfinite(I);
     const double v = (double)I - (double)B;
     const bool in_ap = ok & (near2 < ra2);
@@ -751,6 +766,7 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
       if (s < NS + kApTasks) L.tk[s] = (1 << 28) | pos;
     }
     ntk += __popcll(b2);
+  }
   }
   if (ntk > NS + kApTasks) ntk = NS + kApTasks;   // not reachable
   // edge square roots of the window for the three circles
