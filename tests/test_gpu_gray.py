@@ -187,3 +187,27 @@ def test_stack16_full_size(ctx):
             assert np.max(np.abs(m - m_ref)) <= 2e-6
     del frames, out, mp
     torch.cuda.empty_cache()
+
+
+def test_invalid_arguments_rejected(ctx):
+    """Host-side validation of the gray-scale calls (nothing is launched)."""
+    f = [torch.zeros((8, 8), dtype=torch.float32, device=DEV)]
+    lohi = torch.tensor([[0.0, 1.0]], dtype=torch.float64, device=DEV)
+    bad = [
+        lambda: ctx.zscale(f, nsamples=0),
+        lambda: ctx.zscale(f, nsamples=1001),
+        lambda: ctx.zscale(f, contrast=-1.0),
+        lambda: ctx.gray_map(f, 7, lohi),
+        lambda: ctx.gray_map(f, ipp.IPP_MAP_LOG, lohi, a=-1.0),
+        lambda: ctx.gray_map(f, ipp.IPP_MAP_EXP, lohi, a=1.0),
+        lambda: ctx.gray_map(f, ipp.IPP_MAP_POWER, lohi, a=float("nan")),
+        lambda: ctx.equalize(f, nbins=1),
+        lambda: ctx.equalize(f, nbins=4097),
+    ]
+    for call in bad:
+        with pytest.raises((ipp.IppError, ValueError)):
+            call()
+    # a valid call still works afterwards
+    y = ctx.gray_map(f, ipp.IPP_MAP_LINEAR, lohi)
+    torch.cuda.synchronize()
+    assert float(y[0].abs().max()) == 0.0
