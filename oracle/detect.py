@@ -27,6 +27,8 @@ Readings taken where the text is open:
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from .params import (Params, SRC_INEXACT_SUM_RANGE, SRC_NONPOSITIVE_FLUX)
@@ -165,3 +167,63 @@ def detect(frame: np.ndarray, B32: np.ndarray, R32: np.ndarray, p: Params):
     lab, n = apply_min_area(lab, n, p.min_area)
     return {"det": det, "labels": lab, "n": n,
             "table": source_table(frame, B32, lab, n)}
+
+
+def source_moments(frame: np.ndarray, B32: np.ndarray, lab: np.ndarray,
+                   nlab: int):
+    """Second-order moments of every candidate's footprint and the ellipse
+    they describe (the pre-analysis of Sec. 2.2.5 carried to second order,
+    as SExtractor's X2, Y2, XY, A, B, THETA).  Weights D_i are the same
+    integers as in ``source_table`` (d_i 2^28, clipped likewise); with
+    dx = x - xmin and dy = y - ymin the exact sums S = sum D, Sx = sum D dx,
+    Sy, Sxx = sum D dx^2, Syy, Sxy = sum D dx dy are each rounded to binary64
+    once, and then (binary64, in this order):
+      mx = Sx / S, my = Sy / S,
+      x2 = Sxx / S - mx mx, y2 = Syy / S - my my, xy = Sxy / S - mx my,
+      t = (x2 + y2) / 2, h = (x2 - y2) / 2, r = sqrt(h h + xy xy),
+      a = sqrt(t + r), b = sqrt(max(t - r, 0)),
+      theta = atan2(2 xy, x2 - y2) / 2.
+    Returns float64 [nlab, 6] (x2, y2, xy, a, b, theta); NaN where S <= 0.
+    """
+    I32 = np.asarray(frame, dtype=np.float32)
+    B = np.asarray(B32, dtype=np.float32)
+    h, w = lab.shape
+    flat = lab.ravel()
+    order = np.argsort(flat, kind="stable")
+    starts = np.searchsorted(flat[order], np.arange(nlab + 2))
+    out = np.full((nlab, 6), np.nan)
+    for k in range(1, nlab + 1):
+        idx = order[starts[k]:starts[k + 1]]
+        ys, xs = idx // w, idx % w
+        v = (I32.ravel()[idx].astype(np.float64)
+             - B.ravel()[idx].astype(np.float64))
+        xmin, ymin = int(xs.min()), int(ys.min())
+        S = Sx = Sy = Sxx = Syy = Sxy = 0
+        for vi, xi, yi in zip(v.tolist(), xs.tolist(), ys.tolist()):
+            D = int(round(vi * 2.0 ** _Q))
+            if D > _DMAX or D < -_DMAX:
+                D = _DMAX if D > 0 else -_DMAX
+            dx, dy = xi - xmin, yi - ymin
+            S += D
+            Sx += D * dx
+            Sy += D * dy
+            Sxx += D * dx * dx
+            Syy += D * dy * dy
+            Sxy += D * dx * dy
+        if S <= 0:
+            continue
+        fS = float(S)
+        mx = float(Sx) / fS
+        my = float(Sy) / fS
+        x2 = float(Sxx) / fS - mx * mx
+        y2 = float(Syy) / fS - my * my
+        xy = float(Sxy) / fS - mx * my
+        t = (x2 + y2) / 2.0
+        hd = (x2 - y2) / 2.0
+        r = math.sqrt(hd * hd + xy * xy)
+        a = math.sqrt(t + r)
+        b = math.sqrt(max(t - r, 0.0))
+        theta = math.atan2(2.0 * xy, x2 - y2) / 2.0
+        out[k - 1] = (x2, y2, xy, a, b, theta)
+    return out
+

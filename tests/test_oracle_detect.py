@@ -1,5 +1,6 @@
 """Pins of the detection oracle (Sec. 2.2.5): hand-worked labellings,
 scipy's labelling, closed-form pre-analysis and exact rational sums."""
+import math
 import os
 from fractions import Fraction
 
@@ -154,3 +155,64 @@ def test_out_of_range_pixel_flags_row():
     B = np.zeros_like(I)
     t = _src(I, B, Params(min_area=1))
     assert t["flags"][0] & SRC_INEXACT_SUM_RANGE
+
+
+def _moments_of(mask, dvals):
+    """Moments of one candidate: image 1 + d on a unit sky, label 1."""
+    I = np.ones(mask.shape, dtype=np.float32)
+    I[mask] += np.asarray(dvals, dtype=np.float32)
+    lab = mask.astype(np.int32)
+    return dt.source_moments(I, np.ones_like(I), lab, 1)[0]
+
+
+@pytest.mark.parametrize("w,h", [(5, 3), (4, 7), (6, 6), (1, 9)])
+def test_moments_of_a_uniform_box(w, h):
+    # discrete uniform: variance (n^2 - 1) / 12 along each axis, no xy
+    m = np.zeros((12, 14), dtype=bool)
+    m[2:2 + h, 3:3 + w] = True
+    x2, y2, xy, a, b, th = _moments_of(m, 4.0)
+    assert math.isclose(x2, (w * w - 1) / 12, rel_tol=1e-15, abs_tol=1e-15)
+    assert math.isclose(y2, (h * h - 1) / 12, rel_tol=1e-15, abs_tol=1e-15)
+    assert abs(xy) <= 1e-15
+    big, small = max(x2, y2), min(x2, y2)
+    assert math.isclose(a, math.sqrt(big), rel_tol=1e-15)
+    assert math.isclose(b, math.sqrt(small), rel_tol=1e-15, abs_tol=1e-15)
+    if w > h:
+        assert th == 0.0
+    elif h > w:
+        assert math.isclose(th, math.pi / 2, rel_tol=1e-15)
+
+
+def test_moments_of_a_diagonal_and_a_weighted_pair():
+    n = 7
+    m = np.zeros((10, 10), dtype=bool)
+    m[np.arange(n) + 1, np.arange(n) + 2] = True
+    x2, y2, xy, a, b, th = _moments_of(m, 3.0)
+    v = (n * n - 1) / 12
+    for got in (x2, y2, xy):
+        assert math.isclose(got, v, rel_tol=1e-15)
+    assert math.isclose(a, math.sqrt(2 * v), rel_tol=1e-15) and b == 0.0
+    assert math.isclose(th, math.pi / 4, rel_tol=1e-15)
+    # weights 1 and 2 at x = 0 and x = 3 (one row): mean 2, variance 2
+    m = np.zeros((3, 6), dtype=bool)
+    m[1, 1] = m[1, 4] = True
+    x2, y2, xy, a, b, th = _moments_of(m, [1.0, 2.0])
+    assert (x2, y2, xy, th) == (2.0, 0.0, 0.0, 0.0)
+    assert a == math.sqrt(2.0) and b == 0.0
+
+
+def test_moments_rotate_with_the_shape():
+    m = np.zeros((9, 9), dtype=bool)
+    m[2, 2:7] = True
+    m[2:6, 2] = True
+    m[5, 3] = True                                   # an irregular L
+    rng = np.random.default_rng(5)
+    d = rng.integers(1, 50, m.shape).astype(np.float32)
+    x2, y2, xy, a, b, th = _moments_of(m, d[m])
+    mr = np.rot90(m)                                 # (x, y) -> (y, -x)
+    x2r, y2r, xyr, ar, br, _ = _moments_of(mr, np.rot90(d)[mr])
+    assert math.isclose(x2r, y2, rel_tol=1e-12)
+    assert math.isclose(y2r, x2, rel_tol=1e-12)
+    assert math.isclose(xyr, -xy, rel_tol=1e-12)
+    assert math.isclose(ar, a, rel_tol=1e-12) and math.isclose(br, b,
+                                                              rel_tol=1e-12)
