@@ -287,6 +287,25 @@ ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
                               double b, void* stream);
 
 /*
+ * Second-order moments of each table row's footprint (the pre-analysis of
+ * Sec. 2.2.5 carried to second order, as SExtractor's X2, Y2, XY and the
+ * ellipse A, B, THETA): over the bounding-box pixels whose label is the
+ * row's, with the integer weights D = (I - B32) 2^28 of the source table,
+ * exact sums of D, D dx, D dy, D dx^2, D dy^2, D dx dy (dx, dy from the
+ * bounding-box corner), each rounded once to binary64; then
+ * mx = Sx/S, my = Sy/S, x2 = Sxx/S - mx^2, y2 = Syy/S - my^2,
+ * xy = Sxy/S - mx my, t = (x2 + y2)/2, r = sqrt(((x2 - y2)/2)^2 + xy^2),
+ * a = sqrt(t + r), b = sqrt(max(t - r, 0)), theta = atan2(2 xy, x2 - y2)/2.
+ * Reads the table's frame, label and bounding box (rows: min(capacity,
+ * *n_total)) and maps[f].bkg and maps[f].labels; writes mom, device
+ * double[6 * capacity]: (x2, y2, xy, a, b, theta) per row, NaN where the
+ * weights do not sum to a positive value.
+ */
+ipp_status ipp_source_moments(void* ctx, const ipp_frame* frames, int32_t n,
+                              const ipp_maps* maps, const ipp_sources* src,
+                              double* mom, void* stream);
+
+/*
  * Gray-scale transformations (Sec. 2.2.6): the zscale display range, point
  * maps and histogram equalization.  Frames as elsewhere (mask ignored);
  * outputs out[f] are device float32 h x w arrays with row pitch w.

@@ -151,6 +151,10 @@ def lib():
                                C.POINTER(IppParams), C.c_uint32, C.c_char_p,
                                C.POINTER(C.c_double), vp]
     L.ipp_autotune.restype = i32
+    L.ipp_source_moments.argtypes = [vp, C.POINTER(IppFrame), i32,
+                                     C.POINTER(IppMaps), C.POINTER(IppSources),
+                                     vp, vp]
+    L.ipp_source_moments.restype = i32
     L.ipp_gray_workspace_bytes.argtypes = [i32, i32]
     L.ipp_gray_workspace_bytes.restype = sz
     L.ipp_zscale.argtypes = [vp, C.POINTER(IppFrame), i32, i32, C.c_double,

@@ -319,6 +319,25 @@ class Context:
             float(a), float(b), _stream()))
         return dv, dab
 
+    def source_moments(self, frames, bkg, labels, table: SourceTable):
+        """Second-order moments per table row: float64 tensor [rows, 6]
+        (x2, y2, xy, a, b, theta)."""
+        n = len(frames)
+        self.ensure(frames, Params())
+        maps = (L.IppMaps * n)()
+        for i in range(n):
+            _check_gpu_f32(bkg[i], "bkg")
+            maps[i].bkg = bkg[i].data_ptr()
+            maps[i].labels = labels[i].data_ptr()
+        cap = max(1, table.capacity)
+        mom = torch.full((cap, 6), float("nan"), dtype=torch.float64,
+                         device=frames[0].device)
+        src = table.to_c()
+        self._check(self.lib.ipp_source_moments(
+            self.h, frames_c(frames), n, maps, C.byref(src), _ptr(mom),
+            _stream()))
+        return mom[:min(table.count(), table.capacity)]
+
     # ------------------------------------------------ gray scale (2.2.6)
     def _gray_reserve(self, n, nbins=0):
         need = self.lib.ipp_gray_workspace_bytes(n, nbins)

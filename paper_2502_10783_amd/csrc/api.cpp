@@ -1162,4 +1162,39 @@ ipp_status ipp_equalize(void* ctx, const ipp_frame* frames, int32_t n,
   return IPP_OK;
 }
 
+ipp_status ipp_source_moments(void* ctx, const ipp_frame* frames, int32_t n,
+                              const ipp_maps* maps, const ipp_sources* src,
+                              double* mom, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (!src || src->capacity < 0 || !src->frame || !src->label ||
+      !src->xmin || !src->xmax || !src->ymin || !src->ymax)
+    return fail(c, IPP_E_INVALID_ARG,
+                "sources: frame, label and the bounding box are required");
+  if (!mom) return fail(c, IPP_E_INVALID_ARG, "mom is NULL");
+  ipp_params pd;
+  ipp_params_default(&pd);
+  Plan P;
+  ipp_status st = prepare(c, frames, n, &pd, kPlanFrames, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg || !maps[i].labels)
+      return fail(c, IPP_E_INVALID_ARG,
+                  "maps[f].bkg and maps[f].labels are required");
+    P.fd[i].bkg = maps[i].bkg;
+    P.fd[i].labels = maps[i].labels;
+  }
+  if (src->capacity == 0) return IPP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  IPP_LAUNCH(c, s, "k_source_moments",
+             hipLaunchKernelGGL(k_source_moments,
+                                dim3(grid_for(src->capacity, kWaves, 16384)),
+                                dim3(kBlock), 0, s, w, *src, mom));
+  return IPP_OK;
+}
+
 }  // extern "C"

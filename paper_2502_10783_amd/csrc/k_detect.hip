@@ -1092,6 +1092,130 @@ __global__ __launch_bounds__(kBlock) void k_source_stats(Work wk,
   }
 }
 
+// ---------------------------------------------------------------------
+// Second-order moments of each table row's footprint: one wavefront per
+// row, exact int128 sums of D, D dx, D dy, D dx^2, D dy^2, D dx dy over the
+// bounding box (D = v 2^28 as in the source table, dx and dy from the
+// bounding-box corner), each rounded to binary64 once; then the moments and
+// the ellipse they describe in a fixed order of binary64 operations.
+// ---------------------------------------------------------------------
+namespace {
+struct MomAcc {
+  U128 S, Sx, Sy, Sxx, Syy, Sxy;
+};
+
+__device__ __forceinline__ U128 shfl_xor128(U128 v, int m) {
+  U128 r;
+  const uint32_t l0 = (uint32_t)__shfl_xor((int)(uint32_t)v.lo, m, kWave);
+  const uint32_t l1 = (uint32_t)__shfl_xor((int)(uint32_t)(v.lo >> 32), m,
+                                           kWave);
+  const uint32_t h0 = (uint32_t)__shfl_xor((int)(uint32_t)v.hi, m, kWave);
+  const uint32_t h1 = (uint32_t)__shfl_xor((int)(uint32_t)(v.hi >> 32), m,
+                                           kWave);
+  r.lo = ((uint64_t)l1 << 32) | l0;
+  r.hi = ((uint64_t)h1 << 32) | h0;
+  return r;
+}
+
+__device__ __forceinline__ U128 wave_sum128(U128 v) {
+#pragma unroll
+  for (int m = kWave / 2; m > 0; m >>= 1) v = add128(v, shfl_xor128(v, m));
+  return v;
+}
+
+__device__ __forceinline__ void mom_acc(MomAcc& a, const PixIn& q, int label,
+                                        int dx, int dy) {
+  const double two_q = 268435456.0;                  // 2^28
+  const double dmax = 4611686018427387903.0;         // 2^62 - 1
+  const double v = (double)q.I - (double)q.B;
+  double s = rint(v * two_q);
+  s = fmin(fmax(s, -dmax), dmax);
+  const int64_t D = q.lab == label ? (int64_t)s : 0;
+  a.S = add128(a.S, from_i64(D));
+  a.Sx = add128(a.Sx, mul_i64(D, dx));
+  a.Sy = add128(a.Sy, mul_i64(D, dy));
+  a.Sxx = add128(a.Sxx, mul_i64(D, (int64_t)dx * dx));
+  a.Syy = add128(a.Syy, mul_i64(D, (int64_t)dy * dy));
+  a.Sxy = add128(a.Sxy, mul_i64(D, (int64_t)dx * dy));
+}
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void k_source_moments(Work wk,
+                                                           ipp_sources src,
+                                                           double* mom) {
+  const int lane = threadIdx.x & (kWave - 1);
+  long long nrows = src.capacity;
+  if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
+  const long long wid =
+      blockIdx.x * (long long)kWaves +
+      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const long long nw = (long long)gridDim.x * (kBlock / kWave);
+  for (long long row = wid; row < nrows; row += nw) {
+    const int f = src.frame[row];
+    double* out = mom + 6 * row;
+    if (f < 0 || f >= wk.nframes) {
+      if (lane < 6) out[lane] = __builtin_nan("");
+      continue;
+    }
+    const FrameDev fr = wk.frames[f];
+    const int label = src.label[row];
+    const int xmin = max(src.xmin[row], 0), xmax = min(src.xmax[row], fr.w - 1);
+    const int ymin = max(src.ymin[row], 0), ymax = min(src.ymax[row], fr.h - 1);
+    MomAcc a;
+    a.S = a.Sx = a.Sy = a.Sxx = a.Syy = a.Sxy = from_i64(0);
+    if (xmin <= xmax && ymin <= ymax) {
+      const int bw = xmax - xmin + 1;
+      const long long area = (long long)bw * (ymax - ymin + 1);
+      int ey = lane / bw, ex = lane - (lane / bw) * bw;
+      const int dy = kWave / bw, dx = kWave - (kWave / bw) * bw;
+      // two bounding-box steps per lane, both loaded before either is used
+      for (long long e = lane; e < area; e += 2 * kWave) {
+        const int y0 = ey, x0 = ex;
+        ey += dy; ex += dx;
+        if (ex >= bw) { ex -= bw; ++ey; }
+        const int y1 = ey, x1 = ex;
+        ey += dy; ex += dx;
+        if (ex >= bw) { ex -= bw; ++ey; }
+        const bool two = e + kWave < area;
+        const PixIn q0 = stat_load(fr, xmin + x0, ymin + y0);
+        PixIn q1 = {0, 0.0f, 0.0f};
+        if (two) q1 = stat_load(fr, xmin + x1, ymin + y1);
+        mom_acc(a, q0, label, x0, y0);
+        if (two) mom_acc(a, q1, label, x1, y1);
+      }
+    }
+    a.S = wave_sum128(a.S);
+    a.Sx = wave_sum128(a.Sx);
+    a.Sy = wave_sum128(a.Sy);
+    a.Sxx = wave_sum128(a.Sxx);
+    a.Syy = wave_sum128(a.Syy);
+    a.Sxy = wave_sum128(a.Sxy);
+    if (lane == 0) {
+      const bool pos = (int64_t)a.S.hi > 0 ||
+                       ((int64_t)a.S.hi == 0 && a.S.lo > 0);
+      if (!pos) {
+        for (int k = 0; k < 6; ++k) out[k] = __builtin_nan("");
+      } else {
+        const double fS = to_double(a.S);
+        const double mx = to_double(a.Sx) / fS;
+        const double my = to_double(a.Sy) / fS;
+        const double x2 = to_double(a.Sxx) / fS - mx * mx;
+        const double y2 = to_double(a.Syy) / fS - my * my;
+        const double xy = to_double(a.Sxy) / fS - mx * my;
+        const double t = (x2 + y2) / 2.0;
+        const double hd = (x2 - y2) / 2.0;
+        const double r = sqrt(hd * hd + xy * xy);
+        out[0] = x2;
+        out[1] = y2;
+        out[2] = xy;
+        out[3] = sqrt(t + r);
+        out[4] = sqrt(fmax(t - r, 0.0));
+        out[5] = atan2(2.0 * xy, x2 - y2) / 2.0;
+      }
+    }
+  }
+}
+
 #define IPP_TILE_INST(TH, TW)                                              \
   template __global__ void k_bkg_maps<TH, TW>(Work, ipp_params);           \
   template __global__ void k_tile_ccl<TH, TW, true, true, kTileThreads>(Work, ipp_params, \

@@ -43,6 +43,7 @@ __global__ void k_scatter(Work wk, ipp_params p);
 __global__ void k_rank(Work wk, ipp_params p, ipp_sources src);
 __global__ void k_reclabel(Work wk);
 __global__ void k_source_stats(Work wk, ipp_sources src);
+__global__ void k_source_moments(Work wk, ipp_sources src, double* mom);
 
 template <int NS>
 __global__ void k_aperture_t(Work wk, ipp_params p, ipp_sources src,

@@ -1,0 +1,75 @@
+"""GPU parity of the second-order moments of each candidate (the
+pre-analysis of Sec. 2.2.5 carried to second order) against the oracle.
+
+The integer sums are exact on both sides and every later step is the same
+sequence of binary64 operations, so x2, y2 and xy must match bit for bit;
+a and b go through square roots and theta through atan2, compared to
+1e-14 relative and 1e-13 absolute.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import detect as odt
+from synth import make_frame
+
+import paper_2502_10783_amd as ipp
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ipp.Context(0)
+    yield c
+    c.close()
+
+
+def _cases():
+    a, _, _ = make_frame("single", 0)                        # 1024 x 1024
+    b, _, _ = make_frame("stack16", 3, scale=0.0813)         # 333 x 333
+    return [("single-1024", a, 64), ("stack16-ragged",
+                                      b[:, :317].contiguous(), 32)]
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
+def test_moments_match_oracle(ctx, case):
+    name, img, m = case
+    p = ipp.Params(mesh_h=m, mesh_w=m)
+    frames = [img.to(DEV)]
+    out = ctx.process_batch(frames, p, capacity=20000)
+    mom = ctx.source_moments(frames, out["bkg"], out["labels"], out["table"])
+    torch.cuda.synchronize()
+    mom = mom.cpu().numpy()
+    lab = out["labels"][0].cpu().numpy()
+    n = int(lab.max())
+    assert mom.shape[0] == n
+    ref = odt.source_moments(img.numpy(), out["bkg"][0].cpu().numpy(), lab, n)
+    assert np.array_equal(np.isnan(mom), np.isnan(ref)), name
+    ok = ~np.isnan(ref[:, 0])
+    assert np.array_equal(mom[ok, :3], ref[ok, :3]), name
+    np.testing.assert_allclose(mom[ok, 3:], ref[ok, 3:], rtol=1e-14,
+                               atol=1e-13)
+    # the ellipse axes bound the moments: b^2 <= x2, y2 <= a^2
+    assert np.all(mom[ok, 4] ** 2 <= mom[ok, 0] * (1 + 1e-12) + 1e-12)
+    assert np.all(mom[ok, 0] <= mom[ok, 3] ** 2 * (1 + 1e-12) + 1e-12)
+
+
+def test_moments_of_a_batch_match_per_frame(ctx):
+    imgs = [make_frame("stack16", i, scale=0.06)[0].to(DEV) for i in (1, 2)]
+    p = ipp.Params(mesh_h=32, mesh_w=32)
+    out = ctx.process_batch(imgs, p, capacity=20000)
+    mom = ctx.source_moments(imgs, out["bkg"], out["labels"], out["table"])
+    torch.cuda.synchronize()
+    mom = mom.cpu().numpy()
+    offs = out["table"].frame_offsets.cpu().numpy()
+    for i, img in enumerate(imgs):
+        lab = out["labels"][i].cpu().numpy()
+        n = int(lab.max())
+        ref = odt.source_moments(img.cpu().numpy(),
+                                 out["bkg"][i].cpu().numpy(), lab, n)
+        got = mom[offs[i]:offs[i + 1]]
+        ok = ~np.isnan(ref[:, 0])
+        assert np.array_equal(got[ok, :3], ref[ok, :3])
