@@ -118,6 +118,9 @@ WORKLOADS = {
     "uneven": (256, "256 float32 frames drawn from {512x512, 1024x1024, "
                     "2048x4096, 4096x4096}, star density log-uniform "
                     "1e-5..5e-3 per px, flat sky U(200, 5000)"),
+    "crowded": (32, "32 frames of 10560x10560 float32, 1/f^2 Gaussian "
+                    "random field nebulosity, 100k Moffat stars each, "
+                    "saturated at 65535"),
 }
 
 
