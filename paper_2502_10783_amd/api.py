@@ -74,8 +74,15 @@ def frames_c(frames: Sequence[torch.Tensor], masks=None):
     for i, fr in enumerate(frames):
         _check_gpu_f32(fr, f"frame {i}")
         arr[i].pix = fr.data_ptr()
-        arr[i].mask = (masks[i].data_ptr() if masks is not None
-                       and masks[i] is not None else None)
+        mk = masks[i] if masks is not None else None
+        if mk is not None:
+            # the library reads the mask with the frame's row pitch
+            if not (mk.is_cuda and mk.dtype == torch.uint8 and mk.dim() == 2
+                    and tuple(mk.shape) == tuple(fr.shape)
+                    and mk.stride(1) == 1 and mk.stride(0) == fr.stride(0)):
+                raise ValueError(f"mask {i}: need a uint8 CUDA tensor of the "
+                                 "frame's shape and row pitch")
+        arr[i].mask = mk.data_ptr() if mk is not None else None
         arr[i].pitch = fr.stride(0)
         arr[i].h, arr[i].w = fr.shape
     return arr
@@ -415,8 +422,10 @@ class Context:
 
     def process_batch(self, frames, params: Params, capacity=None,
                       table: Optional[SourceTable] = None, outputs=None,
-                      write_rms=False):
-        """Pipeline mode (Sec. 2.1): the whole path for a batch."""
+                      write_rms=False, masks=None):
+        """Pipeline mode (Sec. 2.1): the whole path for a batch (masks:
+        optional uint8 tensors, non-zero = pixel left out of the
+        background statistics)."""
         self.ensure(frames, params)
         n = len(frames)
         dev = frames[0].device
@@ -444,7 +453,8 @@ class Context:
         src = table.to_c()
         pc = p.to_c()
         self._check(self.lib.ipp_process_batch(
-            self.h, frames_c(frames), n, C.byref(pc), maps, C.byref(src),
+            self.h, frames_c(frames, masks), n, C.byref(pc), maps,
+            C.byref(src),
             _ptr(flags), _ptr(diag), _stream()))
         outputs.update({"table": table, "flags": flags, "diag": diag})
         return outputs

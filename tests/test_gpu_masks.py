@@ -1,0 +1,70 @@
+"""Masks (pixels left out of the background statistics, Sec. 2.2.2) in the
+batched path: the background of each frame against the oracle's with the
+same mask (<= 1e-6), detection against the oracle's on the GPU's maps
+(bit-exact), and a second call of the same batch shape with other masks,
+which replays the captured graph with the new descriptors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import background as obg, detect as odt
+from synth import make_frame
+
+import paper_2502_10783_amd as ipp
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ipp.Context(0)
+    yield c
+    c.close()
+
+
+def _masks(shapes, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, (h, w) in enumerate(shapes):
+        m = rng.random((h, w)) < 0.08
+        y0 = int(rng.integers(0, h - 40))
+        x0 = int(rng.integers(0, w - 70))
+        m[y0:y0 + 40, x0:x0 + 70] = True          # a wholly masked region
+        out.append(m)
+    return out
+
+
+def _check(ctx, imgs, masks, p, op):
+    dev = [torch.from_numpy(i).to(DEV) for i in imgs]
+    mk = [torch.from_numpy(m.astype(np.uint8)).to(DEV) for m in masks]
+    out = ctx.process_batch(dev, p, capacity=20000, write_rms=True, masks=mk)
+    torch.cuda.synchronize()
+    for i, (img, m) in enumerate(zip(imgs, masks)):
+        ref = obg.background(img, op, m)
+        B = out["bkg"][i].cpu().numpy()
+        R = out["rms"][i].cpu().numpy()
+        assert int(out["flags"][i]) == ref["flags"], i
+        assert np.max(np.abs(B - ref["B64"]) / np.abs(ref["B64"])) <= 1e-6, i
+        det = odt.detect(img, B, R, op)
+        assert np.array_equal(out["labels"][i].cpu().numpy(), det["labels"])
+
+
+def test_masked_batch_and_replay(ctx):
+    imgs = [make_frame("single", 2, scale=0.5)[0].numpy(),
+            make_frame("stack16", 4, scale=0.09)[0].numpy()]
+    shapes = [i.shape for i in imgs]
+    kw = dict(mesh_h=32, mesh_w=32)
+    p, op = ipp.Params(**kw), oracle.Params(**kw)
+    _check(ctx, imgs, _masks(shapes, 1), p, op)
+    _check(ctx, imgs, _masks(shapes, 2), p, op)
+
+
+def test_mask_layout_checked(ctx):
+    f = torch.zeros((16, 16), dtype=torch.float32, device=DEV)
+    bad = torch.zeros((16, 15), dtype=torch.uint8, device=DEV)
+    with pytest.raises(ValueError):
+        ctx.process_batch([f], ipp.Params(mesh_h=16, mesh_w=16),
+                          capacity=64, masks=[bad])
