@@ -69,6 +69,16 @@ def _check_gpu_f32(t: torch.Tensor, what: str):
                          "unit column stride")
 
 
+def _check_map(t: torch.Tensor, fr: torch.Tensor, what: str,
+               dtype=torch.float32):
+    """A per-pixel map of frame fr as the library reads it: dense h x w
+    (row pitch w) of the given dtype on the GPU."""
+    if not (t.is_cuda and t.dtype == dtype and t.dim() == 2
+            and tuple(t.shape) == tuple(fr.shape) and t.is_contiguous()):
+        raise ValueError(f"{what}: need a contiguous {dtype} CUDA tensor of "
+                         f"the frame's shape {tuple(fr.shape)}")
+
+
 def frames_c(frames: Sequence[torch.Tensor], masks=None):
     arr = (L.IppFrame * len(frames))()
     for i, fr in enumerate(frames):
@@ -241,8 +251,8 @@ class Context:
         maps = (L.IppMaps * n)()
         labels = []
         for i, fr in enumerate(frames):
-            _check_gpu_f32(bkg[i], "bkg")
-            _check_gpu_f32(rms[i], "rms")
+            _check_map(bkg[i], fr, "bkg")
+            _check_map(rms[i], fr, "rms")
             lab = torch.empty(fr.shape, dtype=torch.int32, device=dev)
             maps[i].bkg, maps[i].rms = bkg[i].data_ptr(), rms[i].data_ptr()
             maps[i].labels = lab.data_ptr()
@@ -261,7 +271,7 @@ class Context:
         n = len(frames)
         maps = (L.IppMaps * n)()
         for i in range(n):
-            _check_gpu_f32(bkg[i], "bkg")
+            _check_map(bkg[i], frames[i], "bkg")
             maps[i].bkg = bkg[i].data_ptr()
         self.ensure(frames, params)
         lohi = None
@@ -283,13 +293,14 @@ class Context:
         n = len(frames)
         maps = (L.IppMaps * n)()
         for i in range(n):
+            _check_map(bkg[i], frames[i], "bkg")
             maps[i].bkg = bkg[i].data_ptr()
         dp = None
         if dpix is not None:
             dp = (C.c_void_p * n)()
             for i in range(n):
                 if dpix[i] is not None:
-                    _check_gpu_f32(dpix[i], "dpix")
+                    _check_map(dpix[i], frames[i], "dpix")
                     dp[i] = dpix[i].data_ptr()
         dxy = None
         if want_dxy:
@@ -305,6 +316,8 @@ class Context:
 
     def asinh(self, v: torch.Tensor, a: float, b: float):
         """y = b * asinh(v / a) (float32, element-wise)."""
+        if not (v.is_cuda and v.dtype == torch.float32):
+            raise ValueError("v: need a float32 CUDA tensor")
         v = v.contiguous()
         y = torch.empty_like(v)
         self._check(self.lib.ipp_asinh(self.h, _ptr(v), _ptr(y), v.numel(),
@@ -314,6 +327,9 @@ class Context:
     def asinh_backward(self, v, dy, a: float, b: float, want_dv=True,
                        want_dab=True):
         """(dL/dv, tensor([dL/da, dL/db]))."""
+        if not (v.is_cuda and dy.is_cuda and v.dtype == torch.float32
+                and dy.dtype == torch.float32 and v.numel() == dy.numel()):
+            raise ValueError("v, dy: need float32 CUDA tensors of one size")
         if want_dab and self.ws_bytes < (1 << 16):
             self.reserve(1 << 16)
         v = v.contiguous()
@@ -333,7 +349,8 @@ class Context:
         self.ensure(frames, Params())
         maps = (L.IppMaps * n)()
         for i in range(n):
-            _check_gpu_f32(bkg[i], "bkg")
+            _check_map(bkg[i], frames[i], "bkg")
+            _check_map(labels[i], frames[i], "labels", torch.int32)
             maps[i].bkg = bkg[i].data_ptr()
             maps[i].labels = labels[i].data_ptr()
         cap = max(1, table.capacity)
@@ -377,6 +394,8 @@ class Context:
         if out is None:
             out = [torch.empty(f.shape, dtype=torch.float32, device=f.device)
                    for f in frames]
+        for i in range(n):
+            _check_map(out[i], frames[i], "out")
         ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in out])
         self._check(self.lib.ipp_gray_map(
             self.h, frames_c(frames), n, int(kind), float(a), _ptr(lohi),
@@ -394,6 +413,8 @@ class Context:
                    for f in frames]
         cnt = (torch.empty((n, nbins), dtype=torch.int32, device=dev)
                if counts else None)
+        for i in range(n):
+            _check_map(out[i], frames[i], "out")
         ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in out])
         self._check(self.lib.ipp_equalize(
             self.h, frames_c(frames), n, int(nbins), ptrs, _ptr(cnt),
@@ -441,6 +462,11 @@ class Context:
                                if write_rms else None)}
         maps = (L.IppMaps * n)()
         for i in range(n):
+            _check_map(outputs["bkg"][i], frames[i], "bkg")
+            _check_map(outputs["labels"][i], frames[i], "labels",
+                       torch.int32)
+            if write_rms:
+                _check_map(outputs["rms"][i], frames[i], "rms")
             maps[i].bkg = outputs["bkg"][i].data_ptr()
             maps[i].labels = outputs["labels"][i].data_ptr()
             if write_rms:

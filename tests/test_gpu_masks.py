@@ -68,3 +68,23 @@ def test_mask_layout_checked(ctx):
     with pytest.raises(ValueError):
         ctx.process_batch([f], ipp.Params(mesh_h=16, mesh_w=16),
                           capacity=64, masks=[bad])
+
+
+def test_map_layouts_checked(ctx):
+    """Maps handed to the library must have the frame's shape, dtype and a
+    dense layout; anything else is refused before a launch."""
+    f = torch.zeros((32, 40), dtype=torch.float32, device=DEV)
+    p = ipp.Params(mesh_h=16, mesh_w=16)
+    small = torch.zeros((32, 39), dtype=torch.float32, device=DEV)
+    wide = torch.zeros((32, 48), dtype=torch.float32, device=DEV)[:, :40]
+    table = ipp.SourceTable(16, 1, DEV)
+    with pytest.raises(ValueError):
+        ctx.detect([f], [small], [f.clone()], p)
+    with pytest.raises(ValueError):
+        ctx.photometry([f], [wide], table, p)
+    with pytest.raises(ValueError):
+        ctx.gray_map([f], ipp.IPP_MAP_LINEAR,
+                     torch.zeros((1, 2), dtype=torch.float64, device=DEV),
+                     out=[small])
+    with pytest.raises(ValueError):
+        ctx.asinh_backward(f, small, 1.0, 1.0)
