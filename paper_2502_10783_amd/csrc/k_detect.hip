@@ -1140,7 +1140,42 @@ __device__ __forceinline__ void mom_acc(MomAcc& a, const PixIn& q, int label,
 }
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void k_source_moments(Work wk,
+// Moments and ellipse from the six sums (binary64, fixed order).
+__device__ __forceinline__ void mom_finish(const MomAcc& a, double* out) {
+  const bool pos = (int64_t)a.S.hi > 0 || ((int64_t)a.S.hi == 0 && a.S.lo > 0);
+  if (!pos) {
+    for (int k = 0; k < 6; ++k) out[k] = __builtin_nan("");
+    return;
+  }
+  const double fS = to_double(a.S);
+  const double mx = to_double(a.Sx) / fS;
+  const double my = to_double(a.Sy) / fS;
+  const double x2 = to_double(a.Sxx) / fS - mx * mx;
+  const double y2 = to_double(a.Syy) / fS - my * my;
+  const double xy = to_double(a.Sxy) / fS - mx * my;
+  const double t = (x2 + y2) / 2.0;
+  const double hd = (x2 - y2) / 2.0;
+  const double r = sqrt(hd * hd + xy * xy);
+  out[0] = x2;
+  out[1] = y2;
+  out[2] = xy;
+  out[3] = sqrt(t + r);
+  out[4] = sqrt(fmax(t - r, 0.0));
+  out[5] = atan2(2.0 * xy, x2 - y2) / 2.0;
+}
+
+// Sum over the 16 lanes of a row (lanes 16k .. 16k+15).
+__device__ __forceinline__ U128 row_sum128(U128 v) {
+#pragma unroll
+  for (int m = 8; m > 0; m >>= 1) v = add128(v, shfl_xor128(v, m));
+  return v;
+}
+
+// One wavefront takes four consecutive rows: those whose bounding box holds
+// at most 16 pixels together, 16 lanes each, then each larger one over the
+// whole wave.
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(4))) void k_source_moments(Work wk,
                                                            ipp_sources src,
                                                            double* mom) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -1150,67 +1185,96 @@ __global__ __launch_bounds__(kBlock) void k_source_moments(Work wk,
       blockIdx.x * (long long)kWaves +
       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const long long nw = (long long)gridDim.x * (kBlock / kWave);
-  for (long long row = wid; row < nrows; row += nw) {
-    const int f = src.frame[row];
-    double* out = mom + 6 * row;
-    if (f < 0 || f >= wk.nframes) {
-      if (lane < 6) out[lane] = __builtin_nan("");
-      continue;
-    }
-    const FrameDev fr = wk.frames[f];
-    const int label = src.label[row];
-    const int xmin = max(src.xmin[row], 0), xmax = min(src.xmax[row], fr.w - 1);
-    const int ymin = max(src.ymin[row], 0), ymax = min(src.ymax[row], fr.h - 1);
-    MomAcc a;
-    a.S = a.Sx = a.Sy = a.Sxx = a.Syy = a.Sxy = from_i64(0);
-    if (xmin <= xmax && ymin <= ymax) {
-      const int bw = xmax - xmin + 1;
-      const long long area = (long long)bw * (ymax - ymin + 1);
-      int ey = lane / bw, ex = lane - (lane / bw) * bw;
-      const int dy = kWave / bw, dx = kWave - (kWave / bw) * bw;
-      // two bounding-box steps per lane, both loaded before either is used
-      for (long long e = lane; e < area; e += 2 * kWave) {
-        const int y0 = ey, x0 = ex;
-        ey += dy; ex += dx;
-        if (ex >= bw) { ex -= bw; ++ey; }
-        const int y1 = ey, x1 = ex;
-        ey += dy; ex += dx;
-        if (ex >= bw) { ex -= bw; ++ey; }
-        const bool two = e + kWave < area;
-        const PixIn q0 = stat_load(fr, xmin + x0, ymin + y0);
-        PixIn q1 = {0, 0.0f, 0.0f};
-        if (two) q1 = stat_load(fr, xmin + x1, ymin + y1);
-        mom_acc(a, q0, label, x0, y0);
-        if (two) mom_acc(a, q1, label, x1, y1);
+  const long long nquads = (nrows + 3) >> 2;
+  const int seg = lane >> 4, sl = lane & 15;
+  for (long long qd = wid; qd < nquads; qd += nw) {
+    const long long r0 = qd * 4;
+    // ---- the small rows, 16 lanes each -----------------------------------
+    {
+      const long long rowp = r0 + seg;
+      bool small = false;
+      int f = 0, label = 0, xmin = 0, ymin = 0, bw = 1, area = 0;
+      if (rowp < nrows) {
+        f = src.frame[rowp];
+        if (f >= 0 && f < wk.nframes) {
+          const FrameDev& fd = wk.frames[f];
+          label = src.label[rowp];
+          xmin = max(src.xmin[rowp], 0);
+          ymin = max(src.ymin[rowp], 0);
+          const int xmax = min(src.xmax[rowp], fd.w - 1);
+          const int ymax = min(src.ymax[rowp], fd.h - 1);
+          if (xmin <= xmax && ymin <= ymax) {
+            bw = xmax - xmin + 1;
+            area = bw * (ymax - ymin + 1);
+            small = area <= 16;
+          }
+        }
       }
-    }
-    a.S = wave_sum128(a.S);
-    a.Sx = wave_sum128(a.Sx);
-    a.Sy = wave_sum128(a.Sy);
-    a.Sxx = wave_sum128(a.Sxx);
-    a.Syy = wave_sum128(a.Syy);
-    a.Sxy = wave_sum128(a.Sxy);
-    if (lane == 0) {
-      const bool pos = (int64_t)a.S.hi > 0 ||
-                       ((int64_t)a.S.hi == 0 && a.S.lo > 0);
-      if (!pos) {
-        for (int k = 0; k < 6; ++k) out[k] = __builtin_nan("");
-      } else {
-        const double fS = to_double(a.S);
-        const double mx = to_double(a.Sx) / fS;
-        const double my = to_double(a.Sy) / fS;
-        const double x2 = to_double(a.Sxx) / fS - mx * mx;
-        const double y2 = to_double(a.Syy) / fS - my * my;
-        const double xy = to_double(a.Sxy) / fS - mx * my;
-        const double t = (x2 + y2) / 2.0;
-        const double hd = (x2 - y2) / 2.0;
-        const double r = sqrt(hd * hd + xy * xy);
-        out[0] = x2;
-        out[1] = y2;
-        out[2] = xy;
-        out[3] = sqrt(t + r);
-        out[4] = sqrt(fmax(t - r, 0.0));
-        out[5] = atan2(2.0 * xy, x2 - y2) / 2.0;
+      const uint64_t smask = __builtin_amdgcn_ballot_w64(small);
+      if (smask) {
+        MomAcc a;
+        a.S = a.Sx = a.Sy = a.Sxx = a.Syy = a.Sxy = from_i64(0);
+        if (small && sl < area) {
+          // small integers: the correctly rounded quotient floors exactly
+          const int ey = (int)((float)sl / (float)bw);
+          const int ex = sl - ey * bw;
+          const FrameDev fr = wk.frames[f];
+          mom_acc(a, stat_load(fr, xmin + ex, ymin + ey), label, ex, ey);
+        }
+        a.S = row_sum128(a.S);
+        a.Sx = row_sum128(a.Sx);
+        a.Sy = row_sum128(a.Sy);
+        a.Sxx = row_sum128(a.Sxx);
+        a.Syy = row_sum128(a.Syy);
+        a.Sxy = row_sum128(a.Sxy);
+        if (small && sl == 0) mom_finish(a, mom + 6 * rowp);
+      }
+      // ---- each larger (or unusable) row over the whole wave -------------
+      for (int k = 0; k < 4; ++k) {
+        const long long row = r0 + k;
+        if (row >= nrows) break;
+        if ((smask >> (16 * k)) & 1ull) continue;
+        const int fk = src.frame[row];
+        double* out = mom + 6 * row;
+        if (fk < 0 || fk >= wk.nframes) {
+          if (lane < 6) out[lane] = __builtin_nan("");
+          continue;
+        }
+        const FrameDev fr = wk.frames[fk];
+        const int lab = src.label[row];
+        const int x0 = max(src.xmin[row], 0), x1 = min(src.xmax[row], fr.w - 1);
+        const int y0 = max(src.ymin[row], 0), y1 = min(src.ymax[row], fr.h - 1);
+        MomAcc a;
+        a.S = a.Sx = a.Sy = a.Sxx = a.Syy = a.Sxy = from_i64(0);
+        if (x0 <= x1 && y0 <= y1) {
+          const int w = x1 - x0 + 1;
+          const long long ar = (long long)w * (y1 - y0 + 1);
+          int ey = lane / w, ex = lane - (lane / w) * w;
+          const int dy = kWave / w, dx = kWave - (kWave / w) * w;
+          // two bounding-box steps per lane, both loaded before either is
+          // summed
+          for (long long e = lane; e < ar; e += 2 * kWave) {
+            const int ya = ey, xa = ex;
+            ey += dy; ex += dx;
+            if (ex >= w) { ex -= w; ++ey; }
+            const int yb = ey, xb = ex;
+            ey += dy; ex += dx;
+            if (ex >= w) { ex -= w; ++ey; }
+            const bool two = e + kWave < ar;
+            const PixIn q0 = stat_load(fr, x0 + xa, y0 + ya);
+            PixIn q1 = {0, 0.0f, 0.0f};
+            if (two) q1 = stat_load(fr, x0 + xb, y0 + yb);
+            mom_acc(a, q0, lab, xa, ya);
+            if (two) mom_acc(a, q1, lab, xb, yb);
+          }
+        }
+        a.S = wave_sum128(a.S);
+        a.Sx = wave_sum128(a.Sx);
+        a.Sy = wave_sum128(a.Sy);
+        a.Sxx = wave_sum128(a.Sxx);
+        a.Syy = wave_sum128(a.Syy);
+        a.Sxy = wave_sum128(a.Sxy);
+        if (lane == 0) mom_finish(a, out);
       }
     }
   }
