@@ -109,3 +109,11 @@ def test_gray_workspace_and_argument_checks(lib):
                             None) == L.IPP_E_INVALID_ARG
     assert lib.ipp_equalize(None, f, 1, 4096, outs, None,
                             None) == L.IPP_E_INVALID_ARG
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library the binding refuses to run (no fallback)."""
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libipp.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        L.lib()
