@@ -474,8 +474,17 @@ class Context:
         p = Params(**{f.name: getattr(params, f.name) for f in fields(params)})
         if write_rms:
             p.flags |= L.IPP_F_WRITE_RMS
-        flags = torch.zeros(n, dtype=torch.int32, device=dev)
-        diag = torch.zeros(4, dtype=torch.int64, device=dev)
+        # frame flags and diagnostics are overwritten by every call: reuse
+        # the caller's buffers so repeated calls keep the same device
+        # addresses (they are part of the captured graph's signature)
+        flags = outputs.get("flags")
+        if not (isinstance(flags, torch.Tensor) and flags.numel() == n
+                and flags.dtype == torch.int32 and flags.device == dev):
+            flags = torch.zeros(n, dtype=torch.int32, device=dev)
+        diag = outputs.get("diag")
+        if not (isinstance(diag, torch.Tensor) and diag.numel() == 4
+                and diag.dtype == torch.int64 and diag.device == dev):
+            diag = torch.zeros(4, dtype=torch.int64, device=dev)
         src = table.to_c()
         pc = p.to_c()
         self._check(self.lib.ipp_process_batch(

@@ -858,6 +858,18 @@ struct StatAcc {
   uint32_t flags;
 };
 
+// The fixed-point weight D = round(v 2^28) of a pixel value.  Beyond the
+// int64 range of the sums it is clamped to +-(2^62 - 1), decided in
+// binary64: every binary64 value >= 2^62 exceeds 2^62 - 1 and every smaller
+// one is at most 2^62 - 512, so the comparison with 2^62 is exact.
+__device__ __forceinline__ int64_t fixed_point_d(double v, bool* clamped) {
+  const double s = rint(v * 268435456.0);            // v 2^28
+  const int64_t dmax = (int64_t)(((uint64_t)1 << 62) - 1);
+  if (s >= 0x1p62) { *clamped = true; return dmax; }
+  if (s <= -0x1p62) { *clamped = true; return -dmax; }
+  return (int64_t)s;
+}
+
 __device__ __forceinline__ void stat_init(StatAcc& a) {
   a.S = {0, 0};
   a.Sx = {0, 0};
@@ -889,17 +901,12 @@ __device__ __forceinline__ PixIn stat_load(const FrameDev& fr, int x, int y) {
 __device__ __forceinline__ void stat_acc(StatAcc& a, const FrameDev& fr,
                                          const PixIn& q, int label, int x,
                                          int y, int xmin, int ymin) {
-  const double two_q = 268435456.0;                  // 2^28
-  const double dmax = 4611686018427387903.0;         // 2^62 - 1
   const bool mem = q.lab == label;
   const float I = q.I, B = q.B;
   const double v = (double)I - (double)B;
-  double s = rint(v * two_q);
   bool inexact = !(exact_range(I) && exact_range(B));
-  if (s > dmax) { s = dmax; inexact = true; }
-  if (s < -dmax) { s = -dmax; inexact = true; }
+  const int64_t D = mem ? fixed_point_d(v, &inexact) : 0;
   if (mem && inexact) a.flags |= IPP_SRC_INEXACT_SUM_RANGE;
-  const int64_t D = mem ? (int64_t)s : 0;
   a.S = add128(a.S, from_i64(D));
   a.Sx = add128(a.Sx, mul_i64(D, x - xmin));
   a.Sy = add128(a.Sy, mul_i64(D, y - ymin));
@@ -1125,12 +1132,9 @@ __device__ __forceinline__ U128 wave_sum128(U128 v) {
 
 __device__ __forceinline__ void mom_acc(MomAcc& a, const PixIn& q, int label,
                                         int dx, int dy) {
-  const double two_q = 268435456.0;                  // 2^28
-  const double dmax = 4611686018427387903.0;         // 2^62 - 1
   const double v = (double)q.I - (double)q.B;
-  double s = rint(v * two_q);
-  s = fmin(fmax(s, -dmax), dmax);
-  const int64_t D = q.lab == label ? (int64_t)s : 0;
+  bool clamped = false;
+  const int64_t D = q.lab == label ? fixed_point_d(v, &clamped) : 0;
   a.S = add128(a.S, from_i64(D));
   a.Sx = add128(a.Sx, mul_i64(D, dx));
   a.Sy = add128(a.Sy, mul_i64(D, dy));

@@ -133,3 +133,19 @@ def test_autotune_and_cache(ctx, tmp_path):
             assert torch.equal(o["bkg"][i], outs[0]["bkg"][i])
         assert np.array_equal(o["table"].rows()["flux_ap"],
                               outs[0]["table"].rows()["flux_ap"])
+
+
+def test_repeated_batches_keep_their_flag_buffers(ctx):
+    """The frame flags and diagnostics are overwritten by every call, so a
+    caller's output dict keeps the same buffers (and device addresses, which
+    the captured graph's signature includes) from call to call."""
+    img = make_frame("stack16", 2, scale=0.05)[0].to(DEV)
+    p = ipp.Params(mesh_h=32, mesh_w=32)
+    out = ctx.process_batch([img], p, capacity=5000)
+    f0, d0 = out["flags"].data_ptr(), out["diag"].data_ptr()
+    lab0 = out["labels"][0].clone()
+    for _ in range(3):
+        out = ctx.process_batch([img], p, table=out["table"], outputs=out)
+    torch.cuda.synchronize()
+    assert out["flags"].data_ptr() == f0 and out["diag"].data_ptr() == d0
+    assert torch.equal(out["labels"][0], lab0)

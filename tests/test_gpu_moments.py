@@ -73,3 +73,39 @@ def test_moments_of_a_batch_match_per_frame(ctx):
         got = mom[offs[i]:offs[i + 1]]
         ok = ~np.isnan(ref[:, 0])
         assert np.array_equal(got[ok, :3], ref[ok, :3])
+
+
+@pytest.mark.timeout(600)
+def test_moments_of_oracle_labels_full_4096(ctx):
+    """A full 4096 x 4096 frame of the 16-frame workload: the oracle's own
+    background, label map and table drive the GPU moments, which must
+    equal the oracle's moments of the same labels (x2, y2, xy bit for
+    bit)."""
+    import time
+    import oracle
+    from oracle import background as obg
+    t0 = time.time()
+    img, _, _ = make_frame("stack16", 0)
+    I = img.numpy()
+    op = oracle.Params()
+    ref = obg.background(I, op)
+    det = odt.detect(I, ref["B32"], ref["R32"], op)
+    n = det["n"]
+    print(f"oracle: {n} candidates in {time.time() - t0:.1f} s", flush=True)
+    t = det["table"]
+    table = ipp.SourceTable(n, 1, DEV)
+    for c in ("label", "xmin", "xmax", "ymin", "ymax"):
+        table.cols[c][:n] = torch.from_numpy(t[c].astype(np.int32)).to(DEV)
+    table.n_total.fill_(n)
+    frames = [img.to(DEV)]
+    mom = ctx.source_moments(frames, [torch.from_numpy(ref["B32"]).to(DEV)],
+                             [torch.from_numpy(det["labels"]).to(DEV)],
+                             table)
+    torch.cuda.synchronize()
+    mom = mom.cpu().numpy()
+    want = odt.source_moments(I, ref["B32"], det["labels"], n)
+    assert np.array_equal(np.isnan(mom), np.isnan(want))
+    ok = ~np.isnan(want[:, 0])
+    assert np.array_equal(mom[ok, :3], want[ok, :3])
+    np.testing.assert_allclose(mom[ok, 3:], want[ok, 3:], rtol=1e-14,
+                               atol=1e-13)

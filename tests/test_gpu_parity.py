@@ -256,3 +256,123 @@ def test_mesh_variants(ctx, case):
                                ref["rms_raw"], rtol=1e-11, atol=0)
     B = out["bkg"][0].cpu().numpy()
     assert np.max(np.abs(B - ref["B64"]) / np.abs(ref["B64"])) <= 1e-6, name
+
+
+EST_CASES = [
+    # (id, estimator, clip_iters, clip_sigma, median_factor, mean_factor)
+    ("median-eq1", oracle.params.EST_MEDIAN, 3, 3.0, 3.0, 2.0),
+    ("mean-eq2", oracle.params.EST_MEAN, 3, 3.0, 3.0, 2.0),
+    ("mode-eq4", oracle.params.EST_MODE, 3, 3.0, 3.0, 2.0),
+    ("mode-eq4-factors", oracle.params.EST_MODE, 3, 3.0, 2.5, 1.5),
+    ("sextractor-1pass", oracle.params.EST_SEXTRACTOR, 1, 3.0, 3.0, 2.0),
+    ("sextractor-0pass", oracle.params.EST_SEXTRACTOR, 0, 3.0, 3.0, 2.0),
+    ("sextractor-5pass-2.5sigma", oracle.params.EST_SEXTRACTOR, 5, 2.5, 3.0,
+     2.0),
+    ("median-8pass-2sigma", oracle.params.EST_MEDIAN, 8, 2.0, 3.0, 2.0),
+]
+
+
+@pytest.mark.parametrize("case", EST_CASES, ids=lambda c: c[0])
+def test_estimators_and_clip_settings(ctx, case):
+    """Eq. 1, 2 and 4 and non-default clipping (passes, k) through the
+    region kernel and the fused path, against the oracle."""
+    name, est, iters, k, mf, af = case
+    img, _, _ = make_frame("stack16", 6, scale=0.125)          # 512 x 512
+    kw = dict(mesh_h=32, mesh_w=32, estimator=est, clip_iters=iters,
+              clip_sigma=k, median_factor=mf, mean_factor=af)
+    p, op = _params(**kw)
+    out = ctx.background([img.to(DEV)], p, mesh=True)
+    torch.cuda.synchronize()
+    ref = obg.background(img.numpy(), op)
+    assert np.array_equal(out["n_used"][0].cpu().numpy(), ref["n_used"])
+    braw = out["bkg_raw"][0].cpu().numpy()
+    rraw = out["rms_raw"][0].cpu().numpy()
+    eb = np.max(np.abs(braw - ref["bkg_raw"]) / np.abs(ref["bkg_raw"]))
+    er = np.max(np.abs(rraw - ref["rms_raw"]) / np.abs(ref["rms_raw"]))
+    print(f"{name}: mesh bkg rel {eb:.2e}, rms rel {er:.2e}", flush=True)
+    assert eb <= 1e-12 and er <= 1e-11, (eb, er)
+    B = out["bkg"][0].cpu().numpy()
+    assert np.max(np.abs(B - ref["B64"]) / np.abs(ref["B64"])) <= 1e-6
+    fused = ctx.process_batch([img.to(DEV)], p, capacity=20000)
+    torch.cuda.synchronize()
+    assert torch.equal(fused["bkg"][0], out["bkg"][0])
+
+
+def _flat_maps(h, w, b=100.0, r=10.0):
+    return (np.full((h, w), np.float32(b), dtype=np.float32),
+            np.full((h, w), np.float32(r), dtype=np.float32))
+
+
+def _detect_vs_oracle(ctx, I, B32, R32, p, op):
+    det = odt.detect(I, B32, R32, op)
+    out = ctx.detect([torch.from_numpy(I).to(DEV)],
+                     [torch.from_numpy(B32).to(DEV)],
+                     [torch.from_numpy(R32).to(DEV)], p,
+                     capacity=det["n"] + 64)
+    torch.cuda.synchronize()
+    tab = out["table"].rows()
+    assert tab["label"].size == det["n"]
+    assert np.array_equal(out["labels"][0].cpu().numpy(), det["labels"])
+    _cmp_table(tab, det["table"])
+    return det
+
+
+def test_nonpositive_flux_branch(ctx):
+    """A threshold below the sky (det_nsigma < 0) detects candidates whose
+    values sum to <= 0: both sides take the unweighted centroid and flag
+    the row.  A hand-built frame (sums -30 and exactly 0) and a noise frame
+    with many candidates of either sign."""
+    B32, R32 = _flat_maps(40, 70)
+    I = B32 - 100.0
+    for y, x in ((1, 1), (1, 2), (2, 1)):
+        I[y, x] = 90.0
+    I[5, 5], I[5, 6], I[6, 6] = 105.0, 95.0, 100.0
+    p, op = _params(min_area=1, det_nsigma=-5.0)
+    det = _detect_vs_oracle(ctx, I, B32, R32, p, op)
+    assert det["n"] == 2
+    assert all(f & oracle.params.SRC_NONPOSITIVE_FLUX
+               for f in det["table"]["flags"])
+    rng = np.random.default_rng(11)
+    B32, R32 = _flat_maps(300, 277)
+    # v ~ N(-16, 8) against t = -8: a sixth of the pixels are detected and
+    # a candidate's values average about -4
+    I = (B32 + rng.normal(-16.0, 8.0, B32.shape)).astype(np.float32)
+    p, op = _params(det_nsigma=-0.8, min_area=3)
+    det = _detect_vs_oracle(ctx, I, B32, R32, p, op)
+    neg = np.count_nonzero(det["table"]["flags"]
+                           & oracle.params.SRC_NONPOSITIVE_FLUX)
+    print(f"noise frame: {det['n']} candidates, {neg} with sum <= 0",
+          flush=True)
+    assert neg > 0
+
+
+def test_huge_values_are_clamped_like_the_oracle(ctx):
+    """Finite values whose fixed-point weight v 2^28 reaches 2^62 are
+    clamped to 2^62 - 1 on both sides (flux, centroid and moments)."""
+    img, _, _ = make_frame("single", 0, scale=0.25)             # 256 x 256
+    I = img.numpy().copy()
+    op = oracle.Params(mesh_h=32, mesh_w=32)
+    ref = obg.background(I, op)
+    det0 = odt.detect(I, ref["B32"], ref["R32"], op)
+    t = det0["table"]
+    big = np.argsort(t["npix"])[-3:]
+    for j, val in zip(big, (1e11, 2.0 ** 34, 3e38)):
+        I[t["peak_y"][j], t["peak_x"][j]] = np.float32(val)
+    p = ipp.Params(mesh_h=32, mesh_w=32)
+    det = _detect_vs_oracle(ctx, I, ref["B32"], ref["R32"], p, op)
+    flagged = det["table"]["flags"] & oracle.params.SRC_INEXACT_SUM_RANGE
+    assert np.count_nonzero(flagged) >= 3
+    lab = torch.from_numpy(det["labels"]).to(DEV)
+    n = det["n"]
+    table = ipp.SourceTable(n, 1, DEV)
+    for c in ("label", "xmin", "xmax", "ymin", "ymax"):
+        table.cols[c][:n] = torch.from_numpy(
+            det["table"][c].astype(np.int32)).to(DEV)
+    table.n_total.fill_(n)
+    mom = ctx.source_moments([torch.from_numpy(I).to(DEV)],
+                             [torch.from_numpy(ref["B32"]).to(DEV)], [lab],
+                             table).cpu().numpy()
+    want = odt.source_moments(I, ref["B32"], det["labels"], n)
+    ok = ~np.isnan(want[:, 0])
+    assert np.array_equal(np.isnan(mom), np.isnan(want))
+    assert np.array_equal(mom[ok, :3], want[ok, :3])

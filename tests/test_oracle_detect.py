@@ -10,7 +10,7 @@ import scipy.ndimage
 
 from oracle import Params
 from oracle import detect as dt
-from oracle.params import SRC_INEXACT_SUM_RANGE
+from oracle.params import SRC_INEXACT_SUM_RANGE, SRC_NONPOSITIVE_FLUX
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -216,3 +216,44 @@ def test_moments_rotate_with_the_shape():
     assert math.isclose(xyr, -xy, rel_tol=1e-12)
     assert math.isclose(ar, a, rel_tol=1e-12) and math.isclose(br, b,
                                                               rel_tol=1e-12)
+
+
+def test_nonpositive_flux_takes_the_unweighted_centroid():
+    """Sec. 2.2.5 pre-analysis with a threshold below the sky (nsigma < 0):
+    candidates whose values sum to <= 0 take the plain pixel mean as their
+    centre and carry the flag (closed forms)."""
+    B = np.full((8, 9), 100.0, dtype=np.float32)
+    I = B - 100.0                       # v = -100: below t = -50
+    for y, x in ((1, 1), (1, 2), (2, 1)):
+        I[y, x] = 90.0                  # v = -10: detected, sum -30
+    I[5, 5], I[5, 6], I[6, 6] = 105.0, 95.0, 100.0    # v = 5, -5, 0: sum 0
+    R = np.full_like(B, 10.0)
+    p = Params(min_area=1, det_nsigma=-5.0)
+    d = dt.detect(I, B, R, p)
+    t = d["table"]
+    assert d["n"] == 2
+    assert t["flux_iso"].tolist() == [-30.0, 0.0]
+    assert t["x"][0] == 1.0 + 1.0 / 3.0 and t["y"][0] == 1.0 + 1.0 / 3.0
+    assert t["x"][1] == 5.0 + 2.0 / 3.0 and t["y"][1] == 5.0 + 1.0 / 3.0
+    assert all(f & SRC_NONPOSITIVE_FLUX for f in t["flags"])
+    # peak: the largest value, the first of equal ones in raster order
+    assert (t["peak"][0], t["peak_x"][0], t["peak_y"][0]) == (-10.0, 1, 1)
+    assert (t["peak"][1], t["peak_x"][1], t["peak_y"][1]) == (5.0, 5, 5)
+
+
+def test_huge_value_is_clamped_below_two_to_the_62():
+    """A finite value whose fixed-point integer D = v 2^28 exceeds the
+    int64 sum range is clamped to 2^62 - 1 (not 2^62) and flags the row."""
+    I = np.full((4, 4), 1.0, dtype=np.float32)
+    B = np.zeros_like(I)
+    I[1, 2] = np.float32(1e11)          # v 2^28 ~ 2.7e19 > 2^62
+    I[0, 0] = np.float32(2.0 ** 34)     # v 2^28 = 2^62 exactly: clamped too
+    t = _src(I, B, Params(min_area=1))
+    dmax = (1 << 62) - 1
+    S = 2 * dmax + 14 * (1 << 28)
+    assert t["flux_iso"][0] == float(Fraction(S, 1 << 28))
+    Sx = dmax * 2 + dmax * 0 + sum((1 << 28) * x for x in range(4)
+                                   for y in range(4)
+                                   if (y, x) not in ((1, 2), (0, 0)))
+    assert t["x"][0] == float(Sx) / float(S)
+    assert t["flags"][0] & SRC_INEXACT_SUM_RANGE
