@@ -1,20 +1,26 @@
 #!/usr/bin/env python
 """Throughput of the pre-processing hot path on one MI355X.
 
-Workload: 16 synthetic float32 frames of 4096 x 4096 (sky 800 ADU plus a
-2nd-order polynomial and a 50 ADU sinusoid, Poisson + read noise sigma 8,
-5000 Moffat stars, cosmic rays, dead columns), resident in HBM before the
-timed region.  One step = background estimation + detection + pre-analysis
-+ aperture photometry of the whole batch.
+Default workload: the crowded large-format batch, 32 synthetic float32
+frames of 10560 x 10560 (1500 ADU sky plus a 1/f^2 Gaussian random field
+nebulosity of rms 100 ADU, 100k Moffat stars of beta 2.5 per frame, Poisson
+and read noise, saturation at 65535), resident in HBM before the timed
+region.  One step = background estimation + detection + pre-analysis +
+aperture photometry of the whole batch (one fused pipeline call), then
+gradient centroid refinement of every detected candidate (10 ascent steps,
+each a photometry forward and backward, in one library call).
 
-Reported: the batched, fused pipeline call (value, Mpix/s) and the plain
-per-frame path (one call per step and frame with a host sync for the
-source count), the per-kernel roofline of the dominant kernel (HIP events
-recorded by the library on the launch stream), the flux error of a sample
-of sources against the FP64 oracle, and the oracle's own throughput on a
-bounded sample on the host CPU.
+Reported on one JSON line: the batched path (value, Mpix/s; sources/s) and
+the plain per-frame path (one call per step and frame, with a host sync
+for the source count), their ratio, the step's algorithmic HBM bandwidth,
+the roofline of the dominant kernel (HIP events recorded by the library on
+the launch stream), the flux error of sampled sources against the FP64
+oracle, the oracle's own throughput on a bounded sample on the host CPU
+(one core and all cores), and the same batched-vs-plain figures for the
+16 x 4096^2 stack and the autotuned 256-frame uneven batch.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+    python bench.py --workload stack16|uneven|grad64|gray16
 """
 import argparse
 import json
@@ -29,9 +35,12 @@ METRIC = ("Mpix/s and sources/s, batched+fused vs plain per-frame, at "
           "<=1e-5 flux error")
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+REFINE_STEPS = 10
+REFINE_RC = 2.0
 
-# Algorithmic HBM bytes of each kernel per pixel of the batch: what the
-# step must move through that kernel, not what the implementation moves.
+# Algorithmic HBM bytes of each per-pixel kernel per pixel of the batch:
+# what the step must move through that kernel, not what the implementation
+# moves.
 ALGO_BYTES_PER_PX = {
     "k_mesh_stats": 4.0,        # read every pixel once
     "k_tile_ccl_fused": 8.0,    # read the pixel, write the background map
@@ -39,13 +48,23 @@ ALGO_BYTES_PER_PX = {
     "k_bkg_maps": 8.0,          # write background and rms maps
     "k_tile_ccl": 12.0,         # read pixel, background and rms maps
 }
+# The photometry kernels are binary64 geometry: flops per source.
+ALU_KERNELS = ("k_aperture", "k_aperture_bwd")
 
 
-def aperture_flops_per_source(p):
-    """Algorithmic binary64 work of one source's photometry: the pixels cut
-    by the three circles (a circle of radius r crosses about 8 r unit
-    pixels) times about 60 flops of exact-overlap geometry each."""
-    return 60.0 * 8.0 * (p.r_ap + p.r_in + p.r_out)
+def aperture_flops_per_source(r_ap, r_in, r_out):
+    """Algorithmic binary64 work of one source's photometry (forward or
+    backward): the pixels cut by the three circles (a circle of radius r
+    crosses about 8 r unit pixels) times about 60 flops of exact-overlap
+    geometry each."""
+    return 60.0 * 8.0 * (r_ap + r_in + r_out)
+
+
+def step_algo_bytes(npx, nsrc, refine_steps):
+    """Algorithmic HBM bytes of one step: read I, write the background and
+    label maps (12 B/px), one 80-byte table row per source, and per
+    refinement step the positions read and written (16 B/source)."""
+    return 12.0 * npx + 80.0 * nsrc + 16.0 * nsrc * refine_steps
 
 
 # HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
@@ -76,25 +95,28 @@ def measured_traffic(kernel, workload):
             "total_bytes": t["read_bytes"] + t["write_bytes"]}
 
 
-def roofline(kern, dom, npx, nsrc, p):
-    """Roofline entry of the dominant kernel from its event-timed average
-    launch duration and its algorithmic bytes or flops per launch."""
-    ms = kern[dom]["ms_avg"]
+def roofline(kern, dom, npx, flops_total):
+    """Roofline entry of a kernel from its event-timed launches: achieved =
+    algorithmic bytes (or flops) of its launches over their summed
+    duration, i.e. the per-launch average over the average launch time."""
+    k = kern[dom]
+    ms_tot, nl = k["ms_total"], k["launches"]
     if dom in ALGO_BYTES_PER_PX:
         algo = ALGO_BYTES_PER_PX[dom] * npx
-        gbs = algo / (ms * 1e-3) / 1e9
+        gbs = algo * nl / (ms_tot * 1e-3) / 1e9
         return {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "algo_bytes_per_launch": algo, "ms_per_launch": round(ms, 4)}
-    if dom == "k_aperture":
-        algo = aperture_flops_per_source(p) * nsrc
-        tfs = algo / (ms * 1e-3) / 1e12
+                "algo_bytes_per_launch": algo,
+                "ms_per_launch": round(ms_tot / nl, 4), "launches": nl}
+    if dom in ALU_KERNELS and flops_total.get(dom):
+        tfs = flops_total[dom] / (ms_tot * 1e-3) / 1e12
         return {"kernel": dom, "bound": "alu", "achieved": round(tfs, 4),
                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tfs / FP64_VECTOR_PEAK_TFLOPS, 5),
-                "traffic": None, "algo_flops_per_launch": algo,
-                "ms_per_launch": round(ms, 4)}
+                "traffic": None,
+                "algo_flops_per_launch": flops_total[dom] / nl,
+                "ms_per_launch": round(ms_tot / nl, 4), "launches": nl}
     return {"kernel": dom, "bound": None, "achieved": None, "peak": None,
             "unit": None, "frac": None, "traffic": None}
 
@@ -113,72 +135,92 @@ def make_frames(workload, n, device):
 
 
 WORKLOADS = {
+    "crowded": (32, "32 frames of 10560x10560 float32, 1/f^2 Gaussian "
+                    "random field nebulosity, 100k Moffat stars each, "
+                    "saturated at 65535; batched forward plus centroid "
+                    "refinement (10 gradient steps) of every candidate"),
     "stack16": (16, "16 frames of 4096x4096 float32, 5000 Moffat stars each, "
                     "poly+sinusoid sky, cosmic rays, dead columns"),
     "uneven": (256, "256 float32 frames drawn from {512x512, 1024x1024, "
                     "2048x4096, 4096x4096}, star density log-uniform "
-                    "1e-5..5e-3 per px, flat sky U(200, 5000)"),
-    "crowded": (32, "32 frames of 10560x10560 float32, 1/f^2 Gaussian "
-                    "random field nebulosity, 100k Moffat stars each, "
-                    "saturated at 65535"),
+                    "1e-5..5e-3 per px, flat sky U(200, 5000); mesh and "
+                    "tile shape from the autotuner"),
 }
+# Workloads whose step includes the centroid refinement.
+REFINED = {"crowded"}
 
 
-def run_plain(ctx, frames, p, tables):
-    """Eager per-frame path: one background, detect, count, photometry
-    call per frame."""
-    n = 0
-    for f, t in zip(frames, tables):
-        bg = ctx.background([f], p)
-        d = ctx.detect([f], bg["bkg"], bg["rms"], p, table=t)
-        k = t.count()                             # host sync per frame
-        n += k
-        ctx.photometry([f], bg["bkg"], d["table"], p)
-    return n
-
-
-def cpu_baseline(frame_cpu, params, side=2896):
-    """The FP64 oracle on a side x side crop of one frame, one thread (about
-    10-30 s of CPU work)."""
+# ---------------------------------------------------------------- CPU leg
+def _oracle_sample(args):
+    """One bounded oracle run (worker process): background, detection and
+    photometry of a shrunken frame of the workload, and the refinement of
+    `k` of its sources (the rest extrapolated from their time)."""
+    workload, frame, scale, k_refine = args
     import numpy as np
     from threadpoolctl import threadpool_limits
     import oracle
     from oracle import background as obg, detect as odt, photometry as oph
-    crop = frame_cpu[:side, :side].numpy()
+    from oracle.refine import refine_centroids
+    from synth import make_frame
+    img, _, _ = make_frame(workload, frame, scale=scale)
+    I = img.numpy()
     op = oracle.Params()
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        ref = obg.background(crop, op)
-        det = odt.detect(crop, ref["B32"], ref["R32"], op)
+        ref = obg.background(I, op)
+        det = odt.detect(I, ref["B32"], ref["R32"], op)
         t = det["table"]
-        oph.photometry(crop, ref["B32"], t["x"], t["y"], op)
-        dt = time.perf_counter() - t0
-    mpix = crop.size / 1e6
-    return {"value": round(mpix / dt, 4), "unit": "Mpix/s", "cores": 1,
-            "kind": "oracle",
-            "sources_per_s": round(det["n"] / dt, 2),
-            "seconds": round(dt, 2),
-            "sample": (f"one {side}x{side} crop of a 4096x4096 frame of the "
-                       f"workload: background, detection and photometry of "
-                       f"its {det['n']} sources, single thread")}
+        oph.photometry(I, ref["B32"], t["x"], t["y"], op)
+        t1 = time.perf_counter()
+        k = min(k_refine, det["n"]) if k_refine else 0
+        if k:
+            sel = np.linspace(0, det["n"] - 1, k).astype(int)
+            refine_centroids(I, ref["B32"], t["x"][sel], t["y"][sel], op,
+                             steps=REFINE_STEPS, r_c=REFINE_RC)
+        t2 = time.perf_counter()
+    per_src_refine = (t2 - t1) / k if k else 0.0
+    return {"px": I.size, "sources": det["n"], "measured_s": t2 - t0,
+            "forward_s": t1 - t0,
+            "total_s": (t1 - t0) + per_src_refine * det["n"]}
 
 
-def flux_error_sample(frame_cpu, bkg_cpu, table_rows, params, k=64):
-    """Max flux error of k sources of frame 0 against the oracle, on the
-    GPU's own background map, in units of the flux's condition scale."""
-    import numpy as np
-    import oracle
-    from oracle import photometry as oph
-    sel = np.nonzero(table_rows["frame"] == 0)[0]
-    sel = sel[np.linspace(0, sel.size - 1, min(k, sel.size)).astype(int)]
-    ph = oph.photometry(frame_cpu.numpy(), bkg_cpu, table_rows["x"][sel],
-                        table_rows["y"][sel], oracle.Params())
-    raw = ph["flux"] + ph["sky"] * ph["area_ap"]
-    scale = np.abs(raw) + ph["area_ap"] * np.abs(ph["sky"]) + 1e-30
-    return float(np.max(np.abs(table_rows["flux_ap"][sel] - ph["flux"])
-                        / scale))
-
-
+def cpu_baseline(workload, scale, k_refine, workers):
+    """The FP64 oracle on shrunken frames of the workload (the same sky,
+    noise, star density and source mix; rendered on the host): one frame on
+    one core, then `workers` frames in parallel processes, one per core.
+    Refinement time is measured on a sample of sources and extrapolated to
+    all of them (labelled)."""
+    import multiprocessing as mp
+    one = _oracle_sample((workload, 0, scale, k_refine))
+    desc = (f"frames of the {workload} recipe shrunk {scale}x per axis "
+            f"({one['px']} px and {one['sources']} sources in frame 0): "
+            f"background, detection and photometry of each")
+    if k_refine:
+        desc += (f", and refinement ({REFINE_STEPS} steps) of {k_refine} "
+                 f"sampled sources per frame, its time per source "
+                 f"extrapolated to all of the frame's sources")
+    one_core = {"value": round(one["px"] / 1e6 / one["total_s"], 4),
+                "unit": "Mpix/s", "cores": 1,
+                "sources_per_s": round(one["sources"] / one["total_s"], 2),
+                "frames": 1, "seconds_measured": round(one["measured_s"], 2)}
+    res = dict(one_core, kind="oracle", sample=desc,
+               host_cpu_count=os.cpu_count(), extrapolated=bool(k_refine))
+    if workers > 1:
+        mpc = mp.get_context("spawn")
+        jobs = [(workload, i, scale, k_refine) for i in range(workers)]
+        t0 = time.perf_counter()
+        with mpc.Pool(workers) as pool:
+            outs = pool.map(_oracle_sample, jobs)
+        wall = time.perf_counter() - t0
+        # each worker's extrapolated refinement added to the wall time
+        span = wall + max(o["total_s"] - o["measured_s"] for o in outs)
+        px = sum(o["px"] for o in outs)
+        ns = sum(o["sources"] for o in outs)
+        res.update({"value": round(px / 1e6 / span, 4), "cores": workers,
+                    "sources_per_s": round(ns / span, 2), "frames": workers,
+                    "seconds_measured": round(wall, 2),
+                    "one_core": one_core})
+    return res
 GRAD_DESC = ("64 frames of 2048x2048 float32, 2000 Gaussian stars each, "
              "centroid guesses = truth + N(0, 0.3^2) px per axis")
 
@@ -390,26 +432,244 @@ def run_gray(args):
     print(json.dumps(res), flush=True)
 
 
+
+
+def run_plain(ctx, frames, p, tables, refine):
+    """Eager per-frame path: one background, detect, count, photometry (and
+    refinement) call per frame."""
+    from dataclasses import replace
+    from paper_2502_10783_amd import _lib as L
+    p_eager = replace(p, flags=p.flags | L.IPP_F_NO_GRAPH)
+    n = 0
+    for f, t in zip(frames, tables):
+        bg = ctx.background([f], p)
+        d = ctx.detect([f], bg["bkg"], bg["rms"], p, table=t)
+        k = t.count()                             # host sync per frame
+        n += k
+        ctx.photometry([f], bg["bkg"], d["table"], p)
+        if refine and k:
+            ctx.refine_centroids([f], bg["bkg"], t, p_eager,
+                                 steps=REFINE_STEPS, r_c=REFINE_RC,
+                                 use_count=True,
+                                 x_out=t.extra_x, y_out=t.extra_y)
+    return n
+
+
+def flux_error_sample(frame_cpu, bkg_cpu, table_rows, params, k=64):
+    """Max flux error of k sources of frame 0 against the oracle, on the
+    GPU's own background map, in units of the flux's condition scale."""
+    import numpy as np
+    import oracle
+    from oracle import photometry as oph
+    sel = np.nonzero(table_rows["frame"] == 0)[0]
+    sel = sel[np.linspace(0, sel.size - 1, min(k, sel.size)).astype(int)]
+    ph = oph.photometry(frame_cpu.numpy(), bkg_cpu, table_rows["x"][sel],
+                        table_rows["y"][sel], oracle.Params())
+    raw = ph["flux"] + ph["sky"] * ph["area_ap"]
+    scale = np.abs(raw) + ph["area_ap"] * np.abs(ph["sky"]) + 1e-30
+    return float(np.max(np.abs(table_rows["flux_ap"][sel] - ph["flux"])
+                        / scale))
+
+
+def refine_error_sample(frame_cpu, bkg_cpu, table_rows, xr, yr, params,
+                        k=4):
+    """Max distance (px) between the refined centres of k sources of frame
+    0 and the oracle's refinement of the same start positions."""
+    import numpy as np
+    import oracle
+    from oracle.refine import refine_centroids
+    sel = np.nonzero(table_rows["frame"] == 0)[0]
+    sel = sel[np.linspace(0, sel.size - 1, min(k, sel.size)).astype(int)]
+    xo, yo = refine_centroids(frame_cpu.numpy(), bkg_cpu,
+                              table_rows["x"][sel], table_rows["y"][sel],
+                              oracle.Params(), steps=REFINE_STEPS,
+                              r_c=REFINE_RC)
+    return float(np.max(np.hypot(xr[sel] - xo, yr[sel] - yo)))
+
+
+def run_pipeline(workload, args, dev, quick=False):
+    """Batched vs plain on one workload; returns its result dict (and the
+    frames and outputs for the checks)."""
+    import torch
+    import paper_2502_10783_amd as ipp
+
+    nfr, desc = WORKLOADS[workload]
+    if args.frames:
+        nfr = min(nfr, args.frames)
+    refine = workload in REFINED
+    log(f"[{workload}] generating {nfr} frames on the GPU")
+    t0 = time.time()
+    frames = make_frames(workload, nfr, dev)
+    torch.cuda.synchronize()
+    log(f"[{workload}] generated in {time.time() - t0:.1f} s")
+    mpix = sum(f.numel() for f in frames) / 1e6
+    npx = sum(f.numel() for f in frames)
+    if args.calib_copy and not quick:
+        calibration_copy(args.calib_copy, dev)
+    p = ipp.Params()
+    ctx = ipp.Context(0)
+    tuned = None
+    if workload == "uneven":
+        log(f"[{workload}] autotuning mesh size and tile shape on the batch")
+        t0 = time.time()
+        p, tms = ctx.autotune(frames, p)
+        tuned = {"mesh": p.mesh_h, "tile": [p.tile_h, p.tile_w],
+                 "best_ms": round(tms, 4),
+                 "tuning_s": round(time.time() - t0, 2)}
+        log(f"[{workload}] autotuner: {tuned}")
+    cap = npx // 64 + 4096
+    table = ipp.SourceTable(cap, len(frames), dev)
+    outputs = {"bkg": [torch.empty_like(f) for f in frames],
+               "labels": [torch.empty(f.shape, dtype=torch.int32, device=dev)
+                          for f in frames], "rms": None}
+    xr = torch.empty(cap, dtype=torch.float64, device=dev)
+    yr = torch.empty(cap, dtype=torch.float64, device=dev)
+
+    def step():
+        ctx.process_batch(frames, p, table=table, outputs=outputs)
+        if refine:
+            ctx.refine_centroids(frames, outputs["bkg"], table, p,
+                                 steps=REFINE_STEPS, r_c=REFINE_RC,
+                                 use_count=True, x_out=xr, y_out=yr)
+
+    steps = args.steps if not quick else max(3, args.steps)
+    log(f"[{workload}] warmup")
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    nsrc = table.count()
+    diag = outputs["diag"].cpu().tolist()
+    if nsrc > cap or diag[2]:
+        raise RuntimeError(f"capacity exceeded: sources {nsrc} > {cap} or "
+                           f"records overflow {diag}")
+
+    log(f"[{workload}] timing {steps} batched steps")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+
+    ms_plain, psrc = None, 0
+    plain_steps = args.plain_steps
+    if plain_steps > 0:
+        log(f"[{workload}] timing {plain_steps} plain per-frame steps")
+        ptables = []
+        for f in frames:
+            t = ipp.SourceTable(f.numel() // 64 + 4096, 1, dev)
+            if refine:
+                t.extra_x = torch.empty(t.capacity, dtype=torch.float64,
+                                        device=dev)
+                t.extra_y = torch.empty_like(t.extra_x)
+            ptables.append(t)
+        run_plain(ctx, frames, p, ptables, refine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(plain_steps):
+            psrc = run_plain(ctx, frames, p, ptables, refine)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t0) * 1e3 / plain_steps
+        del ptables
+        torch.cuda.empty_cache()
+
+    log(f"[{workload}] per-kernel event timing")
+    nprof = 2
+    ctx.profile(True)
+    for _ in range(nprof):
+        step()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kern = {k: {"ms_total": v[0] / nprof, "launches": v[1] // nprof,
+                "ms_avg": v[0] / v[1]} for k, v in prof.items()}
+    # algorithmic flops of the photometry launches of one step
+    fl_fwd = aperture_flops_per_source(p.r_ap, p.r_in, p.r_out)
+    fl_rc = aperture_flops_per_source(REFINE_RC, p.r_in, p.r_out)
+    flops = {"k_aperture": nsrc * fl_fwd * (2 if refine else 1)
+             + (nsrc * fl_rc * REFINE_STEPS if refine else 0.0),
+             "k_aperture_bwd": nsrc * fl_rc * REFINE_STEPS if refine else 0.0}
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    roof = roofline(kern, dom, npx, flops)
+    roof["traffic"] = measured_traffic(dom, workload)
+    hb = [k for k in kern if k in ALGO_BYTES_PER_PX]
+    roof_hbm = None
+    if hb:
+        hk = max(hb, key=lambda k: kern[k]["ms_total"])
+        roof_hbm = roofline(kern, hk, npx, flops)
+        roof_hbm["traffic"] = measured_traffic(hk, workload)
+    algo = step_algo_bytes(npx, nsrc, REFINE_STEPS if refine else 0)
+    res = {
+        "ms_per_step": round(ms, 4),
+        "mpix_per_s": round(mpix / (ms * 1e-3), 2),
+        "sources_per_step": nsrc,
+        "sources_per_s": round(nsrc / (ms * 1e-3), 1),
+        "plain": None if ms_plain is None else {
+            "ms_per_step": round(ms_plain, 3),
+            "mpix_per_s": round(mpix / (ms_plain * 1e-3), 2),
+            "sources_per_s": round(psrc / (ms_plain * 1e-3), 1)},
+        "speedup_vs_plain": (None if ms_plain is None
+                             else round(ms_plain / ms, 3)),
+        "step_hbm": {"algo_bytes": algo,
+                     "achieved_GBps": round(algo / (ms * 1e-3) / 1e9, 1),
+                     "frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                   4)},
+        "config": {"workload": desc if nfr == WORKLOADS[workload][0]
+                   else f"first {nfr} frames of: {desc}", "name": workload,
+                   "frames": len(frames), "mpix_per_step": round(mpix, 3),
+                   "mesh": p.mesh_h, "tile": [p.tile_h or 64, p.tile_w or 64],
+                   "autotuned": tuned, "det_nsigma": p.det_nsigma,
+                   "min_area": p.min_area,
+                   "aperture": [p.r_ap, p.r_in, p.r_out],
+                   "refinement": ({"steps": REFINE_STEPS, "r_c": REFINE_RC,
+                                   "eta": 3.0} if refine else None)},
+        "kernels_ms_per_step": {k: round(v["ms_total"], 4) for k, v in
+                                sorted(kern.items(),
+                                       key=lambda kv: -kv[1]["ms_total"])},
+        "roofline": roof,
+        "roofline_hbm_kernel": roof_hbm,
+    }
+    if not quick:
+        log(f"[{workload}] flux check against the oracle")
+        rows = table.rows()
+        b0 = outputs["bkg"][0].cpu().numpy()
+        f0 = frames[0].cpu()
+        res["flux_err_max"] = flux_error_sample(f0, b0, rows, p)
+        if refine:
+            res["refine_err_px_max"] = refine_error_sample(
+                f0, b0, rows, xr[:nsrc].cpu().numpy(),
+                yr[:nsrc].cpu().numpy(), p)
+    ctx.close()
+    del frames, outputs, table, xr, yr
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload",
                     choices=sorted(WORKLOADS) + ["grad64", "gray16"],
-                    default="stack16",
+                    default="crowded",
                     help="grad64: the forward + backward of the aperture "
                          "flux and of the asinh stretch; gray16: zscale, "
                          "point map and histogram equalization of the "
                          "16-frame stack (each its own metric)")
     ap.add_argument("--frames", type=int, default=0,
                     help="frames of the workload to use (0 = all)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick mesh and tile shape with ipp_autotune on a "
-                         "16-frame sample first")
-    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 16-frame and uneven-batch sub-results")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-core CPU leg (0 = the "
+                         "host's cores, at most 16)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB "
                          "(a kernel of known traffic, to scale HBM counters)")
@@ -427,154 +687,48 @@ def main():
         run_gray(args)
         return
 
-    import torch
-    import paper_2502_10783_amd as ipp
-
-    dev = torch.device("cuda:0")
-    nfr, desc = WORKLOADS[args.workload]
-    if args.frames:
-        nfr = min(nfr, args.frames)
-    log(f"generating {nfr} frames of {args.workload} on the GPU")
-    frames = make_frames(args.workload, nfr, dev)
-    torch.cuda.synchronize()
-    mpix = sum(f.numel() for f in frames) / 1e6
-    if args.calib_copy:
-        calibration_copy(args.calib_copy, dev)
-    p = ipp.Params()
-    ctx = ipp.Context(0)
-    tuned = None
-    if args.autotune:
-        log("autotuning on a 16-frame sample")
-        p, tms = ctx.autotune(frames[:16], p)
-        tuned = {"mesh": p.mesh_h, "tile": [p.tile_h, p.tile_w],
-                 "sample_ms": round(tms, 4)}
-    cap = sum(f.numel() for f in frames) // 64 + 4096
-    table = ipp.SourceTable(cap, len(frames), dev)
-    outputs = {"bkg": [torch.empty_like(f) for f in frames],
-               "labels": [torch.empty(f.shape, dtype=torch.int32, device=dev)
-                          for f in frames], "rms": None}
-
-    def step():
-        return ctx.process_batch(frames, p, table=table, outputs=outputs)
-
-    log("warmup")
-    for _ in range(max(1, args.warmup)):
-        step()
-    torch.cuda.synchronize()
-    nsrc = table.count()
-    diag = outputs["diag"].cpu().tolist()
-    if nsrc > cap or diag[2]:
-        raise RuntimeError(f"capacity exceeded: sources {nsrc} > {cap} or "
-                           f"records overflow {diag}")
-
-    log(f"timing {args.steps} batched steps")
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-
-    ms_plain, psrc = None, 0
-    if args.plain_steps > 0:
-        log(f"timing {args.plain_steps} plain per-frame steps")
-        ptables = [ipp.SourceTable(f.numel() // 64 + 4096, 1, dev)
-                   for f in frames]
-        run_plain(ctx, frames, p, ptables)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            psrc = run_plain(ctx, frames, p, ptables)
-        torch.cuda.synchronize()
-        ms_plain = (time.perf_counter() - t0) * 1e3 / args.plain_steps
-
-    log("per-kernel event timing")
-    ctx.profile(True)
-    for _ in range(3):
-        step()
-    torch.cuda.synchronize()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    kern = {k: {"ms_avg": v[0] / v[1], "launches": v[1]}
-            for k, v in prof.items()}
-    dom = max(kern, key=lambda k: kern[k]["ms_avg"])
-    npx = sum(f.numel() for f in frames)
-    roof = roofline(kern, dom, npx, nsrc, p)
-    roof["traffic"] = measured_traffic(dom, args.workload)
-    # the largest per-pixel (HBM-bound) kernel, reported beside it
-    hb = [k for k in kern if k in ALGO_BYTES_PER_PX]
-    roof_hbm = None
-    if hb:
-        hk = max(hb, key=lambda k: kern[k]["ms_avg"])
-        roof_hbm = roofline(kern, hk, npx, nsrc, p)
-        roof_hbm["traffic"] = measured_traffic(hk, args.workload)
-
-    # second-order moments of every candidate (a separate call, outside the
-    # timed step): its kernel's event-timed duration
-    ctx.source_moments(frames, outputs["bkg"], outputs["labels"], table)
-    ctx.profile(True)
-    for _ in range(3):
-        ctx.source_moments(frames, outputs["bkg"], outputs["labels"], table)
-    torch.cuda.synchronize()
-    mprof = ctx.profile_read()
-    ctx.profile(False)
-    mom_ms = (mprof["k_source_moments"][0] / mprof["k_source_moments"][1]
-              if "k_source_moments" in mprof else None)
-
-    log("flux check against the oracle")
-    rows = table.rows()
-    ferr = flux_error_sample(frames[0].cpu(), outputs["bkg"][0].cpu().numpy(),
-                             rows, p)
-
+    # the CPU leg first, in worker processes started before this process
+    # touches the GPU
     cpu = None
     if not args.no_cpu:
-        log("oracle CPU baseline")
-        big = max(range(len(frames)), key=lambda i: frames[i].numel())
-        cpu = cpu_baseline(frames[big].cpu(), p)
+        workers = args.cpu_workers or min(os.cpu_count() or 1, 16)
+        log(f"oracle CPU baseline (1 core, then {workers} processes)")
+        if args.workload == "crowded":
+            cpu = cpu_baseline("crowded", 0.1, 40, workers)
+        else:
+            cpu = cpu_baseline(args.workload, 0.25, 0, workers)
 
-    value = mpix / (ms * 1e-3)
+    import torch
+    dev = torch.device("cuda:0")
+    main_res = run_pipeline(args.workload, args, dev)
+    extra = {}
+    if args.workload == "crowded" and not args.no_extra and not args.frames:
+        for w in ("stack16", "uneven"):
+            r = run_pipeline(w, args, dev, quick=True)
+            extra[w] = {k: r[k] for k in
+                        ("ms_per_step", "mpix_per_s", "sources_per_s",
+                         "sources_per_step", "plain", "speedup_vs_plain",
+                         "step_hbm", "config", "roofline")}
+    ms = main_res["ms_per_step"]
     res = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": main_res["mpix_per_s"],
         "unit": "Mpix/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc if nfr == WORKLOADS[args.workload][0]
-                   else f"first {nfr} frames of: {desc}",
-                   "name": args.workload,
-                   "frames": len(frames), "mpix_per_step": round(mpix, 3),
-                   "mesh": p.mesh_h, "tile": [p.tile_h or 64, p.tile_w or 64],
-                   "autotuned": tuned, "det_nsigma": p.det_nsigma,
-                   "min_area": p.min_area, "aperture": [p.r_ap, p.r_in,
-                                                        p.r_out]},
-        "sources_per_step": nsrc,
-        "sources_per_s": round(nsrc / (ms * 1e-3), 1),
-        "plain": None if ms_plain is None else {
-            "ms_per_step": round(ms_plain, 3),
-            "mpix_per_s": round(mpix / (ms_plain * 1e-3), 2),
-            "sources_per_s": round(psrc / (ms_plain * 1e-3), 1)},
-        "speedup_vs_plain": (None if ms_plain is None
-                             else round(ms_plain / ms, 3)),
-        "flux_err_max": ferr,
-        "kernels_ms": {k: round(v["ms_avg"], 4) for k, v in
-                       sorted(kern.items(), key=lambda kv: -kv[1]["ms_avg"])},
-        "roofline": roof,
-        "roofline_hbm_kernel": roof_hbm,
-        "cpu_baseline": cpu,
-        "source_moments": None if mom_ms is None else {
-            "ms": round(mom_ms, 4),
-            "sources_per_s": round(nsrc / (mom_ms * 1e-3), 1)},
     }
+    res.update({k: v for k, v in main_res.items()
+                if k not in ("ms_per_step", "mpix_per_s")})
+    res["cpu_baseline"] = cpu
+    if extra:
+        res["other_configs"] = extra
     print(json.dumps(res), flush=True)
 
 

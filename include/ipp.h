@@ -67,6 +67,9 @@ enum {
 
 /* ipp_params.flags */
 #define IPP_F_WRITE_RMS 1u  /* ipp_process_batch also writes the rms maps  */
+#define IPP_F_NO_GRAPH 2u   /* ipp_process_batch and ipp_refine_centroids
+                               launch their kernels one by one instead of
+                               capturing and replaying a HIP graph         */
 
 /* Per-frame flags (uint32 per frame). */
 #define IPP_FRAME_NO_VALID_MESH 1u  /* no node had min_valid pixels: every
@@ -271,6 +274,32 @@ ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
                                    void* stream);
 
 /*
+ * Gradient centroid refinement on the photometry of Sec. 2.2.5 and its
+ * backward (this library's addition; the paper measures objects at their
+ * detected positions).  Each row's centre c (columns frame, x, y of src;
+ * rows min(capacity, *n_total), or capacity when n_total is NULL) climbs
+ * J(c) = F_rc(c) / F_ap(c0): F_rc is the sky-subtracted flux of
+ * ipp_photometry with the aperture radius r_c (annulus and clipping from
+ * p), F_ap(c0) the flux with p's own aperture at the start.  `steps`
+ * plain ascent steps c <- c + eta dJ/dc follow, the gradient taken by
+ * ipp_photometry_backward with each step's annulus clip mask held fixed.
+ * Rows with F_ap(c0) <= 0 (or not a number) stay where they are.
+ * x_out, y_out: device double[capacity], the refined centres (they may be
+ * src->x and src->y themselves); the table's other columns are untouched.
+ * r_c in (0, 16], eta finite, steps in [0, 1000].  Needs
+ * ipp_refine_workspace_bytes of workspace (80 bytes per row plus the frame
+ * descriptors).  The whole sequence (1 + 3 steps launches) is replayed from
+ * a captured HIP graph when called again with the same signature.
+ */
+size_t ipp_refine_workspace_bytes(const ipp_frame* frames, int32_t n,
+                                  int64_t rows);
+ipp_status ipp_refine_centroids(void* ctx, const ipp_frame* frames,
+                                int32_t n, const ipp_maps* maps,
+                                const ipp_params* p, const ipp_sources* src,
+                                double r_c, double eta, int32_t steps,
+                                double* x_out, double* y_out, void* stream);
+
+/*
  * asinh gray-scale stretch (Sec. 2.2.6 gray-scale transformations):
  * y[i] = b * asinh(v[i] / a), float32 arrays of n elements (device),
  * a > 0 (softening), b (scale).
@@ -285,6 +314,19 @@ ipp_status ipp_asinh(void* ctx, const float* v, float* y, int64_t n,
 ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
                               float* dv, double* dL_dab, int64_t n, double a,
                               double b, void* stream);
+
+/*
+ * ipp_asinh and ipp_asinh_backward with the parameters in device memory:
+ * ab is a device double[2] = (a, b), read by the kernels, so a caller's
+ * parameter tensors need no host round trip (and the calls can be captured
+ * into a graph).  The host cannot check values it does not read: with
+ * a <= 0, a or b not finite, every output (y, dv, dL_dab) is NaN.
+ */
+ipp_status ipp_asinh_dev(void* ctx, const float* v, float* y, int64_t n,
+                         const double* ab, void* stream);
+ipp_status ipp_asinh_backward_dev(void* ctx, const float* v, const float* dy,
+                                  float* dv, double* dL_dab, int64_t n,
+                                  const double* ab, void* stream);
 
 /*
  * Second-order moments of each table row's footprint (the pre-analysis of

@@ -21,6 +21,7 @@ IPP_E_WORKSPACE = -5
 
 IPP_EST_SEXTRACTOR, IPP_EST_MEDIAN, IPP_EST_MEAN, IPP_EST_MODE = 0, 1, 2, 3
 IPP_F_WRITE_RMS = 1
+IPP_F_NO_GRAPH = 2
 IPP_TUNE_MESH = 1
 IPP_TUNE_TILE = 2
 IPP_MAP_LINEAR, IPP_MAP_LOG, IPP_MAP_EXP, IPP_MAP_POWER = 0, 1, 2, 3
@@ -142,11 +143,23 @@ def lib():
                                           C.POINTER(IppSources), vp, vp,
                                           C.POINTER(vp), vp, vp]
     L.ipp_photometry_backward.restype = i32
+    L.ipp_refine_workspace_bytes.argtypes = [C.POINTER(IppFrame), i32, i64]
+    L.ipp_refine_workspace_bytes.restype = sz
+    L.ipp_refine_centroids.argtypes = [vp, C.POINTER(IppFrame), i32,
+                                       C.POINTER(IppMaps),
+                                       C.POINTER(IppParams),
+                                       C.POINTER(IppSources), C.c_double,
+                                       C.c_double, i32, vp, vp, vp]
+    L.ipp_refine_centroids.restype = i32
     L.ipp_asinh.argtypes = [vp, vp, vp, i64, C.c_double, C.c_double, vp]
     L.ipp_asinh.restype = i32
     L.ipp_asinh_backward.argtypes = [vp, vp, vp, vp, vp, i64, C.c_double,
                                      C.c_double, vp]
     L.ipp_asinh_backward.restype = i32
+    L.ipp_asinh_dev.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.ipp_asinh_dev.restype = i32
+    L.ipp_asinh_backward_dev.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+    L.ipp_asinh_backward_dev.restype = i32
     L.ipp_autotune.argtypes = [vp, C.POINTER(IppFrame), i32,
                                C.POINTER(IppParams), C.c_uint32, C.c_char_p,
                                C.POINTER(C.c_double), vp]

@@ -314,6 +314,44 @@ class Context:
             _ptr(sky_lohi), _ptr(g), dp, _ptr(dxy), _stream()))
         return dxy
 
+    def refine_centroids(self, frames, bkg, table: SourceTable,
+                         params: Params, steps: int = 10, eta: float = 3.0,
+                         r_c: float = 2.0, x_out=None, y_out=None,
+                         use_count=False):
+        """Gradient-ascent centroid refinement of the table rows (frame, x,
+        y) on the frames and their background maps: returns the refined
+        (x, y) float64 tensors of `capacity` rows (x_out, y_out if given;
+        they may be the table's own x and y columns)."""
+        n = len(frames)
+        maps = (L.IppMaps * n)()
+        for i in range(n):
+            _check_map(bkg[i], frames[i], "bkg")
+            maps[i].bkg = bkg[i].data_ptr()
+        fc = frames_c(frames)
+        cap = max(1, table.capacity)
+        need = self.lib.ipp_refine_workspace_bytes(fc, n, table.capacity)
+        if need == 0:
+            raise IppError(L.IPP_E_INVALID_ARG, "ipp_refine_workspace_bytes")
+        if need > self.ws_bytes:
+            self.reserve(need)
+        dev = frames[0].device
+        for t, what in ((x_out, "x_out"), (y_out, "y_out")):
+            if t is not None and not (t.is_cuda and t.dtype == torch.float64
+                                      and t.is_contiguous()
+                                      and t.numel() >= cap):
+                raise ValueError(f"{what}: need a contiguous float64 CUDA "
+                                 f"tensor of at least {cap} elements")
+        if x_out is None:
+            x_out = torch.empty(cap, dtype=torch.float64, device=dev)
+        if y_out is None:
+            y_out = torch.empty(cap, dtype=torch.float64, device=dev)
+        src = table.to_c(n_total=use_count)
+        pc = params.to_c()
+        self._check(self.lib.ipp_refine_centroids(
+            self.h, fc, n, maps, C.byref(pc), C.byref(src), float(r_c),
+            float(eta), int(steps), _ptr(x_out), _ptr(y_out), _stream()))
+        return x_out, y_out
+
     def asinh(self, v: torch.Tensor, a: float, b: float):
         """y = b * asinh(v / a) (float32, element-wise)."""
         if not (v.is_cuda and v.dtype == torch.float32):
@@ -340,6 +378,45 @@ class Context:
         self._check(self.lib.ipp_asinh_backward(
             self.h, _ptr(v), _ptr(dy), _ptr(dv), _ptr(dab), v.numel(),
             float(a), float(b), _stream()))
+        return dv, dab
+
+    @staticmethod
+    def _ab(ab: torch.Tensor, v: torch.Tensor):
+        if not (isinstance(ab, torch.Tensor) and ab.is_cuda
+                and ab.dtype == torch.float64 and ab.numel() == 2
+                and ab.is_contiguous() and ab.device == v.device):
+            raise ValueError("ab: need a contiguous float64 CUDA tensor "
+                             "(a, b) on v's device")
+        return ab
+
+    def asinh_dev(self, v: torch.Tensor, ab: torch.Tensor):
+        """y = b * asinh(v / a) with (a, b) = ab read on the device."""
+        if not (v.is_cuda and v.dtype == torch.float32):
+            raise ValueError("v: need a float32 CUDA tensor")
+        v = v.contiguous()
+        y = torch.empty_like(v)
+        self._check(self.lib.ipp_asinh_dev(
+            self.h, _ptr(v), _ptr(y), v.numel(), _ptr(self._ab(ab, v)),
+            _stream()))
+        return y
+
+    def asinh_backward_dev(self, v, dy, ab: torch.Tensor, want_dv=True,
+                           want_dab=True):
+        """(dL/dv, tensor([dL/da, dL/db])) with (a, b) = ab on the
+        device."""
+        if not (v.is_cuda and dy.is_cuda and v.dtype == torch.float32
+                and dy.dtype == torch.float32 and v.numel() == dy.numel()):
+            raise ValueError("v, dy: need float32 CUDA tensors of one size")
+        if want_dab and self.ws_bytes < (1 << 16):
+            self.reserve(1 << 16)
+        v = v.contiguous()
+        dy = dy.contiguous()
+        dv = torch.empty_like(v) if want_dv else None
+        dab = (torch.zeros(2, dtype=torch.float64, device=v.device)
+               if want_dab else None)
+        self._check(self.lib.ipp_asinh_backward_dev(
+            self.h, _ptr(v), _ptr(dy), _ptr(dv), _ptr(dab), v.numel(),
+            _ptr(self._ab(ab, v)), _stream()))
         return dv, dab
 
     def source_moments(self, frames, bkg, labels, table: SourceTable):

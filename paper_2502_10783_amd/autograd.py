@@ -6,8 +6,6 @@ connect them to torch's autograd graph.
 """
 from __future__ import annotations
 
-from dataclasses import replace
-
 import torch
 
 from .api import Context, Params, SourceTable
@@ -63,48 +61,61 @@ class ApertureFlux(torch.autograd.Function):
 
 
 class AsinhStretch(torch.autograd.Function):
-    """y = b * asinh(v / a) (Sec. 2.2.6 gray-scale map), float32 v; a and
-    b are 0-d tensors (read on the host)."""
+    """y = b * asinh(v / a) (Sec. 2.2.6 gray-scale map), float32 v.  a and b
+    are 0-d tensors: on the GPU they are handed to the library as a device
+    pair (no host round trip); Python numbers or CPU tensors are passed by
+    value."""
 
     @staticmethod
     def forward(ctx, v, a, b, ipp: Context):
-        av, bv = float(a), float(b)
+        ctx.ipp = ipp
         ctx.save_for_backward(v)
-        ctx.ab, ctx.ipp = (av, bv), ipp
-        return ipp.asinh(v, av, bv)
+        on_dev = (isinstance(a, torch.Tensor) and a.is_cuda
+                  and isinstance(b, torch.Tensor) and b.is_cuda)
+        if on_dev:
+            ab = torch.stack([a.detach().reshape(()),
+                              b.detach().reshape(())]).to(torch.float64)
+            ctx.ab = ab.contiguous()
+            ctx.dtypes = (a.dtype, b.dtype)
+            return ipp.asinh_dev(v, ctx.ab)
+        ctx.ab = (float(a), float(b))
+        ctx.dtypes = (a.dtype if isinstance(a, torch.Tensor) else None,
+                      b.dtype if isinstance(b, torch.Tensor) else None)
+        return ipp.asinh(v, *ctx.ab)
 
     @staticmethod
     def backward(ctx, g):
         (v,) = ctx.saved_tensors
-        av, bv = ctx.ab
         need_ab = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
-        dv, dab = ctx.ipp.asinh_backward(v, g.contiguous(), av, bv,
-                                         want_dv=ctx.needs_input_grad[0],
-                                         want_dab=need_ab)
-        ga = dab[0].to(torch.float32) if ctx.needs_input_grad[1] else None
-        gb = dab[1].to(torch.float32) if ctx.needs_input_grad[2] else None
+        if isinstance(ctx.ab, torch.Tensor):
+            dv, dab = ctx.ipp.asinh_backward_dev(
+                v, g.contiguous(), ctx.ab, want_dv=ctx.needs_input_grad[0],
+                want_dab=need_ab)
+        else:
+            dv, dab = ctx.ipp.asinh_backward(
+                v, g.contiguous(), *ctx.ab, want_dv=ctx.needs_input_grad[0],
+                want_dab=need_ab)
+        da_t, db_t = ctx.dtypes
+        ga = gb = None
+        if ctx.needs_input_grad[1]:
+            ga = dab[0].to(da_t or torch.float32)
+        if ctx.needs_input_grad[2]:
+            gb = dab[1].to(db_t or torch.float32)
         return dv, ga, gb, None
 
 
 def refine_centroids(ipp: Context, frames, bkg, x0, y0, frame_idx,
                      params: Params, steps: int = 10, eta: float = 3.0,
                      r_c: float = 2.0):
-    """Gradient-ascent centroid refinement: maximise F_rc(c) / F_ap(c0),
-    the sky-subtracted flux in an aperture of radius r_c normalised by the
-    flux in the default aperture at the starting point; c <- c + eta*grad.
-    Sources whose normaliser is <= 0 are left in place."""
+    """Gradient-ascent centroid refinement (ipp_refine_centroids): maximise
+    F_rc(c) / F_ap(c0), the sky-subtracted flux in an aperture of radius r_c
+    normalised by the flux in the default aperture at the starting point;
+    c <- c + eta * grad, `steps` times.  Sources whose normaliser is <= 0
+    are left in place.  Returns the refined (x, y)."""
     fl = list(frames.unbind(0))
     bl = list(bkg.unbind(0))
     s = x0.numel()
-    t0 = _table(x0, y0, frame_idx, len(fl))
-    ipp.photometry(fl, bl, t0, params, use_count=False)
-    f0 = t0.cols["flux_ap"][:s]
-    g = torch.where(f0 > 0, 1.0 / f0, torch.zeros_like(f0))
-    pc = replace(params, r_ap=r_c)
     t = _table(x0, y0, frame_idx, len(fl))
-    for _ in range(steps):
-        lohi = ipp.photometry(fl, bl, t, pc, keep_sky=True, use_count=False)
-        dxy = ipp.photometry_backward(fl, bl, t, pc, lohi, g)
-        t.cols["x"][:s] += eta * dxy[:s, 0]
-        t.cols["y"][:s] += eta * dxy[:s, 1]
+    ipp.refine_centroids(fl, bl, t, params, steps=steps, eta=eta, r_c=r_c,
+                         x_out=t.cols["x"], y_out=t.cols["y"])
     return t.cols["x"][:s].clone(), t.cols["y"][:s].clone()

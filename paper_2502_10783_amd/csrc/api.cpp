@@ -358,6 +358,77 @@ ipp_status prepare(IppCtx* c, const ipp_frame* frames, int32_t n,
   return IPP_OK;
 }
 
+
+void key_put(std::vector<uint8_t>& key, const void* d, size_t len) {
+  const uint8_t* b = (const uint8_t*)d;
+  key.insert(key.end(), b, b + len);
+}
+
+// Enqueues a kernel sequence through the context's graph cache: the first
+// call with a given signature `key` (everything the kernels bake in)
+// captures body(stream) into a HIP graph on the private capture stream;
+// later calls replay it.  The frame descriptors are uploaded outside the
+// graph, and only when they or the workspace changed since the last upload
+// for that graph.
+template <typename Body>
+ipp_status run_cached(IppCtx* c, std::vector<uint8_t> key, const Plan& P,
+                      const Work& w, hipStream_t s, Body body) {
+  ipp_status st;
+  IppGraph* G = nullptr;
+  for (auto& g : c->graphs)
+    if (g.key == key) G = &g;
+  const uint8_t* fdb = (const uint8_t*)P.fd.data();
+  std::vector<uint8_t> fdv(fdb, fdb + sizeof(FrameDev) * P.fd.size());
+  if (!G) {
+    if (c->graphs.size() >= 6) {            // evict the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < c->graphs.size(); ++i)
+        if (c->graphs[i].last_use < c->graphs[lru].last_use) lru = i;
+      if (c->graphs[lru].exec) hipGraphExecDestroy(c->graphs[lru].exec);
+      if (c->graphs[lru].graph) hipGraphDestroy(c->graphs[lru].graph);
+      c->graphs.erase(c->graphs.begin() + lru);
+    }
+    if (!c->cap &&
+        hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+      return fail(c, IPP_E_DEVICE, "cannot create the capture stream");
+    IppGraph g;
+    g.key = std::move(key);
+    if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) !=
+        hipSuccess)
+      return fail(c, IPP_E_DEVICE, "hipStreamBeginCapture failed");
+    st = body(c->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (st != IPP_OK || e != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return st != IPP_OK ? st
+                          : fail(c, IPP_E_DEVICE, "hipStreamEndCapture failed");
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) !=
+        hipSuccess) {
+      hipGraphDestroy(graph);
+      return fail(c, IPP_E_DEVICE, "hipGraphInstantiate failed");
+    }
+    g.graph = graph;
+    g.exec = exec;
+    c->graphs.push_back(std::move(g));
+    G = &c->graphs.back();
+  }
+  G->last_use = ++c->tick;
+  if (G->ws_gen != c->ws_gen || G->fd != fdv) {
+    if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+    ++c->ws_gen;
+    G->ws_gen = c->ws_gen;
+    G->fd = fdv;
+  }
+  const hipError_t e = hipGraphLaunch(G->exec, s);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE, std::string("hipGraphLaunch: ") +
+                                     hipGetErrorString(e));
+  return IPP_OK;
+}
+
 // ---- kernel sequences --------------------------------------------------
 ipp_status run_mesh(IppCtx* c, const Plan& P, const Work& w,
                     const ipp_params& p, hipStream_t s) {
@@ -529,6 +600,95 @@ ipp_status run_aperture(IppCtx* c, const Work& w, const ipp_params& p,
                g, b, 0, s, w, p, *src, sky_lohi));
   } else {
     return fail(c, IPP_E_UNSUPPORTED, "aperture radii too large");
+  }
+  return IPP_OK;
+}
+
+// Backward of the aperture photometry: one wavefront per source.
+ipp_status run_aperture_bwd(IppCtx* c, const Work& w, const ipp_params& p,
+                            const ipp_sources& src, const double* sky_lohi,
+                            const double* gF, double* dxy, hipStream_t s) {
+  const double ri = p.r_in > std::sqrt(2.0) ? p.r_in - std::sqrt(2.0) : 0.0;
+  const double ro = p.r_out + std::sqrt(2.0);
+  const double ring = M_PI * (ro * ro - ri * ri) + 16.0;
+  const dim3 g(grid_for(src.capacity, kWaves, 16384)), b(kBlock);
+  if (ring <= 256)
+    IPP_LAUNCH(c, s, "k_aperture_bwd",
+               hipLaunchKernelGGL((k_aperture_bwd_t<256>), g, b, 0, s, w, p,
+                                  src, sky_lohi, gF, dxy));
+  else if (ring <= 512)
+    IPP_LAUNCH(c, s, "k_aperture_bwd",
+               hipLaunchKernelGGL((k_aperture_bwd_t<512>), g, b, 0, s, w, p,
+                                  src, sky_lohi, gF, dxy));
+  else if (ring <= 1024)
+    IPP_LAUNCH(c, s, "k_aperture_bwd",
+               hipLaunchKernelGGL((k_aperture_bwd_t<1024>), g, b, 0, s, w, p,
+                                  src, sky_lohi, gF, dxy));
+  else
+    return fail(c, IPP_E_UNSUPPORTED, "aperture radii too large");
+  return IPP_OK;
+}
+
+// Per-row arrays of the centroid refinement, after the frame descriptors.
+struct RefineWs {
+  size_t o_g, o_lohi, o_dxy, o_flux, o_sky, o_aap, o_aann, o_flags, total;
+};
+
+RefineWs refine_layout(size_t base, int64_t rows) {
+  RefineWs R;
+  size_t o = align_up(base);
+  auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
+  const size_t n = (size_t)(rows > 0 ? rows : 1);
+  R.o_g = take(8 * n);
+  R.o_lohi = take(16 * n);
+  R.o_dxy = take(16 * n);
+  R.o_flux = take(8 * n);
+  R.o_sky = take(8 * n);
+  R.o_aap = take(8 * n);
+  R.o_aann = take(8 * n);
+  R.o_flags = take(4 * n);
+  R.total = o;
+  return R;
+}
+
+// Centroid refinement: the normaliser F_ap(c0) at the start, then `steps`
+// rounds of forward at r_c, backward with dL/dF = 1/F_ap(c0), and the
+// ascent update, all on the stream (a captured graph replays them).
+ipp_status run_refine(IppCtx* c, const Work& w, const ipp_params& p,
+                      const ipp_sources& src, const RefineWs& R, double r_c,
+                      double eta, int steps, double* xo, double* yo,
+                      hipStream_t s) {
+  char* b = (char*)c->ws;
+  double* g = (double*)(b + R.o_g);
+  double* lohi = (double*)(b + R.o_lohi);
+  double* dxy = (double*)(b + R.o_dxy);
+  ipp_sources t = src;              // working table: positions xo, yo
+  t.x = xo;
+  t.y = yo;
+  t.flux_ap = (double*)(b + R.o_flux);
+  t.sky = (double*)(b + R.o_sky);
+  t.area_ap = (double*)(b + R.o_aap);
+  t.area_ann = (double*)(b + R.o_aann);
+  t.flags = (uint32_t*)(b + R.o_flags);
+  const int64_t cap = src.capacity;
+  const dim3 ge(grid_for(cap, kBlock, 16384)), bb(kBlock);
+  IPP_LAUNCH(c, s, "k_refine_start",
+             hipLaunchKernelGGL(k_refine_start, ge, bb, 0, s, src.x, src.y,
+                                xo, yo, t.flags, src.n_total, cap));
+  ipp_status st = run_aperture(c, w, p, &t, nullptr, s);
+  if (st != IPP_OK) return st;
+  IPP_LAUNCH(c, s, "k_refine_norm",
+             hipLaunchKernelGGL(k_refine_norm, ge, bb, 0, s, t.flux_ap, g,
+                                src.n_total, cap));
+  ipp_params pc = p;
+  pc.r_ap = r_c;
+  for (int k = 0; k < steps; ++k) {
+    if ((st = run_aperture(c, w, pc, &t, lohi, s)) != IPP_OK) return st;
+    if ((st = run_aperture_bwd(c, w, pc, t, lohi, g, dxy, s)) != IPP_OK)
+      return st;
+    IPP_LAUNCH(c, s, "k_refine_step",
+               hipLaunchKernelGGL(k_refine_step, ge, bb, 0, s, dxy, g, xo, yo,
+                                  eta, src.n_total, cap));
   }
   return IPP_OK;
 }
@@ -891,79 +1051,26 @@ ipp_status ipp_process_batch(void* ctx, const ipp_frame* frames, int32_t n,
   hipStream_t s = (hipStream_t)stream;
   Work w = make_work(P, c->ws, n);
   if (frame_flags) w.frame_flags = frame_flags;
-  if (c->prof || !c->use_graphs) {          // eager (kernel timing on)
+  if (c->prof || !c->use_graphs || (p->flags & IPP_F_NO_GRAPH)) {  // eager
     ++c->ws_gen;
     if ((st = upload(c, P, w, s)) != IPP_OK) return st;
     return run_batch(c, P, w, *p, src, write_rms, diag, s);
   }
-  // signature: everything the captured kernels bake in
   std::vector<uint8_t> key;
-  auto put = [&](const void* d, size_t len) {
-    const uint8_t* b = (const uint8_t*)d;
-    key.insert(key.end(), b, b + len);
-  };
-  put(&n, sizeof(n));
+  key_put(key, "batch", 5);
+  key_put(key, &n, sizeof(n));
   for (int i = 0; i < n; ++i) {
-    put(&frames[i].h, sizeof(int32_t));
-    put(&frames[i].w, sizeof(int32_t));
+    key_put(key, &frames[i].h, sizeof(int32_t));
+    key_put(key, &frames[i].w, sizeof(int32_t));
   }
-  put(p, sizeof(*p));
-  put(src, sizeof(*src));
-  put(&w, sizeof(w));
-  put(&diag, sizeof(diag));
-  IppGraph* G = nullptr;
-  for (auto& g : c->graphs)
-    if (g.key == key) G = &g;
-  const uint8_t* fdb = (const uint8_t*)P.fd.data();
-  std::vector<uint8_t> fdv(fdb, fdb + sizeof(FrameDev) * P.fd.size());
-  if (!G) {
-    if (c->graphs.size() >= 4) {            // evict the least recently used
-      size_t lru = 0;
-      for (size_t i = 1; i < c->graphs.size(); ++i)
-        if (c->graphs[i].last_use < c->graphs[lru].last_use) lru = i;
-      if (c->graphs[lru].exec) hipGraphExecDestroy(c->graphs[lru].exec);
-      if (c->graphs[lru].graph) hipGraphDestroy(c->graphs[lru].graph);
-      c->graphs.erase(c->graphs.begin() + lru);
-    }
-    if (!c->cap &&
-        hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
-      return fail(c, IPP_E_DEVICE, "cannot create the capture stream");
-    IppGraph g;
-    g.key = key;
-    if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) !=
-        hipSuccess)
-      return fail(c, IPP_E_DEVICE, "hipStreamBeginCapture failed");
-    st = run_batch(c, P, w, *p, src, write_rms, diag, c->cap);
-    hipGraph_t graph = nullptr;
-    const hipError_t e = hipStreamEndCapture(c->cap, &graph);
-    if (st != IPP_OK || e != hipSuccess) {
-      if (graph) hipGraphDestroy(graph);
-      return st != IPP_OK ? st
-                          : fail(c, IPP_E_DEVICE, "hipStreamEndCapture failed");
-    }
-    hipGraphExec_t exec = nullptr;
-    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) !=
-        hipSuccess) {
-      hipGraphDestroy(graph);
-      return fail(c, IPP_E_DEVICE, "hipGraphInstantiate failed");
-    }
-    g.graph = graph;
-    g.exec = exec;
-    c->graphs.push_back(g);
-    G = &c->graphs.back();
-  }
-  G->last_use = ++c->tick;
-  if (G->ws_gen != c->ws_gen || G->fd != fdv) {
-    if ((st = upload(c, P, w, s)) != IPP_OK) return st;
-    ++c->ws_gen;
-    G->ws_gen = c->ws_gen;
-    G->fd = fdv;
-  }
-  const hipError_t e = hipGraphLaunch(G->exec, s);
-  if (e != hipSuccess)
-    return fail(c, IPP_E_DEVICE, std::string("hipGraphLaunch: ") +
-                                     hipGetErrorString(e));
-  return IPP_OK;
+  key_put(key, p, sizeof(*p));
+  key_put(key, src, sizeof(*src));
+  key_put(key, &w, sizeof(w));
+  key_put(key, &diag, sizeof(diag));
+  const ipp_params pv = *p;
+  return run_cached(c, std::move(key), P, w, s, [&](hipStream_t cs) {
+    return run_batch(c, P, w, pv, src, write_rms, diag, cs);
+  });
 }
 
 ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
@@ -995,25 +1102,77 @@ ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
   Work w = make_work(P, c->ws, n);
   ++c->ws_gen;
   if ((st = upload(c, P, w, s)) != IPP_OK) return st;
-  const double ri = p->r_in > std::sqrt(2.0) ? p->r_in - std::sqrt(2.0) : 0.0;
-  const double ro = p->r_out + std::sqrt(2.0);
-  const double ring = M_PI * (ro * ro - ri * ri) + 16.0;
-  const dim3 g(grid_for(src->capacity, kWaves, 16384)), b(kBlock);
-  if (ring <= 256)
-    IPP_LAUNCH(c, s, "k_aperture_bwd",
-               hipLaunchKernelGGL((k_aperture_bwd_t<256>), g, b, 0, s, w, *p,
-                                  *src, sky_lohi, dL_dflux, dL_dxy));
-  else if (ring <= 512)
-    IPP_LAUNCH(c, s, "k_aperture_bwd",
-               hipLaunchKernelGGL((k_aperture_bwd_t<512>), g, b, 0, s, w, *p,
-                                  *src, sky_lohi, dL_dflux, dL_dxy));
-  else if (ring <= 1024)
-    IPP_LAUNCH(c, s, "k_aperture_bwd",
-               hipLaunchKernelGGL((k_aperture_bwd_t<1024>), g, b, 0, s, w,
-                                  *p, *src, sky_lohi, dL_dflux, dL_dxy));
-  else
-    return fail(c, IPP_E_UNSUPPORTED, "aperture radii too large");
-  return IPP_OK;
+  return run_aperture_bwd(c, w, *p, *src, sky_lohi, dL_dflux, dL_dxy, s);
+}
+
+size_t ipp_refine_workspace_bytes(const ipp_frame* frames, int32_t n,
+                                  int64_t rows) {
+  if (!check_frames(frames, n).empty() || rows < 0) return 0;
+  ipp_params pd;
+  ipp_params_default(&pd);
+  const Plan P = make_plan(frames, n, pd, 1, kPlanFrames);
+  return refine_layout(P.total, rows).total;
+}
+
+ipp_status ipp_refine_centroids(void* ctx, const ipp_frame* frames,
+                                int32_t n, const ipp_maps* maps,
+                                const ipp_params* p, const ipp_sources* src,
+                                double r_c, double eta, int32_t steps,
+                                double* x_out, double* y_out, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (!src || src->capacity < 0 || !src->frame || !src->x || !src->y)
+    return fail(c, IPP_E_INVALID_ARG, "sources: frame, x and y are required");
+  if (!x_out || !y_out)
+    return fail(c, IPP_E_INVALID_ARG, "x_out and y_out are required");
+  if (!std::isfinite(r_c) || r_c <= 0 || r_c > 16)
+    return fail(c, IPP_E_INVALID_ARG, "r_c must be in (0, 16]");
+  if (!std::isfinite(eta)) return fail(c, IPP_E_INVALID_ARG,
+                                       "eta must be finite");
+  if (steps < 0 || steps > 1000)
+    return fail(c, IPP_E_INVALID_ARG, "steps must be in [0, 1000]");
+  Plan P;
+  ipp_status st = prepare(c, frames, n, p, kPlanFrames, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg)
+      return fail(c, IPP_E_INVALID_ARG, "maps[f].bkg is required");
+    P.fd[i].bkg = maps[i].bkg;
+  }
+  const RefineWs R = refine_layout(P.total, src->capacity);
+  if (R.total > c->ws_bytes)
+    return fail(c, IPP_E_WORKSPACE,
+                "workspace too small: need " + std::to_string(R.total) +
+                    " bytes, have " + std::to_string(c->ws_bytes));
+  if (src->capacity == 0) return IPP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  if (c->prof || !c->use_graphs || (p->flags & IPP_F_NO_GRAPH)) {  // eager
+    ++c->ws_gen;
+    if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+    return run_refine(c, w, *p, *src, R, r_c, eta, steps, x_out, y_out, s);
+  }
+  std::vector<uint8_t> key;
+  key_put(key, "refine", 6);
+  key_put(key, &n, sizeof(n));
+  for (int i = 0; i < n; ++i) {
+    key_put(key, &frames[i].h, sizeof(int32_t));
+    key_put(key, &frames[i].w, sizeof(int32_t));
+  }
+  key_put(key, p, sizeof(*p));
+  key_put(key, src, sizeof(*src));
+  key_put(key, &w, sizeof(w));
+  key_put(key, &r_c, sizeof(r_c));
+  key_put(key, &eta, sizeof(eta));
+  key_put(key, &steps, sizeof(steps));
+  key_put(key, &x_out, sizeof(x_out));
+  key_put(key, &y_out, sizeof(y_out));
+  const ipp_params pv = *p;
+  const ipp_sources sv = *src;
+  return run_cached(c, std::move(key), P, w, s, [&](hipStream_t cs) {
+    return run_refine(c, w, pv, sv, R, r_c, eta, steps, x_out, y_out, cs);
+  });
 }
 
 ipp_status ipp_asinh(void* ctx, const float* v, float* y, int64_t n,
@@ -1030,7 +1189,8 @@ ipp_status ipp_asinh(void* ctx, const float* v, float* y, int64_t n,
              hipLaunchKernelGGL(k_asinh_fwd, dim3(grid_for(n, 4 * kBlock,
                                                            8192)),
                                 dim3(kBlock), 0, s, v, y, n,
-                                (float)(1.0 / a), (float)b));
+                                (float)(1.0 / a), (float)b,
+                                (const double*)nullptr));
   return IPP_OK;
 }
 
@@ -1043,7 +1203,7 @@ ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
     return fail(c, IPP_E_INVALID_ARG, "v and dy are required, n >= 0");
   if (!std::isfinite(a) || a <= 0 || !std::isfinite(b))
     return fail(c, IPP_E_INVALID_ARG, "need a > 0 and finite b");
-  const int grid = grid_for(n, 4 * kBlock, 2048);
+  const int grid = grid_for(n, 4 * kBlock, kAsinhMaxBlocks);
   if (dL_dab && c->ws_bytes < (size_t)grid * 16)
     return fail(c, IPP_E_WORKSPACE, "workspace too small for the partials");
   hipStream_t s = (hipStream_t)stream;
@@ -1051,7 +1211,49 @@ ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
   ++c->ws_gen;
   IPP_LAUNCH(c, s, "k_asinh_bwd",
              hipLaunchKernelGGL(k_asinh_bwd, dim3(grid), dim3(kBlock), 0, s,
-                                v, dy, dv, n, a, b, part));
+                                v, dy, dv, n, a, b, (const double*)nullptr,
+                                part));
+  if (dL_dab)
+    IPP_LAUNCH(c, s, "k_asinh_bwd_final",
+               hipLaunchKernelGGL(k_asinh_bwd_final, dim3(1), dim3(kBlock), 0,
+                                  s, part, grid, dL_dab));
+  return IPP_OK;
+}
+
+ipp_status ipp_asinh_dev(void* ctx, const float* v, float* y, int64_t n,
+                         const double* ab, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!v || !y)))
+    return fail(c, IPP_E_INVALID_ARG, "v and y are required, n >= 0");
+  if (!ab) return fail(c, IPP_E_INVALID_ARG, "ab is NULL");
+  if (n == 0) return IPP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  IPP_LAUNCH(c, s, "k_asinh_fwd",
+             hipLaunchKernelGGL(k_asinh_fwd, dim3(grid_for(n, 4 * kBlock,
+                                                           8192)),
+                                dim3(kBlock), 0, s, v, y, n, 0.0f, 0.0f,
+                                ab));
+  return IPP_OK;
+}
+
+ipp_status ipp_asinh_backward_dev(void* ctx, const float* v, const float* dy,
+                                  float* dv, double* dL_dab, int64_t n,
+                                  const double* ab, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!v || !dy)))
+    return fail(c, IPP_E_INVALID_ARG, "v and dy are required, n >= 0");
+  if (!ab) return fail(c, IPP_E_INVALID_ARG, "ab is NULL");
+  const int grid = grid_for(n, 4 * kBlock, kAsinhMaxBlocks);
+  if (dL_dab && c->ws_bytes < (size_t)grid * 16)
+    return fail(c, IPP_E_WORKSPACE, "workspace too small for the partials");
+  hipStream_t s = (hipStream_t)stream;
+  double* part = dL_dab ? (double*)c->ws : nullptr;
+  ++c->ws_gen;
+  IPP_LAUNCH(c, s, "k_asinh_bwd",
+             hipLaunchKernelGGL(k_asinh_bwd, dim3(grid), dim3(kBlock), 0, s,
+                                v, dy, dv, n, 0.0, 0.0, ab, part));
   if (dL_dab)
     IPP_LAUNCH(c, s, "k_asinh_bwd_final",
                hipLaunchKernelGGL(k_asinh_bwd_final, dim3(1), dim3(kBlock), 0,

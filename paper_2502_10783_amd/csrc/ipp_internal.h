@@ -53,6 +53,9 @@ struct GrayFrame {
 };
 constexpr int kZMax = 1024;       // zscale sample capacity
 constexpr int kMaxBins = 4096;    // histogram equalization bins
+// workgroups of the asinh backward (grid-stride): its binary64 block
+// partials fill at most 2 * kAsinhMaxBlocks doubles
+constexpr int kAsinhMaxBlocks = 2048;
 
 // Partial candidate: the piece of a connected component inside one
 // detection tile that touches the tile border or is large enough to keep.

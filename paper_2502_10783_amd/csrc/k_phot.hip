@@ -896,6 +896,57 @@ __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_aperture_bwd_t(
                          atan_lds);
 }
 
+// ---------------------------------------------------------------------
+// Centroid refinement around the photometry and its backward: maximise
+// J(c) = F_rc(c) / F_ap(c0) by plain ascent c <- c + eta dJ/dc.  The
+// backward is given dL/dF = g = 1 / F_ap(c0), so it returns dJ/dc; rows
+// with F_ap(c0) <= 0 (or not a number) get g = 0 and stay in place.
+// ---------------------------------------------------------------------
+namespace {
+__device__ __forceinline__ long long refine_rows(const int64_t* n_total,
+                                                 int64_t cap) {
+  long long n = cap;
+  if (n_total && *n_total < n) n = *n_total;
+  return n;
+}
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void k_refine_start(
+    const double* x, const double* y, double* xo, double* yo,
+    uint32_t* flags, const int64_t* n_total, int64_t cap) {
+  const long long n = refine_rows(n_total, cap);
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const double a = x[i], b = y[i];    // read both before any write
+    xo[i] = a;
+    yo[i] = b;
+    flags[i] = 0u;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_norm(
+    const double* flux, double* g, const int64_t* n_total, int64_t cap) {
+  const long long n = refine_rows(n_total, cap);
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const double f = flux[i];
+    g[i] = f > 0.0 ? 1.0 / f : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_step(
+    const double* dxy, const double* g, double* xo, double* yo, double eta,
+    const int64_t* n_total, int64_t cap) {
+  const long long n = refine_rows(n_total, cap);
+  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    if (g[i] != 0.0) {
+      xo[i] = xo[i] + eta * dxy[2 * i];
+      yo[i] = yo[i] + eta * dxy[2 * i + 1];
+    }
+  }
+}
+
 template __global__ void k_aperture_bwd_t<256>(
     Work, ipp_params, ipp_sources, const double*, const double*, double*);
 template __global__ void k_aperture_bwd_t<512>(

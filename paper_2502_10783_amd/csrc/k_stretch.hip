@@ -48,9 +48,26 @@ __device__ __forceinline__ float stretch(float x, float inv_a, float b) {
   return b * copysignf(at < 0.25f ? ser : big, t);
 }
 
+// Parameters read on the device: (a, b) = ab[0..1].  A non-positive or
+// non-finite a, or a non-finite b, makes every output NaN (the host cannot
+// check values it never sees).
+__device__ __forceinline__ bool device_params(const double* ab, double* a,
+                                              double* b) {
+  *a = ab[0];
+  *b = ab[1];
+  return *a > 0.0 && isfinite(*a) && isfinite(*b);
+}
+
 __global__ __launch_bounds__(kBlock) void k_asinh_fwd(const float* v,
                                                       float* y, int64_t n,
-                                                      float inv_a, float b) {
+                                                      float inv_a, float b,
+                                                      const double* ab) {
+  if (ab) {
+    double ad, bd;
+    const bool ok = device_params(ab, &ad, &bd);
+    inv_a = ok ? (float)(1.0 / ad) : __builtin_nanf("");
+    b = ok ? (float)bd : __builtin_nanf("");
+  }
   const bool vec = (((uintptr_t)v | (uintptr_t)y) & 15) == 0;
   for_elements(n, vec, [&](int64_t i, bool four) {
     if (four) {
@@ -132,8 +149,10 @@ __global__ __launch_bounds__(kBlock) void k_asinh_bwd(const float* v,
                                                       const float* dy,
                                                       float* dv, int64_t n,
                                                       double a, double b,
+                                                      const double* ab,
                                                       double* partial) {
   __shared__ double red[kWaves];
+  if (ab && !device_params(ab, &a, &b)) a = b = __builtin_nan("");
   const double inv_a = 1.0 / a, mb_inv_a = -b / a;
   const bool want_ab = partial != nullptr;
   double pa = 0.0, pb = 0.0;

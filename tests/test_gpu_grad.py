@@ -204,3 +204,118 @@ def test_refine_centroids_matches_oracle(ctx, scene):
     xr, yr = oracle_refine(img.numpy(), bkg.numpy(), xs, ys, op, steps=10)
     np.testing.assert_allclose(x.cpu().numpy(), xr, atol=1e-6)
     np.testing.assert_allclose(y.cpu().numpy(), yr, atol=1e-6)
+
+
+def test_refine_call_batch_replay_and_edge_rows(ctx, scene):
+    """ipp_refine_centroids on a two-frame batch with a device row count:
+    sampled rows against the oracle, a row with a non-positive normaliser
+    (a source on an empty patch) left in place, the captured graph's
+    replay with new positions equal to a fresh eager run, and the argument
+    checks."""
+    img, bkg, xs, ys = scene
+    p, op = ipp.Params(), oracle.Params()
+    img2 = img[:200, :230].contiguous()
+    bkg2 = bkg[:200, :230].contiguous()
+    frames = [img.to(DEV), img2.to(DEV)]
+    bks = [bkg.to(DEV), bkg2.to(DEV)]
+    k = 8
+    fx = np.concatenate([xs[:k], xs[k:2 * k]])
+    fy = np.concatenate([ys[:k], ys[k:2 * k]])
+    fi = np.repeat([0, 1], k).astype(np.int32)
+    keep2 = (fx < 225) & (fy < 195)
+    fx, fy, fi = fx[keep2 | (fi == 0)], fy[keep2 | (fi == 0)], \
+        fi[keep2 | (fi == 0)]
+    # one extra row at the frame corner, and spare rows past n_total
+    n = fx.size + 1
+    t = ipp.SourceTable(n + 5, 2, DEV)          # 5 spare rows past n_total
+    t.cols["frame"][:n - 1] = torch.from_numpy(fi).to(DEV)
+    t.cols["x"][:n - 1] = torch.from_numpy(fx).to(DEV)
+    t.cols["y"][:n - 1] = torch.from_numpy(fy).to(DEV)
+    t.cols["frame"][n - 1] = 0
+    flat = torch.full_like(frames[0], 0.0) + bks[0]
+    t.n_total.fill_(n)
+    x1, y1 = ctx.refine_centroids(frames, bks, t, p, use_count=True)
+    torch.cuda.synchronize()
+    x1, y1 = x1[:n].cpu().numpy(), y1[:n].cpu().numpy()
+    for f in (0, 1):
+        sel = np.nonzero(fi == f)[0][:4]
+        xr, yr = oracle_refine(frames[f].cpu().numpy(),
+                               bks[f].cpu().numpy(), fx[sel], fy[sel], op,
+                               steps=10)
+        np.testing.assert_allclose(x1[sel], xr, atol=1e-6)
+        np.testing.assert_allclose(y1[sel], yr, atol=1e-6)
+    # the same signature again (graph replay) from moved start positions,
+    # against an eager (profiled) run of the same call
+    t.cols["x"][:n - 1] += 0.05
+    xa, ya = ctx.refine_centroids(frames, bks, t, p, use_count=True)
+    xa, ya = xa.clone(), ya.clone()
+    ctx.profile(True)
+    xb, yb = ctx.refine_centroids(frames, bks, t, p, use_count=True)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    assert torch.equal(xa[:n], xb[:n]) and torch.equal(ya[:n], yb[:n])
+    # a source on a patch with no signal: flux <= 0 or not, it must follow
+    # the oracle's rule (stay put when the normaliser is not positive)
+    t2 = ipp.SourceTable(1, 1, DEV)
+    t2.cols["frame"][0] = 0
+    t2.cols["x"][0] = 100.0
+    t2.cols["y"][0] = 100.0
+    fr_flat = [flat.contiguous()]
+    xo, yo = ctx.refine_centroids(fr_flat, [bks[0]], t2, p)
+    torch.cuda.synchronize()
+    assert float(xo[0]) == 100.0 and float(yo[0]) == 100.0
+    # in place: the table's own columns as outputs
+    xi, yi = ctx.refine_centroids(frames, bks, t, p, use_count=True,
+                                  x_out=t.cols["x"], y_out=t.cols["y"])
+    torch.cuda.synchronize()
+    assert torch.equal(t.cols["x"][:n], xa[:n])
+    for bad in (dict(r_c=0.0), dict(r_c=17.0), dict(steps=-1),
+                dict(eta=float("nan"))):
+        with pytest.raises(ipp.IppError):
+            ctx.refine_centroids(frames, bks, t, p, **bad)
+
+
+def test_asinh_device_parameters_and_graph_replay(ctx):
+    """The stretch with (a, b) read on the device equals the call with the
+    values passed by value, bit for bit; an invalid a gives NaN; and both
+    calls captured in a torch CUDA graph replay correctly after the
+    parameter tensor is changed in place (eager work and syncs between the
+    replays)."""
+    g = torch.Generator(device="cpu")
+    g.manual_seed(5)
+    v = (torch.randn(300001, generator=g) * 200.0).to(DEV)
+    dy = torch.randn(300001, generator=g).to(DEV)
+    ab = torch.tensor([30.0, 1.5], dtype=torch.float64, device=DEV)
+    y0 = ctx.asinh(v, 30.0, 1.5)
+    dv0, dab0 = ctx.asinh_backward(v, dy, 30.0, 1.5)
+    y1 = ctx.asinh_dev(v, ab)
+    dv1, dab1 = ctx.asinh_backward_dev(v, dy, ab)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1) and torch.equal(dv0, dv1)
+    assert torch.equal(dab0, dab1)
+    bad = torch.tensor([0.0, 1.0], dtype=torch.float64, device=DEV)
+    assert torch.isnan(ctx.asinh_dev(v[:100], bad)).all()
+    _, dbad = ctx.asinh_backward_dev(v[:100], dy[:100], bad)
+    assert torch.isnan(dbad).all()
+    # capture: warm up on a side stream, then record both calls
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.asinh_dev(v, ab)
+        ctx.asinh_backward_dev(v, dy, ab)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        yg = ctx.asinh_dev(v, ab)
+        dvg, dabg = ctx.asinh_backward_dev(v, dy, ab)
+    for a, b in ((30.0, 1.5), (7.0, 2.0), (120.0, 0.25), (7.0, 2.0)):
+        ab.copy_(torch.tensor([a, b], dtype=torch.float64))
+        graph.replay()
+        torch.cuda.synchronize()
+        ye = ctx.asinh(v, a, b)
+        dve, dabe = ctx.asinh_backward(v, dy, a, b)
+        torch.cuda.synchronize()
+        assert torch.equal(yg, ye), (a, b)
+        assert torch.equal(dvg, dve), (a, b)
+        assert torch.equal(dabg, dabe), (a, b)
