@@ -16,6 +16,8 @@ Intelligence Era"):
 * ``detect``     -- Sec. 2.2.5 (Source Detection Function): pixel detection
   above a threshold, connection of pixels into candidates, and the
   pre-analysis of each candidate (peak value and total flux).
+* ``deblend``    -- Sec. 2.2.5: multi-threshold deblending of the
+  candidates into objects, and cleaning.
 * ``photometry`` -- Sec. 2.2.5, last paragraph: per-object aperture
   photometry, with exact circle/pixel overlaps and a local sky annulus, and
   its adjoint (gradients with the sky clip mask held fixed).
@@ -32,7 +34,7 @@ IEEE binary64; sums that decide results are exact (``math.fsum`` or Python
 integers) and rounded once.
 """
 from .params import Params
-from . import background, detect, photometry, stretch, refine, gray
+from . import background, detect, deblend, photometry, stretch, refine, gray
 
 __all__ = ["Params", "background", "detect", "photometry", "stretch",
-           "refine", "gray"]
+           "refine", "gray", "deblend"]

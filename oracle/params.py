@@ -17,6 +17,7 @@ SRC_ANNULUS_OFF_EDGE = 2     # annulus pixel outside the frame or not finite
 SRC_NO_SKY = 4               # no annulus pixel survived: sky taken as 0
 SRC_INEXACT_SUM_RANGE = 8    # a pixel of the source is outside the exact range
 SRC_NONPOSITIVE_FLUX = 16    # isophotal flux <= 0: unweighted centroid used
+SRC_BLENDED = 32             # object split off a candidate by deblending
 
 
 @dataclass
@@ -39,3 +40,8 @@ class Params:
     r_out: float = 12.0
     sky_clip_iters: int = 3
     sky_clip_sigma: float = 3.0
+    # deblending and cleaning (Sec. 2.2.5); SExtractor's usual settings
+    deblend_nthresh: int = 32    # levels between threshold and peak
+    deblend_mincont: float = 0.005   # flux fraction of a separate branch
+    deblend_clean: bool = True
+    clean_param: float = 1.0     # scale of the neighbours' modelled light
