@@ -329,6 +329,25 @@ ipp_status ipp_asinh_backward_dev(void* ctx, const float* v, const float* dy,
                                   const double* ab, void* stream);
 
 /*
+ * ipp_asinh_backward without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): same arguments, results and
+ * error checks as ipp_asinh_backward, but the block partials of dL_dab live
+ * in a static device array of the library (2 * 2048 doubles = 32 KiB per
+ * GPU, held until the process ends) instead of the context workspace, so
+ * no ipp_ctx_reserve is needed.  Any n is accepted: at most 2048
+ * grid-stride workgroups write partials, each its own slot, before the
+ * final reduction reads them (nothing must start at zero).  Calls that
+ * overlap on one GPU share that array and race: serialise them (one
+ * stream, or events between streams).  IPP_E_CAPACITY if the partials
+ * would not fit the array.
+ */
+ipp_status ipp_asinh_backward_noalloc(void* ctx, const float* v,
+                                      const float* dy, float* dv,
+                                      double* dL_dab, int64_t n, double a,
+                                      double b, void* stream);
+
+/*
  * Second-order moments of each table row's footprint (the pre-analysis of
  * Sec. 2.2.5 carried to second order, as SExtractor's X2, Y2, XY and the
  * ellipse A, B, THETA): over the bounding-box pixels whose label is the

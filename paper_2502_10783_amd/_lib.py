@@ -160,6 +160,9 @@ def lib():
     L.ipp_asinh_dev.restype = i32
     L.ipp_asinh_backward_dev.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
     L.ipp_asinh_backward_dev.restype = i32
+    L.ipp_asinh_backward_noalloc.argtypes = [vp, vp, vp, vp, vp, i64,
+                                             C.c_double, C.c_double, vp]
+    L.ipp_asinh_backward_noalloc.restype = i32
     L.ipp_autotune.argtypes = [vp, C.POINTER(IppFrame), i32,
                                C.POINTER(IppParams), C.c_uint32, C.c_char_p,
                                C.POINTER(C.c_double), vp]

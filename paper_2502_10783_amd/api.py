@@ -419,6 +419,29 @@ class Context:
             _ptr(self._ab(ab, v)), _stream()))
         return dv, dab
 
+    def asinh_backward_noalloc(self, v, dy, a: float, b: float,
+                               dv=None, dab=None):
+        """ipp_asinh_backward_noalloc: the backward with its partials in the
+        library's static scratch; writes into the given dv (float32, like
+        v) and dab (float64 [2]) tensors, either may be None."""
+        if not (v.is_cuda and dy.is_cuda and v.dtype == torch.float32
+                and dy.dtype == torch.float32 and v.numel() == dy.numel()
+                and v.is_contiguous() and dy.is_contiguous()):
+            raise ValueError("v, dy: need contiguous float32 CUDA tensors of "
+                             "one size")
+        if dv is not None and not (dv.is_cuda and dv.dtype == torch.float32
+                                   and dv.numel() == v.numel()
+                                   and dv.is_contiguous()):
+            raise ValueError("dv: need a contiguous float32 CUDA tensor "
+                             "of v's size")
+        if dab is not None and not (dab.is_cuda and dab.dtype ==
+                                    torch.float64 and dab.numel() == 2):
+            raise ValueError("dab: need a float64 CUDA tensor of 2 elements")
+        self._check(self.lib.ipp_asinh_backward_noalloc(
+            self.h, _ptr(v), _ptr(dy), _ptr(dv), _ptr(dab), v.numel(),
+            float(a), float(b), _stream()))
+        return dv, dab
+
     def source_moments(self, frames, bkg, labels, table: SourceTable):
         """Second-order moments per table row: float64 tensor [rows, 6]
         (x2, y2, xy, a, b, theta)."""

@@ -859,6 +859,9 @@ ipp_status ipp_ctx_create(void** ctx, int32_t device) {
   if (hipGetDeviceCount(&count) != hipSuccess || device >= count)
     return IPP_E_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return IPP_E_DEVICE;
+  // the allocation-free calls find their scratch at this device's address
+  double* scratch_ptr = nullptr;
+  if (asinh_scratch(device, &scratch_ptr) != hipSuccess) return IPP_E_DEVICE;
   IppCtx* c = new (std::nothrow) IppCtx();
   if (!c) return IPP_E_DEVICE;
   c->device = device;
@@ -1209,6 +1212,42 @@ ipp_status ipp_asinh_backward(void* ctx, const float* v, const float* dy,
   hipStream_t s = (hipStream_t)stream;
   double* part = dL_dab ? (double*)c->ws : nullptr;
   ++c->ws_gen;
+  IPP_LAUNCH(c, s, "k_asinh_bwd",
+             hipLaunchKernelGGL(k_asinh_bwd, dim3(grid), dim3(kBlock), 0, s,
+                                v, dy, dv, n, a, b, (const double*)nullptr,
+                                part));
+  if (dL_dab)
+    IPP_LAUNCH(c, s, "k_asinh_bwd_final",
+               hipLaunchKernelGGL(k_asinh_bwd_final, dim3(1), dim3(kBlock), 0,
+                                  s, part, grid, dL_dab));
+  return IPP_OK;
+}
+
+ipp_status ipp_asinh_backward_noalloc(void* ctx, const float* v,
+                                      const float* dy, float* dv,
+                                      double* dL_dab, int64_t n, double a,
+                                      double b, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (n < 0 || (n > 0 && (!v || !dy)))
+    return fail(c, IPP_E_INVALID_ARG, "v and dy are required, n >= 0");
+  if (!std::isfinite(a) || a <= 0 || !std::isfinite(b))
+    return fail(c, IPP_E_INVALID_ARG, "need a > 0 and finite b");
+  // grid-stride workgroups, at most kAsinhMaxBlocks of them: their
+  // partials always fit the static scratch, whatever n is
+  const int grid = grid_for(n, 4 * kBlock, kAsinhMaxBlocks);
+  if (grid > kAsinhMaxBlocks)
+    return fail(c, IPP_E_CAPACITY,
+                "more block partials than the static scratch holds (" +
+                    std::to_string(2 * kAsinhMaxBlocks) + " doubles)");
+  double* part = nullptr;
+  if (dL_dab) {
+    const hipError_t e = asinh_scratch(c->device, &part);
+    if (e != hipSuccess)
+      return fail(c, IPP_E_DEVICE, std::string("scratch lookup: ") +
+                                       hipGetErrorString(e));
+  }
+  hipStream_t s = (hipStream_t)stream;
   IPP_LAUNCH(c, s, "k_asinh_bwd",
              hipLaunchKernelGGL(k_asinh_bwd, dim3(grid), dim3(kBlock), 0, s,
                                 v, dy, dv, n, a, b, (const double*)nullptr,

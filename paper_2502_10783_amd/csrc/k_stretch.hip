@@ -3,10 +3,43 @@
 // Element-wise and HBM-bound: 8 B/px forward (read v, write y), 12 B/px
 // backward (read v and dL/dy, write dL/dv).  The parameter gradients are
 // binary64 block partials reduced in a fixed order by one workgroup.
+#include <mutex>
+
 #include "ipp_internal.h"
 #include "kernels.h"
 
 namespace ipp {
+
+// Scratch of the allocation-free backward: the binary64 block partials of
+// the two parameter gradients.  One copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: kernels are given the address from asinh_scratch().
+static __device__ __align__(256) double scratch[2 * kAsinhMaxBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t asinh_scratch(int device, double** ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (double*)p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 // Elements i (float4 groups when every pointer is 16-byte aligned), two
 // groups per thread and step, so that several loads are in flight.

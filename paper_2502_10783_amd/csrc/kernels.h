@@ -74,6 +74,10 @@ __global__ void k_asinh_bwd(const float* v, const float* dy, float* dv,
                             double* partial);
 __global__ void k_asinh_bwd_final(const double* partial, int nb,
                                   double* out);
+// Device address of the file-scope scratch of the asinh backward on
+// `device` (2 * kAsinhMaxBlocks doubles), looked up on first use with that
+// device current and kept per device.  hipSuccess or the lookup's error.
+hipError_t asinh_scratch(int device, double** ptr);
 
 __global__ void k_zscale(const GrayFrame* frames, double contrast,
                          double krej, int max_iter, double* z1z2,
