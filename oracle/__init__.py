@@ -18,6 +18,8 @@ Intelligence Era"):
   pre-analysis of each candidate (peak value and total flux).
 * ``deblend``    -- Sec. 2.2.5: multi-threshold deblending of the
   candidates into objects, and cleaning.
+* ``kron``       -- Sec. 2.2.5: AUTO (Kron) photometry, the Kron radius
+  and an exact ellipse-pixel overlap.
 * ``photometry`` -- Sec. 2.2.5, last paragraph: per-object aperture
   photometry, with exact circle/pixel overlaps and a local sky annulus, and
   its adjoint (gradients with the sky clip mask held fixed).
@@ -34,7 +36,8 @@ IEEE binary64; sums that decide results are exact (``math.fsum`` or Python
 integers) and rounded once.
 """
 from .params import Params
-from . import background, detect, deblend, photometry, stretch, refine, gray
+from . import (background, detect, deblend, kron, photometry, stretch,
+               refine, gray)
 
 __all__ = ["Params", "background", "detect", "photometry", "stretch",
-           "refine", "gray", "deblend"]
+           "refine", "gray", "deblend", "kron"]
