@@ -86,6 +86,8 @@ enum {
                                          outside the exact-sum range        */
 #define IPP_SRC_NONPOSITIVE_FLUX 16u  /* isophotal flux <= 0: unweighted
                                          centroid                           */
+#define IPP_SRC_BLENDED 32u           /* an object of a candidate that
+                                         deblending split                   */
 
 /*
  * Method parameters.  Defaults (ipp_params_default) are the settings of
@@ -287,7 +289,7 @@ ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
  * x_out, y_out: device double[capacity], the refined centres (they may be
  * src->x and src->y themselves); the table's other columns are untouched.
  * r_c in (0, 16], eta finite, steps in [0, 1000].  Needs
- * ipp_refine_workspace_bytes of workspace (80 bytes per row plus the frame
+ * ipp_refine_workspace_bytes of workspace (76 bytes per row plus the frame
  * descriptors).  The whole sequence (1 + 3 steps launches) is replayed from
  * a captured HIP graph when called again with the same signature.
  */
@@ -348,6 +350,68 @@ ipp_status ipp_asinh_backward_noalloc(void* ctx, const float* v,
                                       double b, void* stream);
 
 /*
+ * Deblending and cleaning (Sec. 2.2.5, the phases between detection and
+ * photometry): every candidate of a detection (label map + table) is split
+ * into objects by multi-threshold deblending, and objects that cleaning
+ * finds to be light of a brighter neighbour are merged back.
+ *
+ *  - Levels: t0 = det_nsigma R32 at the candidate's peak pixel;
+ *    q = (peak / t0)^(1/nthresh) by log2(nthresh) square roots;
+ *    t_i = t_{i-1} q, i = 1 .. nthresh-1 (binary64).  Candidates of one
+ *    pixel, or with t0 <= 0, stay whole.
+ *  - Tree: at each level the candidate's pixels with v = I - B32 above it
+ *    form components (p->connectivity), nested in the level below.
+ *  - Contrast: a node is significant iff fl(S 2^-28) - n t_i (S the exact
+ *    sum of the source table's weights D over its n pixels) exceeds
+ *    mincont times the candidate's flux.
+ *  - Pruning, bottom up: a leaf is one object; a node with two or more
+ *    significant children stands for their objects, with one for that
+ *    child's objects when it has two or more, else for itself.
+ *  - The object nodes' pixels are seeds, numbered in raster order of their
+ *    first pixels; every other pixel goes to the seed whose model
+ *    F s2 / (s2 + d^2)^2 is largest (F, barycentre and s2 = x2 + y2 + 1/6
+ *    from the seed's exact moments; ties to the lower index).
+ *  - Cleaning (clean != 0): an object whose mean value minus
+ *    clean_param F s2 / (pi (s2 + d^2)^2) summed over the brighter objects
+ *    of its candidate (at its seed barycentre) falls below t0 joins the
+ *    brightest contributor.
+ *
+ * Inputs: frames; maps[f].bkg, .rms and .labels (the detection's); cand,
+ * the detection table (frame, label, npix, bounding box, peak, peak_x,
+ * peak_y, frame_offsets; rows min(capacity, *n_total)); p (det_nsigma,
+ * connectivity).  Outputs: objects[f], device int32 h x w per frame:
+ * 0 outside the candidates, objects numbered 1..K per frame candidate by
+ * candidate and within a candidate in seed order; obj, the object table:
+ * frame, label (the object number), npix, bounding box, then the
+ * pre-analysis of ipp_detect over the object map (peak, peak_x, peak_y,
+ * flux_iso, x, y, flags, with IPP_SRC_BLENDED on objects of split
+ * candidates), n_total, frame_offsets; parent, device int32[obj capacity]:
+ * the candidate label of each object.  Rows beyond obj->capacity are not
+ * written (n_total still counts them).  Scratch: the workspace beyond the
+ * fixed part (ipp_deblend_workspace_bytes with scratch_bytes); a candidate
+ * needs about 44 B per bounding-box pixel plus 300 B per pixel.  diag
+ * (device int64[4], nullable): [0] scratch bytes needed, [1] available,
+ * [2] nonzero if candidates were left whole for lack of scratch, [3]
+ * objects found.
+ */
+typedef struct ipp_deblend_params {
+  int32_t nthresh;        /* levels: a power of two in [2, 64] (32)       */
+  int32_t clean;          /* cleaning pass (1)                            */
+  double mincont;         /* contrast fraction, >= 0 (0.005)              */
+  double clean_param;     /* scale of the neighbours' light, >= 0 (1.0)   */
+} ipp_deblend_params;
+
+void ipp_deblend_params_default(ipp_deblend_params* d);
+size_t ipp_deblend_workspace_bytes(const ipp_frame* frames, int32_t n,
+                                   int64_t cand_capacity,
+                                   int64_t scratch_bytes);
+ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
+                       const ipp_params* p, const ipp_deblend_params* dp,
+                       const ipp_maps* maps, const ipp_sources* cand,
+                       int32_t* const* objects, ipp_sources* obj,
+                       int32_t* parent, int64_t* diag, void* stream);
+
+/*
  * Second-order moments of each table row's footprint (the pre-analysis of
  * Sec. 2.2.5 carried to second order, as SExtractor's X2, Y2, XY and the
  * ellipse A, B, THETA): over the bounding-box pixels whose label is the
@@ -365,6 +429,40 @@ ipp_status ipp_asinh_backward_noalloc(void* ctx, const float* v,
 ipp_status ipp_source_moments(void* ctx, const ipp_frame* frames, int32_t n,
                               const ipp_maps* maps, const ipp_sources* src,
                               double* mom, void* stream);
+
+/*
+ * AUTO (Kron) photometry (Sec. 2.2.5 lists auto photometry among the
+ * per-object measurements; Sec. 3.3 compares auto magnitudes): for each
+ * table row (frame, x, y; rows min(capacity, *n_total)) with the second
+ * moments mom[6 row + 0..2] = (x2, y2, xy) of ipp_source_moments:
+ *  - X = x2 + 1/12, Y = y2 + 1/12, det = X Y - xy^2 (the moments
+ *    regularised by a uniform unit pixel); q(dx, dy) = (Y dx^2 + X dy^2
+ *    - 2 xy dx dy) / det is 1 on the one-sigma ellipse;
+ *  - Kron radius: r1 = sum sqrt(q) v / sum v over the in-frame pixel
+ *    centres with q <= search^2 (v = I - B32), R = max(kron_factor r1,
+ *    kron_min), or kron_min when sum v <= 0 (flag 2);
+ *  - AUTO flux = sum of v times the exact area of each pixel inside the
+ *    ellipse q <= R^2 around (x, y), area = the sum of those areas; a
+ *    pixel belongs to the ellipse iff the smallest q over its square is
+ *    below R^2; ellipse pixels off the frame or not finite are skipped
+ *    (flag 4; the frame's one-pixel surround is examined, and an ellipse
+ *    centred off the frame is flagged);
+ *  - rows with unusable moments (det <= 0 or not finite) get NaN (flag 1).
+ * Outputs (device, per row): kron (R), flux, area, flags.  ap nullable:
+ * defaults kron_factor 2.5, kron_min 3.5, search 6.
+ */
+typedef struct ipp_auto_params {
+  double kron_factor;     /* k in R = k r1 (2.5)                          */
+  double kron_min;        /* smallest R (3.5)                             */
+  double search;          /* search ellipse for r1, in sigmas (6)         */
+} ipp_auto_params;
+
+void ipp_auto_params_default(ipp_auto_params* a);
+ipp_status ipp_photometry_auto(void* ctx, const ipp_frame* frames, int32_t n,
+                               const ipp_maps* maps, const ipp_sources* src,
+                               const double* mom, const ipp_auto_params* ap,
+                               double* kron, double* flux, double* area,
+                               uint32_t* flags, void* stream);
 
 /*
  * Gray-scale transformations (Sec. 2.2.6): the zscale display range, point

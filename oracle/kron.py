@@ -21,8 +21,10 @@ SExtractor documents it:
   sum v <= 0 or r1 is not finite.
 * AUTO flux.  F = sum v_i w_i over in-frame pixels, w_i the exact area of
   pixel i inside the ellipse q <= R^2 centred on the barycentre; A = sum w.
-  Pixels of the ellipse outside the frame or not finite are skipped and
-  flag the row.
+  A pixel belongs to the ellipse iff the smallest q over its square is
+  below R^2 (rational operations, so both sides decide alike); pixels of
+  the ellipse outside the frame or not finite are skipped and flag the
+  row.
 * Exact overlap.  With Q = [[Y, -xy], [-xy, X]] / (det R^2) = L^T L (L
   upper triangular, the Cholesky factor), u = L d maps the ellipse onto
   the unit disk and the pixel square onto a parallelogram; the overlap is
@@ -116,6 +118,24 @@ def ellipse_overlap(sh, R: float, cx: float, cy: float, px: int,
     return area / (l11 * l22)
 
 
+def min_q(sh, x0: float, x1: float, y0: float, y1: float) -> float:
+    """Smallest q over the square [x0, x1] x [y0, y1] (offsets from the
+    centre): 0 when the centre lies in it, else the smallest of the edges'
+    minima (on an edge q is a convex quadratic in one offset, smallest at
+    its stationary point clamped to the edge)."""
+    X, Y, xy, det = sh
+    if x0 <= 0.0 <= x1 and y0 <= 0.0 <= y1:
+        return 0.0
+    best = math.inf
+    for dx in (x0, x1):
+        dy = min(max(xy * dx / X, y0), y1)
+        best = min(best, qform(sh, dx, dy))
+    for dy in (y0, y1):
+        dx = min(max(xy * dy / Y, x0), x1)
+        best = min(best, qform(sh, dx, dy))
+    return best
+
+
 def _window(sh, cx, cy, r):
     """Pixel bounds of the ellipse q <= r^2 (its bounding box, widened by
     half a pixel)."""
@@ -153,18 +173,27 @@ def auto_one(img, B, cx, cy, x2, y2, xy):
     else:
         R = KRON_RMIN
         flags |= AUTO_RMIN
-    # AUTO flux over the Kron ellipse
+    # AUTO flux over the Kron ellipse.  The window is cut to the frame and
+    # a ring of one pixel around it: an ellipse centred in the frame that
+    # reaches outside meets that ring (it is convex), and one centred
+    # outside the frame is flagged outright.
     x0, x1, y0, y1 = _window(sh, cx, cy, R)
+    x0, x1 = max(x0, -1), min(x1, w)
+    y0, y1 = max(y0, -1), min(y1, h)
+    if not (-0.5 <= cx <= w - 0.5 and -0.5 <= cy <= h - 0.5):
+        flags |= AUTO_OFF_EDGE
     flux = area = 0.0
     for py in range(y0, y1 + 1):
         for px in range(x0, x1 + 1):
-            wgt = ellipse_overlap(sh, R, cx, cy, px, py)
-            if wgt <= 0.0:
+            # the pixel meets the open ellipse (an exact predicate)
+            if not min_q(sh, px - 0.5 - cx, px + 0.5 - cx, py - 0.5 - cy,
+                         py + 0.5 - cy) < R * R:
                 continue
             if not (0 <= px < w and 0 <= py < h) or \
                     not math.isfinite(float(img[py, px])):
                 flags |= AUTO_OFF_EDGE
                 continue
+            wgt = ellipse_overlap(sh, R, cx, cy, px, py)
             v = float(img[py, px]) - float(B[py, px])
             flux += wgt * v
             area += wgt

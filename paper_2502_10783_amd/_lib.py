@@ -32,6 +32,7 @@ IPP_SRC_ANNULUS_OFF_EDGE = 2
 IPP_SRC_NO_SKY = 4
 IPP_SRC_INEXACT_SUM_RANGE = 8
 IPP_SRC_NONPOSITIVE_FLUX = 16
+IPP_SRC_BLENDED = 32
 
 
 class IppParams(C.Structure):
@@ -65,6 +66,16 @@ class IppMesh(C.Structure):
     _fields_ = [("bkg_raw", C.c_void_p), ("rms_raw", C.c_void_p),
                 ("n_used", C.c_void_p), ("bkg", C.c_void_p),
                 ("rms", C.c_void_p)]
+
+
+class IppDeblendParams(C.Structure):
+    _fields_ = [("nthresh", C.c_int32), ("clean", C.c_int32),
+                ("mincont", C.c_double), ("clean_param", C.c_double)]
+
+
+class IppAutoParams(C.Structure):
+    _fields_ = [("kron_factor", C.c_double), ("kron_min", C.c_double),
+                ("search", C.c_double)]
 
 
 SOURCE_COLUMNS = (
@@ -167,6 +178,25 @@ def lib():
                                C.POINTER(IppParams), C.c_uint32, C.c_char_p,
                                C.POINTER(C.c_double), vp]
     L.ipp_autotune.restype = i32
+    L.ipp_deblend_params_default.argtypes = [C.POINTER(IppDeblendParams)]
+    L.ipp_deblend_params_default.restype = None
+    L.ipp_deblend_workspace_bytes.argtypes = [C.POINTER(IppFrame), i32, i64,
+                                              i64]
+    L.ipp_deblend_workspace_bytes.restype = sz
+    L.ipp_deblend.argtypes = [vp, C.POINTER(IppFrame), i32,
+                              C.POINTER(IppParams),
+                              C.POINTER(IppDeblendParams), C.POINTER(IppMaps),
+                              C.POINTER(IppSources), C.POINTER(vp),
+                              C.POINTER(IppSources), vp, vp, vp]
+    L.ipp_deblend.restype = i32
+    L.ipp_auto_params_default.argtypes = [C.POINTER(IppAutoParams)]
+    L.ipp_auto_params_default.restype = None
+    L.ipp_photometry_auto.argtypes = [vp, C.POINTER(IppFrame), i32,
+                                      C.POINTER(IppMaps),
+                                      C.POINTER(IppSources), vp,
+                                      C.POINTER(IppAutoParams), vp, vp, vp,
+                                      vp, vp]
+    L.ipp_photometry_auto.restype = i32
     L.ipp_source_moments.argtypes = [vp, C.POINTER(IppFrame), i32,
                                      C.POINTER(IppMaps), C.POINTER(IppSources),
                                      vp, vp]

@@ -47,6 +47,21 @@ class Params:
         return c
 
 
+@dataclass
+class DeblendParams:
+    """Deblending and cleaning parameters (ipp_deblend_params)."""
+    nthresh: int = 32
+    clean: int = 1
+    mincont: float = 0.005
+    clean_param: float = 1.0
+
+    def to_c(self) -> L.IppDeblendParams:
+        c = L.IppDeblendParams()
+        for f in fields(self):
+            setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
 class IppError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{L.lib().ipp_status_string(status).decode()}"
@@ -441,6 +456,96 @@ class Context:
             self.h, _ptr(v), _ptr(dy), _ptr(dv), _ptr(dab), v.numel(),
             float(a), float(b), _stream()))
         return dv, dab
+
+    def deblend(self, frames, bkg, rms, labels, table: SourceTable,
+                params: Params, dparams: Optional[DeblendParams] = None,
+                capacity=None, scratch_bytes=None):
+        """Sec. 2.2.5 deblending and cleaning of the detection's candidates
+        (label maps and table): returns the object maps, the object table,
+        each object's parent candidate label and the diagnostics.  The
+        scratch pool grows (and the call is repeated) when a first try
+        reports it too small."""
+        n = len(frames)
+        dev = frames[0].device
+        dp = dparams or DeblendParams()
+        npx = sum(f.numel() for f in frames)
+        if capacity is None:
+            capacity = 2 * max(table.capacity, 1) + 1024
+        if scratch_bytes is None:
+            scratch_bytes = 64 * npx + (1 << 20)
+        fc = frames_c(frames)
+        maps = (L.IppMaps * n)()
+        objs = []
+        for i, fr in enumerate(frames):
+            _check_map(bkg[i], fr, "bkg")
+            _check_map(rms[i], fr, "rms")
+            _check_map(labels[i], fr, "labels", torch.int32)
+            maps[i].bkg = bkg[i].data_ptr()
+            maps[i].rms = rms[i].data_ptr()
+            maps[i].labels = labels[i].data_ptr()
+            objs.append(torch.empty(fr.shape, dtype=torch.int32, device=dev))
+        optr = (C.c_void_p * n)(*[o.data_ptr() for o in objs])
+        obj = SourceTable(capacity, n, dev)
+        parent = torch.zeros(max(1, capacity), dtype=torch.int32, device=dev)
+        diag = torch.zeros(4, dtype=torch.int64, device=dev)
+        pc = params.to_c()
+        dpc = dp.to_c()
+        for _ in range(3):
+            need = self.lib.ipp_deblend_workspace_bytes(
+                fc, n, table.capacity, int(scratch_bytes))
+            if need == 0:
+                raise IppError(L.IPP_E_INVALID_ARG,
+                               "ipp_deblend_workspace_bytes")
+            if need > self.ws_bytes:
+                self.reserve(need)
+            cand = table.to_c()
+            oc = obj.to_c()
+            self._check(self.lib.ipp_deblend(
+                self.h, fc, n, C.byref(pc), C.byref(dpc), maps,
+                C.byref(cand), optr, C.byref(oc), _ptr(parent), _ptr(diag),
+                _stream()))
+            d = diag.cpu().tolist()
+            if not (d[2] & 1):
+                break
+            scratch_bytes = int(d[0]) + (1 << 20)
+        return {"objects": objs, "table": obj, "parent": parent,
+                "diag": diag}
+
+    def photometry_auto(self, frames, bkg, table: SourceTable,
+                        moments: torch.Tensor, kron_factor=2.5, kron_min=3.5,
+                        search=6.0, use_count=True):
+        """AUTO (Kron) photometry of the table rows (frame, x, y) with their
+        second moments (rows x 6, as source_moments returns): dict of
+        float64 kron radius, flux, area and int32 flags per row."""
+        n = len(frames)
+        maps = (L.IppMaps * n)()
+        for i in range(n):
+            _check_map(bkg[i], frames[i], "bkg")
+            maps[i].bkg = bkg[i].data_ptr()
+        cap = max(1, table.capacity)
+        if not (moments.is_cuda and moments.dtype == torch.float64 and
+                moments.is_contiguous() and moments.dim() == 2 and
+                moments.shape[1] == 6):
+            raise ValueError("moments: need a contiguous float64 CUDA "
+                             "tensor of rows x 6")
+        mom = moments
+        if mom.shape[0] < cap:
+            mom = torch.full((cap, 6), float("nan"), dtype=torch.float64,
+                             device=moments.device)
+            mom[:moments.shape[0]] = moments
+        self.ensure(frames, Params())
+        dev = frames[0].device
+        out = {k: torch.empty(cap, dtype=torch.float64, device=dev)
+               for k in ("kron_radius", "flux", "area")}
+        out["flags"] = torch.empty(cap, dtype=torch.int32, device=dev)
+        ap = L.IppAutoParams(float(kron_factor), float(kron_min),
+                             float(search))
+        src = table.to_c(n_total=use_count)
+        self._check(self.lib.ipp_photometry_auto(
+            self.h, frames_c(frames), n, maps, C.byref(src), _ptr(mom),
+            C.byref(ap), _ptr(out["kron_radius"]), _ptr(out["flux"]),
+            _ptr(out["area"]), _ptr(out["flags"]), _stream()))
+        return out
 
     def source_moments(self, frames, bkg, labels, table: SourceTable):
         """Second-order moments per table row: float64 tensor [rows, 6]

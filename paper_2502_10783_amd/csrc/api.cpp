@@ -4,12 +4,14 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "ipp_internal.h"
+#include "deblend_core.h"
 #include "kernels.h"
 
 using namespace ipp;
@@ -690,6 +692,44 @@ ipp_status run_refine(IppCtx* c, const Work& w, const ipp_params& p,
                hipLaunchKernelGGL(k_refine_step, ge, bb, 0, s, dxy, g, xo, yo,
                                   eta, src.n_total, cap));
   }
+  return IPP_OK;
+}
+
+// Deblending: fixed per-call arrays after the frame descriptors, then the
+// scratch pool (the rest of the workspace).
+struct DeblendWs {
+  size_t o_fd2, o_need, o_off, o_cnt, o_ooff, o_blk, o_tot, o_pool;
+  int64_t nblk;
+};
+
+DeblendWs deblend_layout(size_t base, int32_t n, int64_t cap) {
+  DeblendWs D;
+  size_t o = align_up(base);
+  auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
+  const size_t rows = (size_t)cap + 1;
+  D.nblk = (int64_t)((rows + 1023) / 1024);
+  D.o_fd2 = take(sizeof(FrameDev) * (size_t)n);
+  D.o_need = take(8 * rows);
+  D.o_off = take(8 * rows);
+  D.o_cnt = take(8 * rows);
+  D.o_ooff = take(8 * rows);
+  D.o_blk = take(8 * (size_t)(D.nblk + 1));
+  D.o_tot = take(8 * 4);
+  D.o_pool = o;
+  return D;
+}
+
+ipp_status scan64(IppCtx* c, const int64_t* in, int64_t* blk, int64_t nblk,
+                  int64_t* out, int64_t n, int64_t* total, hipStream_t s) {
+  IPP_LAUNCH(c, s, "k_scan64_blocks",
+             hipLaunchKernelGGL(k_scan64_blocks, dim3((unsigned)nblk),
+                                dim3(kBlock), 0, s, in, blk, n));
+  IPP_LAUNCH(c, s, "k_scan64_top",
+             hipLaunchKernelGGL(k_scan64_top, dim3(1), dim3(kBlock), 0, s,
+                                blk, nblk, total));
+  IPP_LAUNCH(c, s, "k_scan64_apply",
+             hipLaunchKernelGGL(k_scan64_apply, dim3((unsigned)nblk),
+                                dim3(kBlock), 0, s, in, blk, out, n));
   return IPP_OK;
 }
 
@@ -1400,6 +1440,200 @@ ipp_status ipp_equalize(void* ctx, const ipp_frame* frames, int32_t n,
              hipLaunchKernelGGL(k_eq_map, dim3(grid_for(G.rows, 32, 2048)),
                                 dim3(kBlock), 0, s, fr, n, G.rows, nbins, mm,
                                 cdf));
+  return IPP_OK;
+}
+
+void ipp_deblend_params_default(ipp_deblend_params* d) {
+  if (!d) return;
+  d->nthresh = 32;
+  d->clean = 1;
+  d->mincont = 0.005;
+  d->clean_param = 1.0;
+}
+
+size_t ipp_deblend_workspace_bytes(const ipp_frame* frames, int32_t n,
+                                   int64_t cand_capacity,
+                                   int64_t scratch_bytes) {
+  if (!check_frames(frames, n).empty() || cand_capacity < 0 ||
+      scratch_bytes < 0)
+    return 0;
+  ipp_params pd;
+  ipp_params_default(&pd);
+  const Plan P = make_plan(frames, n, pd, 1, kPlanFrames);
+  return deblend_layout(P.total, n, cand_capacity).o_pool +
+         align_up((size_t)scratch_bytes);
+}
+
+ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
+                       const ipp_params* p, const ipp_deblend_params* dp,
+                       const ipp_maps* maps, const ipp_sources* cand,
+                       int32_t* const* objects, ipp_sources* obj,
+                       int32_t* parent, int64_t* diag, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (!dp) return fail(c, IPP_E_INVALID_ARG, "deblend params are NULL");
+  if (dp->nthresh < 2 || dp->nthresh > db::kMaxLevels ||
+      (dp->nthresh & (dp->nthresh - 1)))
+    return fail(c, IPP_E_INVALID_ARG,
+                "nthresh must be a power of two in [2, 64]");
+  if (!std::isfinite(dp->mincont) || dp->mincont < 0 ||
+      !std::isfinite(dp->clean_param) || dp->clean_param < 0)
+    return fail(c, IPP_E_INVALID_ARG,
+                "mincont and clean_param must be finite and >= 0");
+  if (!cand || cand->capacity < 0 || !cand->frame || !cand->label ||
+      !cand->npix || !cand->xmin || !cand->xmax || !cand->ymin ||
+      !cand->ymax || !cand->peak || !cand->peak_x || !cand->peak_y ||
+      !cand->frame_offsets)
+    return fail(c, IPP_E_INVALID_ARG,
+                "candidates: frame, label, npix, bounding box, peak, "
+                "peak_x, peak_y and frame_offsets are required");
+  std::string m = check_sources(obj, true);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, "objects: " + m);
+  if (!parent) return fail(c, IPP_E_INVALID_ARG, "parent is NULL");
+  if (!objects) return fail(c, IPP_E_INVALID_ARG, "objects is NULL");
+  Plan P;
+  ipp_status st = prepare(c, frames, n, p, kPlanFrames, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg || !maps[i].rms || !maps[i].labels || !objects[i])
+      return fail(c, IPP_E_INVALID_ARG,
+                  "maps[f].bkg, .rms, .labels and objects[f] are required");
+    P.fd[i].bkg = maps[i].bkg;
+    P.fd[i].rms = maps[i].rms;
+    P.fd[i].labels = maps[i].labels;
+    P.fd[i].objects = objects[i];
+  }
+  const int64_t cap = cand->capacity;
+  const DeblendWs D = deblend_layout(P.total, n, cap);
+  if (D.o_pool > c->ws_bytes)
+    return fail(c, IPP_E_WORKSPACE,
+                "workspace too small: need at least " +
+                    std::to_string(D.o_pool) + " bytes, have " +
+                    std::to_string(c->ws_bytes));
+  const int64_t pool_units = (int64_t)((c->ws_bytes - D.o_pool) / 256);
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  std::vector<FrameDev> fd2(P.fd);
+  for (auto& d : fd2) d.labels = d.objects;
+  char* b = (char*)c->ws;
+  hipError_t e = hipMemcpyAsync(b + D.o_fd2, fd2.data(),
+                                sizeof(FrameDev) * fd2.size(),
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE, std::string("descriptor upload failed: ") +
+                                     hipGetErrorString(e));
+  Work w2 = w;
+  w2.frames = (FrameDev*)(b + D.o_fd2);
+  int64_t* need = (int64_t*)(b + D.o_need);
+  int64_t* off = (int64_t*)(b + D.o_off);
+  int64_t* cnt = (int64_t*)(b + D.o_cnt);
+  int64_t* ooff = (int64_t*)(b + D.o_ooff);
+  int64_t* blk = (int64_t*)(b + D.o_blk);
+  int64_t* tot = (int64_t*)(b + D.o_tot);
+  char* pool = b + D.o_pool;
+  const int64_t rows = cap + 1;
+  IPP_LAUNCH(c, s, "k_fill_i64",
+             hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s,
+                                w.counters, (int64_t)4, (int64_t)0));
+  IPP_LAUNCH(c, s, "k_db_need",
+             hipLaunchKernelGGL(k_db_need,
+                                dim3(grid_for(rows, kBlock, 16384)),
+                                dim3(kBlock), 0, s, *cand, need));
+  if ((st = scan64(c, need, blk, D.nblk, off, rows, tot, s)) != IPP_OK)
+    return st;
+  const dim3 g1(grid_for(rows, 64, 1 << 20));
+  IPP_LAUNCH(c, s, "k_db_run",
+             hipLaunchKernelGGL(k_db_run, g1, dim3(64), 0, s, w, *cand, off,
+                                tot, pool, pool_units, p->det_nsigma,
+                                p->connectivity, dp->nthresh, dp->clean,
+                                dp->mincont, dp->clean_param, cnt));
+  if ((st = scan64(c, cnt, blk, D.nblk, ooff, rows, tot + 1, s)) != IPP_OK)
+    return st;
+  int64_t maxpix = 1;
+  for (int i = 0; i < n; ++i)
+    maxpix = std::max<int64_t>(maxpix, (int64_t)frames[i].h * frames[i].w);
+  IPP_LAUNCH(c, s, "k_db_zero",
+             hipLaunchKernelGGL(k_db_zero,
+                                dim3(grid_for(maxpix, kBlock, 1024),
+                                     std::min(n, 65535)),
+                                dim3(kBlock), 0, s, w));
+  IPP_LAUNCH(c, s, "k_db_write",
+             hipLaunchKernelGGL(k_db_write, g1, dim3(64), 0, s, w, *cand,
+                                off, tot, pool, pool_units, cnt, ooff, *obj,
+                                parent));
+  IPP_LAUNCH(c, s, "k_db_offsets",
+             hipLaunchKernelGGL(k_db_offsets,
+                                dim3(grid_for((int64_t)n + 1, kBlock, 4096)),
+                                dim3(kBlock), 0, s, w, *cand, ooff, tot + 1,
+                                *obj));
+  IPP_LAUNCH(c, s, "k_source_stats",
+             hipLaunchKernelGGL(k_source_stats,
+                                dim3(grid_for(obj->capacity, 4, 4096)),
+                                dim3(kBlock), 0, s, w2, *obj));
+  IPP_LAUNCH(c, s, "k_db_flags",
+             hipLaunchKernelGGL(k_db_flags,
+                                dim3(grid_for(obj->capacity, kBlock, 4096)),
+                                dim3(kBlock), 0, s, *cand, cnt, tot + 1,
+                                *obj, parent));
+  if (diag)
+    IPP_LAUNCH(c, s, "k_db_diag",
+               hipLaunchKernelGGL(k_db_diag, dim3(1), dim3(64), 0, s, tot,
+                                  pool_units, w.counters, diag));
+  return IPP_OK;
+}
+
+void ipp_auto_params_default(ipp_auto_params* a) {
+  if (!a) return;
+  a->kron_factor = 2.5;
+  a->kron_min = 3.5;
+  a->search = 6.0;
+}
+
+ipp_status ipp_photometry_auto(void* ctx, const ipp_frame* frames, int32_t n,
+                               const ipp_maps* maps, const ipp_sources* src,
+                               const double* mom, const ipp_auto_params* ap,
+                               double* kron, double* flux, double* area,
+                               uint32_t* flags, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  if (!src || src->capacity < 0 || !src->frame || !src->x || !src->y)
+    return fail(c, IPP_E_INVALID_ARG, "sources: frame, x and y are required");
+  if (!mom || !kron || !flux || !area || !flags)
+    return fail(c, IPP_E_INVALID_ARG,
+                "mom, kron, flux, area and flags are required");
+  ipp_auto_params a;
+  ipp_auto_params_default(&a);
+  if (ap) a = *ap;
+  if (!std::isfinite(a.kron_factor) || a.kron_factor <= 0 ||
+      !std::isfinite(a.kron_min) || a.kron_min <= 0 ||
+      !std::isfinite(a.search) || a.search <= 0 || a.search > 64)
+    return fail(c, IPP_E_INVALID_ARG,
+                "kron_factor and kron_min must be > 0, search in (0, 64]");
+  ipp_params pd;
+  ipp_params_default(&pd);
+  Plan P;
+  ipp_status st = prepare(c, frames, n, &pd, kPlanFrames, &P);
+  if (st != IPP_OK) return st;
+  if (!maps) return fail(c, IPP_E_INVALID_ARG, "maps is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!maps[i].bkg)
+      return fail(c, IPP_E_INVALID_ARG, "maps[f].bkg is required");
+    P.fd[i].bkg = maps[i].bkg;
+  }
+  if (src->capacity == 0) return IPP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  Work w = make_work(P, c->ws, n);
+  ++c->ws_gen;
+  if ((st = upload(c, P, w, s)) != IPP_OK) return st;
+  IPP_LAUNCH(c, s, "k_kron",
+             hipLaunchKernelGGL(k_kron,
+                                dim3(grid_for(src->capacity, kWaves, 16384)),
+                                dim3(kBlock), 0, s, w, *src, mom,
+                                a.kron_factor, a.kron_min, a.search, kron,
+                                flux, area, flags));
   return IPP_OK;
 }
 

@@ -39,6 +39,7 @@ struct FrameDev {
   double* o_rms;
   float* dpix;           // pixel gradient (photometry backward), or null
   int32_t line0[2];      // first mesh line of each spline pass
+  int32_t* objects;      // object map written by deblending, or null
 };
 
 // Frame of the gray-scale calls: input, output and the zscale sample grid.

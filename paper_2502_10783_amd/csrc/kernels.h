@@ -79,6 +79,37 @@ __global__ void k_asinh_bwd_final(const double* partial, int nb,
 // device current and kept per device.  hipSuccess or the lookup's error.
 hipError_t asinh_scratch(int device, double** ptr);
 
+// Deblending (k_deblend.hip): see that file for the sequence.
+__global__ void k_db_need(ipp_sources cand, int64_t* need);
+__global__ void k_scan64_blocks(const int64_t* in, int64_t* blocks,
+                                int64_t n);
+__global__ void k_scan64_top(int64_t* blocks, int64_t nblocks,
+                             int64_t* total);
+__global__ void k_scan64_apply(const int64_t* in, const int64_t* blocks,
+                               int64_t* out, int64_t n);
+__global__ void k_db_run(Work wk, ipp_sources cand, const int64_t* off,
+                         const int64_t* tot, char* pool, int64_t pool_units,
+                         double nsigma, int conn, int nthresh, int clean,
+                         double mincont, double kc, int64_t* cnt);
+__global__ void k_db_zero(Work wk);
+__global__ void k_db_write(Work wk, ipp_sources cand, const int64_t* off,
+                           const int64_t* tot, const char* pool,
+                           int64_t pool_units, const int64_t* cnt,
+                           const int64_t* ooff, ipp_sources obj,
+                           int32_t* parent);
+__global__ void k_db_offsets(Work wk, ipp_sources cand, const int64_t* ooff,
+                             const int64_t* total, ipp_sources obj);
+__global__ void k_db_flags(ipp_sources cand, const int64_t* cnt,
+                           const int64_t* total, ipp_sources obj,
+                           const int32_t* parent);
+__global__ void k_db_diag(const int64_t* tot, int64_t pool_units,
+                          const int64_t* counters, int64_t* diag);
+
+// AUTO (Kron) photometry: one wavefront per row (k_kron.hip).
+__global__ void k_kron(Work wk, ipp_sources src, const double* mom,
+                       double kfac, double rmin, double search, double* kron,
+                       double* flux, double* area, uint32_t* flags);
+
 __global__ void k_zscale(const GrayFrame* frames, double contrast,
                          double krej, int max_iter, double* z1z2,
                          double* info);

@@ -117,3 +117,40 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libipp.so")
     with pytest.raises(RuntimeError, match="missing"):
         L.lib()
+
+
+def test_deblend_kron_refine_host_checks(lib):
+    d = L.IppDeblendParams()
+    lib.ipp_deblend_params_default(C.byref(d))
+    assert (d.nthresh, d.clean, d.mincont, d.clean_param) == \
+        (32, 1, 0.005, 1.0)
+    a = L.IppAutoParams()
+    lib.ipp_auto_params_default(C.byref(a))
+    assert (a.kron_factor, a.kron_min, a.search) == (2.5, 3.5, 6.0)
+    f = _frames([(128, 96), (64, 64)])
+    w0 = lib.ipp_deblend_workspace_bytes(f, 2, 1000, 0)
+    w1 = lib.ipp_deblend_workspace_bytes(f, 2, 1000, 1 << 20)
+    assert w0 > 4 * 8 * 1000 and w1 >= w0 + (1 << 20)
+    assert lib.ipp_deblend_workspace_bytes(f, 2, -1, 0) == 0
+    assert lib.ipp_deblend_workspace_bytes(None, 2, 10, 0) == 0
+    r0 = lib.ipp_refine_workspace_bytes(f, 2, 1000)
+    assert r0 > 76 * 1000
+    assert lib.ipp_refine_workspace_bytes(f, 2, -5) == 0
+    p = _defaults(lib)
+    maps = (L.IppMaps * 2)()
+    src = L.IppSources()
+    outs = (C.c_void_p * 2)(1, 2)
+    assert lib.ipp_deblend(None, f, 2, C.byref(p), C.byref(d), maps,
+                           C.byref(src), outs, C.byref(src), None, None,
+                           None) == L.IPP_E_INVALID_ARG
+    assert lib.ipp_photometry_auto(None, f, 2, maps, C.byref(src), None,
+                                   None, None, None, None, None,
+                                   None) == L.IPP_E_INVALID_ARG
+    assert lib.ipp_refine_centroids(None, f, 2, maps, C.byref(p),
+                                    C.byref(src), 2.0, 3.0, 10, None, None,
+                                    None) == L.IPP_E_INVALID_ARG
+    assert lib.ipp_asinh_dev(None, None, None, 0, None,
+                             None) == L.IPP_E_INVALID_ARG
+    assert lib.ipp_asinh_backward_noalloc(None, None, None, None, None, 0,
+                                          1.0, 1.0,
+                                          None) == L.IPP_E_INVALID_ARG

@@ -138,3 +138,20 @@ def test_flags():
     # valid moments; forced with |xy| > sqrt(X Y))
     R, f, a, fl = kr.auto_one(img, B, 15.0, 15.0, 1.0, 1.0, 2.0)
     assert fl == kr.AUTO_BAD_SHAPE
+
+
+def test_min_q_is_the_minimum_over_the_square():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        x2, y2 = rng.uniform(0.2, 5.0, 2)
+        xy = rng.uniform(-0.9, 0.9) * math.sqrt(x2 * y2)
+        sh = kr.shape(x2, y2, xy)
+        x0, y0 = rng.uniform(-4, 4, 2)
+        x1, y1 = x0 + 1.0, y0 + 1.0
+        g = np.linspace(0, 1, 201)
+        gx, gy = np.meshgrid(x0 + g, y0 + g)
+        brute = np.min([kr.qform(sh, a, b) for a, b in
+                        zip(gx.ravel(), gy.ravel())])
+        m = kr.min_q(sh, x0, x1, y0, y1)
+        assert m <= brute + 1e-12
+        assert m >= brute - 1e-3 * (1 + brute)
