@@ -20,6 +20,9 @@ Intelligence Era"):
   candidates into objects, and cleaning.
 * ``kron``       -- Sec. 2.2.5: AUTO (Kron) photometry, the Kron radius
   and an exact ellipse-pixel overlap.
+* ``subtract``   -- Sec. 2.2.4 (Image Subtraction Function): the
+  spatially varying stamp convolution of Eq. 8-10 and the difference image
+  (the kernel fit is not part of this path).
 * ``photometry`` -- Sec. 2.2.5, last paragraph: per-object aperture
   photometry, with exact circle/pixel overlaps and a local sky annulus, and
   its adjoint (gradients with the sky clip mask held fixed).
@@ -37,7 +40,7 @@ integers) and rounded once.
 """
 from .params import Params
 from . import (background, detect, deblend, kron, photometry, stretch,
-               refine, gray)
+               refine, gray, subtract)
 
 __all__ = ["Params", "background", "detect", "photometry", "stretch",
-           "refine", "gray", "deblend", "kron"]
+           "refine", "gray", "deblend", "kron", "subtract"]
