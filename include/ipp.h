@@ -465,6 +465,45 @@ ipp_status ipp_photometry_auto(void* ctx, const ipp_frame* frames, int32_t n,
                                uint32_t* flags, void* stream);
 
 /*
+ * Stamp convolution and image subtraction (Sec. 2.2.4, Eq. 8-10).  The
+ * template frames R (aligned with the science frames I, same shapes) are
+ * convolved with the kernel
+ *   K(u, v) = sum_n a_n(x, y) exp(-(u^2 + v^2) / (2 sigma_k^2)) u^i v^j,
+ * the basis ordered by Gaussian (as given), then i = 0..order_k, then
+ * j = 0..order_k - i, u (columns) and v (rows) in [-hw, hw]; and
+ * D = (I + B) - R (x) K is written (zero where Eq. 10 holds).  a_n and the
+ * background difference B are polynomials in xn = (2x - (W-1)) / (W-1),
+ * yn likewise (0 on a one-pixel axis): sum over p = 0..d, q = 0..d-p of
+ * c_pq xn^p yn^q, coefficients in that order; each stamp (stamp x stamp
+ * pixels, partial at the right and bottom edges) uses them at its centre
+ * (the centre of its actual extent).  R is zero outside the frame.  coef:
+ * device double array, per frame nbasis * P(spatial_order) coefficients
+ * (basis by basis) then P(bkg_order), P(d) = (d+1)(d+2)/2, frames one
+ * after another.  diff[f]: device float32 h x w.  The kernel fit itself
+ * is not part of this call.  Products are summed in binary32 per kernel
+ * row and the rows in binary64.
+ */
+#define IPP_SUB_MAX_GAUSS 4
+typedef struct ipp_subtract_params {
+  int32_t half_width;         /* hw, 1..15 (10: 21 x 21 kernels)          */
+  int32_t stamp;              /* stamp size, 1..32 (21)                    */
+  int32_t n_gauss;            /* 1..4 (3)                                  */
+  int32_t spatial_order;      /* degree of a_n(x, y), 0..4 (2)             */
+  int32_t bkg_order;          /* degree of B(x, y), 0..4 (1)               */
+  int32_t order[IPP_SUB_MAX_GAUSS];  /* max i + j per Gaussian, 0..7
+                                        (6, 4, 2)                          */
+  double sigma[IPP_SUB_MAX_GAUSS];   /* widths > 0 (0.7, 1.5, 3.0)         */
+} ipp_subtract_params;
+
+void ipp_subtract_params_default(ipp_subtract_params* sp);
+/* Coefficients per frame (nbasis * P(spatial) + P(bkg)); 0 if invalid. */
+int64_t ipp_subtract_coef_count(const ipp_subtract_params* sp);
+ipp_status ipp_subtract(void* ctx, const ipp_frame* sci,
+                        const ipp_frame* tmpl, int32_t n,
+                        const ipp_subtract_params* sp, const double* coef,
+                        float* const* diff, void* stream);
+
+/*
  * Gray-scale transformations (Sec. 2.2.6): the zscale display range, point
  * maps and histogram equalization.  Frames as elsewhere (mask ignored);
  * outputs out[f] are device float32 h x w arrays with row pitch w.

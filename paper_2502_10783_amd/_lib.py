@@ -78,6 +78,13 @@ class IppAutoParams(C.Structure):
                 ("search", C.c_double)]
 
 
+class IppSubtractParams(C.Structure):
+    _fields_ = [("half_width", C.c_int32), ("stamp", C.c_int32),
+                ("n_gauss", C.c_int32), ("spatial_order", C.c_int32),
+                ("bkg_order", C.c_int32), ("order", C.c_int32 * 4),
+                ("sigma", C.c_double * 4)]
+
+
 SOURCE_COLUMNS = (
     ("frame", "int32"), ("label", "int32"), ("npix", "int32"),
     ("xmin", "int32"), ("xmax", "int32"), ("ymin", "int32"),
@@ -197,6 +204,15 @@ def lib():
                                       C.POINTER(IppAutoParams), vp, vp, vp,
                                       vp, vp]
     L.ipp_photometry_auto.restype = i32
+    L.ipp_subtract_params_default.argtypes = [
+        C.POINTER(IppSubtractParams)]
+    L.ipp_subtract_params_default.restype = None
+    L.ipp_subtract_coef_count.argtypes = [C.POINTER(IppSubtractParams)]
+    L.ipp_subtract_coef_count.restype = i64
+    L.ipp_subtract.argtypes = [vp, C.POINTER(IppFrame), C.POINTER(IppFrame),
+                               i32, C.POINTER(IppSubtractParams), vp,
+                               C.POINTER(vp), vp]
+    L.ipp_subtract.restype = i32
     L.ipp_source_moments.argtypes = [vp, C.POINTER(IppFrame), i32,
                                      C.POINTER(IppMaps), C.POINTER(IppSources),
                                      vp, vp]

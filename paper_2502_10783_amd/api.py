@@ -62,6 +62,28 @@ class DeblendParams:
         return c
 
 
+@dataclass
+class SubtractParams:
+    """Stamp convolution and subtraction parameters
+    (ipp_subtract_params)."""
+    half_width: int = 10
+    stamp: int = 21
+    sigmas: tuple = (0.7, 1.5, 3.0)
+    orders: tuple = (6, 4, 2)
+    spatial_order: int = 2
+    bkg_order: int = 1
+
+    def to_c(self) -> L.IppSubtractParams:
+        c = L.IppSubtractParams()
+        c.half_width, c.stamp = self.half_width, self.stamp
+        c.n_gauss = len(self.sigmas)
+        c.spatial_order, c.bkg_order = self.spatial_order, self.bkg_order
+        for g, (s, o) in enumerate(zip(self.sigmas, self.orders)):
+            c.sigma[g] = s
+            c.order[g] = o
+        return c
+
+
 class IppError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{L.lib().ipp_status_string(status).decode()}"
@@ -545,6 +567,31 @@ class Context:
             self.h, frames_c(frames), n, maps, C.byref(src), _ptr(mom),
             C.byref(ap), _ptr(out["kron_radius"]), _ptr(out["flux"]),
             _ptr(out["area"]), _ptr(out["flags"]), _stream()))
+        return out
+
+    def subtract(self, frames, templates, sp: SubtractParams, coef):
+        """Sec. 2.2.4: difference images D = (I + B) - R (x) K of each frame
+        I against its aligned template R; coef: float64 tensor [n, count]
+        of the kernel and background polynomial coefficients."""
+        n = len(frames)
+        spc = sp.to_c()
+        per = self.lib.ipp_subtract_coef_count(C.byref(spc))
+        if per == 0:
+            raise IppError(L.IPP_E_INVALID_ARG, "invalid subtract params")
+        if not (coef.is_cuda and coef.dtype == torch.float64 and
+                coef.is_contiguous() and coef.numel() == n * per):
+            raise ValueError(f"coef: need a contiguous float64 CUDA tensor "
+                             f"of {n} x {per} coefficients")
+        for i in range(n):
+            _check_gpu_f32(templates[i], f"template {i}")
+        if self.ws_bytes < 4096 + 64 * n:
+            self.reserve(4096 + 64 * n)
+        out = [torch.empty(f.shape, dtype=torch.float32, device=f.device)
+               for f in frames]
+        ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in out])
+        self._check(self.lib.ipp_subtract(
+            self.h, frames_c(frames), frames_c(templates), n, C.byref(spc),
+            _ptr(coef), ptrs, _stream()))
         return out
 
     def source_moments(self, frames, bkg, labels, table: SourceTable):

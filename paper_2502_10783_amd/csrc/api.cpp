@@ -1637,6 +1637,129 @@ ipp_status ipp_photometry_auto(void* ctx, const ipp_frame* frames, int32_t n,
   return IPP_OK;
 }
 
+void ipp_subtract_params_default(ipp_subtract_params* sp) {
+  if (!sp) return;
+  std::memset(sp, 0, sizeof(*sp));
+  sp->half_width = 10;
+  sp->stamp = 21;
+  sp->n_gauss = 3;
+  sp->spatial_order = 2;
+  sp->bkg_order = 1;
+  const int ord[3] = {6, 4, 2};
+  const double sig[3] = {0.7, 1.5, 3.0};
+  for (int g = 0; g < 3; ++g) {
+    sp->order[g] = ord[g];
+    sp->sigma[g] = sig[g];
+  }
+}
+
+namespace {
+std::string check_subtract(const ipp_subtract_params* sp) {
+  if (!sp) return "subtract params are NULL";
+  if (sp->half_width < 1 || sp->half_width > kSubMaxHw)
+    return "half_width must be in [1, 15]";
+  if (sp->stamp < 1 || sp->stamp > kSubMaxStamp)
+    return "stamp must be in [1, 32]";
+  if (sp->n_gauss < 1 || sp->n_gauss > kSubMaxGauss)
+    return "n_gauss must be in [1, 4]";
+  if (sp->spatial_order < 0 || sp->spatial_order > 4 || sp->bkg_order < 0 ||
+      sp->bkg_order > 4)
+    return "spatial_order and bkg_order must be in [0, 4]";
+  for (int g = 0; g < sp->n_gauss; ++g) {
+    if (sp->order[g] < 0 || sp->order[g] > kSubMaxOrder)
+      return "orders must be in [0, 7]";
+    if (!std::isfinite(sp->sigma[g]) || sp->sigma[g] <= 0)
+      return "sigmas must be finite and > 0";
+  }
+  return "";
+}
+int64_t sub_nbasis(const ipp_subtract_params* sp) {
+  int64_t nb = 0;
+  for (int g = 0; g < sp->n_gauss; ++g)
+    nb += (int64_t)(sp->order[g] + 1) * (sp->order[g] + 2) / 2;
+  return nb;
+}
+}  // namespace
+
+int64_t ipp_subtract_coef_count(const ipp_subtract_params* sp) {
+  if (!check_subtract(sp).empty()) return 0;
+  const int64_t ps = (sp->spatial_order + 1) * (sp->spatial_order + 2) / 2;
+  const int64_t pb = (sp->bkg_order + 1) * (sp->bkg_order + 2) / 2;
+  return sub_nbasis(sp) * ps + pb;
+}
+
+ipp_status ipp_subtract(void* ctx, const ipp_frame* sci,
+                        const ipp_frame* tmpl, int32_t n,
+                        const ipp_subtract_params* sp, const double* coef,
+                        float* const* diff, void* stream) {
+  IppCtx* c = (IppCtx*)ctx;
+  if (!c) return IPP_E_INVALID_ARG;
+  std::string m = check_subtract(sp);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  m = check_frames(sci, n);
+  if (m.empty()) m = check_frames(tmpl, n);
+  if (!m.empty()) return fail(c, IPP_E_INVALID_ARG, m);
+  if (!coef || !diff) return fail(c, IPP_E_INVALID_ARG,
+                                  "coef and diff are required");
+  const int64_t per = ipp_subtract_coef_count(sp);
+  std::vector<SubFrame> fr(n);
+  int64_t stamps = 0;
+  for (int i = 0; i < n; ++i) {
+    if (tmpl[i].h != sci[i].h || tmpl[i].w != sci[i].w)
+      return fail(c, IPP_E_INVALID_ARG,
+                  "template " + std::to_string(i) +
+                      " differs in shape from its frame");
+    if (!diff[i])
+      return fail(c, IPP_E_INVALID_ARG,
+                  "diff[" + std::to_string(i) + "] is NULL");
+    SubFrame& d = fr[i];
+    d.I = sci[i].pix;
+    d.R = tmpl[i].pix;
+    d.pitchI = sci[i].pitch;
+    d.pitchR = tmpl[i].pitch;
+    d.h = sci[i].h;
+    d.w = sci[i].w;
+    d.nsy = (d.h + sp->stamp - 1) / sp->stamp;
+    d.nsx = (d.w + sp->stamp - 1) / sp->stamp;
+    d.stamp0 = stamps;
+    stamps += (int64_t)d.nsy * d.nsx;
+    d.D = diff[i];
+    d.coef = coef + (int64_t)i * per;
+  }
+  const size_t need = sizeof(SubFrame) * (size_t)n;
+  if (need > c->ws_bytes)
+    return fail(c, IPP_E_WORKSPACE,
+                "workspace too small: need " + std::to_string(need) +
+                    " bytes, have " + std::to_string(c->ws_bytes));
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws, fr.data(), need, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess)
+    return fail(c, IPP_E_DEVICE, std::string("descriptor upload failed: ") +
+                                     hipGetErrorString(e));
+  ++c->ws_gen;
+  SubBasis bs;
+  std::memset(&bs, 0, sizeof(bs));
+  bs.hw = sp->half_width;
+  bs.stamp = sp->stamp;
+  bs.ngauss = sp->n_gauss;
+  bs.spatial_order = sp->spatial_order;
+  bs.bkg_order = sp->bkg_order;
+  bs.nbasis = (int32_t)sub_nbasis(sp);
+  for (int g = 0; g < sp->n_gauss; ++g) {
+    bs.order[g] = sp->order[g];
+    bs.sigma[g] = sp->sigma[g];
+  }
+  IPP_LAUNCH(c, s, "k_subtract",
+             hipLaunchKernelGGL(k_subtract,
+                                dim3((unsigned)std::min<int64_t>(stamps,
+                                                                 1 << 20)),
+                                dim3(kBlock), 0, s, (const SubFrame*)c->ws,
+                                n, bs, stamps));
+  return IPP_OK;
+}
+
 ipp_status ipp_source_moments(void* ctx, const ipp_frame* frames, int32_t n,
                               const ipp_maps* maps, const ipp_sources* src,
                               double* mom, void* stream) {

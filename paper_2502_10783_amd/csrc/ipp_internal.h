@@ -42,6 +42,29 @@ struct FrameDev {
   int32_t* objects;      // object map written by deblending, or null
 };
 
+// Stamp convolution and subtraction (k_subtract.hip).
+constexpr int kSubMaxHw = 15;       // kernel half-width
+constexpr int kSubMaxStamp = 32;    // stamp size
+constexpr int kSubMaxGauss = 4;     // Gaussians of the basis
+constexpr int kSubMaxOrder = 7;     // order i + j of each
+constexpr int kSubMaxBasis = kSubMaxGauss * (kSubMaxOrder + 1) *
+                             (kSubMaxOrder + 2) / 2;
+struct SubFrame {
+  const float* I;        // science frame
+  const float* R;        // template, same shape
+  int64_t pitchI, pitchR;
+  int32_t h, w;
+  int32_t nsy, nsx;      // stamps per column and per row
+  int64_t stamp0;        // first stamp of the frame in the batch
+  float* D;              // difference, dense h x w
+  const double* coef;    // a_n polynomials, then B's
+};
+struct SubBasis {
+  int32_t hw, stamp, ngauss, spatial_order, bkg_order, nbasis;
+  int32_t order[kSubMaxGauss];
+  double sigma[kSubMaxGauss];
+};
+
 // Frame of the gray-scale calls: input, output and the zscale sample grid.
 struct GrayFrame {
   const float* pix;

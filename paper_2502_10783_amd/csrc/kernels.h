@@ -110,6 +110,10 @@ __global__ void k_kron(Work wk, ipp_sources src, const double* mom,
                        double kfac, double rmin, double search, double* kron,
                        double* flux, double* area, uint32_t* flags);
 
+// Stamp convolution and subtraction: one workgroup per stamp.
+__global__ void k_subtract(const SubFrame* frames, int nframes, SubBasis bs,
+                           int64_t total_stamps);
+
 __global__ void k_zscale(const GrayFrame* frames, double contrast,
                          double krej, int max_iter, double* z1z2,
                          double* info);
