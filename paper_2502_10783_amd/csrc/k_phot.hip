@@ -2,16 +2,16 @@
 // aperture photometry).
 //
 // One wavefront per source, four sources per workgroup, no workgroup
-// barriers.  The wave classifies every pixel of the source's window with
-// the exact membership predicates (cheap), accumulates the aperture pixels
-// that lie wholly inside the aperture, and compacts the rest of the work
-// into its LDS slice: the aperture pixels cut by the circle, the annulus
-// values with their weights, and the annulus pixels cut by either circle.
-// The exact overlap areas (binary64; one atan2 per circle and pixel) are then
-// computed over those dense task lists with every lane busy.  The annulus
-// (value, weight) pairs are sorted in registers with a bitonic network;
-// the k-sigma clipping of the sky works on contiguous ranges of the sorted
-// values and the weighted sky sum is a sum over the final range.
+// barriers.  The wave walks the source's window with the exact membership
+// predicates (from per-column and per-row distance tables), sums the
+// pixels wholly inside the aperture, appends every annulus value to its
+// LDS slice and lists every pixel cut by one of the three circles as one
+// task per circle.  The annulus values are sorted in registers with a
+// bitonic network and the k-sigma clipping of the sky works on contiguous
+// ranges of the sorted values.  Only then are the exact overlap areas
+// (binary64) computed, one uniform code path over the dense task list with
+// every lane busy: each cut pixel adds its overlap (aperture) or the
+// difference of its annulus weight from 1 (annulus survivors) to the sums.
 #include <type_traits>
 
 #include "ipp_internal.h"
@@ -22,27 +22,174 @@ namespace ipp {
 
 namespace {
 
-constexpr int kApTasks = 320;   // aperture pixels cut by a circle, r <= 16
 constexpr int kEdges = 36;      // pixel edges per axis of a window, r <= 16
+// Pixels cut by one circle of radius r <= 16: a cut pixel's square holds
+// points inside and outside the circle, so the circle crosses it; each of
+// the circle's four monotone quarter arcs crosses at most r + 1 column and
+// r + 1 row lines, so it passes through at most 2r + 3 squares.
+constexpr int kCutCap = 8 * 16 + 16;
+constexpr int kTaskCap = 3 * kCutCap;
+
+// A source's window of pixels: columns [xa, xa + nwx), rows [ya, ya + nwy).
+// Loads take 32-bit byte offsets from a wave-uniform row base (the window's
+// first in-frame row; pitch <= 2^24 and at most 35 rows).  A window wholly
+// inside the frame needs neither clamping nor an inside test: its offsets
+// advance by constant steps.
+struct Window {
+  int xa, ya, nwx, nwy, npx, ry0, fw, fh;
+  bool interior;
+  const char* wpix;
+  const char* wbkg;
+  uint32_t pitchB, wB;
+
+  __device__ void init(const FrameDev& fr, int xa_, int xb, int ya_, int yb) {
+    xa = xa_;
+    ya = ya_;
+    nwx = xb - xa + 1;
+    nwy = yb - ya + 1;
+    npx = nwx * nwy;
+    fw = fr.w;
+    fh = fr.h;
+    ry0 = min(max(ya, 0), fr.h - 1);
+    wpix = uniform_ptr((const char*)(fr.pix + (int64_t)ry0 * fr.pitch));
+    wbkg = uniform_ptr((const char*)(fr.bkg + (int64_t)ry0 * fr.w));
+    pitchB = (uint32_t)fr.pitch * 4u;
+    wB = (uint32_t)fr.w * 4u;
+    interior = xa >= 0 && ya >= 0 && xb < fr.w && yb < fr.h;
+  }
+  // v = I - B of the in-frame pixel (px, py)
+  __device__ double value_at(int px, int py) const {
+    const uint32_t qr = (uint32_t)(py - ry0);
+    return (double)gld((const float*)(wpix + (qr * pitchB + (uint32_t)px * 4u))) -
+           (double)gld((const float*)(wbkg + (qr * wB + (uint32_t)px * 4u)));
+  }
+  // Every pixel of the window, 64 a round: visit(live, pos, ok, v) with
+  // pos = wy << 6 | wx, ok = the pixel lies in the frame and I is finite,
+  // v = I - B.  Lanes past the window's end visit with live = false (a
+  // valid position, ok = false).  The loads of kChunk rounds are issued
+  // before any is used, so their latencies overlap.
+  template <int kChunk, bool EDGE, typename F>
+  __device__ void walk_t(int lane, F&& visit) const {
+    const int dwr = kWave / nwx, dwc = kWave - (kWave / nwx) * nwx;
+    int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;  // window row, col
+    uint32_t offp = (uint32_t)wr * pitchB + (uint32_t)(xa + wc) * 4u;
+    uint32_t offb = (uint32_t)wr * wB + (uint32_t)(xa + wc) * 4u;
+    const uint32_t stepP = (uint32_t)dwr * pitchB + (uint32_t)dwc * 4u;
+    const uint32_t stepB = (uint32_t)dwr * wB + (uint32_t)dwc * 4u;
+    const uint32_t wrapP = pitchB - (uint32_t)nwx * 4u;
+    const uint32_t wrapB = wB - (uint32_t)nwx * 4u;
+    for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
+      float Iv[kChunk], Bv[kChunk];
+      int pos[kChunk];
+      bool ins[kChunk];
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (e0 + c * kWave >= npx) break;            // wave-uniform
+        const bool live = e0 + c * kWave + lane < npx;
+        pos[c] = (wr << 6) | wc;
+        if constexpr (EDGE) {
+          // loads clamped into the frame: every lane loads, no branches
+          const int px = xa + wc, py = ya + wr;
+          ins[c] = live & (px >= 0) & (px < fw) & (py >= 0) & (py < fh);
+          const uint32_t qx = (uint32_t)min(max(px, 0), fw - 1);
+          const uint32_t qr = (uint32_t)(min(max(py, 0), fh - 1) - ry0);
+          Iv[c] = gld((const float*)(wpix + (qr * pitchB + qx * 4u)));
+          Bv[c] = gld((const float*)(wbkg + (qr * wB + qx * 4u)));
+        } else {
+          // a lane past the window end loads the window's first pixel
+          ins[c] = live;
+          Iv[c] = gld((const float*)(wpix + (live ? offp : 0u)));
+          Bv[c] = gld((const float*)(wbkg + (live ? offb : 0u)));
+        }
+        wr += dwr;
+        wc += dwc;
+        offp += stepP;
+        offb += stepB;
+        if (wc >= nwx) {
+          wc -= nwx;
+          ++wr;
+          offp += wrapP;
+          offb += wrapB;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (e0 + c * kWave >= npx) break;            // wave-uniform
+        const bool live = e0 + c * kWave + lane < npx;
+        visit(live, pos[c], ins[c] & isfinite(Iv[c]),
+              (double)Iv[c] - (double)Bv[c]);
+      }
+    }
+  }
+  template <int kChunk, typename F>
+  __device__ void walk(int lane, F&& visit) const {
+    if (interior) walk_t<kChunk, false>(lane, visit);
+    else walk_t<kChunk, true>(lane, visit);
+  }
+};
+
+// Per window column and row: the squared nearest and farthest offsets from
+// the centre (a pixel's distances are sums of one of each: the same two
+// rounded squares and the same addition as computing them per pixel) and,
+// at every column (row) edge q, the roots sqrt(r^2 - min(|q|, r)^2) of the
+// three circles (aperture, outer, inner), for the exact overlaps.
+struct WinTables {
+  double2 colT[kEdges];
+  double2 rowT[kEdges];
+  double sq[3 * 2 * kEdges];       // [circle][axis][edge]
+
+  __device__ void fill(const Window& W, double cx, double cy,
+                       const ipp_params& p, int lane) {
+    const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
+    const double ro2 = p.r_out * p.r_out;
+    const int ne = (W.nwx > W.nwy ? W.nwx : W.nwy) + 1;   // <= kEdges
+    for (int e = lane; e < 2 * ne; e += kWave) {
+      const bool col = e < ne;
+      const int j = col ? e : e - ne;
+      const double a = col ? fabs((double)(W.xa + j) - cx)
+                           : fabs((double)(W.ya + j) - cy);
+      const double n = fmax(a - 0.5, 0.0), fo = a + 0.5;
+      double2 t;
+      t.x = n * n;
+      t.y = fo * fo;
+      const double q = col ? ((double)(W.xa + j) - 0.5) - cx
+                           : ((double)(W.ya + j) - 0.5) - cy;
+      const int ax = col ? 0 : kEdges;
+      if (j < kEdges) {
+        (col ? colT : rowT)[j] = t;
+        sq[ax + j] = edge_root(q, p.r_ap, ra2);
+        sq[2 * kEdges + ax + j] = edge_root(q, p.r_out, ro2);
+        sq[4 * kEdges + ax + j] = edge_root(q, p.r_in, ri2);
+      }
+    }
+  }
+  // squared nearest and farthest distance of the pixel at pos (a position
+  // past the window's end reads a valid row of the table)
+  __device__ void dist2(int pos, double* near2, double* far2) const {
+    const double2 tc = colT[pos & 63];
+    const double2 tr = rowT[min(pos >> 6, kEdges - 1)];
+    *near2 = tc.x + tr.x;
+    *far2 = tc.y + tr.y;
+  }
+};
+
+// Circle of a task: 0 the aperture, 1 the outer, 2 the inner annulus circle.
+__device__ __forceinline__ void task_circle(const ipp_params& p, int c,
+                                            double* r, double* r2) {
+  const double rr = c == 0 ? p.r_ap : (c == 1 ? p.r_out : p.r_in);
+  *r = rr;
+  *r2 = rr * rr;
+}
 
 template <int NS>
 struct ApLds {
-  double pv[NS];                // annulus values
-  double pw[NS];                // annulus weights
-  // exact-overlap tasks: kind << 28 | annulus slot << 12 | wy << 6 | wx
-  // (kind 0: cut by the aperture; 1: cut by the outer circle only; 2: by
-  // the inner circle only; 3: by both)
-  // the task list is consumed before the annulus values are sorted; the
-  // sort's transposes and the sorted values then use the same space
-  union {
-    struct {
-      int tk[NS + kApTasks];
-      // square roots at the window's column and row edges for the
-      // aperture, outer and inner circle: [circle][axis][edge]
-      double sq[3 * 2 * kEdges];
-    };
-    double xs[NS + kWave];
-  };
+  // the annulus values as they are found; once read into registers, the
+  // sort's transposes and then the sorted values
+  double xs[NS + kWave];
+  // pixels cut by a circle: circle << 12 | wy << 6 | wx (circle 0: the
+  // aperture, 1: the outer and 2: the inner annulus circle)
+  int tk[kTaskCap];
+  WinTables T;
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -212,7 +359,11 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   constexpr int PL = NS / kWave;
   constexpr int P = PL == 4 ? 2 : (PL == 8 ? 3 : 4);
   static_assert((1 << P) == PL, "NS is 256, 512 or 1024");
-  const int lane = threadIdx.x & (kWave - 1);
+  // the lane number made opaque to the compiler at every row: addresses
+  // derived from it are formed where they are used instead of being kept
+  // in registers across the whole row loop
+  int lane = threadIdx.x & (kWave - 1);
+  asm volatile("" : "+v"(lane));
   const int f = src.frame[row];
   const double cx = src.x[row], cy = src.y[row];
   const bool fok = f >= 0 && f < wk.nframes;
@@ -231,225 +382,66 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   }
   const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
   // window bounds: wave-uniform values, kept in scalar registers
-  const int xa = __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5));
-  const int xb = __builtin_amdgcn_readfirstlane((int)floor(cx + R + 0.5));
-  const int ya = __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5));
-  const int yb = __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5));
-  const int nwx = xb - xa + 1, npx = nwx * (yb - ya + 1);
-
-  // ---- classify the window; compact the work -------------------------
-  // Per pixel: the exact membership predicates, the value I - B and a place
-  // in one of the compacted lists.  The count of pixels wholly inside the
-  // aperture and the off-edge flags are wave-uniform (ballots).
-  uint32_t flags = 0;                  // wave-uniform
-  int nfull = 0;                       // pixels wholly inside the aperture
-  double a_ap = 0.0, raw = 0.0;
-  int nann = 0, ntk = 0;
+  Window W;
+  W.init(fr, __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5)),
+         __builtin_amdgcn_readfirstlane((int)floor(cx + R + 0.5)),
+         __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5)),
+         __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5)));
   // squared radii as the membership predicates form them
   const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
   const double ro2 = p.r_out * p.r_out;
-  const int dwr = kWave / nwx, dwc = kWave - (kWave / nwx) * nwx;
-  // Row base of the window's first in-frame row (wave-uniform); loads take
-  // 32-bit byte offsets from it (pitch <= 2^24, at most 35 rows).
-  const int ry0 = min(max(ya, 0), fr.h - 1);
-  const char* wpix =
-      uniform_ptr((const char*)(fr.pix + (int64_t)ry0 * fr.pitch));
-  const char* wbkg = uniform_ptr((const char*)(fr.bkg + (int64_t)ry0 * fr.w));
-  const uint32_t pitchB = (uint32_t)fr.pitch * 4u, wB = (uint32_t)fr.w * 4u;
-  // A window wholly inside the frame needs neither clamping nor an inside
-  // test: its offsets advance by constant steps.
-  const bool interior = xa >= 0 && ya >= 0 && xb < fr.w && yb < fr.h;
-
-  // Squared nearest and farthest offsets of every window column and row
-  // from the centre (the pixel's distances are sums of one of each: the
-  // same two rounded squares and the same addition as computing them per
-  // pixel).  They occupy the edge-root table, which is filled only after
-  // the classification.
-  double2* colT = (double2*)L.sq;              // [kEdges]
-  double2* rowT = colT + kEdges;               // [kEdges]
-  for (int e = lane; e < 2 * kEdges; e += kWave) {
-    const bool col = e < kEdges;
-    const int j = col ? e : e - kEdges;
-    const double a = col ? fabs((double)(xa + j) - cx)
-                         : fabs((double)(ya + j) - cy);
-    const double n = fmax(a - 0.5, 0.0), fo = a + 0.5;
-    double2 t;
-    t.x = n * n;
-    t.y = fo * fo;
-    (col ? colT : rowT)[j] = t;
-  }
+  L.T.fill(W, cx, cy, p, lane);
   wave_lds_sync();
 
-  auto classify = [&](auto edge_tag) {
-    constexpr bool EDGE = decltype(edge_tag)::value;
-    int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;  // window row, col
-    uint32_t offp = (uint32_t)wr * pitchB + (uint32_t)(xa + wc) * 4u;
-    uint32_t offb = (uint32_t)wr * wB + (uint32_t)(xa + wc) * 4u;
-    const uint32_t stepP = (uint32_t)dwr * pitchB + (uint32_t)dwc * 4u;
-    const uint32_t stepB = (uint32_t)dwr * wB + (uint32_t)dwc * 4u;
-    const uint32_t wrapP = pitchB - (uint32_t)nwx * 4u;
-    const uint32_t wrapB = wB - (uint32_t)nwx * 4u;
-    // Chunks of kChunk rounds of 64 pixels: all loads of a chunk are issued
-    // before any is used, so their latencies overlap.
-    constexpr int kChunk = 8;
-    for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
-      float Iv[kChunk], Bv[kChunk];
-      uint32_t st[kChunk];
-      int pos[kChunk];
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        if (e0 + c * kWave >= npx) break;            // wave-uniform
-        const int e = e0 + c * kWave + lane;
-        const int px = xa + wc, py = ya + wr;
-        const bool live = e < npx;
-        pos[c] = (wr << 6) | wc;
-        // nearest and farthest point of the pixel square (touches / within)
-        // (a lane past the window end reads a valid row of the table)
-        const double2 tc = colT[wc], tr = rowT[min(wr, kEdges - 1)];
-        const double near2 = tc.x + tr.x, far2 = tc.y + tr.y;
-        // (bitwise logic: no branches)
-        const bool in_ap = live & (near2 < ra2);
-        const bool in_ann = live & (near2 < ro2) & !(far2 <= ri2);
-        bool inside = true;
-        if constexpr (EDGE) {
-          // loads clamped into the frame: every lane loads, no branches
-          inside = (px >= 0) & (px < fr.w) & (py >= 0) & (py < fr.h);
-          const uint32_t qx = (uint32_t)min(max(px, 0), fr.w - 1);
-          const uint32_t qr = (uint32_t)(min(max(py, 0), fr.h - 1) - ry0);
-          Iv[c] = gld((const float*)(wpix + (qr * pitchB + qx * 4u)));
-          Bv[c] = gld((const float*)(wbkg + (qr * wB + qx * 4u)));
-        } else {
-          // a lane past the window end loads the window's first pixel
-          Iv[c] = gld((const float*)(wpix + (live ? offp : 0u)));
-          Bv[c] = gld((const float*)(wbkg + (live ? offb : 0u)));
-        }
-        st[c] = (uint32_t)in_ap | ((uint32_t)in_ann << 1) |
-                ((uint32_t)inside << 2) | ((uint32_t)(far2 <= ra2) << 3) |
-                ((uint32_t)!(far2 <= ro2) << 4) |
-                ((uint32_t)(near2 < ri2) << 5);
-        wr += dwr;
-        wc += dwc;
-        offp += stepP;
-        offb += stepB;
-        if (wc >= nwx) {
-          wc -= nwx;
-          ++wr;
-          offp += wrapP;
-          offb += wrapB;
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        if (e0 + c * kWave >= npx) break;            // wave-uniform
-        const bool in_ap = st[c] & 1u, in_ann = st[c] & 2u;
-        const bool ok = ((st[c] & 4u) != 0) & isfinite(Iv[c]);
-        const double v = (double)Iv[c] - (double)Bv[c];
-        if (ballot(in_ap & !ok)) flags |= IPP_SRC_APERTURE_OFF_EDGE;
-        if (ballot(in_ann & !ok)) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
-        const bool whole = (st[c] & 8u) != 0;
-        const bool full = in_ap & ok & whole;
-        const bool ap_cut = in_ap & ok & !whole;
-        const bool ann = in_ann & ok;
-        const bool ann_cut = ann & ((st[c] & 48u) != 0);
-        nfull += __popcll(ballot(full));
-        if (full) raw += v;
-        const uint64_t b1 = ballot(ap_cut);
-        if (ap_cut) {
-          const int s = ntk + lanes_before(b1);
-          if (s < NS + kApTasks) L.tk[s] = pos[c];
-        }
-        ntk += __popcll(b1);
-        const uint64_t b2 = ballot(ann);
-        int slot = 0;
-        if (ann) {
-          slot = nann + lanes_before(b2);
-          if (slot < NS) {
-            L.pv[slot] = v;
-            L.pw[slot] = 1.0;
-          }
-        }
-        nann += __popcll(b2);
-        const uint64_t b3 = ballot(ann_cut);
-        if (ann_cut) {
-          const int s = ntk + lanes_before(b3);
-          const int kind = (int)((st[c] >> 4) & 3u);
-          if (s < NS + kApTasks && slot < NS)
-            L.tk[s] = (kind << 28) | (slot << 12) | pos[c];
-        }
-        ntk += __popcll(b3);
-      }
+  // ---- walk the window: sums, annulus values, cut pixels ---------------
+  int nfull = 0;                       // pixels wholly inside the aperture
+  int nann = 0, ntk = 0;               // wave-uniform list lengths
+  double raw = 0.0;                    // per lane: sum of v over them
+  bool bad_ap = false, bad_ann = false;
+  W.walk<4>(lane, [&](bool live, int q, bool ok, double v) {
+    double near2, far2;
+    L.T.dist2(q, &near2, &far2);
+    const bool in_ap = live & (near2 < ra2);
+    const bool in_ann = live & (near2 < ro2) & !(far2 <= ri2);
+    bad_ap |= in_ap & !ok;
+    bad_ann |= in_ann & !ok;
+    const bool ap_whole = far2 <= ra2;
+    const bool full = in_ap & ok & ap_whole;
+    nfull += __popcll(ballot(full));
+    if (full) raw += v;
+    const bool ann = in_ann & ok;
+    const uint64_t ba = ballot(ann);
+    if (ann) {
+      const int s = nann + lanes_before(ba);
+      if (s < NS) L.xs[s] = v;
     }
-  };
-  if (interior) classify(std::false_type{});
-  else classify(std::true_type{});
+    nann += __popcll(ba);
+    // one task per circle that cuts the pixel
+    const bool c0 = in_ap & ok & !ap_whole;
+    const bool c1 = ann & !(far2 <= ro2);
+    const bool c2 = ann & (near2 < ri2);
+    const uint64_t b0 = ballot(c0), b1 = ballot(c1), b2 = ballot(c2);
+    if (c0) {
+      const int s = ntk + lanes_before(b0);
+      if (s < kTaskCap) L.tk[s] = q;
+    }
+    ntk += __popcll(b0);
+    if (c1) {
+      const int s = ntk + lanes_before(b1);
+      if (s < kTaskCap) L.tk[s] = (1 << 12) | q;
+    }
+    ntk += __popcll(b1);
+    if (c2) {
+      const int s = ntk + lanes_before(b2);
+      if (s < kTaskCap) L.tk[s] = (2 << 12) | q;
+    }
+    ntk += __popcll(b2);
+  });
   if (nann > NS) nann = NS;            // not reachable: NS bounds the ring
-  if (ntk > NS + kApTasks) ntk = NS + kApTasks;  // not reachable either
-  wave_lds_sync();
-
-  // ---- exact overlaps over one dense task list ---------------------------
-  // Every lane computes one overlap per task (two only for a pixel cut by
-  // both annulus circles), whatever circle the task belongs to.
-  // The square roots depend on one pixel edge and one circle each: they
-  // are taken once per window edge (the window spans at most 34 pixels).
-  {
-    const double r2a = p.r_ap * p.r_ap, r2o = p.r_out * p.r_out;
-    const double r2i = p.r_in * p.r_in;
-    for (int e = lane; e < 6 * kEdges; e += kWave) {
-      const int c = e / (2 * kEdges), j = e % kEdges;
-      const bool col = (e / kEdges) % 2 == 0;
-      const double r = c == 0 ? p.r_ap : (c == 1 ? p.r_out : p.r_in);
-      const double r2 = c == 0 ? r2a : (c == 1 ? r2o : r2i);
-      const double q = col ? ((double)(xa + j) - 0.5) - cx
-                           : ((double)(ya + j) - 0.5) - cy;
-      L.sq[e] = edge_root(q, r, r2);
-    }
-  }
-  wave_lds_sync();
-  {
-    const double r2a = p.r_ap * p.r_ap, r2o = p.r_out * p.r_out;
-    const double r2i = p.r_in * p.r_in;
-    // overlap of a task pixel with circle c (0 aperture, 1 outer, 2 inner)
-    auto overlap_c = [&](int c, double r, double r2, int wx, int wy,
-                         const double* coef) {
-      const int px = xa + wx, py = ya + wy;
-      if (!touches(cx, cy, r, px, py)) return 0.0;
-      if (within(cx, cy, r, px, py)) return 1.0;
-      const double* sq = L.sq + c * 2 * kEdges;
-      return overlap_cut(cx, cy, r, r2, px, py, sq[wx], sq[wx + 1],
-                         sq[kEdges + wy], sq[kEdges + wy + 1], coef);
-    };
-    for (int j = lane; j < ntk; j += kWave) {
-      // the series coefficients are read where they are used (an offset the
-      // compiler cannot hoist keeps them out of registers across the loop)
-      int co = 0;
-      asm volatile("" : "+s"(co));
-      const double* coef = atan_lds + co;
-      const int t = L.tk[j];
-      const int kind = t >> 28, slot = (t >> 12) & 0x3FF;
-      const int wx = t & 63, wy = (t >> 6) & 63;
-      const int px = xa + wx, py = ya + wy;
-      const int c = kind == 0 ? 0 : (kind == 2 ? 2 : 1);
-      const double r = kind == 0 ? p.r_ap : (kind == 2 ? p.r_in : p.r_out);
-      const double r2 = kind == 0 ? r2a : (kind == 2 ? r2i : r2o);
-      double w = overlap_c(c, r, r2, wx, wy, coef);
-      if (kind == 0) {
-        // only the aperture needs the value here (annulus values are in
-        // the value list already)
-        const uint32_t qr = (uint32_t)(py - ry0);
-        const float I =
-            gld((const float*)(wpix + (qr * pitchB + (uint32_t)px * 4u)));
-        const double v =
-            (double)I -
-            (double)gld((const float*)(wbkg + (qr * wB + (uint32_t)px * 4u)));
-        a_ap += w;
-        raw += w * v;
-      } else {
-        if (kind == 3) w -= overlap_c(2, p.r_in, r2i, wx, wy, coef);
-        else if (kind == 2) w = 1.0 - w;
-        L.pw[slot] = w;
-      }
-    }
-  }
+  if (ntk > kTaskCap) ntk = kTaskCap;  // not reachable either
+  uint32_t flags = 0;                  // wave-uniform
+  if (ballot(bad_ap)) flags |= IPP_SRC_APERTURE_OFF_EDGE;
+  if (ballot(bad_ann)) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
   wave_lds_sync();
 
   // ---- sort the annulus values ------------------------------------------
@@ -457,8 +449,9 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
 #pragma unroll
   for (int k = 0; k < PL; ++k) {
     const int e = lane * PL + k;
-    sv[k] = e < nann ? L.pv[e] : __builtin_inf();
+    sv[k] = e < nann ? L.xs[e] : __builtin_inf();
   }
+  wave_lds_sync();                     // read before the network writes
   wave_sort<P>(sv, L.xs, lane);
 
   // ---- k-sigma clipping on the sorted range [a, bnd) ---------------------
@@ -512,21 +505,52 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     a += cl;
     bnd -= ch;
   }
-  // the survivors are the values in [vlo, vhi] (clipping is by value)
+  // the survivors are the values in [vlo, vhi] (clipping is by value);
+  // with weight 1 each they sum to su
   double vlo = 0.0, vhi = -1.0;
   if (bnd > a) { vlo = sorted_at<P>(L.xs, a); vhi = sorted_at<P>(L.xs, bnd - 1); }
-  double num = 0.0, den = 0.0;
-  for (int j = lane; j < nann; j += kWave) {
-    const double v = L.pv[j], w = L.pw[j];
-    if (v >= vlo && v <= vhi) {
-      num += w * v;
-      den += w;
+  double su = 0.0;
+#pragma unroll
+  for (int k = 0; k < PL; ++k) {
+    const int e = lane * PL + k;
+    su += (e >= a && e < bnd) ? sv[k] : 0.0;
+  }
+  su = wave_sum(su);                   // before the sorted registers die
+
+  // ---- exact overlaps of the cut pixels ----------------------------------
+  // One overlap per task, whatever circle it belongs to.  An aperture task
+  // adds w and w v; an annulus task of a survivor corrects its weight 1:
+  // by w - 1 for the outer circle and by -w for the inner one (a pixel cut
+  // by both gets w_out - w_in).
+  double acut = 0.0, dnum = 0.0, dden = 0.0;
+  for (int j = lane; j < ntk; j += kWave) {
+    // the series coefficients are read where they are used (an offset the
+    // compiler cannot hoist keeps them out of registers across the loop)
+    int co = 0;
+    asm volatile("" : "+s"(co));
+    const double* coef = atan_lds + co;
+    const int t = L.tk[j];
+    const int c = t >> 12, wx = t & 63, wy = (t >> 6) & 63;
+    const int px = W.xa + wx, py = W.ya + wy;
+    double r, r2;
+    task_circle(p, c, &r, &r2);
+    const double* sq = L.T.sq + c * 2 * kEdges;
+    const double w = overlap_cut(cx, cy, r, r2, px, py, sq[wx], sq[wx + 1],
+                                 sq[kEdges + wy], sq[kEdges + wy + 1], coef);
+    const double v = W.value_at(px, py);
+    if (c == 0) {
+      acut += w;
+      raw += w * v;
+    } else if (v >= vlo && v <= vhi) {
+      const double dw = c == 1 ? w - 1.0 : -w;
+      dden += dw;
+      dnum += dw * v;
     }
   }
-  num = wave_sum(num);
-  den = wave_sum(den);
-  a_ap = (double)nfull + wave_sum(a_ap);
+  const double a_ap = (double)nfull + wave_sum(acut);
   raw = wave_sum(raw);
+  const double num = su + wave_sum(dnum);
+  const double den = (double)(bnd - a) + wave_sum(dden);
   if (lane == 0) {
     double sky = 0.0;
     if (den > 0.0) sky = num / den; else flags |= IPP_SRC_NO_SKY;
@@ -545,7 +569,7 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
 // NS: sort size (>= the annulus pixel count bound).
 template <int NS>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_aperture_t(
+__attribute__((amdgpu_waves_per_eu(NS <= 512 ? 4 : 1))) void k_aperture_t(
     Work wk, ipp_params p,
                                                        ipp_sources src,
                                                        double* sky_lohi) {
@@ -587,99 +611,13 @@ namespace {
 
 template <int NS>
 struct BwLds {
-  // cut pixels: kind << 28 | wy << 6 | wx (kind 0: aperture, 1: annulus
-  // survivor), and their weights
-  int tk[NS + kApTasks];
-  double tw[NS + kApTasks];
-  double sq[3 * 2 * kEdges];     // edge square roots, as in the forward
+  // pixels cut by a circle: circle << 12 | wy << 6 | wx (circle 0: the
+  // aperture, 1: the outer and 2: the inner circle of a survivor), and the
+  // pixel weight each adds (w, w - 1, -w)
+  int tk[kTaskCap];
+  double tw[kTaskCap];
+  WinTables T;
 };
-
-// Per pixel of a source window, round by round (64 pixels): its window
-// position, the exact membership distances and its two values.  Windows
-// inside the frame load through 32-bit offsets advanced by constant steps;
-// others through offsets clamped into the frame.
-struct WinWalk {
-  int xa, ya, nwx, npx, ry0;
-  bool interior;
-  const char* wpix;
-  const char* wbkg;
-  uint32_t pitchB, wB, stepP, stepB, wrapP, wrapB;
-  int w, h, dwr, dwc;
-  int wr, wc;
-  uint32_t offp, offb;
-
-  __device__ void init(const FrameDev& fr, int xa_, int xb, int ya_, int yb,
-                       int lane) {
-    xa = xa_;
-    ya = ya_;
-    nwx = xb - xa + 1;
-    npx = nwx * (yb - ya + 1);
-    w = fr.w;
-    h = fr.h;
-    ry0 = min(max(ya, 0), fr.h - 1);
-    wpix = uniform_ptr((const char*)(fr.pix + (int64_t)ry0 * fr.pitch));
-    wbkg = uniform_ptr((const char*)(fr.bkg + (int64_t)ry0 * fr.w));
-    pitchB = (uint32_t)fr.pitch * 4u;
-    wB = (uint32_t)fr.w * 4u;
-    interior = xa >= 0 && ya >= 0 && xb < fr.w && yb < fr.h;
-    dwr = kWave / nwx;
-    dwc = kWave - dwr * nwx;
-    stepP = (uint32_t)dwr * pitchB + (uint32_t)dwc * 4u;
-    stepB = (uint32_t)dwr * wB + (uint32_t)dwc * 4u;
-    wrapP = pitchB - (uint32_t)nwx * 4u;
-    wrapB = wB - (uint32_t)nwx * 4u;
-    wr = lane / nwx;
-    wc = lane - wr * nwx;
-    offp = (uint32_t)wr * pitchB + (uint32_t)(xa + wc) * 4u;
-    offb = (uint32_t)wr * wB + (uint32_t)(xa + wc) * 4u;
-  }
-  // values of the current pixel; inside: the pixel lies in the frame
-  __device__ void load(bool live, float* I, float* B, bool* inside) const {
-    const int px = xa + wc, py = ya + wr;
-    if (interior) {
-      *inside = true;
-      *I = gld((const float*)(wpix + (live ? offp : 0u)));
-      *B = gld((const float*)(wbkg + (live ? offb : 0u)));
-    } else {
-      *inside = (px >= 0) & (px < w) & (py >= 0) & (py < h);
-      const uint32_t qx = (uint32_t)min(max(px, 0), w - 1);
-      const uint32_t qr = (uint32_t)(min(max(py, 0), h - 1) - ry0);
-      *I = gld((const float*)(wpix + (qr * pitchB + qx * 4u)));
-      *B = gld((const float*)(wbkg + (qr * wB + qx * 4u)));
-    }
-  }
-  __device__ void advance() {
-    wr += dwr;
-    wc += dwc;
-    offp += stepP;
-    offb += stepB;
-    if (wc >= nwx) {
-      wc -= nwx;
-      ++wr;
-      offp += wrapP;
-      offb += wrapB;
-    }
-  }
-  // value of window pixel (wx, wy) (in the frame)
-  __device__ double value_at(int wx, int wy) const {
-    const uint32_t qr = (uint32_t)(ya + wy - ry0);
-    const uint32_t qx = (uint32_t)(xa + wx);
-    return (double)gld((const float*)(wpix + (qr * pitchB + qx * 4u))) -
-           (double)gld((const float*)(wbkg + (qr * wB + qx * 4u)));
-  }
-};
-
-// Nearest and farthest squared distance of window pixel (px, py) from the
-// centre (the membership predicates compare them with r^2).
-__device__ __forceinline__ void pixel_dist2(double cx, double cy, int px,
-                                            int py, double* near2,
-                                            double* far2) {
-  const double ax = fabs((double)px - cx), ay = fabs((double)py - cy);
-  const double nx = fmax(ax - 0.5, 0.0), ny = fmax(ay - 0.5, 0.0);
-  const double fx = ax + 0.5, fy = ay + 0.5;
-  *near2 = nx * nx + ny * ny;
-  *far2 = fx * fx + fy * fy;
-}
 
 template <int NS>
 __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
@@ -687,7 +625,8 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
                                  const double* sky_lohi, const double* gF,
                                  double* dxy, long long row, BwLds<NS>& L,
                                  const double* atan_lds) {
-  const int lane = threadIdx.x & (kWave - 1);
+  int lane = threadIdx.x & (kWave - 1);
+  asm volatile("" : "+v"(lane));
   const int f = src.frame[row];
   const double cx = src.x[row], cy = src.y[row];
   const double g = gF[row];
@@ -700,88 +639,58 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
   const double vlo = sky_lohi[2 * row], vhi = sky_lohi[2 * row + 1];
   const double R = p.r_ap > p.r_out ? p.r_ap : p.r_out;
-  // window bounds: wave-uniform values, kept in scalar registers
-  const int xa = __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5));
-  const int xb = __builtin_amdgcn_readfirstlane((int)floor(cx + R + 0.5));
-  const int ya = __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5));
-  const int yb = __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5));
+  Window W;
+  W.init(fr, __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5)),
+         __builtin_amdgcn_readfirstlane((int)floor(cx + R + 0.5)),
+         __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5)),
+         __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5)));
   const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
   const double ro2 = p.r_out * p.r_out;
+  L.T.fill(W, cx, cy, p, lane);
+  wave_lds_sync();
 
   // ---- pass 1: whole pixels summed, cut pixels listed ------------------
-  // (aperture members: the square meets the disk; annulus survivors: it
+  // Aperture members: the square meets the disk; annulus survivors: it
   // meets the outer disk, is not inside the inner one, and its value lies
-  // in the forward's [vlo, vhi])
-  WinWalk W0;
-  W0.init(fr, xa, xb, ya, yb, lane);
-  double A = 0.0, Wt = 0.0, Sv = 0.0;
-  int ntk = 0;
-  // chunks of kBChunk rounds of 64 pixels: the loads of a chunk are all
-  // issued before any is used
-  constexpr int kBChunk = 4;
-  for (int e00 = 0; e00 < W0.npx; e00 += kBChunk * kWave) {
-  float Iv[kBChunk], Bv[kBChunk];
-  bool insv[kBChunk];
-  int posv[kBChunk];
-#pragma unroll
-  for (int c = 0; c < kBChunk; ++c) {
-    if (e00 + c * kWave >= W0.npx) break;          // wave-uniform
-    posv[c] = (W0.wr << 6) | W0.wc;
-    W0.load(e00 + c * kWave + lane < W0.npx, &Iv[c], &Bv[c], &insv[c]);
-    W0.advance();
-  }
-#pragma unroll
-  for (int c = 0; c < kBChunk; ++c) {
-    const int e0 = e00 + c * kWave;
-    if (e0 >= W0.npx) break;                       // wave-uniform
-    const bool live = e0 + lane < W0.npx;
-    const int pos = posv[c];
-    const int px = xa + (pos & 63), py = ya + (pos >> 6);
-    const float I = Iv[c], B = Bv[c];
-    const bool inside = insv[c];
+  // in the forward's [vlo, vhi].  Every survivor counts with weight 1 here;
+  // its cut tasks correct that weight.
+  int nwhole = 0, nsurv = 0, ntk = 0;  // wave-uniform
+  double Sv = 0.0;                     // per lane: sum of survivor values
+  W.walk<4>(lane, [&](bool live, int q, bool ok, double v) {
     double near2, far2;
-    pixel_dist2(cx, cy, px, py, &near2, &far2);
-    const bool ok = live & inside & isfinite(I);
-    const double v = (double)I - (double)B;
-    const bool in_ap = ok & (near2 < ra2);
-    const bool in_ann = ok & (near2 < ro2) & !(far2 <= ri2) & (v >= vlo) &
-                        (v <= vhi);
-    const bool ap_whole = in_ap & (far2 <= ra2);
-    const bool ann_whole = in_ann & (far2 <= ro2) & !(near2 < ri2);
-    A += ap_whole ? 1.0 : 0.0;
-    if (ann_whole) {
-      Wt += 1.0;
-      Sv += v;
+    L.T.dist2(q, &near2, &far2);
+    const bool in_ap = live & ok & (near2 < ra2);
+    const bool surv = live & ok & (near2 < ro2) & !(far2 <= ri2) &
+                      (v >= vlo) & (v <= vhi);
+    const bool ap_whole = far2 <= ra2;
+    nwhole += __popcll(ballot(in_ap & ap_whole));
+    nsurv += __popcll(ballot(surv));
+    if (surv) Sv += v;
+    const bool c0 = in_ap & !ap_whole;
+    const bool c1 = surv & !(far2 <= ro2);
+    const bool c2 = surv & (near2 < ri2);
+    const uint64_t b0 = ballot(c0), b1 = ballot(c1), b2 = ballot(c2);
+    if (c0) {
+      const int s = ntk + lanes_before(b0);
+      if (s < kTaskCap) L.tk[s] = q;
     }
-    const bool ap_cut = in_ap & !ap_whole, ann_cut = in_ann & !ann_whole;
-    const uint64_t b1 = ballot(ap_cut);
-    if (ap_cut) {
+    ntk += __popcll(b0);
+    if (c1) {
       const int s = ntk + lanes_before(b1);
-      if (s < NS + kApTasks) L.tk[s] = pos;
+      if (s < kTaskCap) L.tk[s] = (1 << 12) | q;
     }
     ntk += __popcll(b1);
-    const uint64_t b2 = ballot(ann_cut);
-    if (ann_cut) {
+    if (c2) {
       const int s = ntk + lanes_before(b2);
-      if (s < NS + kApTasks) L.tk[s] = (1 << 28) | pos;
+      if (s < kTaskCap) L.tk[s] = (2 << 12) | q;
     }
     ntk += __popcll(b2);
-  }
-  }
-  if (ntk > NS + kApTasks) ntk = NS + kApTasks;   // not reachable
-  // edge square roots of the window for the three circles
-  for (int e = lane; e < 6 * kEdges; e += kWave) {
-    const int c = e / (2 * kEdges), j = e % kEdges;
-    const bool col = (e / kEdges) % 2 == 0;
-    const double r = c == 0 ? p.r_ap : (c == 1 ? p.r_out : p.r_in);
-    const double r2 = c == 0 ? ra2 : (c == 1 ? ro2 : ri2);
-    const double q = col ? ((double)(xa + j) - 0.5) - cx
-                         : ((double)(ya + j) - 0.5) - cy;
-    L.sq[e] = edge_root(q, r, r2);
-  }
+  });
+  if (ntk > kTaskCap) ntk = kTaskCap;   // not reachable
   wave_lds_sync();
 
   // ---- pass 2: the cut pixels' weights and centre derivatives ----------
+  double A = 0.0, Wt = 0.0;                            // cut-pixel parts
   double tvx = 0.0, tvy = 0.0, tax = 0.0, tay = 0.0;   // aperture terms
   double svx = 0.0, svy = 0.0, swx = 0.0, swy = 0.0;   // sky terms
   for (int j = lane; j < ntk; j += kWave) {
@@ -789,40 +698,39 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
     asm volatile("" : "+s"(co));
     const double* coef = atan_lds + co;
     const int t = L.tk[j];
-    const int wx = t & 63, wy = (t >> 6) & 63;
-    const int px = xa + wx, py = ya + wy;
-    const double v = W0.value_at(wx, wy);
-    // overlap and its centre derivative for circle c
-    auto circle = [&](int c, double r, double r2, double* gx, double* gy) {
-      const double* sq = L.sq + c * 2 * kEdges;
-      const double hx0 = sq[wx], hx1 = sq[wx + 1];
-      const double xs0 = sq[kEdges + wy], xs1 = sq[kEdges + wy + 1];
-      overlap_grad_roots(cx, cy, px, py, hx0, hx1, xs0, xs1, gx, gy);
-      if (!touches(cx, cy, r, px, py)) return 0.0;
-      if (within(cx, cy, r, px, py)) return 1.0;
-      return overlap_cut(cx, cy, r, r2, px, py, hx0, hx1, xs0, xs1, coef);
-    };
-    double w, gx, gy;
-    if ((t >> 28) == 0) {
-      w = circle(0, p.r_ap, ra2, &gx, &gy);
+    const int c = t >> 12, wx = t & 63, wy = (t >> 6) & 63;
+    const int px = W.xa + wx, py = W.ya + wy;
+    double r, r2;
+    task_circle(p, c, &r, &r2);
+    const double* sq = L.T.sq + c * 2 * kEdges;
+    const double hx0 = sq[wx], hx1 = sq[wx + 1];
+    const double xs0 = sq[kEdges + wy], xs1 = sq[kEdges + wy + 1];
+    double gx, gy;
+    overlap_grad_roots(cx, cy, px, py, hx0, hx1, xs0, xs1, &gx, &gy);
+    const double w = overlap_cut(cx, cy, r, r2, px, py, hx0, hx1, xs0, xs1,
+                                 coef);
+    const double v = W.value_at(px, py);
+    double tw;
+    if (c == 0) {
       A += w;
       tvx += v * gx; tvy += v * gy;
       tax += gx; tay += gy;
+      tw = w;
     } else {
-      double ix, iy;
-      w = circle(1, p.r_out, ro2, &gx, &gy) -
-          circle(2, p.r_in, ri2, &ix, &iy);
-      gx -= ix;
-      gy -= iy;
-      Wt += w;
-      Sv += w * v;
+      // the inner circle's overlap and its derivative enter negated
+      const double s = c == 1 ? 1.0 : -1.0;
+      tw = c == 1 ? w - 1.0 : -w;
+      gx *= s;
+      gy *= s;
+      Wt += tw;
+      Sv += tw * v;
       svx += v * gx; svy += v * gy;
       swx += gx; swy += gy;
     }
-    L.tw[j] = w;
+    L.tw[j] = tw;
   }
-  A = wave_sum(A);
-  Wt = wave_sum(Wt);
+  A = (double)nwhole + wave_sum(A);
+  Wt = (double)nsurv + wave_sum(Wt);
   Sv = wave_sum(Sv);
   tvx = wave_sum(tvx); tvy = wave_sum(tvy);
   tax = wave_sum(tax); tay = wave_sum(tay);
@@ -841,32 +749,25 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   float* dp = fr.dpix;
   if (!dp) { wave_lds_sync(); return; }
 
-  // ---- pass 3: scatter dL/dv (whole pixels, then the cut ones) ---------
+  // ---- pass 3: scatter dL/dv ---------------------------------------------
+  // whole aperture pixels get g, every survivor ks (its weight 1); the cut
+  // tasks add g w, ks (w - 1) or -ks w
   const double ks = Wt > 0.0 ? -g * A / Wt : 0.0;
-  WinWalk W1;
-  W1.init(fr, xa, xb, ya, yb, lane);
-  for (int e0 = 0; e0 < W1.npx; e0 += kWave) {
-    const bool live = e0 + lane < W1.npx;
-    const int px = xa + W1.wc, py = ya + W1.wr;
-    float I, B;
-    bool inside;
-    W1.load(live, &I, &B, &inside);
+  W.walk<4>(lane, [&](bool live, int q, bool ok, double v) {
     double near2, far2;
-    pixel_dist2(cx, cy, px, py, &near2, &far2);
-    W1.advance();
-    const bool ok = live & inside & isfinite(I);
-    const double v = (double)I - (double)B;
-    const bool ap_whole = ok & (near2 < ra2) & (far2 <= ra2);
-    const bool ann_whole = ok & (near2 < ro2) & !(far2 <= ri2) &
-                           (v >= vlo) & (v <= vhi) & (far2 <= ro2) &
-                           !(near2 < ri2);
-    const double gd = (ap_whole ? g : 0.0) + (ann_whole ? ks : 0.0);
-    if (gd != 0.0) atomicAdd(&dp[(int64_t)py * fr.w + px], (float)gd);
-  }
+    L.T.dist2(q, &near2, &far2);
+    const bool ap_whole = live & ok & (near2 < ra2) & (far2 <= ra2);
+    const bool surv = live & ok & (near2 < ro2) & !(far2 <= ri2) &
+                      (v >= vlo) & (v <= vhi);
+    const double gd = (ap_whole ? g : 0.0) + (surv ? ks : 0.0);
+    if (gd != 0.0)
+      atomicAdd(&dp[(int64_t)(W.ya + (q >> 6)) * fr.w + W.xa + (q & 63)],
+                (float)gd);
+  });
   for (int j = lane; j < ntk; j += kWave) {
     const int t = L.tk[j];
-    const int px = xa + (t & 63), py = ya + ((t >> 6) & 63);
-    const double k = (t >> 28) == 0 ? g : ks;
+    const int px = W.xa + (t & 63), py = W.ya + ((t >> 6) & 63);
+    const double k = (t >> 12) == 0 ? g : ks;
     atomicAdd(&dp[(int64_t)py * fr.w + px], (float)(k * L.tw[j]));
   }
   wave_lds_sync();
@@ -876,7 +777,7 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
 
 template <int NS>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_aperture_bwd_t(
+__attribute__((amdgpu_waves_per_eu(3))) void k_aperture_bwd_t(
     Work wk, ipp_params p, ipp_sources src, const double* sky_lohi,
     const double* gF, double* dxy) {
   __shared__ BwLds<NS> L[kWaves];

@@ -5,10 +5,13 @@
 // 0 <= x, y <= r it is x*y when the corner lies in the circle and otherwise
 // y*xs + P(x) - P(xs) with xs = sqrt(r^2 - y^2) and
 // P(s) = int_0^s sqrt(r^2 - u^2) du = (s sqrt(r^2 - s^2) + r^2 asin(s/r))/2
-// (its angle term evaluated with atan2, see corner_g).
+// (its angle term evaluated as the angle of a rotation, see corner_g).
 // A pixel's overlap is the inclusion-exclusion of G over its corners; for
 // r >= 3/4 the four angle terms are summed as one rotation and recovered by
-// a single atan2 (see corner_rot).
+// a single angle evaluation (see corner_rot).  Angles come from the
+// Maclaurin series of atan, its coefficients read from a table in LDS, after
+// argument halvings where the argument is large: no library call, so no
+// constant of a library routine is kept in registers.
 // Membership (the pixel square meets the open disk) and full containment
 // are decided by the exact predicates below, so that every pixel that a
 // rounding residue could move in or out is classified the same way on
@@ -34,6 +37,43 @@ __device__ __forceinline__ bool within(double cx, double cy, double r,
   return fx * fx + fy * fy <= r * r;
 }
 
+// Coefficients of the Maclaurin series of atan through the power 33:
+// (-1)^k / (2k + 1), k = 0..16.
+constexpr int kAtanTerms = 17;
+__device__ __forceinline__ double atan_coef(int k) {
+  return (k & 1 ? -1.0 : 1.0) / (double)(2 * k + 1);
+}
+
+// atan(t) for |t| <= 0.3 from the series (coefficient table coef): the
+// first term left out is below 2e-20 relative.
+__device__ __forceinline__ double atan_series(double t, const double* coef) {
+  const double t2 = t * t;
+  double s = coef[kAtanTerms - 1];
+#pragma unroll
+  for (int k = kAtanTerms - 2; k >= 0; --k) s = fma(s, t2, coef[k]);
+  return t * s;
+}
+
+// atan(t) for |t| <= 1: two halvings atan t = 2 atan(t / (1 + sqrt(1 + t^2)))
+// bring the argument below tan(pi/16) < 0.2, then the series.
+__device__ __forceinline__ double atan_unit(double t, const double* coef) {
+  t = t / (1.0 + sqrt(fma(t, t, 1.0)));
+  t = t / (1.0 + sqrt(fma(t, t, 1.0)));
+  return 4.0 * atan_series(t, coef);
+}
+
+// Angle in (-pi, pi] of the direction (c, s), c and s not both zero.
+__device__ __forceinline__ double angle_of(double c, double s,
+                                           const double* coef) {
+  constexpr double kHalfPi = 1.5707963267948966;
+  constexpr double kPi = 3.141592653589793;
+  const double ac = fabs(c), as = fabs(s);
+  double a = as <= ac ? atan_unit(as / ac, coef)
+                      : kHalfPi - atan_unit(ac / as, coef);
+  if (c < 0.0) a = kPi - a;
+  return s < 0.0 ? -a : a;
+}
+
 // G for a corner (x, y) outside the circle, 0 <= x, y <= r, with
 // xs = sqrt(r^2 - y^2) and hx = sqrt(r^2 - x^2):
 //   G = y xs + P(x) - P(xs)
@@ -41,15 +81,16 @@ __device__ __forceinline__ bool within(double cx, double cy, double r,
 // With a = asin(x/r) and b = asin(y/r) the angle asin(x/r) - asin(xs/r) is
 // a + b - pi/2, whose direction (cos, sin) is proportional to
 // (hx y + x xs, x y - xs hx): the cosine is a sum of non-negative products,
-// so atan2 of the pair is accurate up to the right angle, where asin of the
-// sine alone would lose half its digits.  The two square roots depend on
-// one coordinate each, so a pixel needs four.
+// so the angle of the pair is accurate up to the right angle, where asin of
+// the sine alone would lose half its digits.  The two square roots depend
+// on one coordinate each, so a pixel needs four.
 __device__ __forceinline__ double corner_g(double ax, double ay, double hx,
-                                           double xs, double r2) {
+                                           double xs, double r2,
+                                           const double* coef) {
   if (ax * ax + ay * ay <= r2) return ax * ay;
   const double c = hx * ay + ax * xs;
   const double s = ax * ay - xs * hx;
-  return 0.5 * ((ay * xs + ax * hx) + r2 * atan2(s, c));
+  return 0.5 * ((ay * xs + ax * hx) + r2 * angle_of(c, s, coef));
 }
 
 // The same corner as a rotation: corner_rot adds the corner's non-angular
@@ -57,7 +98,7 @@ __device__ __forceinline__ double corner_g(double ax, double ay, double hx,
 // the circle has no angle term.  After all four corners the summed angle is
 // the arc of the circle that lies inside the pixel, and lin plus r^2/2 times
 // that angle is the overlap.  The factors are left unnormalised (length
-// r^2 each); atan2 does not depend on the length.
+// r^2 each); the angle does not depend on the length.
 __device__ __forceinline__ void corner_rot(double ax, double ay, double hx,
                                            double xs, double sig, double r2,
                                            double& lin, double& re,
@@ -72,26 +113,13 @@ __device__ __forceinline__ void corner_rot(double ax, double ay, double hx,
   re = nre;
 }
 
-// Coefficients of the Maclaurin series of atan through the power 33:
-// (-1)^k / (2k + 1), k = 0..16.
-constexpr int kAtanTerms = 17;
-__device__ __forceinline__ double atan_coef(int k) {
-  return (k & 1 ? -1.0 : 1.0) / (double)(2 * k + 1);
-}
-
-// Angle in [0, pi) of the rotation (re, im).  With a coefficient table
-// (atan_coef, in LDS) and |im| <= 0.3 re: the series of atan(im / re), whose
-// first term left out is below 2e-20 relative; otherwise atan2.
+// Angle in [0, pi) of the rotation (re, im): the series of atan(im / re)
+// when |im| <= 0.3 re (every cut pixel of a circle of radius 5 or more),
+// otherwise the general angle.
 __device__ __forceinline__ double rotor_angle(double re, double im,
                                               const double* coef) {
-  if (coef && fabs(im) <= 0.3 * re) {
-    const double t = im / re, t2 = t * t;
-    double s = coef[kAtanTerms - 1];
-#pragma unroll
-    for (int k = kAtanTerms - 2; k >= 0; --k) s = fma(s, t2, coef[k]);
-    return t * s;
-  }
-  return atan2(im, re);
+  if (fabs(im) <= 0.3 * re) return atan_series(im / re, coef);
+  return angle_of(re, im, coef);
 }
 
 // Overlap of the pixel square [px-1/2, px+1/2] x [py-1/2, py+1/2] with the
@@ -104,12 +132,12 @@ __device__ __forceinline__ double rotor_angle(double re, double im,
 // two antipodal points), so for r >= 3/4 the summed corner angle lies in
 // [0, pi) and one angle of the composed rotation returns it; smaller
 // circles, whose arc inside one pixel can reach the whole circle, take one
-// atan2 per corner.
+// angle per corner.  coef: the atan series coefficients (atan_coef).
 __device__ __forceinline__ double overlap_cut(double cx, double cy, double r,
                                               double r2, int px, int py,
                                               double hx0, double hx1,
                                               double xs0, double xs1,
-                                              const double* coef = nullptr) {
+                                              const double* coef) {
   const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
   const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
   const double ax0 = fmin(fabs(x0), r), ax1 = fmin(fabs(x1), r);
@@ -124,40 +152,16 @@ __device__ __forceinline__ double overlap_cut(double cx, double cy, double r,
     corner_rot(ax0, ay0, hx0, xs0, sx0 * sy0, r2, lin, re, im);
     return fma(0.5 * r2, rotor_angle(re, im, coef), lin);
   }
-  return sx1 * sy1 * corner_g(ax1, ay1, hx1, xs1, r2) -
-         sx0 * sy1 * corner_g(ax0, ay1, hx0, xs1, r2) -
-         sx1 * sy0 * corner_g(ax1, ay0, hx1, xs0, r2) +
-         sx0 * sy0 * corner_g(ax0, ay0, hx0, xs0, r2);
+  return sx1 * sy1 * corner_g(ax1, ay1, hx1, xs1, r2, coef) -
+         sx0 * sy1 * corner_g(ax0, ay1, hx0, xs1, r2, coef) -
+         sx1 * sy0 * corner_g(ax1, ay0, hx1, xs0, r2, coef) +
+         sx0 * sy0 * corner_g(ax0, ay0, hx0, xs0, r2, coef);
 }
 
 // Square root term of one pixel edge at offset q from the centre.
 __device__ __forceinline__ double edge_root(double q, double r, double r2) {
   const double a = fmin(fabs(q), r);
   return sqrt(fmax(r2 - a * a, 0.0));
-}
-
-// Overlap of pixel (px, py) with the disk of radius r about (cx, cy).
-// r2 = r * r, passed in so that a caller can precompute it.
-__device__ __forceinline__ double overlap_pre(double cx, double cy, double r,
-                                              double r2, int px, int py) {
-  if (!touches(cx, cy, r, px, py)) return 0.0;
-  if (within(cx, cy, r, px, py)) return 1.0;
-  const double hx0 = edge_root(((double)px - 0.5) - cx, r, r2);
-  const double hx1 = edge_root(((double)px + 0.5) - cx, r, r2);
-  const double xs0 = edge_root(((double)py - 0.5) - cy, r, r2);
-  const double xs1 = edge_root(((double)py + 0.5) - cy, r, r2);
-  return overlap_cut(cx, cy, r, r2, px, py, hx0, hx1, xs0, xs1);
-}
-
-__device__ __forceinline__ double overlap(double cx, double cy, double r,
-                                          int px, int py) {
-  return overlap_pre(cx, cy, r, r * r, px, py);
-}
-
-__device__ __forceinline__ double chord(double x, double y, double r) {
-  if (r <= 0.0 || fabs(x) >= r) return 0.0;
-  const double h = sqrt(r * r - x * x);
-  return copysign(fmin(fabs(y), h), y);
 }
 
 // (d/dcx, d/dcy) of the overlap of pixel (px, py) with the disk of radius
@@ -173,18 +177,6 @@ __device__ __forceinline__ void overlap_grad_roots(double cx, double cy,
   auto ch = [](double h, double y) { return copysign(fmin(fabs(y), h), y); };
   *gx = -(ch(hx1, y1) - ch(hx0, y1) - ch(hx1, y0) + ch(hx0, y0));
   *gy = -(ch(xs1, x1) - ch(xs0, x1) - ch(xs1, x0) + ch(xs0, x0));
-}
-
-// (d/dcx, d/dcy) of overlap(cx, cy, r, px, py).
-__device__ __forceinline__ void overlap_grad(double cx, double cy, double r,
-                                             int px, int py, double* gx,
-                                             double* gy) {
-  const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
-  const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
-  *gx = -(chord(x1, y1, r) - chord(x0, y1, r) - chord(x1, y0, r) +
-          chord(x0, y0, r));
-  *gy = -(chord(y1, x1, r) - chord(y0, x1, r) - chord(y1, x0, r) +
-          chord(y0, x0, r));
 }
 
 }  // namespace ipp

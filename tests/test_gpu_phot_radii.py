@@ -1,7 +1,8 @@
 """GPU parity of aperture photometry over the radius range the ABI accepts.
 
-The kernel evaluates a pixel's overlap with one atan2 of the composed corner
-rotations for r >= 3/4 and with one atan2 per corner below that, sizes its
+The kernel evaluates a pixel's overlap with one angle of the composed corner
+rotations for r >= 3/4 and with one angle per corner below that (the atan
+series, after argument halvings for large angles), sizes its
 annulus sort by the ring bound (256, 512 or 1024 slots) and loads windows
 inside the frame from a scalar base and windows over an edge with clamped
 loads.  Each radius set below drives a different combination; the centres
