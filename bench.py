@@ -49,7 +49,7 @@ ALGO_BYTES_PER_PX = {
     "k_tile_ccl": 12.0,         # read pixel, background and rms maps
 }
 # The photometry kernels are binary64 geometry: flops per source.
-ALU_KERNELS = ("k_aperture", "k_aperture_bwd")
+ALU_KERNELS = ("k_aperture", "k_aperture_bwd", "k_refine")
 
 
 def aperture_flops_per_source(r_ap, r_in, r_out):
@@ -589,9 +589,11 @@ def run_pipeline(workload, args, dev, quick=False):
     # algorithmic flops of the photometry launches of one step
     fl_fwd = aperture_flops_per_source(p.r_ap, p.r_in, p.r_out)
     fl_rc = aperture_flops_per_source(REFINE_RC, p.r_in, p.r_out)
-    flops = {"k_aperture": nsrc * fl_fwd * (2 if refine else 1)
-             + (nsrc * fl_rc * REFINE_STEPS if refine else 0.0),
-             "k_aperture_bwd": nsrc * fl_rc * REFINE_STEPS if refine else 0.0}
+    # (the refinement: the normaliser with the default aperture, then per
+    # step a forward and a backward at r_c, all in k_refine)
+    flops = {"k_aperture": nsrc * fl_fwd,
+             "k_refine": (nsrc * (fl_fwd + 2 * fl_rc * REFINE_STEPS)
+                          if refine else 0.0)}
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
     roof = roofline(kern, dom, npx, flops)
     roof["traffic"] = measured_traffic(dom, workload)

@@ -288,10 +288,12 @@ ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
  * Rows with F_ap(c0) <= 0 (or not a number) stay where they are.
  * x_out, y_out: device double[capacity], the refined centres (they may be
  * src->x and src->y themselves); the table's other columns are untouched.
- * r_c in (0, 16], eta finite, steps in [0, 1000].  Needs
- * ipp_refine_workspace_bytes of workspace (76 bytes per row plus the frame
- * descriptors).  The whole sequence (1 + 3 steps launches) is replayed from
- * a captured HIP graph when called again with the same signature.
+ * r_c in (0, 16], eta finite, steps in [0, 1000].  One kernel launch: a
+ * wavefront takes each row through the normaliser and every step (forward
+ * and gradient from the same exact overlaps).  Needs
+ * ipp_refine_workspace_bytes of workspace (the frame descriptors; rows is
+ * checked, not counted).  The launch is replayed from a captured HIP graph
+ * when called again with the same signature.
  */
 size_t ipp_refine_workspace_bytes(const ipp_frame* frames, int32_t n,
                                   int64_t rows);

@@ -631,67 +631,26 @@ ipp_status run_aperture_bwd(IppCtx* c, const Work& w, const ipp_params& p,
   return IPP_OK;
 }
 
-// Per-row arrays of the centroid refinement, after the frame descriptors.
-struct RefineWs {
-  size_t o_g, o_lohi, o_dxy, o_flux, o_sky, o_aap, o_aann, o_flags, total;
-};
-
-RefineWs refine_layout(size_t base, int64_t rows) {
-  RefineWs R;
-  size_t o = align_up(base);
-  auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
-  const size_t n = (size_t)(rows > 0 ? rows : 1);
-  R.o_g = take(8 * n);
-  R.o_lohi = take(16 * n);
-  R.o_dxy = take(16 * n);
-  R.o_flux = take(8 * n);
-  R.o_sky = take(8 * n);
-  R.o_aap = take(8 * n);
-  R.o_aann = take(8 * n);
-  R.o_flags = take(4 * n);
-  R.total = o;
-  return R;
-}
-
-// Centroid refinement: the normaliser F_ap(c0) at the start, then `steps`
-// rounds of forward at r_c, backward with dL/dF = 1/F_ap(c0), and the
-// ascent update, all on the stream (a captured graph replays them).
+// Centroid refinement: one launch; each wavefront takes a row through the
+// normaliser F_ap(c0) and all `steps` forward, gradient and update rounds.
 ipp_status run_refine(IppCtx* c, const Work& w, const ipp_params& p,
-                      const ipp_sources& src, const RefineWs& R, double r_c,
-                      double eta, int steps, double* xo, double* yo,
-                      hipStream_t s) {
-  char* b = (char*)c->ws;
-  double* g = (double*)(b + R.o_g);
-  double* lohi = (double*)(b + R.o_lohi);
-  double* dxy = (double*)(b + R.o_dxy);
-  ipp_sources t = src;              // working table: positions xo, yo
-  t.x = xo;
-  t.y = yo;
-  t.flux_ap = (double*)(b + R.o_flux);
-  t.sky = (double*)(b + R.o_sky);
-  t.area_ap = (double*)(b + R.o_aap);
-  t.area_ann = (double*)(b + R.o_aann);
-  t.flags = (uint32_t*)(b + R.o_flags);
-  const int64_t cap = src.capacity;
-  const dim3 ge(grid_for(cap, kBlock, 16384)), bb(kBlock);
-  IPP_LAUNCH(c, s, "k_refine_start",
-             hipLaunchKernelGGL(k_refine_start, ge, bb, 0, s, src.x, src.y,
-                                xo, yo, t.flags, src.n_total, cap));
-  ipp_status st = run_aperture(c, w, p, &t, nullptr, s);
-  if (st != IPP_OK) return st;
-  IPP_LAUNCH(c, s, "k_refine_norm",
-             hipLaunchKernelGGL(k_refine_norm, ge, bb, 0, s, t.flux_ap, g,
-                                src.n_total, cap));
-  ipp_params pc = p;
-  pc.r_ap = r_c;
-  for (int k = 0; k < steps; ++k) {
-    if ((st = run_aperture(c, w, pc, &t, lohi, s)) != IPP_OK) return st;
-    if ((st = run_aperture_bwd(c, w, pc, t, lohi, g, dxy, s)) != IPP_OK)
-      return st;
-    IPP_LAUNCH(c, s, "k_refine_step",
-               hipLaunchKernelGGL(k_refine_step, ge, bb, 0, s, dxy, g, xo, yo,
-                                  eta, src.n_total, cap));
-  }
+                      const ipp_sources& src, double r_c, double eta,
+                      int steps, double* xo, double* yo, hipStream_t s) {
+  const double ri = p.r_in > std::sqrt(2.0) ? p.r_in - std::sqrt(2.0) : 0.0;
+  const double ro = p.r_out + std::sqrt(2.0);
+  const double ring = M_PI * (ro * ro - ri * ri) + 16.0;
+  const dim3 g(grid_for(src.capacity, kWaves, 16384)), b(kBlock);
+  if (ring <= 256)
+    IPP_LAUNCH(c, s, "k_refine", hipLaunchKernelGGL((k_refine_t<256>), g, b,
+               0, s, w, p, r_c, eta, steps, src, xo, yo));
+  else if (ring <= 512)
+    IPP_LAUNCH(c, s, "k_refine", hipLaunchKernelGGL((k_refine_t<512>), g, b,
+               0, s, w, p, r_c, eta, steps, src, xo, yo));
+  else if (ring <= 1024)
+    IPP_LAUNCH(c, s, "k_refine", hipLaunchKernelGGL((k_refine_t<1024>), g, b,
+               0, s, w, p, r_c, eta, steps, src, xo, yo));
+  else
+    return fail(c, IPP_E_UNSUPPORTED, "aperture radii too large");
   return IPP_OK;
 }
 
@@ -1153,8 +1112,8 @@ size_t ipp_refine_workspace_bytes(const ipp_frame* frames, int32_t n,
   if (!check_frames(frames, n).empty() || rows < 0) return 0;
   ipp_params pd;
   ipp_params_default(&pd);
-  const Plan P = make_plan(frames, n, pd, 1, kPlanFrames);
-  return refine_layout(P.total, rows).total;
+  // the frame descriptors only: every step of a row lives in its wavefront
+  return make_plan(frames, n, pd, 1, kPlanFrames).total;
 }
 
 ipp_status ipp_refine_centroids(void* ctx, const ipp_frame* frames,
@@ -1183,10 +1142,9 @@ ipp_status ipp_refine_centroids(void* ctx, const ipp_frame* frames,
       return fail(c, IPP_E_INVALID_ARG, "maps[f].bkg is required");
     P.fd[i].bkg = maps[i].bkg;
   }
-  const RefineWs R = refine_layout(P.total, src->capacity);
-  if (R.total > c->ws_bytes)
+  if (P.total > c->ws_bytes)
     return fail(c, IPP_E_WORKSPACE,
-                "workspace too small: need " + std::to_string(R.total) +
+                "workspace too small: need " + std::to_string(P.total) +
                     " bytes, have " + std::to_string(c->ws_bytes));
   if (src->capacity == 0) return IPP_OK;
   hipStream_t s = (hipStream_t)stream;
@@ -1194,7 +1152,7 @@ ipp_status ipp_refine_centroids(void* ctx, const ipp_frame* frames,
   if (c->prof || !c->use_graphs || (p->flags & IPP_F_NO_GRAPH)) {  // eager
     ++c->ws_gen;
     if ((st = upload(c, P, w, s)) != IPP_OK) return st;
-    return run_refine(c, w, *p, *src, R, r_c, eta, steps, x_out, y_out, s);
+    return run_refine(c, w, *p, *src, r_c, eta, steps, x_out, y_out, s);
   }
   std::vector<uint8_t> key;
   key_put(key, "refine", 6);
@@ -1214,7 +1172,7 @@ ipp_status ipp_refine_centroids(void* ctx, const ipp_frame* frames,
   const ipp_params pv = *p;
   const ipp_sources sv = *src;
   return run_cached(c, std::move(key), P, w, s, [&](hipStream_t cs) {
-    return run_refine(c, w, pv, sv, R, r_c, eta, steps, x_out, y_out, cs);
+    return run_refine(c, w, pv, sv, r_c, eta, steps, x_out, y_out, cs);
   });
 }
 

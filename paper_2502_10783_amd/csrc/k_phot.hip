@@ -138,10 +138,10 @@ struct WinTables {
   double2 rowT[kEdges];
   double sq[3 * 2 * kEdges];       // [circle][axis][edge]
 
-  __device__ void fill(const Window& W, double cx, double cy,
-                       const ipp_params& p, int lane) {
-    const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
-    const double ro2 = p.r_out * p.r_out;
+  __device__ void fill(const Window& W, double cx, double cy, double r_ap,
+                       double r_in, double r_out, int lane) {
+    const double ra2 = r_ap * r_ap, ri2 = r_in * r_in;
+    const double ro2 = r_out * r_out;
     const int ne = (W.nwx > W.nwy ? W.nwx : W.nwy) + 1;   // <= kEdges
     for (int e = lane; e < 2 * ne; e += kWave) {
       const bool col = e < ne;
@@ -157,9 +157,9 @@ struct WinTables {
       const int ax = col ? 0 : kEdges;
       if (j < kEdges) {
         (col ? colT : rowT)[j] = t;
-        sq[ax + j] = edge_root(q, p.r_ap, ra2);
-        sq[2 * kEdges + ax + j] = edge_root(q, p.r_out, ro2);
-        sq[4 * kEdges + ax + j] = edge_root(q, p.r_in, ri2);
+        sq[ax + j] = edge_root(q, r_ap, ra2);
+        sq[2 * kEdges + ax + j] = edge_root(q, r_out, ro2);
+        sq[4 * kEdges + ax + j] = edge_root(q, r_in, ri2);
       }
     }
   }
@@ -174,9 +174,10 @@ struct WinTables {
 };
 
 // Circle of a task: 0 the aperture, 1 the outer, 2 the inner annulus circle.
-__device__ __forceinline__ void task_circle(const ipp_params& p, int c,
-                                            double* r, double* r2) {
-  const double rr = c == 0 ? p.r_ap : (c == 1 ? p.r_out : p.r_in);
+__device__ __forceinline__ void task_circle(double r_ap, double r_in,
+                                            double r_out, int c, double* r,
+                                            double* r2) {
+  const double rr = c == 0 ? r_ap : (c == 1 ? r_out : r_in);
   *r = rr;
   *r2 = rr * rr;
 }
@@ -351,36 +352,27 @@ __device__ __forceinline__ double sorted_at(const double* xs, int e) {
   return xs[e + (e >> P)];
 }
 
-template <int NS>
-__device__ void aperture_one(const Work& wk, const ipp_params& p,
-                             ipp_sources& src, double* sky_lohi,
-                             long long row, ApLds<NS>& L,
-                             const double* atan_lds) {
+// Photometry of one source whose frame and centre are valid: the sums of
+// the aperture flux and the sky, and with GRAD the centre derivative of
+// the flux with the sky clip mask held fixed (as the backward below).
+struct ApOut {
+  double raw;          // sum of w v over the aperture
+  double a_ap;         // aperture area (sum of w)
+  double num, den;     // sum of m w v and of m w over the annulus
+  double vlo, vhi;     // the sky survivors' value range (empty: vlo > vhi)
+  uint32_t flags;
+  double dfx, dfy;     // dF/dcx, dF/dcy (GRAD)
+};
+
+template <int NS, bool GRAD>
+__device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
+                               double r_ap, double cx, double cy,
+                               ApLds<NS>& L, const double* atan_lds,
+                               int lane) {
   constexpr int PL = NS / kWave;
   constexpr int P = PL == 4 ? 2 : (PL == 8 ? 3 : 4);
   static_assert((1 << P) == PL, "NS is 256, 512 or 1024");
-  // the lane number made opaque to the compiler at every row: addresses
-  // derived from it are formed where they are used instead of being kept
-  // in registers across the whole row loop
-  int lane = threadIdx.x & (kWave - 1);
-  asm volatile("" : "+v"(lane));
-  const int f = src.frame[row];
-  const double cx = src.x[row], cy = src.y[row];
-  const bool fok = f >= 0 && f < wk.nframes;
-  const double R = p.r_ap > p.r_out ? p.r_ap : p.r_out;
-  if (!fok || !(isfinite(cx) && isfinite(cy)) || fabs(cx) > 1e9 ||
-      fabs(cy) > 1e9) {
-    if (lane == 0) {
-      src.flux_ap[row] = __builtin_nan("");
-      src.sky[row] = __builtin_nan("");
-      src.area_ap[row] = 0.0;
-      src.area_ann[row] = 0.0;
-      src.flags[row] |= IPP_SRC_APERTURE_OFF_EDGE | IPP_SRC_NO_SKY;
-      if (sky_lohi) { sky_lohi[2 * row] = 0.0; sky_lohi[2 * row + 1] = -1.0; }
-    }
-    return;
-  }
-  const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
+  const double R = r_ap > p.r_out ? r_ap : p.r_out;
   // window bounds: wave-uniform values, kept in scalar registers
   Window W;
   W.init(fr, __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5)),
@@ -388,14 +380,17 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
          __builtin_amdgcn_readfirstlane((int)ceil(cy - R - 0.5)),
          __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5)));
   // squared radii as the membership predicates form them
-  const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
+  const double ra2 = r_ap * r_ap, ri2 = p.r_in * p.r_in;
   const double ro2 = p.r_out * p.r_out;
-  L.T.fill(W, cx, cy, p, lane);
+  L.T.fill(W, cx, cy, r_ap, p.r_in, p.r_out, lane);
   wave_lds_sync();
 
   // ---- walk the window: sums, annulus values, cut pixels ---------------
+  // Aperture tasks are listed from the front of the task list, annulus
+  // tasks from its back, so that the few rounds of aperture tasks (whose
+  // angles may need the general path) are not spread over the list.
   int nfull = 0;                       // pixels wholly inside the aperture
-  int nann = 0, ntk = 0;               // wave-uniform list lengths
+  int nann = 0, nt0 = 0, nt1 = 0;      // wave-uniform list lengths
   double raw = 0.0;                    // per lane: sum of v over them
   bool bad_ap = false, bad_ann = false;
   W.walk<4>(lane, [&](bool live, int q, bool ok, double v) {
@@ -422,26 +417,28 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     const bool c2 = ann & (near2 < ri2);
     const uint64_t b0 = ballot(c0), b1 = ballot(c1), b2 = ballot(c2);
     if (c0) {
-      const int s = ntk + lanes_before(b0);
+      const int s = nt0 + lanes_before(b0);
       if (s < kTaskCap) L.tk[s] = q;
     }
-    ntk += __popcll(b0);
+    nt0 += __popcll(b0);
     if (c1) {
-      const int s = ntk + lanes_before(b1);
-      if (s < kTaskCap) L.tk[s] = (1 << 12) | q;
+      const int s = kTaskCap - 1 - (nt1 + lanes_before(b1));
+      if (s >= 0) L.tk[s] = (1 << 12) | q;
     }
-    ntk += __popcll(b1);
+    nt1 += __popcll(b1);
     if (c2) {
-      const int s = ntk + lanes_before(b2);
-      if (s < kTaskCap) L.tk[s] = (2 << 12) | q;
+      const int s = kTaskCap - 1 - (nt1 + lanes_before(b2));
+      if (s >= 0) L.tk[s] = (2 << 12) | q;
     }
-    ntk += __popcll(b2);
+    nt1 += __popcll(b2);
   });
   if (nann > NS) nann = NS;            // not reachable: NS bounds the ring
-  if (ntk > kTaskCap) ntk = kTaskCap;  // not reachable either
-  uint32_t flags = 0;                  // wave-uniform
-  if (ballot(bad_ap)) flags |= IPP_SRC_APERTURE_OFF_EDGE;
-  if (ballot(bad_ann)) flags |= IPP_SRC_ANNULUS_OFF_EDGE;
+  // not reachable either (the two ends cannot meet)
+  if (nt0 + nt1 > kTaskCap) { nt0 = min(nt0, kTaskCap); nt1 = kTaskCap - nt0; }
+  ApOut o;
+  o.flags = 0;                         // wave-uniform
+  if (ballot(bad_ap)) o.flags |= IPP_SRC_APERTURE_OFF_EDGE;
+  if (ballot(bad_ann)) o.flags |= IPP_SRC_ANNULUS_OFF_EDGE;
   wave_lds_sync();
 
   // ---- sort the annulus values ------------------------------------------
@@ -491,12 +488,12 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
     }
     const int cl = max(nlo - a, 0), ch = max(nhi - (NS - bnd), 0);
     if (cl == 0 && ch == 0) break;
+    // the removed values are the sorted ranges [a, a + cl) and
+    // [bnd - ch, bnd): one lane reads each from LDS (usually one round)
     double r1 = 0.0, r2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < PL; ++k) {
-      const int e = lane * PL + k;
-      const bool gone = (e >= a && e < a + cl) || (e >= bnd - ch && e < bnd);
-      const double d = gone ? sv[k] - c0 : 0.0;
+    for (int j = lane; j < cl + ch; j += kWave) {
+      const int e = j < cl ? a + j : bnd - ch + (j - cl);
+      const double d = sorted_at<P>(L.xs, e) - c0;
       r1 += d;
       r2 += d * d;
     }
@@ -507,8 +504,13 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   }
   // the survivors are the values in [vlo, vhi] (clipping is by value);
   // with weight 1 each they sum to su
-  double vlo = 0.0, vhi = -1.0;
-  if (bnd > a) { vlo = sorted_at<P>(L.xs, a); vhi = sorted_at<P>(L.xs, bnd - 1); }
+  o.vlo = 0.0;
+  o.vhi = -1.0;
+  if (bnd > a) {
+    o.vlo = sorted_at<P>(L.xs, a);
+    o.vhi = sorted_at<P>(L.xs, bnd - 1);
+  }
+  const double vlo = o.vlo, vhi = o.vhi;
   double su = 0.0;
 #pragma unroll
   for (int k = 0; k < PL; ++k) {
@@ -521,47 +523,156 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
   // One overlap per task, whatever circle it belongs to.  An aperture task
   // adds w and w v; an annulus task of a survivor corrects its weight 1:
   // by w - 1 for the outer circle and by -w for the inner one (a pixel cut
-  // by both gets w_out - w_in).
+  // by both gets w_out - w_in).  With GRAD the centre derivatives of the
+  // same overlaps (chords at the pixel's corners) are summed alongside.
   double acut = 0.0, dnum = 0.0, dden = 0.0;
+  double tvx = 0.0, tvy = 0.0, tax = 0.0, tay = 0.0;   // aperture terms
+  double svx = 0.0, svy = 0.0, swx = 0.0, swy = 0.0;   // sky terms
+  const int ntk = nt0 + nt1;
   for (int j = lane; j < ntk; j += kWave) {
     // the series coefficients are read where they are used (an offset the
     // compiler cannot hoist keeps them out of registers across the loop)
     int co = 0;
     asm volatile("" : "+s"(co));
     const double* coef = atan_lds + co;
-    const int t = L.tk[j];
+    const int t = L.tk[j < nt0 ? j : kTaskCap - nt1 + (j - nt0)];
     const int c = t >> 12, wx = t & 63, wy = (t >> 6) & 63;
     const int px = W.xa + wx, py = W.ya + wy;
     double r, r2;
-    task_circle(p, c, &r, &r2);
+    task_circle(r_ap, p.r_in, p.r_out, c, &r, &r2);
     const double* sq = L.T.sq + c * 2 * kEdges;
-    const double w = overlap_cut(cx, cy, r, r2, px, py, sq[wx], sq[wx + 1],
-                                 sq[kEdges + wy], sq[kEdges + wy + 1], coef);
+    const double hx0 = sq[wx], hx1 = sq[wx + 1];
+    const double xs0 = sq[kEdges + wy], xs1 = sq[kEdges + wy + 1];
+    const double w = overlap_cut(cx, cy, r, r2, px, py, hx0, hx1, xs0, xs1,
+                                 coef);
     const double v = W.value_at(px, py);
+    double gx = 0.0, gy = 0.0;
+    if constexpr (GRAD)
+      overlap_grad_roots(cx, cy, px, py, hx0, hx1, xs0, xs1, &gx, &gy);
     if (c == 0) {
       acut += w;
       raw += w * v;
+      if constexpr (GRAD) {
+        tvx += v * gx; tvy += v * gy;
+        tax += gx; tay += gy;
+      }
     } else if (v >= vlo && v <= vhi) {
       const double dw = c == 1 ? w - 1.0 : -w;
       dden += dw;
       dnum += dw * v;
+      if constexpr (GRAD) {
+        // the inner circle's overlap enters negated
+        if (c == 2) { gx = -gx; gy = -gy; }
+        svx += v * gx; svy += v * gy;
+        swx += gx; swy += gy;
+      }
     }
   }
-  const double a_ap = (double)nfull + wave_sum(acut);
-  raw = wave_sum(raw);
-  const double num = su + wave_sum(dnum);
-  const double den = (double)(bnd - a) + wave_sum(dden);
-  if (lane == 0) {
-    double sky = 0.0;
-    if (den > 0.0) sky = num / den; else flags |= IPP_SRC_NO_SKY;
-    src.flux_ap[row] = raw - sky * a_ap;
-    src.sky[row] = sky;
-    src.area_ap[row] = a_ap;
-    src.area_ann[row] = den;
-    src.flags[row] |= flags;
-    if (sky_lohi) { sky_lohi[2 * row] = vlo; sky_lohi[2 * row + 1] = vhi; }
+  o.a_ap = (double)nfull + wave_sum(acut);
+  o.raw = wave_sum(raw);
+  o.num = su + wave_sum(dnum);
+  o.den = (double)(bnd - a) + wave_sum(dden);
+  o.dfx = o.dfy = 0.0;
+  if constexpr (GRAD) {
+    tvx = wave_sum(tvx); tvy = wave_sum(tvy);
+    tax = wave_sum(tax); tay = wave_sum(tay);
+    svx = wave_sum(svx); svy = wave_sum(svy);
+    swx = wave_sum(swx); swy = wave_sum(swy);
+    const double sky = o.den > 0.0 ? o.num / o.den : 0.0;
+    double dsx = 0.0, dsy = 0.0;
+    if (o.den > 0.0) {
+      dsx = (svx - sky * swx) / o.den;
+      dsy = (svy - sky * swy) / o.den;
+    }
+    o.dfx = (tvx - sky * tax) - o.a_ap * dsx;
+    o.dfy = (tvy - sky * tay) - o.a_ap * dsy;
   }
-  wave_lds_sync();                     // the slice is reused by the next row
+  wave_lds_sync();                     // the slice is reused next
+  return o;
+}
+
+__device__ __forceinline__ bool centre_ok(double cx, double cy) {
+  return isfinite(cx) && isfinite(cy) && fabs(cx) <= 1e9 && fabs(cy) <= 1e9;
+}
+
+template <int NS>
+__device__ void aperture_one(const Work& wk, const ipp_params& p,
+                             ipp_sources& src, double* sky_lohi,
+                             long long row, ApLds<NS>& L,
+                             const double* atan_lds) {
+  // the lane number made opaque to the compiler at every row: addresses
+  // derived from it are formed where they are used instead of being kept
+  // in registers across the whole row loop
+  int lane = threadIdx.x & (kWave - 1);
+  asm volatile("" : "+v"(lane));
+  const int f = src.frame[row];
+  const double cx = src.x[row], cy = src.y[row];
+  if (!(f >= 0 && f < wk.nframes) || !centre_ok(cx, cy)) {
+    if (lane == 0) {
+      src.flux_ap[row] = __builtin_nan("");
+      src.sky[row] = __builtin_nan("");
+      src.area_ap[row] = 0.0;
+      src.area_ann[row] = 0.0;
+      src.flags[row] |= IPP_SRC_APERTURE_OFF_EDGE | IPP_SRC_NO_SKY;
+      if (sky_lohi) { sky_lohi[2 * row] = 0.0; sky_lohi[2 * row + 1] = -1.0; }
+    }
+    return;
+  }
+  const FrameDev fr = wk.frames[f];     // f is wave-uniform: SGPRs
+  const ApOut o =
+      aperture_eval<NS, false>(fr, p, p.r_ap, cx, cy, L, atan_lds, lane);
+  if (lane == 0) {
+    uint32_t flags = o.flags;
+    double sky = 0.0;
+    if (o.den > 0.0) sky = o.num / o.den; else flags |= IPP_SRC_NO_SKY;
+    src.flux_ap[row] = o.raw - sky * o.a_ap;
+    src.sky[row] = sky;
+    src.area_ap[row] = o.a_ap;
+    src.area_ann[row] = o.den;
+    src.flags[row] |= flags;
+    if (sky_lohi) { sky_lohi[2 * row] = o.vlo; sky_lohi[2 * row + 1] = o.vhi; }
+  }
+}
+
+// Centroid refinement of one source: the normaliser F_ap(c0) with p's
+// aperture, then `steps` ascent steps c <- c + eta g dF_rc/dc (g =
+// 1 / F_ap(c0)), each step's derivative taken with that step's sky clip
+// mask, all in this wave.  Sources with g = 0 (F_ap(c0) <= 0 or not a
+// number) stay in place, and so does a centre that leaves the valid range.
+template <int NS>
+__device__ void refine_one(const Work& wk, const ipp_params& p,
+                           double r_c, double eta, int steps,
+                           const ipp_sources& src, double* xo, double* yo,
+                           long long row, ApLds<NS>& L,
+                           const double* atan_lds) {
+  int lane = threadIdx.x & (kWave - 1);
+  asm volatile("" : "+v"(lane));
+  const int f = src.frame[row];
+  double cx = src.x[row], cy = src.y[row];
+  if ((f >= 0 && f < wk.nframes) && centre_ok(cx, cy)) {
+    const FrameDev fr = wk.frames[f];   // f is wave-uniform: SGPRs
+    // k = -1: the normaliser (its derivative is not used); one call site,
+    // so that the photometry is inlined once
+    double g = 0.0;
+    for (int k = -1; k < steps; ++k) {
+      const ApOut o = aperture_eval<NS, true>(fr, p, k < 0 ? p.r_ap : r_c,
+                                              cx, cy, L, atan_lds, lane);
+      if (k < 0) {
+        const double sky0 = o.den > 0.0 ? o.num / o.den : 0.0;
+        const double F0 = o.raw - sky0 * o.a_ap;
+        g = F0 > 0.0 ? 1.0 / F0 : 0.0;
+      } else {
+        const double dx = g * o.dfx, dy = g * o.dfy;
+        cx = cx + eta * dx;
+        cy = cy + eta * dy;
+      }
+      if (g == 0.0 || !centre_ok(cx, cy)) break;
+    }
+  }
+  if (lane == 0) {
+    xo[row] = cx;
+    yo[row] = cy;
+  }
 }
 
 }  // namespace
@@ -588,6 +699,34 @@ __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 4 : 1))) void k_aperture_t(
   for (long long row = wid; row < nrows; row += nw)
     aperture_one<NS>(wk, p, src, sky_lohi, row, mine, atan_lds);
 }
+
+// Centroid refinement: one wavefront per row, every step in the wave.
+template <int NS>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_refine_t(
+    Work wk, ipp_params p, double r_c, double eta, int steps,
+    ipp_sources src, double* xo, double* yo) {
+  __shared__ ApLds<NS> L[kWaves];
+  __shared__ double atan_lds[kAtanTerms];
+  if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
+  __syncthreads();
+  long long nrows = src.capacity;
+  if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
+  const long long wid =
+      blockIdx.x * (long long)kWaves +
+      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const long long nw = (long long)gridDim.x * kWaves;
+  ApLds<NS>& mine = L[threadIdx.x / kWave];
+  for (long long row = wid; row < nrows; row += nw)
+    refine_one<NS>(wk, p, r_c, eta, steps, src, xo, yo, row, mine, atan_lds);
+}
+
+template __global__ void k_refine_t<256>(Work, ipp_params, double, double,
+                                         int, ipp_sources, double*, double*);
+template __global__ void k_refine_t<512>(Work, ipp_params, double, double,
+                                         int, ipp_sources, double*, double*);
+template __global__ void k_refine_t<1024>(Work, ipp_params, double, double,
+                                          int, ipp_sources, double*, double*);
 
 template __global__ void k_aperture_t<256>(Work, ipp_params, ipp_sources,
                                            double*);
@@ -646,7 +785,7 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
          __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5)));
   const double ra2 = p.r_ap * p.r_ap, ri2 = p.r_in * p.r_in;
   const double ro2 = p.r_out * p.r_out;
-  L.T.fill(W, cx, cy, p, lane);
+  L.T.fill(W, cx, cy, p.r_ap, p.r_in, p.r_out, lane);
   wave_lds_sync();
 
   // ---- pass 1: whole pixels summed, cut pixels listed ------------------
@@ -701,7 +840,7 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
     const int c = t >> 12, wx = t & 63, wy = (t >> 6) & 63;
     const int px = W.xa + wx, py = W.ya + wy;
     double r, r2;
-    task_circle(p, c, &r, &r2);
+    task_circle(p.r_ap, p.r_in, p.r_out, c, &r, &r2);
     const double* sq = L.T.sq + c * 2 * kEdges;
     const double hx0 = sq[wx], hx1 = sq[wx + 1];
     const double xs0 = sq[kEdges + wy], xs1 = sq[kEdges + wy + 1];
@@ -795,57 +934,6 @@ __attribute__((amdgpu_waves_per_eu(3))) void k_aperture_bwd_t(
   for (long long row = wid; row < nrows; row += nw)
     aperture_bwd_one<NS>(wk, p, src, sky_lohi, gF, dxy, row, mine,
                          atan_lds);
-}
-
-// ---------------------------------------------------------------------
-// Centroid refinement around the photometry and its backward: maximise
-// J(c) = F_rc(c) / F_ap(c0) by plain ascent c <- c + eta dJ/dc.  The
-// backward is given dL/dF = g = 1 / F_ap(c0), so it returns dJ/dc; rows
-// with F_ap(c0) <= 0 (or not a number) get g = 0 and stay in place.
-// ---------------------------------------------------------------------
-namespace {
-__device__ __forceinline__ long long refine_rows(const int64_t* n_total,
-                                                 int64_t cap) {
-  long long n = cap;
-  if (n_total && *n_total < n) n = *n_total;
-  return n;
-}
-}  // namespace
-
-__global__ __launch_bounds__(kBlock) void k_refine_start(
-    const double* x, const double* y, double* xo, double* yo,
-    uint32_t* flags, const int64_t* n_total, int64_t cap) {
-  const long long n = refine_rows(n_total, cap);
-  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock) {
-    const double a = x[i], b = y[i];    // read both before any write
-    xo[i] = a;
-    yo[i] = b;
-    flags[i] = 0u;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_refine_norm(
-    const double* flux, double* g, const int64_t* n_total, int64_t cap) {
-  const long long n = refine_rows(n_total, cap);
-  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock) {
-    const double f = flux[i];
-    g[i] = f > 0.0 ? 1.0 / f : 0.0;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_refine_step(
-    const double* dxy, const double* g, double* xo, double* yo, double eta,
-    const int64_t* n_total, int64_t cap) {
-  const long long n = refine_rows(n_total, cap);
-  for (long long i = blockIdx.x * (long long)kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock) {
-    if (g[i] != 0.0) {
-      xo[i] = xo[i] + eta * dxy[2 * i];
-      yo[i] = yo[i] + eta * dxy[2 * i + 1];
-    }
-  }
 }
 
 template __global__ void k_aperture_bwd_t<256>(

@@ -54,17 +54,12 @@ __global__ void k_aperture_bwd_t(Work wk, ipp_params p, ipp_sources src,
                                  const double* sky_lohi, const double* gF,
                                  double* dxy);
 
-// Centroid refinement: start positions copied into the working columns
-// (and the working flags cleared); normaliser g = 1 / F where F > 0, else
-// 0; ascent update c += eta dxy where g != 0.  Rows: min(cap, *n_total).
-__global__ void k_refine_start(const double* x, const double* y, double* xo,
-                               double* yo, uint32_t* flags,
-                               const int64_t* n_total, int64_t cap);
-__global__ void k_refine_norm(const double* flux, double* g,
-                              const int64_t* n_total, int64_t cap);
-__global__ void k_refine_step(const double* dxy, const double* g, double* xo,
-                              double* yo, double eta, const int64_t* n_total,
-                              int64_t cap);
+// Centroid refinement, every step of a row in one wavefront: xo, yo get
+// the refined centres.  Rows: min(capacity, *n_total).
+template <int NS>
+__global__ void k_refine_t(Work wk, ipp_params p, double r_c, double eta,
+                           int steps, ipp_sources src, double* xo,
+                           double* yo);
 
 // ab (nullable): device (a, b) used in place of the value arguments
 __global__ void k_asinh_fwd(const float* v, float* y, int64_t n, float inv_a,

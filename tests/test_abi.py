@@ -134,7 +134,7 @@ def test_deblend_kron_refine_host_checks(lib):
     assert lib.ipp_deblend_workspace_bytes(f, 2, -1, 0) == 0
     assert lib.ipp_deblend_workspace_bytes(None, 2, 10, 0) == 0
     r0 = lib.ipp_refine_workspace_bytes(f, 2, 1000)
-    assert r0 > 76 * 1000
+    assert r0 > 0 and lib.ipp_refine_workspace_bytes(f, 2, 10) == r0
     assert lib.ipp_refine_workspace_bytes(f, 2, -5) == 0
     p = _defaults(lib)
     maps = (L.IppMaps * 2)()
