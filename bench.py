@@ -20,7 +20,7 @@ oracle, the oracle's own throughput on a bounded sample on the host CPU
 16 x 4096^2 stack and the autotuned 256-frame uneven batch.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
-    python bench.py --workload stack16|uneven|grad64|gray16
+    python bench.py --workload stack16|uneven|grad64|gray16|next16
 """
 import argparse
 import json
@@ -318,6 +318,218 @@ def run_grad(args):
             "bytes_per_px": {"forward": 8, "backward": 12}},
         "kernels_ms": {k: round(v0 / v1, 4) for k, (v0, v1) in
                        sorted(prof.items(), key=lambda kv: -kv[1][0])},
+    }
+    print(json.dumps(res), flush=True)
+
+
+SUB_DESC = ("16 pairs of 4096x4096 float32 frames (science and template of "
+            "the 16-frame recipe), 21x21 kernels of 3 Gaussians (sigma 0.7, "
+            "1.5, 3.0 px; orders 6, 4, 2: 49 basis terms) with degree-2 "
+            "spatial coefficients and a degree-1 background, 21x21 stamps")
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def _sub_coef(nfr, sp, seed=7):
+    """Seeded kernel and background coefficients of moderate size (each
+    basis term scaled by 1 / (sigma^(i+j) (i+j)!), so that the kernel stays
+    O(1) over its support); the fit that would produce them is not part of
+    the path."""
+    import math
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ns = (sp.spatial_order + 1) * (sp.spatial_order + 2) // 2
+    nb = (sp.bkg_order + 1) * (sp.bkg_order + 2) // 2
+    rows = []
+    for _ in range(nfr):
+        a = []
+        for s, o in zip(sp.sigmas, sp.orders):
+            for i in range(o + 1):
+                for j in range(o - i + 1):
+                    a.append(rng.normal(0, 1, ns) /
+                             (s ** (i + j) * math.factorial(i + j)))
+        a.append(rng.normal(0, 5, nb))
+        rows.append(np.concatenate(a))
+    return np.stack(rows)
+
+
+def _next_cpu_sample(args):
+    """The oracle on small pieces of the 16-frame recipe (one process):
+    stamp subtraction of a 24 x 24 crop, deblending and cleaning of the
+    candidates of a 512 x 512 crop, AUTO photometry of 50 of them."""
+    import time as _t
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle
+    from oracle import background as obg, detect as odt, deblend as odb
+    from oracle import kron as okr, subtract as osb
+    from synth import make_frame
+    from paper_2502_10783_amd.api import SubtractParams
+    frame = args
+    with threadpool_limits(1):
+        img, _, _ = make_frame("stack16", frame, scale=0.125)   # 512 x 512
+        I = img.numpy()
+        op = oracle.Params()
+        sp = SubtractParams()
+        coef = _sub_coef(1, sp, seed=frame)[0]
+        ns = (sp.spatial_order + 1) * (sp.spatial_order + 2) // 2
+        nbt = len(osb.basis_terms(sp.sigmas, sp.orders))
+        a = coef[:nbt * ns].reshape(nbt, ns)
+        b = coef[nbt * ns:]
+        crop = 96
+        t0 = _t.perf_counter()
+        osb.subtract(I[:crop, :crop], I[1:crop + 1, 1:crop + 1], sp.sigmas,
+                     sp.orders, sp.half_width, a, sp.spatial_order, b,
+                     sp.bkg_order, stamp=sp.stamp)
+        t_sub = _t.perf_counter() - t0
+        ref = obg.background(I, op)
+        det = odt.detect(I, ref["B32"], ref["R32"], op)
+        t0 = _t.perf_counter()
+        odb.deblend(I, ref["B32"], ref["R32"], det["labels"], det["table"],
+                    op)
+        t_db = _t.perf_counter() - t0
+        k = min(200, det["n"])
+        t0 = _t.perf_counter()
+        mom = odt.source_moments(I, ref["B32"], det["labels"], det["n"])
+        okr.auto_photometry(I, ref["B32"], det["table"]["x"][:k],
+                            det["table"]["y"][:k], mom[:k])
+        t_auto = _t.perf_counter() - t0
+    return {"sub_px": crop * crop, "sub_s": t_sub, "db_px": I.size,
+            "db_s": t_db, "auto_src": k, "auto_s": t_auto}
+
+
+def run_next(args):
+    """The widened rows on the 16-frame stack: deblending and cleaning of
+    the detection's candidates (Sec. 2.2.5), second moments and AUTO
+    photometry of the candidates (Sec. 2.2.5, 3.3) and the stamp
+    convolution and difference image against a template (Sec. 2.2.4)."""
+    cpu = None
+    if not args.no_cpu:
+        log("oracle CPU baseline of the widened rows (one core)")
+        t0 = time.time()
+        r = _next_cpu_sample(0)
+        cpu = {"kind": "oracle", "cores": 1,
+               "sample": ("frame 0 of the 16-frame recipe shrunk to "
+                          "512x512: stamp subtraction of a 96x96 crop, "
+                          "deblending and cleaning of all its candidates, "
+                          "moments and AUTO photometry of 200 of them"),
+               "subtract_mpix_per_s": round(r["sub_px"] / r["sub_s"] / 1e6,
+                                            6),
+               "deblend_mpix_per_s": round(r["db_px"] / r["db_s"] / 1e6, 4),
+               "auto_sources_per_s": round(r["auto_src"] / r["auto_s"], 2),
+               "seconds_measured": round(time.time() - t0, 1)}
+    import torch
+    import paper_2502_10783_amd as ipp
+    from paper_2502_10783_amd.api import SubtractParams
+    dev = torch.device("cuda:0")
+    nfr, desc = WORKLOADS["stack16"]
+    if args.frames:
+        nfr = min(nfr, args.frames)
+    log(f"generating {nfr} frames of stack16 on the GPU")
+    frames = make_frames("stack16", nfr, dev)
+    templates = [torch.roll(f, shifts=(1, 1), dims=(0, 1)).contiguous()
+                 for f in frames]
+    npx = sum(f.numel() for f in frames)
+    ctx = ipp.Context(0)
+    p = ipp.Params()
+    table = ipp.SourceTable(npx // 64 + 4096, nfr, dev)
+    outputs = {"bkg": [torch.empty_like(f) for f in frames],
+               "labels": [torch.empty(f.shape, dtype=torch.int32,
+                                      device=dev) for f in frames],
+               "rms": [torch.empty_like(f) for f in frames]}
+    ctx.process_batch(frames, p, table=table, outputs=outputs)
+    torch.cuda.synchronize()
+    nsrc = table.count()
+    sp = SubtractParams()
+    coef = torch.from_numpy(_sub_coef(nfr, sp)).to(dev).contiguous()
+
+    def timed(fn, k):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    holder = {}
+
+    def deblend():
+        holder["db"] = ctx.deblend(frames, outputs["bkg"], outputs["rms"],
+                                   outputs["labels"], table, p)
+
+    def auto():
+        mom = ctx.source_moments(frames, outputs["bkg"], outputs["labels"],
+                                 table)
+        ctx.photometry_auto(frames, outputs["bkg"], table, mom)
+
+    def subtract():
+        ctx.subtract(frames, templates, sp, coef)
+
+    log(f"timing {args.steps} steps of each")
+    ms_db = timed(deblend, args.steps)
+    nobj = holder["db"]["table"].count()
+    db_diag = holder["db"]["diag"].cpu().tolist()
+    ms_auto = timed(auto, args.steps)
+    ms_sub = timed(subtract, args.steps)
+    ctx.profile(True)
+    for _ in range(2):
+        deblend()
+        auto()
+        subtract()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kern = {k: v0 / v1 for k, (v0, v1) in prof.items()}
+    kw = 2 * sp.half_width + 1
+    sub_flops = 2.0 * kw * kw * npx            # one FMA per tap and pixel
+    ks = kern.get("k_subtract")
+    roof = None
+    if ks:
+        tfs = sub_flops / (ks * 1e-3) / 1e12
+        roof = {"kernel": "k_subtract", "bound": "alu",
+                "achieved": round(tfs, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s",
+                "frac": round(tfs / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic("k_subtract", "next16"),
+                "algo_flops_per_launch": sub_flops,
+                "ms_per_launch": round(ks, 4)}
+    res = {
+        "metric": "Mpix/s of the stamp convolution and difference image",
+        "value": round(npx / 1e6 / (ms_sub * 1e-3), 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_sub, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": SUB_DESC, "name": "next16", "frames": nfr,
+                   "kernel": [kw, kw], "stamp": sp.stamp,
+                   "basis": {"sigmas": list(sp.sigmas),
+                             "orders": list(sp.orders)},
+                   "spatial_order": sp.spatial_order,
+                   "bkg_order": sp.bkg_order},
+        "roofline": roof,
+        "deblend": {"workload": "deblending and cleaning of the candidates "
+                                "of the 16-frame stack (" + desc + ")",
+                    "ms_per_step": round(ms_db, 4),
+                    "mpix_per_s": round(npx / 1e6 / (ms_db * 1e-3), 1),
+                    "candidates": nsrc, "objects": nobj,
+                    "diag": db_diag,
+                    "candidates_per_s": round(nsrc / (ms_db * 1e-3), 1)},
+        "auto_photometry": {"workload": "second moments and AUTO (Kron) "
+                                        "photometry of the candidates",
+                            "ms_per_step": round(ms_auto, 4),
+                            "sources": nsrc,
+                            "sources_per_s": round(nsrc / (ms_auto * 1e-3),
+                                                   1)},
+        "kernels_ms": {k: round(v, 4) for k, v in
+                       sorted(kern.items(), key=lambda kv: -kv[1])},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
 
@@ -656,12 +868,15 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload",
-                    choices=sorted(WORKLOADS) + ["grad64", "gray16"],
+                    choices=sorted(WORKLOADS) + ["grad64", "gray16",
+                                                 "next16"],
                     default="crowded",
                     help="grad64: the forward + backward of the aperture "
                          "flux and of the asinh stretch; gray16: zscale, "
                          "point map and histogram equalization of the "
-                         "16-frame stack (each its own metric)")
+                         "16-frame stack; next16: deblending, AUTO "
+                         "photometry and stamp subtraction of the 16-frame "
+                         "stack (each its own metric)")
     ap.add_argument("--frames", type=int, default=0,
                     help="frames of the workload to use (0 = all)")
     ap.add_argument("--plain-steps", type=int, default=1)
@@ -687,6 +902,9 @@ def main():
         return
     if args.workload == "gray16":
         run_gray(args)
+        return
+    if args.workload == "next16":
+        run_next(args)
         return
 
     # the CPU leg first, in worker processes started before this process

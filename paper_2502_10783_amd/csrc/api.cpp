@@ -1709,12 +1709,25 @@ ipp_status ipp_subtract(void* ctx, const ipp_frame* sci,
     bs.order[g] = sp->order[g];
     bs.sigma[g] = sp->sigma[g];
   }
-  IPP_LAUNCH(c, s, "k_subtract",
-             hipLaunchKernelGGL(k_subtract,
-                                dim3((unsigned)std::min<int64_t>(stamps,
-                                                                 1 << 20)),
-                                dim3(kBlock), 0, s, (const SubFrame*)c->ws,
-                                n, bs, stamps));
+  const dim3 g((unsigned)std::min<int64_t>(stamps, 1 << 20));
+  const dim3 b(sub_threads(sp->stamp));
+  const size_t lds = sub_lds_bytes(sp->stamp, sp->half_width);
+  const SubFrame* fd = (const SubFrame*)c->ws;
+  switch (sp->half_width) {
+#define IPP_SUB_CASE(H)                                                   \
+  case H:                                                                 \
+    IPP_LAUNCH(c, s, "k_subtract",                                        \
+               hipLaunchKernelGGL((k_subtract_t<H>), g, b, lds, s, fd, n, \
+                                  bs, stamps));                           \
+    break;
+    IPP_SUB_CASE(1) IPP_SUB_CASE(2) IPP_SUB_CASE(3) IPP_SUB_CASE(4)
+    IPP_SUB_CASE(5) IPP_SUB_CASE(6) IPP_SUB_CASE(7) IPP_SUB_CASE(8)
+    IPP_SUB_CASE(9) IPP_SUB_CASE(10) IPP_SUB_CASE(11) IPP_SUB_CASE(12)
+    IPP_SUB_CASE(13) IPP_SUB_CASE(14) IPP_SUB_CASE(15)
+#undef IPP_SUB_CASE
+    default:
+      return fail(c, IPP_E_INVALID_ARG, "half_width must be in [1, 15]");
+  }
   return IPP_OK;
 }
 

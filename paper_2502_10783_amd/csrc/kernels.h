@@ -105,9 +105,14 @@ __global__ void k_kron(Work wk, ipp_sources src, const double* mom,
                        double kfac, double rmin, double search, double* kron,
                        double* flux, double* area, uint32_t* flags);
 
-// Stamp convolution and subtraction: one workgroup per stamp.
-__global__ void k_subtract(const SubFrame* frames, int nframes, SubBasis bs,
-                           int64_t total_stamps);
+// Stamp convolution and subtraction: one workgroup per stamp, HW = the
+// kernel half-width; launched with sub_threads(stamp) threads and
+// sub_lds_bytes(stamp, HW) bytes of dynamic LDS.
+template <int HW>
+__global__ void k_subtract_t(const SubFrame* frames, int nframes,
+                             SubBasis bs, int64_t total_stamps);
+size_t sub_lds_bytes(int stamp, int hw);
+int sub_threads(int stamp);
 
 __global__ void k_zscale(const GrayFrame* frames, double contrast,
                          double krej, int max_iter, double* z1z2,

@@ -47,10 +47,15 @@ __device__ __forceinline__ double atan_coef(int k) {
 // atan(t) for |t| <= 0.3 from the series (coefficient table coef): the
 // first term left out is below 2e-20 relative.
 __device__ __forceinline__ double atan_series(double t, const double* coef) {
-  const double t2 = t * t;
-  double s = coef[kAtanTerms - 1];
+  // all coefficients requested before the first is used: one wait for the
+  // table instead of one per term
+  double c[kAtanTerms];
 #pragma unroll
-  for (int k = kAtanTerms - 2; k >= 0; --k) s = fma(s, t2, coef[k]);
+  for (int k = 0; k < kAtanTerms; ++k) c[k] = coef[k];
+  const double t2 = t * t;
+  double s = c[kAtanTerms - 1];
+#pragma unroll
+  for (int k = kAtanTerms - 2; k >= 0; --k) s = fma(s, t2, c[k]);
   return t * s;
 }
 
@@ -145,8 +150,15 @@ __device__ __forceinline__ double overlap_cut(double cx, double cy, double r,
   const double sx0 = x0 < 0.0 ? -1.0 : 1.0, sx1 = x1 < 0.0 ? -1.0 : 1.0;
   const double sy0 = y0 < 0.0 ? -1.0 : 1.0, sy1 = y1 < 0.0 ? -1.0 : 1.0;
   if (r >= 0.75) {
-    double lin = 0.0, re = 1.0, im = 0.0;
-    corner_rot(ax1, ay1, hx1, xs1, sx1 * sy1, r2, lin, re, im);
+    // the first corner's rotation is the corner's own (1 times it)
+    double lin, re, im;
+    {
+      const double sig = sx1 * sy1;
+      const bool out = ax1 * ax1 + ay1 * ay1 > r2;
+      lin = sig * (out ? 0.5 * (ay1 * xs1 + ax1 * hx1) : ax1 * ay1);
+      re = out ? hx1 * ay1 + ax1 * xs1 : 1.0;
+      im = out ? sig * (ax1 * ay1 - xs1 * hx1) : 0.0;
+    }
     corner_rot(ax0, ay1, hx0, xs1, -(sx0 * sy1), r2, lin, re, im);
     corner_rot(ax1, ay0, hx1, xs0, -(sx1 * sy0), r2, lin, re, im);
     corner_rot(ax0, ay0, hx0, xs0, sx0 * sy0, r2, lin, re, im);
