@@ -436,7 +436,9 @@ def run_next(args):
                "labels": [torch.empty(f.shape, dtype=torch.int32,
                                       device=dev) for f in frames],
                "rms": [torch.empty_like(f) for f in frames]}
-    ctx.process_batch(frames, p, table=table, outputs=outputs)
+    # the deblending thresholds need the rms maps
+    ctx.process_batch(frames, p, table=table, outputs=outputs,
+                      write_rms=True)
     torch.cuda.synchronize()
     nsrc = table.count()
     sp = SubtractParams()

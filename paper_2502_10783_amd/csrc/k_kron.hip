@@ -13,7 +13,10 @@
 // of the form / R^2) maps the ellipse onto the unit disk and the pixel
 // onto a parallelogram, whose intersection with the disk is summed edge by
 // edge (a triangle where an edge piece lies inside the disk, a circular
-// sector where it lies outside), then divided by det L.
+// sector where it lies outside), then divided by det L.  A pixel whose
+// four corners lie inside the ellipse (q <= R^2 with a relative margin of
+// 1e-12) is wholly inside it, its area exactly 1; only the other member
+// pixels are listed (LDS) and then computed, every lane busy.
 //
 // The membership tests (q against search^2, the frame bounds) use the
 // same binary64 operations as the oracle; the sums are taken over the
@@ -21,6 +24,7 @@
 // sequential sums to rounding).
 #include "ipp_internal.h"
 #include "kernels.h"
+#include "phot_geom.h"
 
 namespace ipp {
 
@@ -54,8 +58,10 @@ __device__ double min_q(double X, double Y, double xy, double det, double x0,
   return best;
 }
 
-// Signed area of the unit disk inside the triangle (0, a, b).
-__device__ double disk_tri(double ax, double ay, double bx, double by) {
+// Signed area of the unit disk inside the triangle (0, a, b); sector
+// angles from the atan series table coef.
+__device__ double disk_tri(double ax, double ay, double bx, double by,
+                           const double* coef) {
   const double dx = bx - ax, dy = by - ay;
   const double A = dx * dx + dy * dy;
   if (A == 0.0) return 0.0;
@@ -84,7 +90,7 @@ __device__ double disk_tri(double ax, double ay, double bx, double by) {
     if (mx * mx + my * my <= 1.0)
       area += 0.5 * cr;
     else
-      area += 0.5 * atan2(cr, px * qx + py * qy);
+      area += 0.5 * angle_of(px * qx + py * qy, cr, coef);
   }
   return area;
 }
@@ -107,7 +113,7 @@ __device__ __forceinline__ Ell ell_map(double X, double Y, double xy,
 
 // Exact area of pixel (px, py) inside the ellipse centred at (cx, cy).
 __device__ double ell_overlap(const Ell& e, double cx, double cy, int px,
-                              int py) {
+                              int py, const double* coef) {
   const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
   const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
   // corners in counter-clockwise order for x right, y up: a positive sum
@@ -117,7 +123,7 @@ __device__ double ell_overlap(const Ell& e, double cx, double cy, int px,
   double a = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    a += disk_tri(ux[k], uy[k], ux[(k + 1) & 3], uy[(k + 1) & 3]);
+    a += disk_tri(ux[k], uy[k], ux[(k + 1) & 3], uy[(k + 1) & 3], coef);
   return a * e.inv_det;
 }
 
@@ -129,6 +135,14 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
                                                  double search, double* kron,
                                                  double* flux, double* area,
                                                  uint32_t* flags) {
+  // pixels of the Kron ellipse cut by its boundary: py << 16 | px offsets
+  // from the window corner, per wave
+  constexpr int kCut = 1024;
+  __shared__ int cut_lds[kWaves][kCut];
+  __shared__ double atan_lds[kAtanTerms];
+  if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
+  __syncthreads();
+  int* cut = cut_lds[threadIdx.x / kWave];
   const int lane = threadIdx.x & (kWave - 1);
   long long nrows = src.capacity;
   if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
@@ -209,23 +223,68 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
     double fs = 0.0, as = 0.0;
     bool edge = false;
     const double R2 = R * R;
-    for (int e = lane; e < npx2; e += kWave) {
-      const int py = ya2 + e / nwx2, px = xa2 + e % nwx2;
-      // the pixel meets the open ellipse: an exact predicate
-      if (!(min_q(X, Y, xy, det, (double)px - 0.5 - cx, (double)px + 0.5 - cx,
-                  (double)py - 0.5 - cy, (double)py + 0.5 - cy) < R2))
-        continue;
-      const bool in = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
-      float I = 0.0f;
-      if (in) I = fr.pix[(int64_t)py * fr.pitch + px];
-      if (!in || !isfinite(I)) {
-        edge = true;
-        continue;
+    // corners inside: q det <= R^2 det (1 - 1e-12), no division
+    const double lim = R2 * det * (1.0 - 1e-12);
+    // members wholly inside are summed here, the others listed, in chunks
+    // of kCut pixels of the window (so that the list cannot overflow)
+    for (int e0 = 0; e0 < npx2; e0 += kCut) {
+      int ncut = 0;
+      const int e1 = min(npx2, e0 + kCut);
+      for (int eb = e0; eb < e1; eb += kWave) {
+        const int e = eb + lane;
+        bool listed = false;
+        int pos = 0;
+        if (e < e1) {
+          const int wy = e / nwx2, wx = e - (e / nwx2) * nwx2;
+          const int py = ya2 + wy, px = xa2 + wx;
+          const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
+          const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
+          // the pixel meets the open ellipse: an exact predicate
+          if (min_q(X, Y, xy, det, x0, x1, y0, y1) < R2) {
+            const bool in = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
+            float I = 0.0f;
+            if (in) I = fr.pix[(int64_t)py * fr.pitch + px];
+            if (!in || !isfinite(I)) {
+              edge = true;
+            } else {
+              auto qd = [&](double dx, double dy) {
+                return Y * dx * dx + X * dy * dy - 2.0 * xy * dx * dy;
+              };
+              if (qd(x0, y0) <= lim && qd(x1, y0) <= lim &&
+                  qd(x0, y1) <= lim && qd(x1, y1) <= lim) {
+                const double v =
+                    (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
+                fs += v;
+                as += 1.0;
+              } else {
+                listed = true;
+                pos = (wy << 16) | wx;
+              }
+            }
+          }
+        }
+        const uint64_t b = ballot(listed);
+        if (listed) cut[ncut + lanes_before(b)] = pos;
+        ncut += __popcll(b);
       }
-      const double w = ell_overlap(el, cx, cy, px, py);
-      const double v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
-      fs += w * v;
-      as += w;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j = lane; j < ncut; j += kWave) {
+        int co = 0;
+        asm volatile("" : "+s"(co));
+        const double* coef = atan_lds + co;
+        const int t = cut[j];
+        const int px = xa2 + (t & 0xFFFF), py = ya2 + (t >> 16);
+        const double w = ell_overlap(el, cx, cy, px, py, coef);
+        const double v = (double)fr.pix[(int64_t)py * fr.pitch + px] -
+                         (double)fr.bkg[(int64_t)py * fr.w + px];
+        fs += w * v;
+        as += w;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     fs = wave_sum(fs);
     as = wave_sum(as);

@@ -44,11 +44,16 @@ __device__ double poly2(const double* c, int d, double xn, double yn) {
 // thread's row segment is whole float4s).
 constexpr int kSubHead = kSubMaxBasis + 2;
 static_assert((kSubHead * sizeof(double)) % 16 == 0, "float4 alignment");
-__host__ __device__ int sub_groups(int stamp) { return (stamp + 3) / 4; }
+constexpr int kSubOut = 4;           // adjacent outputs per thread
+__host__ __device__ int sub_groups(int stamp) {
+  return (stamp + kSubOut - 1) / kSubOut;
+}
 __host__ __device__ int sub_kstride(int hw) { return (2 * hw + 1 + 3) & ~3; }
-__host__ __device__ int sub_nr(int hw) { return (2 * hw + 4 + 3) / 4; }
+__host__ __device__ int sub_nr(int hw) {
+  return (2 * hw + kSubOut + 3) / 4;
+}
 __host__ __device__ int sub_tstride(int stamp, int hw) {
-  return 4 * (sub_groups(stamp) - 1) + 4 * sub_nr(hw);
+  return kSubOut * (sub_groups(stamp) - 1) + 4 * sub_nr(hw);
 }
 size_t sub_lds_bytes(int stamp, int hw) {
   const int kw = 2 * hw + 1, th = stamp + 2 * hw;
@@ -61,16 +66,17 @@ int sub_threads(int stamp) {
   return ((t + kWave - 1) / kWave) * kWave;
 }
 
-// One workgroup per stamp; each thread computes four adjacent outputs of
-// one row, with its template row segment (2 HW + 4 values) and the kernel
-// row in registers: per kernel row 4 (2 HW + 1) FMAs for about HW float4
-// LDS reads.  Each output sums a kernel row's products in binary32, taps
+// One workgroup per stamp (two wavefronts for the default 21-pixel
+// stamps); each thread computes kSubOut adjacent outputs of one row, with
+// its template row segment (2 HW + kSubOut values) and the kernel row in
+// registers: per kernel row kSubOut (2 HW + 1) FMAs for about HW + 2
+// float4 LDS reads.  Each output sums a kernel row's products in binary32, taps
 // in order, and the rows in binary64, rows in order.
 template <int HW>
 __global__ __launch_bounds__(kBlock) void k_subtract_t(
     const SubFrame* frames, int nframes, SubBasis bs, int64_t total_stamps) {
   constexpr int KW = 2 * HW + 1;
-  constexpr int NR = (2 * HW + 4 + 3) / 4;    // float4s of a row segment
+  constexpr int NR = (2 * HW + kSubOut + 3) / 4;  // float4s of a segment
   constexpr int KR = (KW + 3) / 4;            // float4s of a kernel row
   extern __shared__ __align__(16) unsigned char sub_lds[];
   double* a_s = (double*)sub_lds;             // a_n, then B at kSubMaxBasis
@@ -80,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_subtract_t(
   float* tile = ker + KW * ks;
   const int th = S + 2 * HW;
   const int t = threadIdx.x, nt = blockDim.x;
-  const int ly = t / G, lx0 = 4 * (t - (t / G) * G);
+  const int ly = t / G, lx0 = kSubOut * (t - (t / G) * G);
   for (int64_t st = blockIdx.x; st < total_stamps; st += gridDim.x) {
     // frame of this stamp (frames are few: a linear search)
     int f = 0;
@@ -139,7 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_subtract_t(
     __syncthreads();
     const int ow = x1 - x0, oh = y1 - y0;
     if (ly < oh && lx0 < ow) {
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      double acc[kSubOut];
+#pragma unroll
+      for (int i = 0; i < kSubOut; ++i) acc[i] = 0.0;
       for (int vv = 0; vv < KW; ++vv) {          // vv = v + HW
         // R(x - u, y - v) = tile[ly + 2HW - vv][lx + 2HW - uu]
         float r[4 * NR];
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_subtract_t(
           kr[4 * q + 2] = a.z; kr[4 * q + 3] = a.w;
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < kSubOut; ++i) {
           float rs = 0.0f;
 #pragma unroll
           for (int uu = 0; uu < KW; ++uu)        // uu = u + HW
@@ -171,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_subtract_t(
       const double B = a_s[kSubMaxBasis];
       const int64_t gy = y0 + ly;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < kSubOut; ++i) {
         const int lx = lx0 + i;
         if (lx < ow) {
           const int64_t gx = x0 + lx;
