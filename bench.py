@@ -428,6 +428,8 @@ def run_next(args):
     frames = make_frames("stack16", nfr, dev)
     templates = [torch.roll(f, shifts=(1, 1), dims=(0, 1)).contiguous()
                  for f in frames]
+    if args.calib_copy:
+        calibration_copy(args.calib_copy, dev)
     npx = sum(f.numel() for f in frames)
     ctx = ipp.Context(0)
     p = ipp.Params()

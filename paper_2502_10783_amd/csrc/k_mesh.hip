@@ -862,6 +862,8 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
     int below = 0, nS = n0;
     double med = 0, mean = 0, sd = 0;
     bool have = false;
+    // float bounds of the current set (every finite value at the start)
+    float pflo = -__builtin_inff(), pfhi = __builtin_inff();
     for (int it = 0; n0 > 0 && it <= p.clip_iters; ++it) {
       const int r0 = below + (nS - 1) / 2, r1 = below + nS / 2;
       uint32_t k0, k1;
@@ -881,26 +883,52 @@ __attribute__((amdgpu_waves_per_eu(PPL == 64 ? 4 : 6))) void k_mesh_stats_w(Work
       nhi = nhi < khi ? nhi : khi;
       // float bounds of the key interval (a NaN value fails both tests)
       const float flo = key_lo_f(nlo), fhi = key_hi_f(nhi);
-      int cin = 0, cb = 0;
-      double t1 = 0.0, t2 = 0.0;
+      // The new set is the current one less its values outside
+      // [flo, fhi]: only those are visited (a register whose pixels all
+      // stay is skipped by the whole wave) and their moments subtracted.
+      int nrem = 0, nremlo = 0;
+      double q1 = 0.0, q2 = 0.0;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        const float v = key[k];
-        const bool in = v >= flo && v <= fhi;
-        cin += __popcll(__builtin_amdgcn_ballot_w64(v >= flo) &
-                        __builtin_amdgcn_ballot_w64(v <= fhi));
-        cb += __popcll(__builtin_amdgcn_ballot_w64(v < flo));
-        const double d = (double)(in ? v : c0f) - c0;
-        t1 += d;
-        t2 = fma(d, d, t2);
+        const float v = fresh(key[k]);
+        const bool was = v >= pflo && v <= pfhi;
+        const bool lo_ = v < flo;
+        const uint64_t gm = __builtin_amdgcn_ballot_w64(was & (lo_ | (v > fhi)));
+        if (gm) {
+          nrem += __popcll(gm);
+          nremlo += __popcll(__builtin_amdgcn_ballot_w64(was & lo_));
+          const bool gone = (gm >> lane) & 1ull;
+          const double d = gone ? (double)v - c0 : 0.0;
+          q1 += d;
+          q2 = fma(d, d, q2);
+        }
       }
       // summed before the exit test, so that the per-pixel terms are not
       // deferred past it and kept alive
-      cin = uni(cin);
-      cb = uni(cb);
-      t1 = uni(wave_sum(t1));
-      t2 = uni(wave_sum(t2));
+      const int cin = nS - uni(nrem);
+      const int cb = below + uni(nremlo);
+      q1 = uni(wave_sum(q1));
+      q2 = uni(wave_sum(q2));
       if (cin == nS) break;          // nothing rejected: data stabilised
+      double t1 = s1 - q1, t2 = s2 - q2;
+      if (q2 > 16384.0 * t2) {
+        // the removed values dominated the sums: the survivors' moments
+        // are summed afresh, so that no cancellation reaches them
+        t1 = 0.0;
+        t2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          const float v = fresh(key[k]);
+          const bool in = v >= flo && v <= fhi;
+          const double d = (double)(in ? v : c0f) - c0;
+          t1 += d;
+          t2 = fma(d, d, t2);
+        }
+        t1 = uni(wave_sum(t1));
+        t2 = uni(wave_sum(t2));
+      }
+      pflo = flo;
+      pfhi = fhi;
       klo = nlo; khi = nhi; below = cb; nS = cin;
       s1 = t1;
       s2 = t2;
