@@ -1503,11 +1503,19 @@ ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
   if ((st = scan64(c, need, blk, D.nblk, off, rows, tot, s)) != IPP_OK)
     return st;
   const dim3 g1(grid_for(rows, 64, 1 << 20));
-  IPP_LAUNCH(c, s, "k_db_run",
-             hipLaunchKernelGGL(k_db_run, g1, dim3(64), 0, s, w, *cand, off,
-                                tot, pool, pool_units, p->det_nsigma,
-                                p->connectivity, dp->nthresh, dp->clean,
-                                dp->mincont, dp->clean_param, cnt));
+  IPP_LAUNCH(c, s, "k_db_small",
+             hipLaunchKernelGGL(k_db_small,
+                                dim3(grid_for(rows, kWaves, 1 << 16)),
+                                dim3(kBlock), 0, s, w, *cand, off, tot, pool,
+                                pool_units, p->det_nsigma, p->connectivity,
+                                dp->nthresh, dp->clean, dp->mincont,
+                                dp->clean_param, cnt));
+  IPP_LAUNCH(c, s, "k_db_large",
+             hipLaunchKernelGGL(k_db_large, dim3(grid_for(rows, 1, 2048)),
+                                dim3(kBlock), 0, s, w, *cand, off, tot, pool,
+                                pool_units, p->det_nsigma, p->connectivity,
+                                dp->nthresh, dp->clean, dp->mincont,
+                                dp->clean_param, cnt));
   if ((st = scan64(c, cnt, blk, D.nblk, ooff, rows, tot + 1, s)) != IPP_OK)
     return st;
   int64_t maxpix = 1;

@@ -1,8 +1,6 @@
-// Multi-threshold deblending and cleaning of one detection candidate
-// (Sec. 2.2.5: deblending and cleaning phases), one thread per candidate as
-// in the paper's own GPU mapping of these phases.  Host and device code:
-// the kernel runs it per candidate on the GPU; the same routine compiled
-// for the host checks the algorithm against the oracle without a GPU.
+// Records and helpers of multi-threshold deblending and cleaning
+// (Sec. 2.2.5: deblending and cleaning phases), shared by the kernels in
+// k_deblend.hip.
 //
 // Readings (the paper states the phases, not their formulas):
 //  levels   t0 = nsigma R32(peak pixel); q = (peak / t0)^(1/N) by log2(N)
@@ -31,8 +29,14 @@
 // subtree splits, and the intensity can only grow towards the root, so a
 // run of single-child nodes is kept as one chain record (its top node, its
 // bottom node, their intensities).  Chains are created where a node has
-// two or more children; there are at most twice as many chains as leaves,
-// and at most as many leaves as pixels.
+// two or more children, numbered in the raster order of the children's
+// first pixels; there are at most twice as many chains as leaves, and at
+// most as many leaves as pixels.
+//
+// Exact sums: every sum of fixed-point weights is an integer sum, kept as
+// 64-bit sums of 32-bit limbs (a term T = sum_j L_j 2^(32 j), L_0..L_2 in
+// [0, 2^32), L_3 = T >> 96) so that they can be added in any order, by any
+// thread, and rebuilt exactly as a 128-bit integer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,57 +59,70 @@ struct Chain {
   int32_t mode;              // 0 the top node is the object, 1 children's
   int32_t bmode;             // 1 all significant children, 2 the one
   int32_t allsig;            // every node below the top is significant
-  int32_t reached, objof, slot;
+  int32_t reached, objof;    // on the object path; object chain (or -1)
+  int32_t slot;              // seed index of an object chain
+  int32_t first;             // first pixel of an object chain's seed
 };
 
+// One seed / object.  m[s][j]: limb j of the seed sums S = sum d,
+// Sx = sum d dx, Sy = sum d dy, Sxx = sum d dx^2, Syy = sum d dy^2 (dx, dy
+// about the seed's corner); fin: limbs 0 and 1 of the final pixels' sum
+// (d = hi 2^32 + lo, hi the signed part), nfin their count.
 struct Obj {
-  __int128 S, Sx, Sy, Sxx, Syy;      // exact seed sums (about seed corner)
-  __int128 Sfin;                     // exact sum over the final pixels
-  double F, xc, yc, s2;
+  int64_t m[5][4];
+  int64_t fin[2];
   int64_t nfin;
+  double F, xc, yc, s2;
   int32_t xmin, ymin, first, target;
-};
-
-// Per-candidate scratch; A = bounding-box pixels, m = candidate pixels.
-struct Scratch {
-  __int128* accS;   // [A]
-  Obj* objs;        // [m + 1]
-  Chain* chains;    // [2 m + 2]
-  double* val;      // [A] v of members, -inf elsewhere (filled by caller)
-  int32_t* par;     // [A]
-  int32_t* ch;      // [A]
-  int32_t* accN;    // [A]
-  int32_t* roots;   // [A]
-  int32_t* asg;     // [A] out: object index of members, -1 elsewhere
-  int32_t chain_cap, obj_cap;
+  int32_t final_obj, idx;    // object after merges; survivor number
 };
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
-// Bytes of scratch for a bounding box of A pixels holding m candidate
-// pixels, and the carving of a block of that size.
-__host__ __device__ inline size_t scratch_bytes(int64_t A, int64_t m) {
-  return align16(16 * (size_t)A) + align16(sizeof(Obj) * (size_t)(m + 1)) +
+// Per-candidate scratch in the pool; A = bounding-box pixels, m =
+// candidate pixels.  par / ch serve boxes too large for the kernel's LDS;
+// the per-root arrays (indexed by the root's raster rank at a level) serve
+// levels with more roots than the LDS holds.
+struct Pool {
+  double* val;      // [A] v of members, -inf elsewhere
+  int32_t* par;     // [A] union-find parent (also the seed marks)
+  int32_t* ch;      // [A] chain of each pixel's node
+  int32_t* asg;     // [A] out: object index of members, -1 elsewhere
+  int64_t* accL;    // [A] per root: low limb sums
+  int64_t* accH;    // [A] per root: high (signed) limb sums
+  int32_t* accN;    // [A] per root: pixel counts
+  int32_t* pch;     // [A] per root: the parent node's chain
+  int32_t* nch;     // [A] per root: the root's chain at this level
+  Chain* chains;    // [2 m + 2]
+  Obj* objs;        // [m + 1]
+  int32_t chain_cap, obj_cap;
+};
+
+__host__ __device__ inline size_t pool_bytes(int64_t A, int64_t m) {
+  return 3 * align16(8 * (size_t)A) + 6 * align16(4 * (size_t)A) +
          align16(sizeof(Chain) * (size_t)(2 * m + 2)) +
-         align16(8 * (size_t)A) + 5 * align16(4 * (size_t)A);
+         align16(sizeof(Obj) * (size_t)(m + 1));
 }
 
-__host__ __device__ inline Scratch carve(char* b, int64_t A, int64_t m) {
-  Scratch s;
+__host__ __device__ inline Pool carve(char* b, int64_t A, int64_t m) {
+  Pool s;
   size_t o = 0;
-  s.accS = (__int128*)(b + o);
-  o += align16(16 * (size_t)A);
-  s.objs = (Obj*)(b + o);
-  o += align16(sizeof(Obj) * (size_t)(m + 1));
-  s.chains = (Chain*)(b + o);
-  o += align16(sizeof(Chain) * (size_t)(2 * m + 2));
-  s.val = (double*)(b + o);
-  o += align16(8 * (size_t)A);
-  int32_t** ints[] = {&s.par, &s.ch, &s.accN, &s.roots, &s.asg};
-  for (auto p : ints) {
-    *p = (int32_t*)(b + o);
-    o += align16(4 * (size_t)A);
-  }
+  auto take = [&](size_t bytes) {
+    char* r = b + o;
+    o += align16(bytes);
+    return r;
+  };
+  s.val = (double*)take(8 * (size_t)A);
+  s.accL = (int64_t*)take(8 * (size_t)A);
+  s.accH = (int64_t*)take(8 * (size_t)A);
+  s.par = (int32_t*)take(4 * (size_t)A);
+  s.ch = (int32_t*)take(4 * (size_t)A);
+  s.asg = (int32_t*)take(4 * (size_t)A);
+  s.accN = (int32_t*)take(4 * (size_t)A);
+  s.pch = (int32_t*)take(4 * (size_t)A);
+  s.nch = (int32_t*)take(4 * (size_t)A);
+  s.chains = (Chain*)take(sizeof(Chain) * (size_t)(2 * m + 2));
+  s.objs = (Obj*)take(sizeof(Obj) * (size_t)(m + 1));
   s.chain_cap = (int32_t)(2 * m + 2);
   s.obj_cap = (int32_t)(m + 1);
   return s;
@@ -143,317 +160,16 @@ __host__ __device__ inline int64_t fixed_d(double v) {
   return (int64_t)s;
 }
 
-__host__ __device__ inline int uf_find(int32_t* par, int p) {
-  while (par[p] != p) {
-    par[p] = par[par[p]];
-    p = par[p];
-  }
-  return p;
+// The 128-bit value of four limb sums (see the header).
+__host__ __device__ inline __int128 from_limbs4(const int64_t* l) {
+  return (__int128)l[0] + ((__int128)l[1] << 32) + ((__int128)l[2] << 64) +
+         ((__int128)l[3] << 96);
 }
 
-// Union linking the larger root to the smaller: a set's root is its
-// smallest index, i.e. its first pixel in raster order.
-__host__ __device__ inline void uf_union(int32_t* par, int a, int b) {
-  a = uf_find(par, a);
-  b = uf_find(par, b);
-  if (a < b) par[b] = a;
-  else if (b < a) par[a] = b;
-}
-
-struct Cand {
-  int32_t bw, bh, x0, y0;   // bounding box
-  int32_t npix;
-  double t0, peak;
-  int32_t conn, nthresh, clean;
-  double mincont, kc;
-};
-
-// Deblends one candidate whose member values are in s.val.  Returns the
-// number of objects (>= 1) with s.asg set for every member, or -1 when the
-// chain or object records would exceed the scratch (not reachable with the
-// bounds of scratch_bytes).
-__host__ __device__ inline int deblend_one(const Cand& c, Scratch& s) {
-  const int A = c.bw * c.bh;
-  const double two_m28 = 0x1p-28;
-  const double ninf = -__builtin_inf();          // value of non-members
-  for (int p = 0; p < A; ++p) s.asg[p] = s.val[p] != ninf ? 0 : -1;
-  if (!(c.t0 > 0.0) || c.npix < 2 || !(c.peak > c.t0)) return 1;
-
-  // levels
-  double lev[kMaxLevels];
-  double q = c.peak / c.t0;
-  for (int k = c.nthresh; k > 1; k >>= 1) q = sqrt(q);
-  {
-    double t = c.t0;
-    for (int i = 1; i < c.nthresh; ++i) {
-      t = t * q;
-      lev[i] = t;
-    }
-  }
-  // the candidate's flux and the contrast bound
-  __int128 Sroot = 0;
-  for (int p = 0; p < A; ++p)
-    if (s.asg[p] == 0) Sroot += fixed_d(s.val[p]);
-  const double froot = to_f64(Sroot) * two_m28;
-  const double fmin = c.mincont * froot;
-
-  // root chain
-  int nch = 1;
-  {
-    Chain& r = s.chains[0];
-    r.F_top = r.F_bot = froot;
-    r.nobj_sum = 0;
-    r.parent = -1;
-    r.lev_top = r.lev_bot = 0;
-    r.cnt = r.nsig = 0;
-    r.one = -1;
-    r.nobj = 1;
-    r.mode = r.bmode = 0;
-    r.allsig = 1;
-    r.reached = 0;
-    r.objof = -1;
-    r.slot = -1;
-  }
-  for (int p = 0; p < A; ++p) s.ch[p] = 0;
-
-  // levels upward: components, their intensities, chain records
-  for (int i = 1; i < c.nthresh; ++i) {
-    const double t = lev[i];
-    int any = 0;
-    for (int p = 0; p < A; ++p) {
-      const bool up = s.val[p] > t;
-      s.par[p] = up ? p : -1;
-      any |= up;
-    }
-    if (!any) break;
-    for (int y = 0; y < c.bh; ++y) {
-      for (int x = 0; x < c.bw; ++x) {
-        const int p = y * c.bw + x;
-        if (s.par[p] < 0) continue;
-        if (x > 0 && s.par[p - 1] >= 0) uf_union(s.par, p, p - 1);
-        if (y > 0) {
-          const int u = p - c.bw;
-          if (s.par[u] >= 0) uf_union(s.par, p, u);
-          if (c.conn == 8) {
-            if (x > 0 && s.par[u - 1] >= 0) uf_union(s.par, p, u - 1);
-            if (x + 1 < c.bw && s.par[u + 1] >= 0) uf_union(s.par, p, u + 1);
-          }
-        }
-      }
-    }
-    int nroots = 0;
-    for (int p = 0; p < A; ++p) {
-      if (s.par[p] < 0) continue;
-      const int r = uf_find(s.par, p);
-      if (r == p) {                  // the root is the first pixel
-        s.roots[nroots++] = p;
-        s.accS[p] = 0;
-        s.accN[p] = 0;
-      }
-      s.accS[r] += fixed_d(s.val[p]);
-      s.accN[r] += 1;
-    }
-    for (int k = 0; k < nroots; ++k) s.chains[s.ch[s.roots[k]]].cnt = 0;
-    for (int k = 0; k < nroots; ++k) s.chains[s.ch[s.roots[k]]].cnt += 1;
-    for (int k = 0; k < nroots; ++k) {
-      const int r = s.roots[k];
-      const int pc = s.ch[r];
-      const double F = to_f64(s.accS[r]) * two_m28 - (double)s.accN[r] * t;
-      int nc = pc;
-      if (s.chains[pc].cnt == 1) {   // the chain goes on
-        s.chains[pc].lev_bot = i;
-        s.chains[pc].F_bot = F;
-        s.chains[pc].allsig &= F > fmin ? 1 : 0;
-      } else {                       // a branch: a chain per child
-        if (nch >= s.chain_cap) return -1;
-        nc = nch++;
-        Chain& ch = s.chains[nc];
-        ch.F_top = ch.F_bot = F;
-        ch.nobj_sum = 0;
-        ch.parent = pc;
-        ch.lev_top = ch.lev_bot = i;
-        ch.cnt = ch.nsig = 0;
-        ch.one = -1;
-        ch.nobj = 1;
-        ch.mode = ch.bmode = 0;
-        ch.allsig = 1;
-        ch.reached = 0;
-        ch.objof = -1;
-        ch.slot = -1;
-      }
-      s.accN[r] = nc;               // the root's chain at this level
-    }
-    for (int p = 0; p < A; ++p)
-      if (s.par[p] >= 0) s.ch[p] = s.accN[uf_find(s.par, p)];
-  }
-
-  // pruning, children before parents (they were created later)
-  for (int k = nch - 1; k >= 0; --k) {
-    Chain& C = s.chains[k];
-    int bmode = 0;
-    int64_t nb = 1;
-    if (C.nsig >= 2) {
-      bmode = 1;
-      nb = C.nobj_sum;
-    } else if (C.nsig == 1 && s.chains[C.one].nobj >= 2) {
-      bmode = 2;
-      nb = s.chains[C.one].nobj;
-    }
-    C.bmode = bmode;
-    // the chain's top stands for its bottom's objects only if every node
-    // between passes them up (each significant)
-    if (bmode != 0 && C.allsig) {
-      C.mode = 1;
-      C.nobj = (int32_t)nb;
-    } else {
-      C.mode = 0;
-      C.nobj = 1;
-    }
-    if (C.parent >= 0 && C.F_top > fmin) {
-      Chain& P = s.chains[C.parent];
-      P.nsig += 1;
-      P.nobj_sum += C.nobj;
-      P.one = k;
-    }
-  }
-  if (s.chains[0].nobj < 2) return 1;
-
-  // objects, parents before children
-  int K = 0;
-  for (int k = 0; k < nch; ++k) {
-    Chain& C = s.chains[k];
-    if (k == 0) {
-      C.reached = 1;
-    } else {
-      const Chain& P = s.chains[C.parent];
-      C.reached = P.reached && P.mode == 1 &&
-                  ((P.bmode == 1 && C.F_top > fmin) ||
-                   (P.bmode == 2 && P.one == k));
-    }
-    const bool obj = C.reached && C.mode == 0;
-    C.objof = obj ? k : (k > 0 ? s.chains[C.parent].objof : -1);
-    C.slot = -1;
-  }
-  // seeds: object slots in raster order of their first pixels
-  for (int p = 0; p < A; ++p) {
-    if (s.asg[p] < 0) continue;
-    const int o = s.chains[s.ch[p]].objof;
-    if (o < 0) {
-      s.asg[p] = -2;                 // not in a seed
-      continue;
-    }
-    Chain& C = s.chains[o];
-    if (C.slot < 0) {
-      if (K >= s.obj_cap) return -1;
-      C.slot = K;
-      Obj& b = s.objs[K++];
-      b.S = b.Sx = b.Sy = b.Sxx = b.Syy = b.Sfin = 0;
-      b.nfin = 0;
-      b.first = p;
-      b.xmin = p % c.bw;
-      b.ymin = p / c.bw;
-      b.target = -1;
-    }
-    Obj& b = s.objs[C.slot];
-    const int x = p % c.bw;
-    if (x < b.xmin) b.xmin = x;
-    s.asg[p] = C.slot;
-  }
-  // seed moments about each seed's corner, and the models
-  for (int p = 0; p < A; ++p) {
-    const int k = s.asg[p];
-    if (k < 0) continue;
-    Obj& b = s.objs[k];
-    const int64_t d = fixed_d(s.val[p]);
-    const int64_t dx = p % c.bw - b.xmin, dy = p / c.bw - b.ymin;
-    b.S += d;
-    b.Sx += (__int128)d * dx;
-    b.Sy += (__int128)d * dy;
-    b.Sxx += (__int128)d * (dx * dx);
-    b.Syy += (__int128)d * (dy * dy);
-  }
-  for (int k = 0; k < K; ++k) {
-    Obj& b = s.objs[k];
-    const double fS = to_f64(b.S);
-    const double mx = to_f64(b.Sx) / fS;
-    const double my = to_f64(b.Sy) / fS;
-    const double x2 = to_f64(b.Sxx) / fS - mx * mx;
-    const double y2 = to_f64(b.Syy) / fS - my * my;
-    b.F = fS * two_m28;
-    b.xc = (double)(c.x0 + b.xmin) + mx;
-    b.yc = (double)(c.y0 + b.ymin) + my;
-    b.s2 = (x2 + y2) + 1.0 / 6.0;
-  }
-  // the other pixels: the brightest model
-  for (int p = 0; p < A; ++p) {
-    if (s.asg[p] != -2) continue;
-    const double x = (double)(c.x0 + p % c.bw);
-    const double y = (double)(c.y0 + p / c.bw);
-    double best = -1.0;
-    int bk = 0;
-    for (int k = 0; k < K; ++k) {
-      const Obj& b = s.objs[k];
-      const double dx = x - b.xc;
-      const double dy = y - b.yc;
-      const double d2 = dx * dx + dy * dy;
-      const double den = b.s2 + d2;
-      const double sc = (b.F * b.s2) / (den * den);
-      if (sc > best) {
-        best = sc;
-        bk = k;
-      }
-    }
-    s.asg[p] = bk;
-  }
-  if (!c.clean) return K;
-
-  // cleaning
-  for (int p = 0; p < A; ++p) {
-    const int k = s.asg[p];
-    if (k < 0) continue;
-    s.objs[k].Sfin += fixed_d(s.val[p]);
-    s.objs[k].nfin += 1;
-  }
-  const double pi = 3.14159265358979311600;   // binary64 nearest to pi
-  for (int o = 0; o < K; ++o) {
-    Obj& b = s.objs[o];
-    const double mu = to_f64(b.Sfin) * two_m28 / (double)b.nfin;
-    double tot = 0.0, best = -1.0;
-    int bm = -1;
-    for (int m = 0; m < K; ++m) {
-      if (m == o) continue;
-      const Obj& n = s.objs[m];
-      const bool brighter = n.F > b.F || (n.F == b.F && m < o);
-      if (!brighter) continue;
-      const double dx = b.xc - n.xc;
-      const double dy = b.yc - n.yc;
-      const double d2 = dx * dx + dy * dy;
-      double den = n.s2 + d2;
-      den = den * den;
-      den = pi * den;
-      const double cm = c.kc * ((n.F * n.s2) / den);
-      tot += cm;
-      if (cm > best) {
-        best = cm;
-        bm = m;
-      }
-    }
-    b.target = (bm >= 0 && mu - tot < c.t0) ? bm : o;
-  }
-  // follow merges to an object that stays; number the survivors in order
-  int nk = 0;
-  for (int o = 0; o < K; ++o) {
-    int k = o;
-    while (s.objs[k].target != k) k = s.objs[k].target;
-    s.objs[o].first = k;             // final object (reuses the field)
-  }
-  for (int o = 0; o < K; ++o)
-    s.objs[o].xmin = s.objs[o].first == o ? nk++ : -1;  // survivor index
-  for (int p = 0; p < A; ++p) {
-    const int k = s.asg[p];
-    if (k >= 0) s.asg[p] = s.objs[s.objs[k].first].xmin;
-  }
-  return nk;
+// The 128-bit value of a low (unsigned 32-bit terms) and a high (signed)
+// limb sum.
+__host__ __device__ inline __int128 from_limbs2(int64_t lo, int64_t hi) {
+  return (__int128)lo + ((__int128)hi << 32);
 }
 
 }  // namespace db

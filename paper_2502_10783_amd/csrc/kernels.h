@@ -82,10 +82,19 @@ __global__ void k_scan64_top(int64_t* blocks, int64_t nblocks,
                              int64_t* total);
 __global__ void k_scan64_apply(const int64_t* in, const int64_t* blocks,
                                int64_t* out, int64_t n);
-__global__ void k_db_run(Work wk, ipp_sources cand, const int64_t* off,
-                         const int64_t* tot, char* pool, int64_t pool_units,
-                         double nsigma, int conn, int nthresh, int clean,
-                         double mincont, double kc, int64_t* cnt);
+// Bounding boxes up to this many pixels take a wavefront, larger ones a
+// workgroup.
+constexpr int kDbSmallBox = 512;
+__global__ void k_db_small(Work wk, ipp_sources cand, const int64_t* off,
+                           const int64_t* tot, char* pool,
+                           int64_t pool_units, double nsigma, int conn,
+                           int nthresh, int clean, double mincont, double kc,
+                           int64_t* cnt);
+__global__ void k_db_large(Work wk, ipp_sources cand, const int64_t* off,
+                           const int64_t* tot, char* pool,
+                           int64_t pool_units, double nsigma, int conn,
+                           int nthresh, int clean, double mincont, double kc,
+                           int64_t* cnt);
 __global__ void k_db_zero(Work wk);
 __global__ void k_db_write(Work wk, ipp_sources cand, const int64_t* off,
                            const int64_t* tot, const char* pool,

@@ -152,3 +152,48 @@ def test_small_object_capacity_and_scratch_growth(ctx):
     with pytest.raises(ipp.IppError):
         ctx.deblend(frames, Bt, Rt, det["labels"], det["table"], p,
                     ipp.DeblendParams(nthresh=24))
+
+
+def _plateau_spikes(h, w, boxes, seed):
+    """Flat plateaus (20 sigma) carrying single-pixel spikes on a grid of
+    pitch `step` ((y0, x0, size, step) per plateau; step 0: three Gaussian
+    stars instead): components with many roots per level and bounding
+    boxes on both sides of the wavefront / workgroup and LDS limits."""
+    rng = np.random.default_rng(900 + seed)
+    y, x = np.mgrid[0:h, 0:w].astype(np.float64)
+    img = 50.0 + rng.normal(0, 1.0, (h, w))
+    for (y0, x0, n, step) in boxes:
+        img[y0:y0 + n, x0:x0 + n] += 20.0
+        if step == 0:
+            for _ in range(3):
+                xc = rng.uniform(x0 + 4, x0 + n - 4)
+                yc = rng.uniform(y0 + 4, y0 + n - 4)
+                img += rng.uniform(500, 5000) / (2 * np.pi * 2.0) * np.exp(
+                    -((x - xc) ** 2 + (y - yc) ** 2) / 4.0)
+            continue
+        for yy in range(y0, y0 + n, step):
+            for xx in range(x0 + (yy - y0) % 2 * (step == 1),
+                            x0 + n, max(step, 2)):
+                img[yy, xx] += rng.uniform(100, 5000)
+    img = img.astype(np.float32)
+    return img, np.full_like(img, 50.0), np.full_like(img, 1.0)
+
+
+def test_large_boxes_and_many_roots(ctx):
+    # a 90 x 90 plateau with 2025 spikes (box beyond the LDS arrays, more
+    # roots per level than LDS holds, thousands of objects), a 40 x 40
+    # plateau with three stars (a workgroup, LDS arrays) and a 20 x 20 one
+    # (a wavefront)
+    p, dp, op = _params(min_area=3, det_nsigma=2.5, mincont=1e-4)
+    img, B, R = _plateau_spikes(
+        160, 200, [(4, 4, 90, 2), (110, 110, 40, 0), (120, 20, 20, 0)], 0)
+    assert _check(ctx, [img], [B], [R], p, dp, op) >= 2
+
+
+def test_many_roots_in_a_small_box(ctx):
+    # 4-connectivity, a 20 x 20 plateau whose spikes form a checkerboard:
+    # 200 components at the spike levels in a box a wavefront takes
+    p, dp, op = _params(min_area=3, det_nsigma=2.5, connectivity=4,
+                        mincont=1e-4)
+    img, B, R = _plateau_spikes(40, 40, [(8, 8, 20, 1)], 1)
+    assert _check(ctx, [img], [B], [R], p, dp, op) >= 1
