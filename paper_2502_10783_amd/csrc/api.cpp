@@ -48,6 +48,7 @@ struct IppCtx {
   uint64_t tick = 0;
   hipStream_t cap = nullptr;      // private stream used only for capture
   bool use_graphs = true;
+  int n_cu = 256;                 // compute units of the device
 };
 
 namespace {
@@ -864,6 +865,10 @@ ipp_status ipp_ctx_create(void** ctx, int32_t device) {
   IppCtx* c = new (std::nothrow) IppCtx();
   if (!c) return IPP_E_DEVICE;
   c->device = device;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                            device) == hipSuccess && ncu > 0)
+    c->n_cu = ncu;
   *ctx = c;
   return IPP_OK;
 }
@@ -1503,19 +1508,27 @@ ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
   if ((st = scan64(c, need, blk, D.nblk, off, rows, tot, s)) != IPP_OK)
     return st;
   const dim3 g1(grid_for(rows, 64, 1 << 20));
+  // persistent workgroups (as many as fit the device at once) that take
+  // candidates from a counter: tot[2] and tot[3]
+  IPP_LAUNCH(c, s, "k_fill_i64",
+             hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, tot + 2,
+                                (int64_t)2, (int64_t)0));
   IPP_LAUNCH(c, s, "k_db_small",
              hipLaunchKernelGGL(k_db_small,
-                                dim3(grid_for(rows, kWaves, 1 << 16)),
+                                dim3(grid_for(rows, kWaves,
+                                              c->n_cu * kDbSmallPerCu)),
                                 dim3(kBlock), 0, s, w, *cand, off, tot, pool,
                                 pool_units, p->det_nsigma, p->connectivity,
                                 dp->nthresh, dp->clean, dp->mincont,
-                                dp->clean_param, cnt));
+                                dp->clean_param, cnt, tot + 2));
   IPP_LAUNCH(c, s, "k_db_large",
-             hipLaunchKernelGGL(k_db_large, dim3(grid_for(rows, 1, 2048)),
+             hipLaunchKernelGGL(k_db_large,
+                                dim3(grid_for(rows, 1,
+                                              c->n_cu * kDbLargePerCu)),
                                 dim3(kBlock), 0, s, w, *cand, off, tot, pool,
                                 pool_units, p->det_nsigma, p->connectivity,
                                 dp->nthresh, dp->clean, dp->mincont,
-                                dp->clean_param, cnt));
+                                dp->clean_param, cnt, tot + 3));
   if ((st = scan64(c, cnt, blk, D.nblk, ooff, rows, tot + 1, s)) != IPP_OK)
     return st;
   int64_t maxpix = 1;

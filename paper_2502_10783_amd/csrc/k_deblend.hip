@@ -240,16 +240,22 @@ __device__ __forceinline__ void min_at(int* p, int v) {
   __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Union-find over par (-1: not in the level's mask).  Linking always puts
-// the larger root under the smaller, so a component's root is its first
-// pixel; the find does not compress (other threads link concurrently).
-__device__ __forceinline__ int uf_find(const int* par, int x) {
-  int px = ld_at(par + x);
-  while (px != x) {
-    x = px;
-    px = ld_at(par + x);
+// Union-find over par (-1: not in the level's mask).  Every word points to
+// a smaller index of the same component (linking puts the larger root
+// under the smaller), so a component's root is its first pixel.  The find
+// halves the path it walks: a word is overwritten with its grandparent,
+// which keeps both properties; a link that such a write replaces belongs
+// to a union whose atomic found its target already linked, and that union
+// joins the target's new root itself before it returns.
+__device__ __forceinline__ int uf_find(int* par, int x) {
+  while (true) {
+    const int px = ld_at(par + x);
+    if (px == x) return x;
+    const int gp = ld_at(par + px);
+    if (gp == px) return px;
+    st_at(par + x, gp);
+    x = gp;
   }
-  return x;
 }
 __device__ __forceinline__ void uf_unite(int* par, int a, int b) {
   while (true) {
@@ -404,29 +410,53 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
   double t = c.t0;
   for (int i = 1; i < nthresh; ++i) {
     t = t * q;
+    // the level's mask; each horizontal run of a wavefront's 64 pixels
+    // points to its first pixel, which points to the pixel before it when
+    // the run goes on from the previous 64
     bool anyup = false;
     for (int c0 = 0; c0 < A; c0 += T) {
       const int p = c0 + g.tid;
+      bool up = false;
+      int x = 0;
       if (p < A) {
-        const bool up = s.val[p] > t;
-        par[p] = up ? p : -1;
-        anyup |= up;
+        up = s.val[p] > t;
+        x = p - row_of(p) * bw;
+      }
+      anyup |= up;
+      const uint64_t um = ballot(up);
+      const uint64_t starts = (um & ~(um << 1)) | (um & ballot(x == 0)) | (um & 1ull);
+      if (p < A) {
+        int v = -1;
+        if (up) {
+          const int j =
+              63 - __builtin_clzll(starts & ((2ull << g.lane) - 1ull));
+          if (j < g.lane) v = p - (g.lane - j);
+          else v = (g.lane == 0 && x > 0 && s.val[p - 1] > t) ? p - 1 : p;
+        }
+        par[p] = v;
       }
     }
     if (!g.any(anyup)) break;
     g.sync();
+    // links to the row above: a run's first pixel takes its upper-left and
+    // upper neighbours, every pixel its upper-right one (8-connectivity),
+    // which covers every pair of the run and the row above; with
+    // 4-connectivity every pixel its upper neighbour
     for (int c0 = 0; c0 < A; c0 += T) {
       const int p = c0 + g.tid;
       if (p < A && ld_at(par + p) >= 0) {
         const int y = row_of(p), x = p - y * bw;
-        if (x > 0 && ld_at(par + p - 1) >= 0) uf_unite(par, p, p - 1);
         if (y > 0) {
           const int u = p - bw;
-          if (ld_at(par + u) >= 0) uf_unite(par, p, u);
           if (conn == 8) {
-            if (x > 0 && ld_at(par + u - 1) >= 0) uf_unite(par, p, u - 1);
+            if (!(x > 0 && ld_at(par + p - 1) >= 0)) {
+              if (x > 0 && ld_at(par + u - 1) >= 0) uf_unite(par, p, u - 1);
+              if (ld_at(par + u) >= 0) uf_unite(par, p, u);
+            }
             if (x + 1 < bw && ld_at(par + u + 1) >= 0)
               uf_unite(par, p, u + 1);
+          } else if (ld_at(par + u) >= 0) {
+            uf_unite(par, p, u);
           }
         }
       }
@@ -645,30 +675,33 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
               [&](int kk, int v) { min_at(&s.objs[kk].xmin, v); });
   }
   g.sync();
-  // seed moments about each seed's corner
+  // seed moments about each seed's corner, one sum at a time
   for (int c0 = 0; c0 < A; c0 += T) {
     const int p = c0 + g.tid;
     int k = -1;
-    int64_t v[20];
-#pragma unroll
-    for (int j = 0; j < 20; ++j) v[j] = 0;
+    int64_t d = 0, dx = 0, dy = 0;
     if (p < A) {
       k = s.asg[p];
       if (k >= 0) {
         const db::Obj& b = s.objs[k];
         const int y = row_of(p), x = p - y * bw;
-        const int64_t d = db::fixed_d(s.val[p]);
-        const int64_t dx = x - ld_at(&b.xmin), dy = y - b.ymin;
-        limbs4((__int128)d, v);
-        limbs4((__int128)d * dx, v + 4);
-        limbs4((__int128)d * dy, v + 8);
-        limbs4((__int128)d * (dx * dx), v + 12);
-        limbs4((__int128)d * (dy * dy), v + 16);
+        d = db::fixed_d(s.val[p]);
+        dx = x - ld_at(&b.xmin);
+        dy = y - b.ymin;
       }
     }
-    keyed_add<20>(k >= 0, k, v, g.lane, [&](int kk, int j, int64_t sum) {
-      add_at(&s.objs[kk].m[j >> 2][j & 3], sum);
-    });
+    for (int a = 0; a < 5; ++a) {
+      const int64_t f = a == 0   ? 1
+                        : a == 1 ? dx
+                        : a == 2 ? dy
+                        : a == 3 ? dx * dx
+                                 : dy * dy;
+      int64_t v[4];
+      limbs4((__int128)d * f, v);
+      keyed_add<4>(k >= 0, k, v, g.lane, [&](int kk, int j, int64_t sum) {
+        add_at(&s.objs[kk].m[a][j], sum);
+      });
+    }
   }
   g.sync();
   for (int k = g.tid; k < K; k += T) {
@@ -793,15 +826,16 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
 }
 
 // Candidates with bounding boxes of more than amin and at most amax
-// pixels, one per group; with `trivial`, also the counts of the rows
+// pixels, one per group, taken from the queue counter in row order; with
+// `trivial`, also the counts of the rows
 // that need no deblending (beyond the table: 0; single pixels, or every
 // row when the pool is too small: 1).
 template <int NW, int APX, int RCAP>
 __device__ __forceinline__ void db_groups(
     Work wk, ipp_sources cand, const int64_t* off, const int64_t* tot,
     char* pool, int64_t pool_units, double nsigma, int conn, int nthresh,
-    int clean, double mincont, double kc, int64_t* cnt, int64_t amin,
-    int64_t amax, bool trivial) {
+    int clean, double mincont, double kc, int64_t* cnt, int64_t* queue,
+    int64_t amin, int64_t amax, bool trivial) {
   constexpr int G = kBlock / (kWave * NW);
   __shared__ DbLds<NW, APX, RCAP> lds[G];
   const int gi = threadIdx.x / (kWave * NW);
@@ -821,8 +855,24 @@ __device__ __forceinline__ void db_groups(
     }
   }
   if (!fits) return;
-  for (long long r = (long long)blockIdx.x * G + gi; r < n;
-       r += (long long)gridDim.x * G) {
+  __shared__ long long next_row;
+  while (true) {
+    // the next row from the queue (a wavefront's lane 0, or the
+    // workgroup's thread 0 through LDS)
+    long long r = 0;
+    if constexpr (NW == 1) {
+      long long v = 0;
+      if (g.lane == 0)
+        v = (long long)atomicAdd((unsigned long long*)queue, 1ull);
+      r = __shfl(v, 0, kWave);
+    } else {
+      if (g.tid == 0)
+        next_row = (long long)atomicAdd((unsigned long long*)queue, 1ull);
+      __syncthreads();
+      r = next_row;
+      __syncthreads();
+    }
+    if (r >= n) break;
     const int m = cand.npix[r];
     DbCand c;
     c.x0 = cand.xmin[r];
@@ -856,13 +906,14 @@ __device__ __forceinline__ void db_groups(
 }  // namespace
 
 // Boxes of up to 512 pixels: a wavefront per candidate.
-__global__ __launch_bounds__(kBlock) void k_db_small(
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(3))) void k_db_small(
     Work wk, ipp_sources cand, const int64_t* off, const int64_t* tot,
     char* pool, int64_t pool_units, double nsigma, int conn, int nthresh,
-    int clean, double mincont, double kc, int64_t* cnt) {
+    int clean, double mincont, double kc, int64_t* cnt, int64_t* queue) {
   db_groups<1, kDbSmallBox, 128>(wk, cand, off, tot, pool, pool_units,
                                  nsigma, conn, nthresh, clean, mincont, kc,
-                                 cnt, -1, kDbSmallBox, true);
+                                 cnt, queue, -1, kDbSmallBox, true);
 }
 
 // Larger boxes: a workgroup per candidate (LDS arrays up to 4096 pixels
@@ -870,10 +921,10 @@ __global__ __launch_bounds__(kBlock) void k_db_small(
 __global__ __launch_bounds__(kBlock) void k_db_large(
     Work wk, ipp_sources cand, const int64_t* off, const int64_t* tot,
     char* pool, int64_t pool_units, double nsigma, int conn, int nthresh,
-    int clean, double mincont, double kc, int64_t* cnt) {
+    int clean, double mincont, double kc, int64_t* cnt, int64_t* queue) {
   db_groups<kWaves, 4096, 1024>(wk, cand, off, tot, pool, pool_units,
                                 nsigma, conn, nthresh, clean, mincont, kc,
-                                cnt, kDbSmallBox, INT64_MAX, false);
+                                cnt, queue, kDbSmallBox, INT64_MAX, false);
 }
 
 __global__ __launch_bounds__(kBlock) void k_db_zero(Work wk) {

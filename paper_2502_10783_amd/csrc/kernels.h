@@ -85,16 +85,19 @@ __global__ void k_scan64_apply(const int64_t* in, const int64_t* blocks,
 // Bounding boxes up to this many pixels take a wavefront, larger ones a
 // workgroup.
 constexpr int kDbSmallBox = 512;
+// Resident workgroups per compute unit of the two kernels (LDS and
+// register limits); queue: a zeroed counter of taken rows.
+constexpr int kDbSmallPerCu = 3, kDbLargePerCu = 2;
 __global__ void k_db_small(Work wk, ipp_sources cand, const int64_t* off,
                            const int64_t* tot, char* pool,
                            int64_t pool_units, double nsigma, int conn,
                            int nthresh, int clean, double mincont, double kc,
-                           int64_t* cnt);
+                           int64_t* cnt, int64_t* queue);
 __global__ void k_db_large(Work wk, ipp_sources cand, const int64_t* off,
                            const int64_t* tot, char* pool,
                            int64_t pool_units, double nsigma, int conn,
                            int nthresh, int clean, double mincont, double kc,
-                           int64_t* cnt);
+                           int64_t* cnt, int64_t* queue);
 __global__ void k_db_zero(Work wk);
 __global__ void k_db_write(Work wk, ipp_sources cand, const int64_t* off,
                            const int64_t* tot, const char* pool,
