@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 REFINE_STEPS = 10
 REFINE_RC = 2.0
+REFINE_ETA = 3.0
 
 # Algorithmic HBM bytes of each per-pixel kernel per pixel of the batch:
 # what the step must move through that kernel, not what the implementation
@@ -263,6 +264,15 @@ def run_grad(args):
     v = torch.stack(frames) - torch.stack(bkg)
     dy = torch.ones_like(v)
     a, b = 30.0, 1.0
+    xr = torch.empty(s, dtype=torch.float64, device=dev)
+    yr = torch.empty_like(xr)
+
+    def refine():
+        ctx.refine_centroids(frames, bkg, t, p, steps=REFINE_STEPS,
+                             r_c=REFINE_RC, eta=REFINE_ETA, x_out=xr,
+                             y_out=yr)
+    if args.calib_copy:
+        calibration_copy(args.calib_copy, dev)
 
     def timed(fn, k):
         for _ in range(max(1, args.warmup)):
@@ -281,11 +291,13 @@ def run_grad(args):
     ms = timed(step, args.steps)
     ms_fwd = timed(lambda: ctx.asinh(v, a, b), args.steps)
     ms_bwd = timed(lambda: ctx.asinh_backward(v, dy, a, b), args.steps)
+    ms_ref = timed(refine, args.steps)
     ctx.profile(True)
     for _ in range(3):
         step()
         ctx.asinh(v, a, b)
         ctx.asinh_backward(v, dy, a, b)
+        refine()
     torch.cuda.synchronize()
     prof = ctx.profile_read()
     ctx.profile(False)
@@ -316,6 +328,10 @@ def run_grad(args):
             "backward_frac_of_hbm": round(
                 12 * npx / (ms_bwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "bytes_per_px": {"forward": 8, "backward": 12}},
+        "refinement": {
+            "steps": REFINE_STEPS, "r_c": REFINE_RC, "eta": REFINE_ETA,
+            "ms": round(ms_ref, 4),
+            "sources_per_s": round(s / (ms_ref * 1e-3), 1)},
         "kernels_ms": {k: round(v0 / v1, 4) for k, (v0, v1) in
                        sorted(prof.items(), key=lambda kv: -kv[1][0])},
     }
@@ -843,7 +859,7 @@ def run_pipeline(workload, args, dev, quick=False):
                    "min_area": p.min_area,
                    "aperture": [p.r_ap, p.r_in, p.r_out],
                    "refinement": ({"steps": REFINE_STEPS, "r_c": REFINE_RC,
-                                   "eta": 3.0} if refine else None)},
+                                   "eta": REFINE_ETA} if refine else None)},
         "kernels_ms_per_step": {k: round(v["ms_total"], 4) for k, v in
                                 sorted(kern.items(),
                                        key=lambda kv: -kv[1]["ms_total"])},
