@@ -391,7 +391,7 @@ ipp_status ipp_asinh_backward_noalloc(void* ctx, const float* v,
  * the candidate label of each object.  Rows beyond obj->capacity are not
  * written (n_total still counts them).  Scratch: the workspace beyond the
  * fixed part (ipp_deblend_workspace_bytes with scratch_bytes); a candidate
- * needs 48 B per bounding-box pixel plus 400 B per pixel.  diag
+ * needs 48 B per bounding-box pixel plus 368 B per pixel.  diag
  * (device int64[4], nullable): [0] scratch bytes needed, [1] available,
  * [2] nonzero if candidates were left whole for lack of scratch, [3]
  * objects found.

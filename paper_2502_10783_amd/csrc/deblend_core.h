@@ -27,11 +27,11 @@
 // Tree representation: chains.  A node with exactly one child at the next
 // level and that child carry the same objects unless the child's own
 // subtree splits, and the intensity can only grow towards the root, so a
-// run of single-child nodes is kept as one chain record (its top node, its
-// bottom node, their intensities).  Chains are created where a node has
-// two or more children, numbered in the raster order of the children's
-// first pixels; there are at most twice as many chains as leaves, and at
-// most as many leaves as pixels.
+// run of single-child nodes is kept as one chain record (its top node's
+// intensity, and whether every node below the top is significant).  Chains
+// are created where a node has two or more children, numbered in the
+// raster order of the children's first pixels; there are at most twice as
+// many chains as leaves, and at most as many leaves as pixels.
 //
 // Exact sums: every sum of fixed-point weights is an integer sum, kept as
 // 64-bit sums of 32-bit limbs (a term T = sum_j L_j 2^(32 j), L_0..L_2 in
@@ -48,10 +48,9 @@ namespace db {
 constexpr int kMaxLevels = 64;      // nthresh: a power of two in [2, 64]
 
 struct Chain {
-  double F_top, F_bot;       // intensity above level at the top / bottom
+  double F_top;              // intensity above its level of the top node
   int64_t nobj_sum;          // objects of the significant child chains
   int32_t parent;            // chain of the parent node (-1: the root)
-  int32_t lev_top, lev_bot;  // levels of the top and bottom nodes
   int32_t cnt;               // children at the level being built
   int32_t nsig;              // significant child chains
   int32_t one;               // a significant child chain (nsig == 1)

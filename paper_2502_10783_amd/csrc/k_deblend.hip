@@ -159,6 +159,17 @@ struct Grp {
       __syncthreads();
     }
   }
+  // Orders LDS accesses only (a level of a wavefront's candidate whose
+  // shared words are all in LDS: its global stores need not complete).
+  __device__ __forceinline__ void sync_lds() const {
+    if constexpr (NW == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+      __syncthreads();
+    }
+  }
   __device__ __forceinline__ bool any(bool f) const {
     if constexpr (NW == 1) return ballot(f) != 0;
     else return __syncthreads_or(f ? 1 : 0) != 0;
@@ -211,13 +222,18 @@ struct Grp {
   }
 };
 
+// LDS of one group: APX pixels of union-find and chain words, RCAP roots
+// per level, and (a wavefront's candidates, NW = 1) one byte per chain
+// record that a level found a node below the chain's top insignificant.
 template <int NW, int APX, int RCAP>
 struct DbLds {
+  static constexpr int kClr = NW == 1 ? 2 * APX + 16 : 1;
   int par[APX], ch[APX];
   int64_t accL[RCAP], accH[RCAP];
   int accN[RCAP], pch[RCAP], nch[RCAP];
   int red[NW];
   int64_t red64[2 * NW];
+  uint8_t clr[kClr];
 };
 
 // Accesses of words that other threads of the group update atomically.
@@ -324,14 +340,11 @@ __device__ __forceinline__ void limbs4(__int128 t, int64_t* l) {
   l[3] = (int64_t)(t >> 96);
 }
 
-__device__ __forceinline__ void chain_init(db::Chain& c, double F, int parent,
-                                           int lev) {
+__device__ __forceinline__ void chain_init(db::Chain& c, double F,
+                                           int parent) {
   c.F_top = F;
-  c.F_bot = F;
   c.nobj_sum = 0;
   c.parent = parent;
-  c.lev_top = lev;
-  c.lev_bot = lev;
   c.cnt = 0;
   c.nsig = 0;
   c.one = -1;
@@ -369,8 +382,15 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
     else if ((y + 1) * bw <= p) ++y;
     return y;
   };
-  int* par = A <= APX ? L.par : s.par;
-  int* ch = A <= APX ? L.ch : s.ch;
+  // a wavefront's candidate (NW = 1, at most APX pixels and, with either
+  // connectivity, at most APX / 2 roots per level) keeps every word a level
+  // shares in LDS, so its levels synchronise on LDS alone and its chain
+  // records are only written (children counted, significance flags kept in
+  // LDS); a workgroup's candidate may use the pool
+  constexpr bool kLds = NW == 1;
+  static_assert(!kLds || 2 * RCAP >= APX, "a level's roots fit the LDS");
+  int* par = (kLds || A <= APX) ? L.par : s.par;
+  int* ch = (kLds || A <= APX) ? L.ch : s.ch;
   const double ninf = -__builtin_inf();
 
   // members' values, the candidate's flux
@@ -401,19 +421,30 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
   const double fmin = mincont * froot;
   double q = c.peak / c.t0;
   for (int k = nthresh; k > 1; k >>= 1) q = sqrt(q);
-  if (g.tid == 0) chain_init(s.chains[0], froot, -1, 0);
+  if (g.tid == 0) chain_init(s.chains[0], froot, -1);
+  if constexpr (kLds) {
+    if (g.tid == 0) L.clr[0] = 0;
+  }
   g.sync();
 
   // levels upward: components, their intensities, chain records
+  auto lsync = [&] {
+    if constexpr (kLds) g.sync_lds();
+    else g.sync();
+  };
   int nch = 1;
   bool fail = false;
   double t = c.t0;
+  // the last full level: its mask size, roots and per-root arrays
+  int nup_prev = -1, nroots = 0;
+  int64_t *aL = nullptr, *aH = nullptr;
+  int *aN = nullptr, *pc = nullptr, *nc = nullptr;
   for (int i = 1; i < nthresh; ++i) {
     t = t * q;
     // the level's mask; each horizontal run of a wavefront's 64 pixels
     // points to its first pixel, which points to the pixel before it when
     // the run goes on from the previous 64
-    bool anyup = false;
+    int nup = 0;                       // this wave's mask pixels
     for (int c0 = 0; c0 < A; c0 += T) {
       const int p = c0 + g.tid;
       bool up = false;
@@ -422,8 +453,8 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
         up = s.val[p] > t;
         x = p - row_of(p) * bw;
       }
-      anyup |= up;
       const uint64_t um = ballot(up);
+      nup += __popcll(um);
       const uint64_t starts = (um & ~(um << 1)) | (um & ballot(x == 0)) | (um & 1ull);
       if (p < A) {
         int v = -1;
@@ -436,8 +467,37 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
         par[p] = v;
       }
     }
-    if (!g.any(anyup)) break;
-    g.sync();
+    if (!g.any(nup > 0)) break;
+    // the masks are nested, so a mask of the previous full level's size is
+    // that mask: the same components, each its parent node's only child;
+    // every chain goes on and only the intensities above this level change
+    {
+      int all = nup;
+      if constexpr (NW > 1) {
+        __syncthreads();
+        if (g.lane == 0) g.red[g.wave] = nup;
+        __syncthreads();
+        all = 0;
+        for (int w = 0; w < NW; ++w) all += g.red[w];
+      }
+      nup = all;
+    }
+    if (nup == nup_prev) {
+      for (int k = g.tid; k < nroots; k += T) {
+        const double F =
+            db::to_f64(db::from_limbs2(ld_at(aL + k), ld_at(aH + k))) *
+                0x1p-28 -
+            (double)ld_at(aN + k) * t;
+        if (!(F > fmin)) {
+          if constexpr (kLds) L.clr[nc[k]] = 1;
+          else s.chains[nc[k]].allsig = 0;
+        }
+      }
+      lsync();
+      continue;
+    }
+    nup_prev = nup;
+    lsync();
     // links to the row above: a run's first pixel takes its upper-left and
     // upper neighbours, every pixel its upper-right one (8-connectivity),
     // which covers every pair of the run and the row above; with
@@ -461,7 +521,7 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
         }
       }
     }
-    g.sync();
+    lsync();
     for (int c0 = 0; c0 < A; c0 += T) {
       const int p = c0 + g.tid;
       if (p < A && ld_at(par + p) >= 0) {
@@ -469,9 +529,9 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
         if (r != p) st_at(par + p, r);
       }
     }
-    g.sync();
+    lsync();
     // roots in raster order: a root's word becomes -2 - rank
-    int nroots = 0;
+    nroots = 0;
     for (int c0 = 0; c0 < A; c0 += T) {
       const int p = c0 + g.tid;
       const bool isroot = p < A && ld_at(par + p) == p;
@@ -480,18 +540,18 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
       if (isroot) par[p] = -2 - k;
       nroots += tot;
     }
-    const bool rl = nroots <= RCAP;
-    int64_t* aL = rl ? L.accL : s.accL;
-    int64_t* aH = rl ? L.accH : s.accH;
-    int* aN = rl ? L.accN : s.accN;
-    int* pc = rl ? L.pch : s.pch;
-    int* nc = rl ? L.nch : s.nch;
+    const bool rl = kLds || nroots <= RCAP;
+    aL = rl ? L.accL : s.accL;
+    aH = rl ? L.accH : s.accH;
+    aN = rl ? L.accN : s.accN;
+    pc = rl ? L.pch : s.pch;
+    nc = rl ? L.nch : s.nch;
     for (int k = g.tid; k < nroots; k += T) {
       aL[k] = 0;
       aH[k] = 0;
       aN[k] = 0;
     }
-    g.sync();
+    lsync();
     // exact sums of the weights and counts per component
     for (int c0 = 0; c0 < A; c0 += T) {
       const int p = c0 + g.tid;
@@ -516,12 +576,15 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
         else add_at(aN + k, (int)sum);
       });
     }
-    g.sync();
-    // children per parent chain
-    for (int k = g.tid; k < nroots; k += T) st_at(&s.chains[pc[k]].cnt, 0);
-    g.sync();
-    for (int k = g.tid; k < nroots; k += T) add_at(&s.chains[pc[k]].cnt, 1);
-    g.sync();
+    lsync();
+    // children per parent chain (a wavefront's candidate: counted from the
+    // roots' parent words in LDS)
+    if constexpr (!kLds) {
+      for (int k = g.tid; k < nroots; k += T) st_at(&s.chains[pc[k]].cnt, 0);
+      g.sync();
+      for (int k = g.tid; k < nroots; k += T) add_at(&s.chains[pc[k]].cnt, 1);
+      g.sync();
+    }
     // a parent with one child: its chain goes on; else a chain per child,
     // numbered in root order
     for (int k0 = 0; k0 < nroots; k0 += T) {
@@ -534,19 +597,29 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
         F = db::to_f64(db::from_limbs2(ld_at(aL + k), ld_at(aH + k))) *
                 0x1p-28 -
             (double)ld_at(aN + k) * t;
-        fresh = ld_at(&s.chains[pcv].cnt) != 1;
+        if constexpr (kLds) {
+          int nk = 0;
+          for (int j2 = 0; j2 < nroots; ++j2) nk += pc[j2] == pcv ? 1 : 0;
+          fresh = nk != 1;
+        } else {
+          fresh = ld_at(&s.chains[pcv].cnt) != 1;
+        }
       }
       int tot;
       const int j = nch + g.rank(fresh, &tot);
       if (k < nroots) {
         if (!fresh) {
-          db::Chain& C = s.chains[pcv];
-          C.lev_bot = i;
-          C.F_bot = F;
-          C.allsig &= F > fmin ? 1 : 0;
+          if constexpr (kLds) {
+            if (!(F > fmin)) L.clr[pcv] = 1;
+          } else {
+            s.chains[pcv].allsig &= F > fmin ? 1 : 0;
+          }
           nc[k] = pcv;
         } else {
-          if (j < s.chain_cap) chain_init(s.chains[j], F, pcv, i);
+          if (j < s.chain_cap) {
+            chain_init(s.chains[j], F, pcv);
+            if constexpr (kLds) L.clr[j] = 0;
+          }
           nc[k] = j;
         }
       }
@@ -556,7 +629,7 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
       fail = true;
       break;
     }
-    g.sync();
+    lsync();
     for (int c0 = 0; c0 < A; c0 += T) {
       const int p = c0 + g.tid;
       if (p < A) {
@@ -564,10 +637,15 @@ __device__ int deblend_group(const Grp<NW>& g, DbLds<NW, APX, RCAP>& L,
         if (pv != -1) ch[p] = nc[pv <= -2 ? -2 - pv : -2 - ld_at(par + pv)];
       }
     }
-    g.sync();
+    lsync();
   }
   g.sync();
   if (fail) return -1;
+  if constexpr (kLds) {
+    for (int j = g.tid; j < nch; j += T)
+      if (L.clr[j]) s.chains[j].allsig = 0;
+    g.sync();
+  }
 
   // pruning, children before parents (they were created later), then the
   // object path, parents before children: one thread
@@ -911,7 +989,7 @@ __attribute__((amdgpu_waves_per_eu(3))) void k_db_small(
     Work wk, ipp_sources cand, const int64_t* off, const int64_t* tot,
     char* pool, int64_t pool_units, double nsigma, int conn, int nthresh,
     int clean, double mincont, double kc, int64_t* cnt, int64_t* queue) {
-  db_groups<1, kDbSmallBox, 128>(wk, cand, off, tot, pool, pool_units,
+  db_groups<1, kDbSmallBox, kDbSmallBox / 2>(wk, cand, off, tot, pool, pool_units,
                                  nsigma, conn, nthresh, clean, mincont, kc,
                                  cnt, queue, -1, kDbSmallBox, true);
 }
