@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libipp.so")
+# IPP_LIB: another build of the library (e.g. the host-sanitized one)
+LIB_PATH = os.environ.get("IPP_LIB") or os.path.join(_HERE, "libipp.so")
 
 IPP_OK = 0
 IPP_E_INVALID_ARG = -1

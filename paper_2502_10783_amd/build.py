@@ -66,6 +66,47 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+# Host code built with AddressSanitizer and UndefinedBehaviorSanitizer (the
+# device code is unchanged): the validation, planning and launch code of
+# the ABI checked by the CPU tests, e.g.
+#   python paper_2502_10783_amd/build.py --sanitize-host
+#   LD_PRELOAD=$(hipcc --print-file-name=libclang_rt.asan-x86_64.so) \
+#   ASAN_OPTIONS=detect_leaks=0 IPP_LIB=_build/san/libipp_san.so \
+#   python -m pytest tests/test_abi.py -m "not gpu"
+SAN_DIR = os.path.join(BUILD_DIR, "san")
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host",
+       "-fsanitize=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile_san(src: str) -> str:
+    obj = os.path.join(SAN_DIR, os.path.basename(src) + ".o")
+    cmd = ([hipcc()] + [c if c != "-O3" else "-O1" for c in COMMON] +
+           ["-g"] + SAN + ["-x", "hip", "-c", src, "-o", obj])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
+    return obj
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = sources()
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(_compile_san, srcs))
+    out = os.path.join(SAN_DIR, "libipp_san.so")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + SAN[:4]
+    cmd += ["-shared-libsan", "-o", out] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    if verbose:
+        print(f"built {out}")
+    return out
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitize-host" in sys.argv[1:]:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)
     sys.exit(0)
