@@ -137,7 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
                                                  uint32_t* flags) {
   // pixels of the Kron ellipse cut by its boundary: py << 16 | px offsets
   // from the window corner, per wave
-  constexpr int kCut = 1024;
+  constexpr int kCut = 1024;            // a multiple of 64
+  constexpr int kChunk = 4;
   __shared__ int cut_lds[kWaves][kCut];
   __shared__ double atan_lds[kAtanTerms];
   if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
@@ -182,18 +183,42 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
     double num = 0.0, den = 0.0;
     const double s2 = search * search;
     if (xb >= xa && yb >= ya) {
+      // the window (inside the frame) in rounds of 64 pixels, positions
+      // stepped without division, the loads of kChunk rounds issued before
+      // any is used; each lane sums its pixels in window order
       const int nwx = xb - xa + 1;
       const int npx = nwx * (yb - ya + 1);
-      for (int e = lane; e < npx; e += kWave) {
-        const int py = ya + e / nwx, px = xa + e % nwx;
-        const double q = qform(X, Y, xy, det, (double)px - cx,
-                               (double)py - cy);
-        if (!(q <= s2)) continue;
-        const float I = fr.pix[(int64_t)py * fr.pitch + px];
-        if (!isfinite(I)) continue;
-        const double v = (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
-        num += sqrt(q) * v;
-        den += v;
+      const int dwr = kWave / nwx, dwc = kWave - dwr * nwx;
+      int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;
+      for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
+        float Iv[kChunk], Bv[kChunk];
+        int pxs[kChunk], pys[kChunk];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+          const bool live = e0 + c * kWave + lane < npx;
+          pxs[c] = live ? xa + wc : -1;
+          pys[c] = ya + wr;
+          const int qx = live ? xa + wc : xa, qy = live ? ya + wr : ya;
+          Iv[c] = fr.pix[(int64_t)qy * fr.pitch + qx];
+          Bv[c] = fr.bkg[(int64_t)qy * fr.w + qx];
+          wr += dwr;
+          wc += dwc;
+          if (wc >= nwx) {
+            wc -= nwx;
+            ++wr;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+          if (pxs[c] < 0) continue;
+          const double q = qform(X, Y, xy, det, (double)pxs[c] - cx,
+                                 (double)pys[c] - cy);
+          if (!(q <= s2)) continue;
+          if (!isfinite(Iv[c])) continue;
+          const double v = (double)Iv[c] - (double)Bv[c];
+          num += sqrt(q) * v;
+          den += v;
+        }
       }
     }
     num = wave_sum(num);
@@ -227,6 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
     const double lim = R2 * det * (1.0 - 1e-12);
     // members wholly inside are summed here, the others listed, in chunks
     // of kCut pixels of the window (so that the list cannot overflow)
+    // window positions stepped round by round without division
+    const int dwr2 = nwx2 > 0 ? kWave / nwx2 : 0;
+    const int dwc2 = kWave - dwr2 * nwx2;
+    int sy = nwx2 > 0 ? lane / nwx2 : 0, sx = lane - sy * nwx2;
     for (int e0 = 0; e0 < npx2; e0 += kCut) {
       int ncut = 0;
       const int e1 = min(npx2, e0 + kCut);
@@ -234,8 +263,14 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
         const int e = eb + lane;
         bool listed = false;
         int pos = 0;
+        const int wy = sy, wx = sx;          // this round's position
+        sy += dwr2;
+        sx += dwc2;
+        if (sx >= nwx2) {
+          sx -= nwx2;
+          ++sy;
+        }
         if (e < e1) {
-          const int wy = e / nwx2, wx = e - (e / nwx2) * nwx2;
           const int py = ya2 + wy, px = xa2 + wx;
           const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
           const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
