@@ -658,7 +658,7 @@ ipp_status run_refine(IppCtx* c, const Work& w, const ipp_params& p,
 // Deblending: fixed per-call arrays after the frame descriptors, then the
 // scratch pool (the rest of the workspace).
 struct DeblendWs {
-  size_t o_fd2, o_need, o_off, o_cnt, o_ooff, o_blk, o_tot, o_pool;
+  size_t o_fd2, o_need, o_off, o_cnt, o_ooff, o_blk, o_tot, o_big, o_pool;
   int64_t nblk;
 };
 
@@ -674,7 +674,8 @@ DeblendWs deblend_layout(size_t base, int32_t n, int64_t cap) {
   D.o_cnt = take(8 * rows);
   D.o_ooff = take(8 * rows);
   D.o_blk = take(8 * (size_t)(D.nblk + 1));
-  D.o_tot = take(8 * 4);
+  D.o_tot = take(8 * 8);
+  D.o_big = take(4 * rows);
   D.o_pool = o;
   return D;
 }
@@ -1496,23 +1497,28 @@ ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
   int64_t* ooff = (int64_t*)(b + D.o_ooff);
   int64_t* blk = (int64_t*)(b + D.o_blk);
   int64_t* tot = (int64_t*)(b + D.o_tot);
+  int32_t* big = (int32_t*)(b + D.o_big);
   char* pool = b + D.o_pool;
   const int64_t rows = cap + 1;
   IPP_LAUNCH(c, s, "k_fill_i64",
              hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s,
                                 w.counters, (int64_t)4, (int64_t)0));
+  // tot[2], tot[3]: the two kernels' queue counters; tot[4], tot[5]: the
+  // workgroup kernel's list lengths (boxes above kDbBigBox from the front
+  // of `big`, the other large boxes from its back)
+  IPP_LAUNCH(c, s, "k_fill_i64",
+             hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, tot + 2,
+                                (int64_t)4, (int64_t)0));
   IPP_LAUNCH(c, s, "k_db_need",
              hipLaunchKernelGGL(k_db_need,
                                 dim3(grid_for(rows, kBlock, 16384)),
-                                dim3(kBlock), 0, s, *cand, need));
+                                dim3(kBlock), 0, s, *cand, need, big,
+                                tot + 4));
   if ((st = scan64(c, need, blk, D.nblk, off, rows, tot, s)) != IPP_OK)
     return st;
   const dim3 g1(grid_for(rows, 64, 1 << 20));
   // persistent workgroups (as many as fit the device at once) that take
-  // candidates from a counter: tot[2] and tot[3]
-  IPP_LAUNCH(c, s, "k_fill_i64",
-             hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, tot + 2,
-                                (int64_t)2, (int64_t)0));
+  // candidates from a counter
   IPP_LAUNCH(c, s, "k_db_small",
              hipLaunchKernelGGL(k_db_small,
                                 dim3(grid_for(rows, kWaves,
@@ -1528,7 +1534,8 @@ ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
                                 dim3(kBlock), 0, s, w, *cand, off, tot, pool,
                                 pool_units, p->det_nsigma, p->connectivity,
                                 dp->nthresh, dp->clean, dp->mincont,
-                                dp->clean_param, cnt, tot + 3));
+                                dp->clean_param, cnt, tot + 3, big,
+                                tot + 4));
   if ((st = scan64(c, cnt, blk, D.nblk, ooff, rows, tot + 1, s)) != IPP_OK)
     return st;
   int64_t maxpix = 1;

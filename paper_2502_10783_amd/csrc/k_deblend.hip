@@ -49,8 +49,11 @@ __device__ __forceinline__ int64_t block_scan64(int64_t v, int64_t* red,
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void k_db_need(ipp_sources cand,
-                                                    int64_t* need) {
+                                                    int64_t* need,
+                                                    int32_t* big,
+                                                    int64_t* nbig) {
   const long long n = table_rows(cand);
+  const long long rows = cand.capacity + 1;
   for (long long r = blockIdx.x * (long long)kBlock + threadIdx.x;
        r <= cand.capacity; r += (long long)gridDim.x * kBlock) {
     int64_t u = 0;
@@ -58,6 +61,17 @@ __global__ __launch_bounds__(kBlock) void k_db_need(ipp_sources cand,
       const int64_t A = (int64_t)(cand.xmax[r] - cand.xmin[r] + 1) *
                         (cand.ymax[r] - cand.ymin[r] + 1);
       u = (int64_t)((db::pool_bytes(A, cand.npix[r]) + 255) / 256);
+      // the workgroup kernel's rows, largest boxes first (the two ends of
+      // one list of `rows` entries cannot meet)
+      if (A > kDbBigBox) {
+        const long long k =
+            (long long)atomicAdd((unsigned long long*)&nbig[0], 1ull);
+        big[k] = (int32_t)r;
+      } else if (A > kDbSmallBox) {
+        const long long k =
+            (long long)atomicAdd((unsigned long long*)&nbig[1], 1ull);
+        big[rows - 1 - k] = (int32_t)r;
+      }
     }
     need[r] = u;
   }
@@ -913,7 +927,8 @@ __device__ __forceinline__ void db_groups(
     Work wk, ipp_sources cand, const int64_t* off, const int64_t* tot,
     char* pool, int64_t pool_units, double nsigma, int conn, int nthresh,
     int clean, double mincont, double kc, int64_t* cnt, int64_t* queue,
-    int64_t amin, int64_t amax, bool trivial) {
+    int64_t amin, int64_t amax, bool trivial, const int32_t* big = nullptr,
+    const int64_t* nbig = nullptr) {
   constexpr int G = kBlock / (kWave * NW);
   __shared__ DbLds<NW, APX, RCAP> lds[G];
   const int gi = threadIdx.x / (kWave * NW);
@@ -949,6 +964,11 @@ __device__ __forceinline__ void db_groups(
       __syncthreads();
       r = next_row;
       __syncthreads();
+    }
+    if (big) {                         // the workgroup kernel's list
+      const long long nb0 = nbig[0], nb1 = nbig[1];
+      if (r >= nb0 + nb1) break;
+      r = r < nb0 ? big[r] : big[cand.capacity - (r - nb0)];
     }
     if (r >= n) break;
     const int m = cand.npix[r];
@@ -995,14 +1015,18 @@ __attribute__((amdgpu_waves_per_eu(3))) void k_db_small(
 }
 
 // Larger boxes: a workgroup per candidate (LDS arrays up to 4096 pixels
-// and 1024 roots, the pool beyond).
+// and 1024 roots, the pool beyond), taken from the list k_db_need made:
+// boxes over kDbBigBox pixels first, so that the longest candidates start
+// first.
 __global__ __launch_bounds__(kBlock) void k_db_large(
     Work wk, ipp_sources cand, const int64_t* off, const int64_t* tot,
     char* pool, int64_t pool_units, double nsigma, int conn, int nthresh,
-    int clean, double mincont, double kc, int64_t* cnt, int64_t* queue) {
+    int clean, double mincont, double kc, int64_t* cnt, int64_t* queue,
+    const int32_t* big, const int64_t* nbig) {
   db_groups<kWaves, 4096, 1024>(wk, cand, off, tot, pool, pool_units,
                                 nsigma, conn, nthresh, clean, mincont, kc,
-                                cnt, queue, kDbSmallBox, INT64_MAX, false);
+                                cnt, queue, kDbSmallBox, INT64_MAX, false,
+                                big, nbig);
 }
 
 __global__ __launch_bounds__(kBlock) void k_db_zero(Work wk) {

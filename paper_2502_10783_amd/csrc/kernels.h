@@ -75,7 +75,11 @@ __global__ void k_asinh_bwd_final(const double* partial, int nb,
 hipError_t asinh_scratch(int device, double** ptr);
 
 // Deblending (k_deblend.hip): see that file for the sequence.
-__global__ void k_db_need(ipp_sources cand, int64_t* need);
+// need: scratch units per row; big / nbig: the rows of boxes over
+// kDbSmallBox pixels, those over kDbBigBox from the front (nbig[0]), the
+// others from the back (nbig[1]); nbig zeroed by the caller.
+__global__ void k_db_need(ipp_sources cand, int64_t* need, int32_t* big,
+                          int64_t* nbig);
 __global__ void k_scan64_blocks(const int64_t* in, int64_t* blocks,
                                 int64_t n);
 __global__ void k_scan64_top(int64_t* blocks, int64_t nblocks,
@@ -88,6 +92,8 @@ constexpr int kDbSmallBox = 512;
 // Resident workgroups per compute unit of the two kernels (LDS and
 // register limits); queue: a zeroed counter of taken rows.
 constexpr int kDbSmallPerCu = 3, kDbLargePerCu = 2;
+// Boxes over this many pixels are taken first by the workgroup kernel.
+constexpr int kDbBigBox = 2048;
 __global__ void k_db_small(Work wk, ipp_sources cand, const int64_t* off,
                            const int64_t* tot, char* pool,
                            int64_t pool_units, double nsigma, int conn,
@@ -97,7 +103,8 @@ __global__ void k_db_large(Work wk, ipp_sources cand, const int64_t* off,
                            const int64_t* tot, char* pool,
                            int64_t pool_units, double nsigma, int conn,
                            int nthresh, int clean, double mincont, double kc,
-                           int64_t* cnt, int64_t* queue);
+                           int64_t* cnt, int64_t* queue, const int32_t* big,
+                           const int64_t* nbig);
 __global__ void k_db_zero(Work wk);
 __global__ void k_db_write(Work wk, ipp_sources cand, const int64_t* off,
                            const int64_t* tot, const char* pool,
