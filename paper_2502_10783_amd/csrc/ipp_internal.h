@@ -194,10 +194,12 @@ __device__ __forceinline__ int lanes_before(uint64_t m) {
 
 // Lane moves inside rows of 16 lanes (DPP: no LDS round trip).  The
 // patterns used are involutions, so both lanes of a pair add the same two
-// values and every lane ends with a bit-identical sum.
+// values and every lane ends with a bit-identical sum.  Every lane of
+// every row is written (permutations inside a row), so no lane keeps an
+// old value and none is needed.
 template <int CTRL>
 __device__ __forceinline__ int dpp_mov(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
@@ -225,18 +227,35 @@ __device__ __forceinline__ T row16_sum(T v) {
   v = v + dpp_mov<0x140>(v);       // row_mirror
   return v;
 }
-// Wave sums of binary64 and int: rows by DPP, then the four row sums,
-// combined in a fixed order; the result is wave-uniform.
+// Row broadcasts (DPP row_bcast:15 / row_bcast:31): the last lane of the
+// previous row (of row 1) to the rows in ROWS; lanes of other rows read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)dpp_bcast<CTRL, ROWS>((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)dpp_bcast<CTRL, ROWS>((int)(uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Wave sums of binary64 and int: rows by DPP, then the four row sums r0..r3
+// combined as (r0 + r1) + (r2 + r3): rows 1 and 3 add the last lanes of
+// rows 0 and 2, row 3 then adds the last lane of row 1, and lane 63's value
+// is read (addition commutes bit for bit, so the order is that one).  The
+// result is wave-uniform; every lane must be active.
+template <typename T>
+__device__ __forceinline__ T wave_sum_rows(T v) {
+  v = row16_sum(v);
+  v = v + dpp_bcast<0x142, 0xA>(v);
+  v = v + dpp_bcast<0x143, 0x8>(v);
+  return read_lane(v, 63);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-  v = row16_sum(v);
-  return (read_lane(v, 0) + read_lane(v, 16)) +
-         (read_lane(v, 32) + read_lane(v, 48));
+  return wave_sum_rows(v);
 }
-__device__ __forceinline__ int wave_sum(int v) {
-  v = row16_sum(v);
-  return (read_lane(v, 0) + read_lane(v, 16)) +
-         (read_lane(v, 32) + read_lane(v, 48));
-}
+__device__ __forceinline__ int wave_sum(int v) { return wave_sum_rows(v); }
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll

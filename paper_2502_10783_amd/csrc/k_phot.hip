@@ -530,6 +530,7 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   double svx = 0.0, svy = 0.0, swx = 0.0, swy = 0.0;   // sky terms
   const int ntk = nt0 + nt1;
   for (int j = lane; j < ntk; j += kWave) {
+#pragma clang fp contract(fast)
     // the series coefficients are read where they are used (an offset the
     // compiler cannot hoist keeps them out of registers across the loop)
     int co = 0;

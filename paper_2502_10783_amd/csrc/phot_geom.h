@@ -12,8 +12,11 @@
 // Maclaurin series of atan, its coefficients read from a table in LDS, after
 // argument halvings where the argument is large: no library call, so no
 // constant of a library routine is kept in registers.
-// Membership (the pixel square meets the open disk) and full containment
-// are decided by the exact predicates below, so that every pixel that a
+// Inside the overlap formulas products may fuse with the additions that
+// take them (one rounding fewer; the corner's in/out choice there selects
+// between two forms of G that agree on the circle).  Membership (the pixel
+// square meets the open disk) and full containment are decided by the
+// exact predicates below, formed as written, so that every pixel that a
 // rounding residue could move in or out is classified the same way on
 // every device.  dG/dx(x, y) = sign(y) min(|y|, sqrt(r^2 - x^2)) gives the
 // derivative of an overlap with respect to the disk centre.
@@ -92,6 +95,7 @@ __device__ __forceinline__ double angle_of(double c, double s,
 __device__ __forceinline__ double corner_g(double ax, double ay, double hx,
                                            double xs, double r2,
                                            const double* coef) {
+#pragma clang fp contract(fast)
   if (ax * ax + ay * ay <= r2) return ax * ay;
   const double c = hx * ay + ax * xs;
   const double s = ax * ay - xs * hx;
@@ -108,6 +112,7 @@ __device__ __forceinline__ void corner_rot(double ax, double ay, double hx,
                                            double xs, double sig, double r2,
                                            double& lin, double& re,
                                            double& im) {
+#pragma clang fp contract(fast)
   const bool out = ax * ax + ay * ay > r2;
   const double c = hx * ay + ax * xs;
   const double s = sig * (ax * ay - xs * hx);
@@ -143,6 +148,7 @@ __device__ __forceinline__ double overlap_cut(double cx, double cy, double r,
                                               double hx0, double hx1,
                                               double xs0, double xs1,
                                               const double* coef) {
+#pragma clang fp contract(fast)
   const double x0 = ((double)px - 0.5) - cx, x1 = ((double)px + 0.5) - cx;
   const double y0 = ((double)py - 0.5) - cy, y1 = ((double)py + 0.5) - cy;
   const double ax0 = fmin(fabs(x0), r), ax1 = fmin(fabs(x1), r);
