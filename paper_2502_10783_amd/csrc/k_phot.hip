@@ -63,11 +63,15 @@ struct Window {
     return (double)gld((const float*)(wpix + (qr * pitchB + (uint32_t)px * 4u))) -
            (double)gld((const float*)(wbkg + (qr * wB + (uint32_t)px * 4u)));
   }
-  // Every pixel of the window, 64 a round: visit(live, pos, ok, v) with
-  // pos = wy << 6 | wx, ok = the pixel lies in the frame and I is finite,
-  // v = I - B.  Lanes past the window's end visit with live = false (a
-  // valid position, ok = false).  The loads of kChunk rounds are issued
-  // before any is used, so their latencies overlap.
+  // Every pixel of the window, 64 a round: visit(live, pos, ok, v, mok,
+  // mlive) with pos = wy << 6 | wx, ok = the pixel lies in the frame and I
+  // is finite, v = I - B, mok and mlive = the wave's lanes with ok and with
+  // live.  Lanes past the
+  // window's end visit with live = false (a valid position, ok = false).
+  // The loads of kChunk rounds are issued before any is used, so their
+  // latencies overlap.  Lane masks are formed as products of ballots of
+  // single comparisons (each ballot is that comparison's own result): a
+  // ballot of a compound predicate costs two vector instructions more.
   template <int kChunk, bool EDGE, typename F>
   __device__ void walk_t(int lane, F&& visit) const {
     const int dwr = kWave / nwx, dwc = kWave - (kWave / nwx) * nwx;
@@ -82,6 +86,7 @@ struct Window {
       float Iv[kChunk], Bv[kChunk];
       int pos[kChunk];
       bool ins[kChunk];
+      uint64_t mins[kChunk];
 #pragma unroll
       for (int c = 0; c < kChunk; ++c) {
         if (e0 + c * kWave >= npx) break;            // wave-uniform
@@ -91,6 +96,8 @@ struct Window {
           // loads clamped into the frame: every lane loads, no branches
           const int px = xa + wc, py = ya + wr;
           ins[c] = live & (px >= 0) & (px < fw) & (py >= 0) & (py < fh);
+          mins[c] = ballot(live) & ballot(px >= 0) & ballot(px < fw) &
+                    ballot(py >= 0) & ballot(py < fh);
           const uint32_t qx = (uint32_t)min(max(px, 0), fw - 1);
           const uint32_t qr = (uint32_t)(min(max(py, 0), fh - 1) - ry0);
           Iv[c] = gld((const float*)(wpix + (qr * pitchB + qx * 4u)));
@@ -116,8 +123,13 @@ struct Window {
       for (int c = 0; c < kChunk; ++c) {
         if (e0 + c * kWave >= npx) break;            // wave-uniform
         const bool live = e0 + c * kWave + lane < npx;
-        visit(live, pos[c], ins[c] & isfinite(Iv[c]),
-              (double)Iv[c] - (double)Bv[c]);
+        // finite: |I| at most the largest float (false for NaN)
+        const bool fin = fabsf(Iv[c]) <= 3.40282347e38f;
+        // the live lanes as a scalar mask: the first npx - e lanes
+        const int rem = npx - (e0 + c * kWave);
+        const uint64_t mlive = rem >= kWave ? ~0ull : (1ull << rem) - 1ull;
+        visit(live, pos[c], ins[c] & fin, (double)Iv[c] - (double)Bv[c],
+              (EDGE ? mins[c] : mlive) & ballot(fin), mlive);
       }
     }
   }
@@ -364,11 +376,13 @@ struct ApOut {
   double dfx, dfy;     // dF/dcx, dF/dcy (GRAD)
 };
 
+// With GRAD, `norm` (wave-uniform) asks for the flux sums only (raw, not
+// the derivative sums) and its absence for the derivative only (no raw).
 template <int NS, bool GRAD>
 __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
                                double r_ap, double cx, double cy,
                                ApLds<NS>& L, const double* atan_lds,
-                               int lane) {
+                               int lane, bool norm = true) {
   constexpr int PL = NS / kWave;
   constexpr int P = PL == 4 ? 2 : (PL == 8 ? 3 : 4);
   static_assert((1 << P) == PL, "NS is 256, 512 or 1024");
@@ -392,20 +406,25 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   int nfull = 0;                       // pixels wholly inside the aperture
   int nann = 0, nt0 = 0, nt1 = 0;      // wave-uniform list lengths
   double raw = 0.0;                    // per lane: sum of v over them
-  bool bad_ap = false, bad_ann = false;
-  W.walk<4>(lane, [&](bool live, int q, bool ok, double v) {
+  uint64_t bad_ap = 0, bad_ann = 0;    // lanes of members not ok
+  W.walk<4>(lane, [&](bool live, int q, bool ok, double v, uint64_t mok,
+                      uint64_t mlive) {
     double near2, far2;
     L.T.dist2(q, &near2, &far2);
     const bool in_ap = live & (near2 < ra2);
     const bool in_ann = live & (near2 < ro2) & !(far2 <= ri2);
-    bad_ap |= in_ap & !ok;
-    bad_ann |= in_ann & !ok;
     const bool ap_whole = far2 <= ra2;
+    const uint64_t m_ap = mlive & ballot(near2 < ra2);
+    const uint64_t m_ann =
+        mlive & ballot(near2 < ro2) & ~ballot(far2 <= ri2);
+    const uint64_t m_whole = ballot(ap_whole);
+    bad_ap |= m_ap & ~mok;
+    bad_ann |= m_ann & ~mok;
     const bool full = in_ap & ok & ap_whole;
-    nfull += __popcll(ballot(full));
+    nfull += __popcll(m_ap & mok & m_whole);
     if (full) raw += v;
     const bool ann = in_ann & ok;
-    const uint64_t ba = ballot(ann);
+    const uint64_t ba = m_ann & mok;
     if (ann) {
       const int s = nann + lanes_before(ba);
       if (s < NS) L.xs[s] = v;
@@ -415,7 +434,9 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     const bool c0 = in_ap & ok & !ap_whole;
     const bool c1 = ann & !(far2 <= ro2);
     const bool c2 = ann & (near2 < ri2);
-    const uint64_t b0 = ballot(c0), b1 = ballot(c1), b2 = ballot(c2);
+    const uint64_t b0 = m_ap & mok & ~m_whole;
+    const uint64_t b1 = ba & ~ballot(far2 <= ro2);
+    const uint64_t b2 = ba & ballot(near2 < ri2);
     if (c0) {
       const int s = nt0 + lanes_before(b0);
       if (s < kTaskCap) L.tk[s] = q;
@@ -437,8 +458,8 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   if (nt0 + nt1 > kTaskCap) { nt0 = min(nt0, kTaskCap); nt1 = kTaskCap - nt0; }
   ApOut o;
   o.flags = 0;                         // wave-uniform
-  if (ballot(bad_ap)) o.flags |= IPP_SRC_APERTURE_OFF_EDGE;
-  if (ballot(bad_ann)) o.flags |= IPP_SRC_ANNULUS_OFF_EDGE;
+  if (bad_ap) o.flags |= IPP_SRC_APERTURE_OFF_EDGE;
+  if (bad_ann) o.flags |= IPP_SRC_ANNULUS_OFF_EDGE;
   wave_lds_sync();
 
   // ---- sort the annulus values ------------------------------------------
@@ -475,8 +496,9 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
         (n & 1) ? sorted_at<P>(L.xs, a + (n - 1) / 2)
                 : (sorted_at<P>(L.xs, a + n / 2 - 1) +
                    sorted_at<P>(L.xs, a + n / 2)) / 2.0;
-    const double dm = S1 / (double)n;
-    const double var = S2 / (double)n - dm * dm;
+    const double inv_n = 1.0 / (double)n;
+    const double dm = S1 * inv_n;
+    const double var = S2 * inv_n - dm * dm;
     const double sd = sqrt(var > 0.0 ? var : 0.0);
     const double lo = med - p.sky_clip_sigma * sd;
     const double hi = med + p.sky_clip_sigma * sd;
@@ -570,11 +592,11 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     }
   }
   o.a_ap = (double)nfull + wave_sum(acut);
-  o.raw = wave_sum(raw);
+  o.raw = !GRAD || norm ? wave_sum(raw) : 0.0;
   o.num = su + wave_sum(dnum);
   o.den = (double)(bnd - a) + wave_sum(dden);
   o.dfx = o.dfy = 0.0;
-  if constexpr (GRAD) {
+  if (GRAD && !norm) {
     tvx = wave_sum(tvx); tvy = wave_sum(tvy);
     tax = wave_sum(tax); tay = wave_sum(tay);
     svx = wave_sum(svx); svy = wave_sum(svy);
@@ -657,7 +679,8 @@ __device__ void refine_one(const Work& wk, const ipp_params& p,
     double g = 0.0;
     for (int k = -1; k < steps; ++k) {
       const ApOut o = aperture_eval<NS, true>(fr, p, k < 0 ? p.r_ap : r_c,
-                                              cx, cy, L, atan_lds, lane);
+                                              cx, cy, L, atan_lds, lane,
+                                              k < 0);
       if (k < 0) {
         const double sky0 = o.den > 0.0 ? o.num / o.den : 0.0;
         const double F0 = o.raw - sky0 * o.a_ap;
@@ -796,20 +819,27 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   // its cut tasks correct that weight.
   int nwhole = 0, nsurv = 0, ntk = 0;  // wave-uniform
   double Sv = 0.0;                     // per lane: sum of survivor values
-  W.walk<4>(lane, [&](bool live, int q, bool ok, double v) {
+  W.walk<4>(lane, [&](bool live, int q, bool ok, double v, uint64_t mok,
+                      uint64_t) {
     double near2, far2;
     L.T.dist2(q, &near2, &far2);
     const bool in_ap = live & ok & (near2 < ra2);
     const bool surv = live & ok & (near2 < ro2) & !(far2 <= ri2) &
                       (v >= vlo) & (v <= vhi);
     const bool ap_whole = far2 <= ra2;
-    nwhole += __popcll(ballot(in_ap & ap_whole));
-    nsurv += __popcll(ballot(surv));
+    const uint64_t m_ap = mok & ballot(near2 < ra2);
+    const uint64_t m_surv = mok & ballot(near2 < ro2) & ~ballot(far2 <= ri2) &
+                            ballot(v >= vlo) & ballot(v <= vhi);
+    const uint64_t m_whole = ballot(ap_whole);
+    nwhole += __popcll(m_ap & m_whole);
+    nsurv += __popcll(m_surv);
     if (surv) Sv += v;
     const bool c0 = in_ap & !ap_whole;
     const bool c1 = surv & !(far2 <= ro2);
     const bool c2 = surv & (near2 < ri2);
-    const uint64_t b0 = ballot(c0), b1 = ballot(c1), b2 = ballot(c2);
+    const uint64_t b0 = m_ap & ~m_whole;
+    const uint64_t b1 = m_surv & ~ballot(far2 <= ro2);
+    const uint64_t b2 = m_surv & ballot(near2 < ri2);
     if (c0) {
       const int s = ntk + lanes_before(b0);
       if (s < kTaskCap) L.tk[s] = q;
@@ -893,7 +923,8 @@ __device__ void aperture_bwd_one(const Work& wk, const ipp_params& p,
   // whole aperture pixels get g, every survivor ks (its weight 1); the cut
   // tasks add g w, ks (w - 1) or -ks w
   const double ks = Wt > 0.0 ? -g * A / Wt : 0.0;
-  W.walk<4>(lane, [&](bool live, int q, bool ok, double v) {
+  W.walk<4>(lane, [&](bool live, int q, bool ok, double v, uint64_t,
+                      uint64_t) {
     double near2, far2;
     L.T.dist2(q, &near2, &far2);
     const bool ap_whole = live & ok & (near2 < ra2) & (far2 <= ra2);
