@@ -123,13 +123,31 @@ __device__ __forceinline__ void corner_rot(double ax, double ay, double hx,
   re = nre;
 }
 
-// Angle in [0, pi) of the rotation (re, im): the series of atan(im / re)
-// when |im| <= 0.3 re (every cut pixel of a circle of radius 5 or more),
-// otherwise the general angle.
+// Angle in [0, pi) of the rotation (re, im) (im >= 0, not both zero): the
+// series of atan(im / re) once |im| <= 0.3 re, which holds at once for
+// every cut pixel of a circle of radius 5 or more.  A larger angle is
+// first turned back by a right angle if it exceeds one ((re, im) ->
+// (im, -re), so that re > 0), then halved until it qualifies: (re, im) ->
+// (re + |(re, im)|, im) halves the angle of a vector with re > 0 without
+// cancellation (at most four halvings from below a right angle).  Every
+// lane evaluates the series once, whichever path it took.
 __device__ __forceinline__ double rotor_angle(double re, double im,
                                               const double* coef) {
-  if (fabs(im) <= 0.3 * re) return atan_series(im / re, coef);
-  return angle_of(re, im, coef);
+  constexpr double kHalfPi = 1.5707963267948966;
+  double base = 0.0, scale = 1.0;
+  if (!(fabs(im) <= 0.3 * re)) {
+    if (re < 0.0) {
+      const double t = re;
+      re = im;
+      im = -t;
+      base = kHalfPi;
+    }
+    do {
+      re = re + sqrt(fma(re, re, im * im));
+      scale = 2.0 * scale;
+    } while (!(fabs(im) <= 0.3 * re));
+  }
+  return fma(scale, atan_series(im / re, coef), base);
 }
 
 // Overlap of the pixel square [px-1/2, px+1/2] x [py-1/2, py+1/2] with the
