@@ -200,8 +200,12 @@ struct ApLds {
   // sort's transposes and then the sorted values
   double xs[NS + kWave];
   // pixels cut by a circle: circle << 12 | wy << 6 | wx (circle 0: the
-  // aperture, 1: the outer and 2: the inner annulus circle)
-  int tk[kTaskCap];
+  // aperture, 1: the outer and 2: the inner annulus circle).  The lists
+  // start kWave slots in from either end and their counts are clamped
+  // round by round, so a round's appends stay inside the array without a
+  // bound test per lane (the values lists likewise: the count stays at most
+  // NS, and xs has kWave slots more).
+  int tk[kTaskCap + 2 * kWave];
   WinTables T;
 };
 
@@ -425,11 +429,8 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     if (full) raw += v;
     const bool ann = in_ann & ok;
     const uint64_t ba = m_ann & mok;
-    if (ann) {
-      const int s = nann + lanes_before(ba);
-      if (s < NS) L.xs[s] = v;
-    }
-    nann += __popcll(ba);
+    if (ann) L.xs[nann + lanes_before(ba)] = v;
+    nann = min(nann + (int)__popcll(ba), NS);
     // one task per circle that cuts the pixel
     const bool c0 = in_ap & ok & !ap_whole;
     const bool c1 = ann & !(far2 <= ro2);
@@ -437,24 +438,16 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     const uint64_t b0 = m_ap & mok & ~m_whole;
     const uint64_t b1 = ba & ~ballot(far2 <= ro2);
     const uint64_t b2 = ba & ballot(near2 < ri2);
-    if (c0) {
-      const int s = nt0 + lanes_before(b0);
-      if (s < kTaskCap) L.tk[s] = q;
-    }
-    nt0 += __popcll(b0);
-    if (c1) {
-      const int s = kTaskCap - 1 - (nt1 + lanes_before(b1));
-      if (s >= 0) L.tk[s] = (1 << 12) | q;
-    }
-    nt1 += __popcll(b1);
-    if (c2) {
-      const int s = kTaskCap - 1 - (nt1 + lanes_before(b2));
-      if (s >= 0) L.tk[s] = (2 << 12) | q;
-    }
-    nt1 += __popcll(b2);
+    if (c0) L.tk[kWave + nt0 + lanes_before(b0)] = q;
+    nt0 = min(nt0 + (int)__popcll(b0), kTaskCap);
+    if (c1)
+      L.tk[kWave + kTaskCap - 1 - (nt1 + lanes_before(b1))] = (1 << 12) | q;
+    nt1 = min(nt1 + (int)__popcll(b1), kTaskCap);
+    if (c2)
+      L.tk[kWave + kTaskCap - 1 - (nt1 + lanes_before(b2))] = (2 << 12) | q;
+    nt1 = min(nt1 + (int)__popcll(b2), kTaskCap);
   });
-  if (nann > NS) nann = NS;            // not reachable: NS bounds the ring
-  // not reachable either (the two ends cannot meet)
+  // not reachable: NS bounds the ring, and the task lists cannot meet
   if (nt0 + nt1 > kTaskCap) { nt0 = min(nt0, kTaskCap); nt1 = kTaskCap - nt0; }
   ApOut o;
   o.flags = 0;                         // wave-uniform
@@ -481,6 +474,7 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   double S1 = 0.0, S2 = 0.0;
 #pragma unroll
   for (int k = 0; k < PL; ++k) {
+#pragma clang fp contract(fast)
     const int e = lane * PL + k;
     const double d = e < nann ? sv[k] - c0 : 0.0;
     S1 += d;
@@ -514,6 +508,7 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     // [bnd - ch, bnd): one lane reads each from LDS (usually one round)
     double r1 = 0.0, r2 = 0.0;
     for (int j = lane; j < cl + ch; j += kWave) {
+#pragma clang fp contract(fast)
       const int e = j < cl ? a + j : bnd - ch + (j - cl);
       const double d = sorted_at<P>(L.xs, e) - c0;
       r1 += d;
@@ -558,7 +553,7 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     int co = 0;
     asm volatile("" : "+s"(co));
     const double* coef = atan_lds + co;
-    const int t = L.tk[j < nt0 ? j : kTaskCap - nt1 + (j - nt0)];
+    const int t = L.tk[kWave + (j < nt0 ? j : kTaskCap - nt1 + (j - nt0))];
     const int c = t >> 12, wx = t & 63, wy = (t >> 6) & 63;
     const int px = W.xa + wx, py = W.ya + wy;
     double r, r2;
