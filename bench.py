@@ -61,6 +61,25 @@ def aperture_flops_per_source(r_ap, r_in, r_out):
     return 60.0 * 8.0 * (r_ap + r_in + r_out)
 
 
+def kron_flops(mom, kron_r):
+    """Algorithmic binary64 work of AUTO photometry over its sources: the
+    pixels that the Kron ellipse cuts (about 4 (A + B) for semi-axes A, B,
+    as a circle of radius r cuts about 8 r) times the circle overlap's ~60
+    flops plus 8 for the affine map of a pixel's corners.  A, B: the Kron
+    radius times the square roots of the eigenvalues of the moments'
+    covariance regularised by 1/12 on each axis."""
+    import numpy as np
+    X = mom[:, 0] + 1.0 / 12.0
+    Y = mom[:, 1] + 1.0 / 12.0
+    xy = mom[:, 2]
+    tr, det = X + Y, X * Y - xy * xy
+    disc = np.sqrt(np.maximum(tr * tr / 4.0 - det, 0.0))
+    l1, l2 = tr / 2.0 + disc, np.maximum(tr / 2.0 - disc, 0.0)
+    ab = kron_r * (np.sqrt(l1) + np.sqrt(l2))
+    ok = np.isfinite(ab)
+    return float(68.0 * 4.0 * ab[ok].sum())
+
+
 def step_algo_bytes(npx, nsrc, refine_steps):
     """Algorithmic HBM bytes of one step: read I, write the background and
     label maps (12 B/px), one 80-byte table row per source, and per
@@ -481,7 +500,9 @@ def run_next(args):
     def auto():
         mom = ctx.source_moments(frames, outputs["bkg"], outputs["labels"],
                                  table)
-        ctx.photometry_auto(frames, outputs["bkg"], table, mom)
+        holder["mom"] = mom
+        holder["auto"] = ctx.photometry_auto(frames, outputs["bkg"], table,
+                                             mom)
 
     def subtract():
         ctx.subtract(frames, templates, sp, coef)
@@ -514,6 +535,36 @@ def run_next(args):
                 "traffic": measured_traffic("k_subtract", "next16"),
                 "algo_flops_per_launch": sub_flops,
                 "ms_per_launch": round(ks, 4)}
+    # deblending: each of the nthresh levels reads the candidates' pixel
+    # values once and the object map is written once (4 B each)
+    npix_c = int(table.cols["npix"][:nsrc].sum().item())
+    nthr = ipp.DeblendParams().nthresh
+    db_bytes = 4.0 * npix_c * (nthr + 1)
+    kdb = sum(kern.get(k, 0.0) for k in ("k_db_small", "k_db_large",
+                                          "k_db_write"))
+    roof_db = None
+    if kdb:
+        gbs = db_bytes / (kdb * 1e-3) / 1e9
+        roof_db = {"kernel": "k_db_small + k_db_large + k_db_write",
+                   "bound": "hbm", "achieved": round(gbs, 1),
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                   "algo_bytes_per_launch": db_bytes,
+                   "candidate_pixels": npix_c, "levels": nthr,
+                   "ms_per_launch": round(kdb, 4)}
+    roof_kron = None
+    kk = kern.get("k_kron", 0.0) + kern.get("k_kron_big", 0.0)
+    if kk:
+        kf = kron_flops(holder["mom"][:nsrc].cpu().numpy(),
+                        holder["auto"]["kron_radius"][:nsrc].cpu().numpy())
+        tfs = kf / (kk * 1e-3) / 1e12
+        roof_kron = {"kernel": "k_kron + k_kron_big", "bound": "alu",
+                     "achieved": round(tfs, 4),
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tfs / FP64_VECTOR_PEAK_TFLOPS, 5),
+                     "traffic": measured_traffic("k_kron", "next16"),
+                     "algo_flops_per_launch": kf,
+                     "ms_per_launch": round(kk, 4)}
     res = {
         "metric": "Mpix/s of the stamp convolution and difference image",
         "value": round(npx / 1e6 / (ms_sub * 1e-3), 1),
@@ -540,13 +591,15 @@ def run_next(args):
                     "mpix_per_s": round(npx / 1e6 / (ms_db * 1e-3), 1),
                     "candidates": nsrc, "objects": nobj,
                     "diag": db_diag,
-                    "candidates_per_s": round(nsrc / (ms_db * 1e-3), 1)},
+                    "candidates_per_s": round(nsrc / (ms_db * 1e-3), 1),
+                    "roofline": roof_db},
         "auto_photometry": {"workload": "second moments and AUTO (Kron) "
                                         "photometry of the candidates",
                             "ms_per_step": round(ms_auto, 4),
                             "sources": nsrc,
                             "sources_per_s": round(nsrc / (ms_auto * 1e-3),
-                                                   1)},
+                                                   1),
+                            "roofline": roof_kron},
         "kernels_ms": {k: round(v, 4) for k, v in
                        sorted(kern.items(), key=lambda kv: -kv[1])},
         "cpu_baseline": cpu,

@@ -16,7 +16,11 @@
 // sector where it lies outside), then divided by det L.  A pixel whose
 // four corners lie inside the ellipse (q <= R^2 with a relative margin of
 // 1e-12) is wholly inside it, its area exactly 1; only the other member
-// pixels are listed (LDS) and then computed, every lane busy.
+// pixels are listed (LDS) and then computed, every lane busy.  A window of
+// more than kKronBigPx pixels (a large R where the first moment's weights
+// nearly cancel) would hold one wavefront for thousands of rounds: its
+// pass 2 is left to k_kron_big, which splits the window over a
+// workgroup's waves and adds their sums in a fixed order.
 //
 // The membership tests (q against search^2, the frame bounds) use the
 // same binary64 operations as the oracle; the sums are taken over the
@@ -127,6 +131,165 @@ __device__ double ell_overlap(const Ell& e, double cx, double cy, int px,
   return a * e.inv_det;
 }
 
+constexpr int kCut = 1024;     // listed pixels per flush (a multiple of 64)
+constexpr int kChunk = 4;      // rounds whose loads are issued together
+
+__device__ __forceinline__ int lo_px(double v, int a) {
+  return (int)fmax(ceil(v), (double)a);
+}
+__device__ __forceinline__ int hi_px(double v, int b) {
+  return (int)fmin(floor(v), (double)b);
+}
+
+// A row's inputs: frame, centre and the moments regularised by the
+// variance 1/12 of a uniform unit pixel; ok = all usable.
+struct KronRow {
+  int f;
+  double cx, cy, X, Y, xy, det;
+  bool ok;
+};
+
+__device__ __forceinline__ KronRow kron_row(const Work& wk,
+                                            const ipp_sources& src,
+                                            const double* mom,
+                                            long long row) {
+  KronRow r;
+  r.f = src.frame[row];
+  r.cx = src.x[row];
+  r.cy = src.y[row];
+  r.X = mom[6 * row] + 1.0 / 12.0;
+  r.Y = mom[6 * row + 1] + 1.0 / 12.0;
+  r.xy = mom[6 * row + 2];
+  r.det = r.X * r.Y - r.xy * r.xy;
+  r.ok = r.f >= 0 && r.f < wk.nframes && isfinite(r.X) && isfinite(r.Y) &&
+         isfinite(r.xy) && r.det > 0.0 && isfinite(r.cx) && isfinite(r.cy) &&
+         fabs(r.cx) < 1e9 && fabs(r.cy) < 1e9;
+  return r;
+}
+
+// Pass-2 window: the Kron ellipse's bounding box within the frame and a
+// ring of one pixel around it (an ellipse centred in the frame that reaches
+// outside meets the ring: it is convex).
+struct KronWin {
+  int xa, ya, nwx, npx;
+};
+
+__device__ __forceinline__ KronWin kron_window(const FrameDev& fr,
+                                               const KronRow& r, double R) {
+  const double gx = R * sqrt(r.X), gy = R * sqrt(r.Y);
+  const int xa = lo_px(r.cx - gx - 0.5, -1), xb = hi_px(r.cx + gx + 0.5, fr.w);
+  const int ya = lo_px(r.cy - gy - 0.5, -1), yb = hi_px(r.cy + gy + 0.5, fr.h);
+  KronWin k;
+  k.xa = xa;
+  k.ya = ya;
+  k.nwx = max(xb - xa + 1, 0);
+  k.npx = yb >= ya ? k.nwx * (yb - ya + 1) : 0;
+  return k;
+}
+
+// Pass 2 over window pixels [e_begin, e_end) (raster order): members of
+// the open ellipse whose four corners lie inside it add v and area 1, the
+// other members are listed (LDS, kCut pixels of the window at a time) and
+// add w v and w, w the exact overlap; a member off the frame or not finite
+// sets edge.  Each lane accumulates its pixels in window order, then its
+// listed pixels; the pixel loads of kChunk rounds are issued before any is
+// used (clamped into the frame; only members use them).
+__device__ void kron_pass2(const FrameDev& fr, const KronRow& r,
+                           const Ell& el, double R, const KronWin& kw,
+                           int e_begin, int e_end, int lane, int* cut,
+                           const double* atan_lds, double& fs, double& as,
+                           bool& edge) {
+  const double X = r.X, Y = r.Y, xy = r.xy, det = r.det;
+  const double cx = r.cx, cy = r.cy;
+  const double R2 = R * R;
+  // corners inside: q det <= R^2 det (1 - 1e-12), no division
+  const double lim = R2 * det * (1.0 - 1e-12);
+  const int nwx = kw.nwx;
+  if (nwx <= 0 || e_end <= e_begin) return;
+  // window positions stepped round by round without division
+  const int dwr = kWave / nwx, dwc = kWave - dwr * nwx;
+  const int el0 = e_begin + lane;
+  int sy = el0 / nwx, sx = el0 - (el0 / nwx) * nwx;
+  for (int e0 = e_begin; e0 < e_end; e0 += kCut) {
+    int ncut = 0;
+    const int e1 = min(e_end, e0 + kCut);
+    for (int eb = e0; eb < e1; eb += kChunk * kWave) {
+      float Iv[kChunk], Bv[kChunk];
+      int wys[kChunk], wxs[kChunk];
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (eb + c * kWave >= e1) break;             // wave-uniform
+        wys[c] = sy;
+        wxs[c] = sx;
+        const int qx = min(max(kw.xa + sx, 0), fr.w - 1);
+        const int qy = min(max(kw.ya + sy, 0), fr.h - 1);
+        Iv[c] = fr.pix[(int64_t)qy * fr.pitch + qx];
+        Bv[c] = fr.bkg[(int64_t)qy * fr.w + qx];
+        sy += dwr;
+        sx += dwc;
+        if (sx >= nwx) {
+          sx -= nwx;
+          ++sy;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (eb + c * kWave >= e1) break;             // wave-uniform
+        const int e = eb + c * kWave + lane;
+        bool listed = false;
+        int pos = 0;
+        if (e < e1) {
+          const int wy = wys[c], wx = wxs[c];
+          const int py = kw.ya + wy, px = kw.xa + wx;
+          const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
+          const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
+          // the pixel meets the open ellipse: an exact predicate
+          if (min_q(X, Y, xy, det, x0, x1, y0, y1) < R2) {
+            const bool in = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
+            const float I = Iv[c];
+            if (!in || !isfinite(I)) {
+              edge = true;
+            } else {
+              auto qd = [&](double dx, double dy) {
+                return Y * dx * dx + X * dy * dy - 2.0 * xy * dx * dy;
+              };
+              if (qd(x0, y0) <= lim && qd(x1, y0) <= lim &&
+                  qd(x0, y1) <= lim && qd(x1, y1) <= lim) {
+                fs += (double)I - (double)Bv[c];
+                as += 1.0;
+              } else {
+                listed = true;
+                pos = (wy << 16) | wx;
+              }
+            }
+          }
+        }
+        const uint64_t b = ballot(listed);
+        if (listed) cut[ncut + lanes_before(b)] = pos;
+        ncut += __popcll(b);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = lane; j < ncut; j += kWave) {
+      int co = 0;
+      asm volatile("" : "+s"(co));
+      const double* coef = atan_lds + co;
+      const int t = cut[j];
+      const int px = kw.xa + (t & 0xFFFF), py = kw.ya + (t >> 16);
+      const double w = ell_overlap(el, cx, cy, px, py, coef);
+      const double v = (double)fr.pix[(int64_t)py * fr.pitch + px] -
+                       (double)fr.bkg[(int64_t)py * fr.w + px];
+      fs += w * v;
+      as += w;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
@@ -137,8 +300,6 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
                                                  uint32_t* flags) {
   // pixels of the Kron ellipse cut by its boundary: py << 16 | px offsets
   // from the window corner, per wave
-  constexpr int kCut = 1024;            // a multiple of 64
-  constexpr int kChunk = 4;
   __shared__ int cut_lds[kWaves][kCut];
   __shared__ double atan_lds[kAtanTerms];
   if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
@@ -152,17 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const long long nw = (long long)gridDim.x * kWaves;
   for (long long row = wid; row < nrows; row += nw) {
-    const int f = src.frame[row];
-    const double cx = src.x[row], cy = src.y[row];
-    const double X = mom[6 * row] + 1.0 / 12.0;
-    const double Y = mom[6 * row + 1] + 1.0 / 12.0;
-    const double xy = mom[6 * row + 2];
-    const double det = X * Y - xy * xy;
-    const bool ok = f >= 0 && f < wk.nframes && isfinite(X) &&
-                    isfinite(Y) && isfinite(xy) && det > 0.0 &&
-                    isfinite(cx) && isfinite(cy) && fabs(cx) < 1e9 &&
-                    fabs(cy) < 1e9;
-    if (!ok) {
+    const KronRow r = kron_row(wk, src, mom, row);
+    if (!r.ok) {
       if (lane == 0) {
         kron[row] = __builtin_nan("");
         flux[row] = __builtin_nan("");
@@ -171,15 +323,15 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
       }
       continue;
     }
-    const FrameDev fr = wk.frames[f];
+    const double cx = r.cx, cy = r.cy, X = r.X, Y = r.Y, xy = r.xy;
+    const double det = r.det;
+    const FrameDev fr = wk.frames[r.f];
     uint32_t fl = 0;
     // ---- pass 1: first moment over the search ellipse ------------------
     // window bounds clamped in binary64 before the conversion to int
-    auto lo = [](double v, int a) { return (int)fmax(ceil(v), (double)a); };
-    auto hi = [](double v, int b) { return (int)fmin(floor(v), (double)b); };
     const double hx = search * sqrt(X), hy = search * sqrt(Y);
-    const int xa = lo(cx - hx - 0.5, 0), xb = hi(cx + hx + 0.5, fr.w - 1);
-    const int ya = lo(cy - hy - 0.5, 0), yb = hi(cy + hy + 0.5, fr.h - 1);
+    const int xa = lo_px(cx - hx - 0.5, 0), xb = hi_px(cx + hx + 0.5, fr.w - 1);
+    const int ya = lo_px(cy - hy - 0.5, 0), yb = hi_px(cy + hy + 0.5, fr.h - 1);
     double num = 0.0, den = 0.0;
     const double s2 = search * search;
     if (xb >= xa && yb >= ya) {
@@ -233,94 +385,24 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
       fl |= 2u;                                        // R_min used
     }
     // ---- pass 2: exact overlaps with the Kron ellipse -------------------
-    const Ell el = ell_map(X, Y, xy, det, R);
-    // the frame and a ring of one pixel around it: an ellipse centred in
-    // the frame that reaches outside meets the ring (it is convex); one
-    // centred outside is flagged outright
-    const double gx = R * sqrt(X), gy = R * sqrt(Y);
-    const int xa2 = lo(cx - gx - 0.5, -1), xb2 = hi(cx + gx + 0.5, fr.w);
-    const int ya2 = lo(cy - gy - 0.5, -1), yb2 = hi(cy + gy + 0.5, fr.h);
+    // (one centred outside the frame is flagged outright)
     if (!(cx >= -0.5 && cx <= (double)fr.w - 0.5 && cy >= -0.5 &&
           cy <= (double)fr.h - 0.5))
       fl |= 4u;
-    const int nwx2 = max(xb2 - xa2 + 1, 0);
-    const int npx2 = yb2 >= ya2 ? nwx2 * (yb2 - ya2 + 1) : 0;
+    const KronWin kw = kron_window(fr, r, R);
+    if (kw.npx > kKronBigPx) {
+      // a window this large is summed by k_kron_big, a workgroup at once
+      if (lane == 0) {
+        kron[row] = R;
+        flags[row] = fl;
+      }
+      continue;
+    }
+    const Ell el = ell_map(X, Y, xy, det, R);
     double fs = 0.0, as = 0.0;
     bool edge = false;
-    const double R2 = R * R;
-    // corners inside: q det <= R^2 det (1 - 1e-12), no division
-    const double lim = R2 * det * (1.0 - 1e-12);
-    // members wholly inside are summed here, the others listed, in chunks
-    // of kCut pixels of the window (so that the list cannot overflow)
-    // window positions stepped round by round without division
-    const int dwr2 = nwx2 > 0 ? kWave / nwx2 : 0;
-    const int dwc2 = kWave - dwr2 * nwx2;
-    int sy = nwx2 > 0 ? lane / nwx2 : 0, sx = lane - sy * nwx2;
-    for (int e0 = 0; e0 < npx2; e0 += kCut) {
-      int ncut = 0;
-      const int e1 = min(npx2, e0 + kCut);
-      for (int eb = e0; eb < e1; eb += kWave) {
-        const int e = eb + lane;
-        bool listed = false;
-        int pos = 0;
-        const int wy = sy, wx = sx;          // this round's position
-        sy += dwr2;
-        sx += dwc2;
-        if (sx >= nwx2) {
-          sx -= nwx2;
-          ++sy;
-        }
-        if (e < e1) {
-          const int py = ya2 + wy, px = xa2 + wx;
-          const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
-          const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
-          // the pixel meets the open ellipse: an exact predicate
-          if (min_q(X, Y, xy, det, x0, x1, y0, y1) < R2) {
-            const bool in = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
-            float I = 0.0f;
-            if (in) I = fr.pix[(int64_t)py * fr.pitch + px];
-            if (!in || !isfinite(I)) {
-              edge = true;
-            } else {
-              auto qd = [&](double dx, double dy) {
-                return Y * dx * dx + X * dy * dy - 2.0 * xy * dx * dy;
-              };
-              if (qd(x0, y0) <= lim && qd(x1, y0) <= lim &&
-                  qd(x0, y1) <= lim && qd(x1, y1) <= lim) {
-                const double v =
-                    (double)I - (double)fr.bkg[(int64_t)py * fr.w + px];
-                fs += v;
-                as += 1.0;
-              } else {
-                listed = true;
-                pos = (wy << 16) | wx;
-              }
-            }
-          }
-        }
-        const uint64_t b = ballot(listed);
-        if (listed) cut[ncut + lanes_before(b)] = pos;
-        ncut += __popcll(b);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int j = lane; j < ncut; j += kWave) {
-        int co = 0;
-        asm volatile("" : "+s"(co));
-        const double* coef = atan_lds + co;
-        const int t = cut[j];
-        const int px = xa2 + (t & 0xFFFF), py = ya2 + (t >> 16);
-        const double w = ell_overlap(el, cx, cy, px, py, coef);
-        const double v = (double)fr.pix[(int64_t)py * fr.pitch + px] -
-                         (double)fr.bkg[(int64_t)py * fr.w + px];
-        fs += w * v;
-        as += w;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    kron_pass2(fr, r, el, R, kw, 0, kw.npx, lane, cut, atan_lds, fs, as,
+               edge);
     fs = wave_sum(fs);
     as = wave_sum(as);
     if (__builtin_amdgcn_ballot_w64(edge)) fl |= 4u;    // off the frame
@@ -330,6 +412,87 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
       area[row] = as;
       flags[row] = fl;
     }
+  }
+}
+
+// Pass 2 of the rows whose window k_kron left (more than kKronBigPx
+// pixels): each workgroup checks kBigThreads rows at once (one per thread,
+// from the Kron radius k_kron wrote), then takes each such row with all its
+// waves, wave k summing the k-th of kBigWaves equal parts of the window;
+// the parts' sums are added in wave order.
+__global__ __launch_bounds__(kBigThreads) void k_kron_big(
+    Work wk, ipp_sources src, const double* mom, const double* kron,
+    double* flux, double* area, uint32_t* flags) {
+  constexpr int kBigWaves = kBigThreads / kWave;
+  __shared__ int cut_lds[kBigWaves][kCut];
+  __shared__ double atan_lds[kAtanTerms];
+  __shared__ int list[kBigThreads];
+  __shared__ int nlist;
+  __shared__ double part[kBigWaves][2];
+  __shared__ int pedge[kBigWaves];
+  if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
+  if (threadIdx.x == 0) nlist = 0;
+  __syncthreads();
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = threadIdx.x & (kWave - 1);
+  int* cut = cut_lds[wv];
+  long long nrows = src.capacity;
+  if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
+  for (long long base = blockIdx.x * (long long)kBigThreads; base < nrows;
+       base += (long long)gridDim.x * kBigThreads) {
+    {
+      const long long row = base + threadIdx.x;
+      bool big = false;
+      if (row < nrows) {
+        const KronRow r = kron_row(wk, src, mom, row);
+        if (r.ok) {
+          const KronWin kw = kron_window(wk.frames[r.f], r, kron[row]);
+          big = kw.npx > kKronBigPx;
+        }
+      }
+      if (big) list[atomicAdd(&nlist, 1)] = (int)threadIdx.x;
+    }
+    __syncthreads();
+    const int nb = nlist;
+    __syncthreads();                  // every thread has read the count
+    for (int i = 0; i < nb; ++i) {
+      const long long row = base + list[i];
+      const KronRow r = kron_row(wk, src, mom, row);
+      const FrameDev fr = wk.frames[r.f];
+      const double R = kron[row];
+      const KronWin kw = kron_window(fr, r, R);
+      const Ell el = ell_map(r.X, r.Y, r.xy, r.det, R);
+      const int per = (kw.npx + kBigWaves - 1) / kBigWaves;
+      const int eb = min(kw.npx, wv * per), ee = min(kw.npx, eb + per);
+      double fs = 0.0, as = 0.0;
+      bool edge = false;
+      kron_pass2(fr, r, el, R, kw, eb, ee, lane, cut, atan_lds, fs, as,
+                 edge);
+      fs = wave_sum(fs);
+      as = wave_sum(as);
+      const bool any_edge = __builtin_amdgcn_ballot_w64(edge) != 0;
+      if (lane == 0) {
+        part[wv][0] = fs;
+        part[wv][1] = as;
+        pedge[wv] = any_edge ? 1 : 0;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double F = 0.0, A = 0.0;
+        int ed = 0;
+        for (int k = 0; k < kBigWaves; ++k) {
+          F += part[k][0];
+          A += part[k][1];
+          ed |= pedge[k];
+        }
+        flux[row] = F;
+        area[row] = A;
+        if (ed) flags[row] |= 4u;                       // off the frame
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
   }
 }
 

@@ -84,3 +84,68 @@ def test_auto_photometry_matches_oracle(ctx, name):
           f"above the minimum radius", flush=True)
     assert err.max() <= 1e-9
     assert np.any(want["flags"] & okr.AUTO_OFF_EDGE) or name == "single"
+
+
+def _window_px(x, y, m, R, w, h):
+    """Pixels of the pass-2 window (the Kron ellipse's box within the frame
+    and a one-pixel ring), as the kernel bounds it."""
+    import math
+    X, Y = m[0] + 1.0 / 12.0, m[1] + 1.0 / 12.0
+    gx, gy = R * math.sqrt(X), R * math.sqrt(Y)
+    xa = int(max(math.ceil(x - gx - 0.5), -1))
+    xb = int(min(math.floor(x + gx + 0.5), w))
+    ya = int(max(math.ceil(y - gy - 0.5), -1))
+    yb = int(min(math.floor(y + gy + 0.5), h))
+    return max(xb - xa + 1, 0) * max(yb - ya + 1, 0)
+
+
+def test_auto_photometry_large_windows(ctx):
+    """Objects whose Kron ellipse window exceeds 16384 pixels (extended
+    light, wide second moments) take the cooperative pass, the window
+    split over a workgroup's waves; one reaches over the frame edge.  Same
+    bar as above against the oracle."""
+    rng = np.random.default_rng(5)
+    h = w = 600
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    img = 100.0 + rng.normal(0.0, 5.0, (h, w))
+    img += 2000.0 * np.exp(-((xx - 300.0) ** 2 + (yy - 310.0) ** 2) /
+                           (2 * 22.0 ** 2))
+    img += 800.0 * np.exp(-((xx - 280.0) ** 2) / (2 * 30.0 ** 2) -
+                          ((yy - 300.0) ** 2) / (2 * 17.0 ** 2))
+    img += 1500.0 * np.exp(-((xx - 60.0) ** 2 + (yy - 300.0) ** 2) /
+                           (2 * 30.0 ** 2))
+    img = img.astype(np.float32)
+    B = np.full((h, w), 100.0, dtype=np.float32)
+    xs = np.array([300.3, 280.2, 60.5, 100.4, 450.25])
+    ys = np.array([310.7, 300.9, 300.2, 120.6, 450.75])
+    m = np.array([[484.0, 484.0, 0.0, 0, 0, 0],
+                  [900.0, 300.0, 200.0, 0, 0, 0],
+                  [900.0, 900.0, 0.0, 0, 0, 0],
+                  [3.0, 2.5, 0.4, 0, 0, 0],
+                  [484.0, 400.0, -100.0, 0, 0, 0]])
+    k = xs.size
+    table = ipp.SourceTable(k, 1, DEV)
+    table.cols["frame"][:k] = 0
+    table.cols["x"][:k] = torch.from_numpy(xs).to(DEV)
+    table.cols["y"][:k] = torch.from_numpy(ys).to(DEV)
+    table.n_total.fill_(k)
+    out = ctx.photometry_auto([torch.from_numpy(img).to(DEV)],
+                              [torch.from_numpy(B).to(DEV)], table,
+                              torch.from_numpy(m).to(DEV))
+    torch.cuda.synchronize()
+    got = {c: v[:k].cpu().numpy() for c, v in out.items()}
+    want = okr.auto_photometry(img, B, xs, ys, m)
+    big = [_window_px(xs[i], ys[i], m[i], want["kron_radius"][i], w, h)
+           for i in range(k)]
+    print("windows", big, flush=True)
+    assert sum(b > 16384 for b in big) == 4 and min(big) <= 16384
+    assert big[2] > 16384 and want["flags"][2] & okr.AUTO_OFF_EDGE
+    assert want["flags"][4] & okr.AUTO_RMIN
+    assert np.array_equal(got["flags"], want["flags"].astype(np.int32))
+    np.testing.assert_allclose(got["kron_radius"], want["kron_radius"],
+                               rtol=1e-12)
+    np.testing.assert_allclose(got["area"], want["area"], rtol=1e-11,
+                               atol=1e-11)
+    scale = np.abs(want["flux"]) + want["area"] * np.abs(img).max()
+    err = np.abs(got["flux"] - want["flux"]) / scale
+    assert err.max() <= 1e-9
