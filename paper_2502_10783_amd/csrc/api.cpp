@@ -1624,7 +1624,8 @@ ipp_status ipp_photometry_auto(void* ctx, const ipp_frame* frames, int32_t n,
              hipLaunchKernelGGL(k_kron_big,
                                 dim3(grid_for(src->capacity, kBigThreads,
                                               4 * c->n_cu)),
-                                dim3(kBigThreads), 0, s, w, *src, mom, kron,
+                                dim3(kBigThreads), 0, s, w, *src, mom,
+                                a.kron_factor, a.kron_min, a.search, kron,
                                 flux, area, flags));
   return IPP_OK;
 }

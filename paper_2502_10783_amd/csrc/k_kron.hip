@@ -17,9 +17,10 @@
 // four corners lie inside the ellipse (q <= R^2 with a relative margin of
 // 1e-12) is wholly inside it, its area exactly 1; only the other member
 // pixels are listed (LDS) and then computed, every lane busy.  A window of
-// more than kKronBigPx pixels (a large R where the first moment's weights
-// nearly cancel) would hold one wavefront for thousands of rounds: its
-// pass 2 is left to k_kron_big, which splits the window over a
+// more than kKronBigPx pixels (wide moments, or a large R where the first
+// moment's weights nearly cancel) would hold one wavefront for hundreds or
+// thousands of rounds: such a pass (with its pass 1 when the search window
+// is the large one) is left to k_kron_big, which splits the window over a
 // workgroup's waves and adds their sums in a fixed order.
 //
 // The membership tests (q against search^2, the frame bounds) use the
@@ -187,6 +188,80 @@ __device__ __forceinline__ KronWin kron_window(const FrameDev& fr,
   return k;
 }
 
+// Pass-1 window: the search ellipse's box within the frame.
+__device__ __forceinline__ KronWin search_window(const FrameDev& fr,
+                                                 const KronRow& r,
+                                                 double search) {
+  // bounds clamped in binary64 before the conversion to int
+  const double hx = search * sqrt(r.X), hy = search * sqrt(r.Y);
+  const int xa = lo_px(r.cx - hx - 0.5, 0), xb = hi_px(r.cx + hx + 0.5, fr.w - 1);
+  const int ya = lo_px(r.cy - hy - 0.5, 0), yb = hi_px(r.cy + hy + 0.5, fr.h - 1);
+  KronWin k;
+  k.xa = xa;
+  k.ya = ya;
+  k.nwx = xb >= xa ? xb - xa + 1 : 0;
+  k.npx = (xb >= xa && yb >= ya) ? k.nwx * (yb - ya + 1) : 0;
+  return k;
+}
+
+// Pass 1 over search-window pixels [e_begin, e_end) (raster order): the
+// sums sqrt(q) v and v over the pixel centres with q <= search^2 and a
+// finite I; each lane sums its pixels in window order, the loads of kChunk
+// rounds issued before any is used.
+__device__ void kron_pass1(const FrameDev& fr, const KronRow& r,
+                           double search, const KronWin& kw, int e_begin,
+                           int e_end, int lane, double& num, double& den) {
+  const int nwx = kw.nwx;
+  if (nwx <= 0 || e_end <= e_begin) return;
+  const double s2 = search * search;
+  const int dwr = kWave / nwx, dwc = kWave - dwr * nwx;
+  const int el0 = e_begin + lane;
+  int wr = el0 / nwx, wc = el0 - (el0 / nwx) * nwx;
+  for (int e0 = e_begin; e0 < e_end; e0 += kChunk * kWave) {
+    float Iv[kChunk], Bv[kChunk];
+    int pxs[kChunk], pys[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const bool live = e0 + c * kWave + lane < e_end;
+      pxs[c] = live ? kw.xa + wc : -1;
+      pys[c] = kw.ya + wr;
+      const int qx = live ? kw.xa + wc : kw.xa, qy = live ? kw.ya + wr : kw.ya;
+      Iv[c] = fr.pix[(int64_t)qy * fr.pitch + qx];
+      Bv[c] = fr.bkg[(int64_t)qy * fr.w + qx];
+      wr += dwr;
+      wc += dwc;
+      if (wc >= nwx) {
+        wc -= nwx;
+        ++wr;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      if (pxs[c] < 0) continue;
+      const double q = qform(r.X, r.Y, r.xy, r.det, (double)pxs[c] - r.cx,
+                             (double)pys[c] - r.cy);
+      if (!(q <= s2)) continue;
+      if (!isfinite(Iv[c])) continue;
+      const double v = (double)Iv[c] - (double)Bv[c];
+      num += sqrt(q) * v;
+      den += v;
+    }
+  }
+}
+
+// The Kron radius from the first-moment sums (flag 2: R_min used).
+__device__ __forceinline__ double kron_radius(double num, double den,
+                                              double kfac, double rmin,
+                                              uint32_t* fl) {
+  const double r1 = den > 0.0 ? num / den : __builtin_nan("");
+  if (den > 0.0 && isfinite(r1)) {
+    const double R = kfac * r1;
+    return R > rmin ? R : rmin;
+  }
+  *fl |= 2u;
+  return rmin;
+}
+
 // Pass 2 over window pixels [e_begin, e_end) (raster order): members of
 // the open ellipse whose four corners lie inside it add v and area 1, the
 // other members are listed (LDS, kCut pixels of the window at a time) and
@@ -328,62 +403,13 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
     const FrameDev fr = wk.frames[r.f];
     uint32_t fl = 0;
     // ---- pass 1: first moment over the search ellipse ------------------
-    // window bounds clamped in binary64 before the conversion to int
-    const double hx = search * sqrt(X), hy = search * sqrt(Y);
-    const int xa = lo_px(cx - hx - 0.5, 0), xb = hi_px(cx + hx + 0.5, fr.w - 1);
-    const int ya = lo_px(cy - hy - 0.5, 0), yb = hi_px(cy + hy + 0.5, fr.h - 1);
+    const KronWin sw = search_window(fr, r, search);
+    if (sw.npx > kKronBigPx) continue;     // the whole row is k_kron_big's
     double num = 0.0, den = 0.0;
-    const double s2 = search * search;
-    if (xb >= xa && yb >= ya) {
-      // the window (inside the frame) in rounds of 64 pixels, positions
-      // stepped without division, the loads of kChunk rounds issued before
-      // any is used; each lane sums its pixels in window order
-      const int nwx = xb - xa + 1;
-      const int npx = nwx * (yb - ya + 1);
-      const int dwr = kWave / nwx, dwc = kWave - dwr * nwx;
-      int wr = lane / nwx, wc = lane - (lane / nwx) * nwx;
-      for (int e0 = 0; e0 < npx; e0 += kChunk * kWave) {
-        float Iv[kChunk], Bv[kChunk];
-        int pxs[kChunk], pys[kChunk];
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-          const bool live = e0 + c * kWave + lane < npx;
-          pxs[c] = live ? xa + wc : -1;
-          pys[c] = ya + wr;
-          const int qx = live ? xa + wc : xa, qy = live ? ya + wr : ya;
-          Iv[c] = fr.pix[(int64_t)qy * fr.pitch + qx];
-          Bv[c] = fr.bkg[(int64_t)qy * fr.w + qx];
-          wr += dwr;
-          wc += dwc;
-          if (wc >= nwx) {
-            wc -= nwx;
-            ++wr;
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-          if (pxs[c] < 0) continue;
-          const double q = qform(X, Y, xy, det, (double)pxs[c] - cx,
-                                 (double)pys[c] - cy);
-          if (!(q <= s2)) continue;
-          if (!isfinite(Iv[c])) continue;
-          const double v = (double)Iv[c] - (double)Bv[c];
-          num += sqrt(q) * v;
-          den += v;
-        }
-      }
-    }
+    kron_pass1(fr, r, search, sw, 0, sw.npx, lane, num, den);
     num = wave_sum(num);
     den = wave_sum(den);
-    const double r1 = den > 0.0 ? num / den : __builtin_nan("");
-    double R;
-    if (den > 0.0 && isfinite(r1)) {
-      R = kfac * r1;
-      R = R > rmin ? R : rmin;
-    } else {
-      R = rmin;
-      fl |= 2u;                                        // R_min used
-    }
+    const double R = kron_radius(num, den, kfac, rmin, &fl);
     // ---- pass 2: exact overlaps with the Kron ellipse -------------------
     // (one centred outside the frame is flagged outright)
     if (!(cx >= -0.5 && cx <= (double)fr.w - 0.5 && cy >= -0.5 &&
@@ -415,14 +441,16 @@ __global__ __launch_bounds__(kBlock) void k_kron(Work wk, ipp_sources src,
   }
 }
 
-// Pass 2 of the rows whose window k_kron left (more than kKronBigPx
-// pixels): each workgroup checks kBigThreads rows at once (one per thread,
-// from the Kron radius k_kron wrote), then takes each such row with all its
-// waves, wave k summing the k-th of kBigWaves equal parts of the window;
-// the parts' sums are added in wave order.
+// The rows k_kron left: those whose search window holds more than
+// kKronBigPx pixels (both passes here) and those whose Kron ellipse window
+// does (pass 2 here, with the radius k_kron wrote).  Each workgroup checks
+// kBigThreads rows at once (one per thread), then takes each such row with
+// all its waves, wave k summing the k-th of kBigWaves equal parts of a
+// window; the parts' sums are added in wave order.
 __global__ __launch_bounds__(kBigThreads) void k_kron_big(
-    Work wk, ipp_sources src, const double* mom, const double* kron,
-    double* flux, double* area, uint32_t* flags) {
+    Work wk, ipp_sources src, const double* mom, double kfac, double rmin,
+    double search, double* kron, double* flux, double* area,
+    uint32_t* flags) {
   constexpr int kBigWaves = kBigThreads / kWave;
   __shared__ int cut_lds[kBigWaves][kCut];
   __shared__ double atan_lds[kAtanTerms];
@@ -438,6 +466,36 @@ __global__ __launch_bounds__(kBigThreads) void k_kron_big(
   int* cut = cut_lds[wv];
   long long nrows = src.capacity;
   if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
+  // the parts of a window: [eb, ee) of its npx pixels for this wave, and
+  // the sum of two per-wave values over the waves in wave order
+  auto share = [&](int npx, int* eb, int* ee) {
+    const int per = (npx + kBigWaves - 1) / kBigWaves;
+    *eb = min(npx, wv * per);
+    *ee = min(npx, *eb + per);
+  };
+  auto combine = [&](double p0, double p1, bool e, double* s0, double* s1,
+                     bool* any) {
+    p0 = wave_sum(p0);
+    p1 = wave_sum(p1);
+    const bool ae = __builtin_amdgcn_ballot_w64(e) != 0;
+    if (lane == 0) {
+      part[wv][0] = p0;
+      part[wv][1] = p1;
+      pedge[wv] = ae ? 1 : 0;
+    }
+    __syncthreads();
+    double t0 = 0.0, t1 = 0.0;
+    int ed = 0;
+    for (int k = 0; k < kBigWaves; ++k) {
+      t0 += part[k][0];
+      t1 += part[k][1];
+      ed |= pedge[k];
+    }
+    __syncthreads();                  // read before the next use
+    *s0 = t0;
+    *s1 = t1;
+    *any = ed != 0;
+  };
   for (long long base = blockIdx.x * (long long)kBigThreads; base < nrows;
        base += (long long)gridDim.x * kBigThreads) {
     {
@@ -446,8 +504,9 @@ __global__ __launch_bounds__(kBigThreads) void k_kron_big(
       if (row < nrows) {
         const KronRow r = kron_row(wk, src, mom, row);
         if (r.ok) {
-          const KronWin kw = kron_window(wk.frames[r.f], r, kron[row]);
-          big = kw.npx > kKronBigPx;
+          const FrameDev& fr = wk.frames[r.f];
+          big = search_window(fr, r, search).npx > kKronBigPx ||
+                kron_window(fr, r, kron[row]).npx > kKronBigPx;
         }
       }
       if (big) list[atomicAdd(&nlist, 1)] = (int)threadIdx.x;
@@ -459,38 +518,46 @@ __global__ __launch_bounds__(kBigThreads) void k_kron_big(
       const long long row = base + list[i];
       const KronRow r = kron_row(wk, src, mom, row);
       const FrameDev fr = wk.frames[r.f];
-      const double R = kron[row];
+      const KronWin sw = search_window(fr, r, search);
+      const bool both = sw.npx > kKronBigPx;
+      uint32_t fl = 0;
+      double R;
+      int eb, ee;
+      bool e_unused;
+      if (both) {
+        double num = 0.0, den = 0.0;
+        share(sw.npx, &eb, &ee);
+        kron_pass1(fr, r, search, sw, eb, ee, lane, num, den);
+        combine(num, den, false, &num, &den, &e_unused);
+        R = kron_radius(num, den, kfac, rmin, &fl);
+        if (!(r.cx >= -0.5 && r.cx <= (double)fr.w - 0.5 && r.cy >= -0.5 &&
+              r.cy <= (double)fr.h - 0.5))
+          fl |= 4u;
+      } else {
+        R = kron[row];                 // k_kron wrote R and the flags
+      }
       const KronWin kw = kron_window(fr, r, R);
       const Ell el = ell_map(r.X, r.Y, r.xy, r.det, R);
-      const int per = (kw.npx + kBigWaves - 1) / kBigWaves;
-      const int eb = min(kw.npx, wv * per), ee = min(kw.npx, eb + per);
       double fs = 0.0, as = 0.0;
       bool edge = false;
+      share(kw.npx, &eb, &ee);
       kron_pass2(fr, r, el, R, kw, eb, ee, lane, cut, atan_lds, fs, as,
                  edge);
-      fs = wave_sum(fs);
-      as = wave_sum(as);
-      const bool any_edge = __builtin_amdgcn_ballot_w64(edge) != 0;
-      if (lane == 0) {
-        part[wv][0] = fs;
-        part[wv][1] = as;
-        pedge[wv] = any_edge ? 1 : 0;
-      }
-      __syncthreads();
+      bool any_edge;
+      combine(fs, as, edge, &fs, &as, &any_edge);
       if (threadIdx.x == 0) {
-        double F = 0.0, A = 0.0;
-        int ed = 0;
-        for (int k = 0; k < kBigWaves; ++k) {
-          F += part[k][0];
-          A += part[k][1];
-          ed |= pedge[k];
+        if (any_edge) fl |= 4u;                         // off the frame
+        if (both) {
+          kron[row] = R;
+          flags[row] = fl;
+        } else {
+          flags[row] |= fl;
         }
-        flux[row] = F;
-        area[row] = A;
-        if (ed) flags[row] |= 4u;                       // off the frame
+        flux[row] = fs;
+        area[row] = as;
       }
-      __syncthreads();
     }
+    __syncthreads();
     if (threadIdx.x == 0) nlist = 0;
     __syncthreads();
   }

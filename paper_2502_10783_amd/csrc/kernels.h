@@ -120,15 +120,16 @@ __global__ void k_db_diag(const int64_t* tot, int64_t pool_units,
                           const int64_t* counters, int64_t* diag);
 
 // AUTO (Kron) photometry: one wavefront per row (k_kron.hip); rows whose
-// ellipse window holds more than kKronBigPx pixels get their pass 2 from
-// k_kron_big, kBigThreads threads per workgroup, launched after k_kron.
+// search or ellipse window holds more than kKronBigPx pixels are finished
+// by k_kron_big, kBigThreads threads per workgroup, launched after k_kron.
 constexpr int kKronBigPx = 16384;
 constexpr int kBigThreads = 512;
 __global__ void k_kron(Work wk, ipp_sources src, const double* mom,
                        double kfac, double rmin, double search, double* kron,
                        double* flux, double* area, uint32_t* flags);
 __global__ void k_kron_big(Work wk, ipp_sources src, const double* mom,
-                           const double* kron, double* flux, double* area,
+                           double kfac, double rmin, double search,
+                           double* kron, double* flux, double* area,
                            uint32_t* flags);
 
 // Stamp convolution and subtraction: one workgroup per stamp, HW = the

@@ -86,24 +86,29 @@ def test_auto_photometry_matches_oracle(ctx, name):
     assert np.any(want["flags"] & okr.AUTO_OFF_EDGE) or name == "single"
 
 
-def _window_px(x, y, m, R, w, h):
-    """Pixels of the pass-2 window (the Kron ellipse's box within the frame
-    and a one-pixel ring), as the kernel bounds it."""
+def _window_px(x, y, m, R, w, h, ring):
+    """Pixels of a pass window as the kernel bounds it: the box of the
+    ellipse q <= R^2 within the frame (ring = 0: the search window) or
+    within the frame and a one-pixel ring around it (ring = 1: the Kron
+    ellipse's window)."""
     import math
     X, Y = m[0] + 1.0 / 12.0, m[1] + 1.0 / 12.0
     gx, gy = R * math.sqrt(X), R * math.sqrt(Y)
-    xa = int(max(math.ceil(x - gx - 0.5), -1))
-    xb = int(min(math.floor(x + gx + 0.5), w))
-    ya = int(max(math.ceil(y - gy - 0.5), -1))
-    yb = int(min(math.floor(y + gy + 0.5), h))
+    xa = int(max(math.ceil(x - gx - 0.5), -ring))
+    xb = int(min(math.floor(x + gx + 0.5), w - 1 + ring))
+    ya = int(max(math.ceil(y - gy - 0.5), -ring))
+    yb = int(min(math.floor(y + gy + 0.5), h - 1 + ring))
     return max(xb - xa + 1, 0) * max(yb - ya + 1, 0)
 
 
 def test_auto_photometry_large_windows(ctx):
-    """Objects whose Kron ellipse window exceeds 16384 pixels (extended
-    light, wide second moments) take the cooperative pass, the window
-    split over a workgroup's waves; one reaches over the frame edge.  Same
-    bar as above against the oracle."""
+    """Objects whose search or Kron ellipse window exceeds 16384 pixels
+    (extended light and wide second moments; a ring of light at the edge
+    of a small search ellipse, which makes R large) take the cooperative
+    kernel, each window split over a workgroup's waves: four with both
+    passes there (one reaching over the frame edge, one with R = R_min),
+    one with only pass 2 there, one small.  Same bar as above against the
+    oracle."""
     rng = np.random.default_rng(5)
     h = w = 600
     yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
@@ -114,15 +119,18 @@ def test_auto_photometry_large_windows(ctx):
                           ((yy - 300.0) ** 2) / (2 * 17.0 ** 2))
     img += 1500.0 * np.exp(-((xx - 60.0) ** 2 + (yy - 300.0) ** 2) /
                            (2 * 30.0 ** 2))
+    rr = np.sqrt((xx - 400.0) ** 2 + (yy - 150.0) ** 2)
+    img += 300.0 * np.exp(-(rr - 55.0) ** 2 / (2 * 3.0 ** 2))
     img = img.astype(np.float32)
     B = np.full((h, w), 100.0, dtype=np.float32)
-    xs = np.array([300.3, 280.2, 60.5, 100.4, 450.25])
-    ys = np.array([310.7, 300.9, 300.2, 120.6, 450.75])
+    xs = np.array([300.3, 280.2, 60.5, 100.4, 450.25, 400.5])
+    ys = np.array([310.7, 300.9, 300.2, 120.6, 450.75, 150.5])
     m = np.array([[484.0, 484.0, 0.0, 0, 0, 0],
                   [900.0, 300.0, 200.0, 0, 0, 0],
                   [900.0, 900.0, 0.0, 0, 0, 0],
                   [3.0, 2.5, 0.4, 0, 0, 0],
-                  [484.0, 400.0, -100.0, 0, 0, 0]])
+                  [484.0, 400.0, -100.0, 0, 0, 0],
+                  [100.0, 100.0, 0.0, 0, 0, 0]])
     k = xs.size
     table = ipp.SourceTable(k, 1, DEV)
     table.cols["frame"][:k] = 0
@@ -135,11 +143,13 @@ def test_auto_photometry_large_windows(ctx):
     torch.cuda.synchronize()
     got = {c: v[:k].cpu().numpy() for c, v in out.items()}
     want = okr.auto_photometry(img, B, xs, ys, m)
-    big = [_window_px(xs[i], ys[i], m[i], want["kron_radius"][i], w, h)
-           for i in range(k)]
-    print("windows", big, flush=True)
-    assert sum(b > 16384 for b in big) == 4 and min(big) <= 16384
-    assert big[2] > 16384 and want["flags"][2] & okr.AUTO_OFF_EDGE
+    s1 = [_window_px(xs[i], ys[i], m[i], 6.0, w, h, 0) for i in range(k)]
+    s2 = [_window_px(xs[i], ys[i], m[i], want["kron_radius"][i], w, h, 1)
+          for i in range(k)]
+    print("search windows", s1, "ellipse windows", s2, flush=True)
+    assert [b > 16384 for b in s1] == [True, True, True, False, True, False]
+    assert s2[5] > 16384 and s2[3] <= 16384
+    assert want["flags"][2] & okr.AUTO_OFF_EDGE
     assert want["flags"][4] & okr.AUTO_RMIN
     assert np.array_equal(got["flags"], want["flags"].astype(np.int32))
     np.testing.assert_allclose(got["kron_radius"], want["kron_radius"],
