@@ -1516,7 +1516,6 @@ ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
                                 tot + 4));
   if ((st = scan64(c, need, blk, D.nblk, off, rows, tot, s)) != IPP_OK)
     return st;
-  const dim3 g1(grid_for(rows, 64, 1 << 20));
   // persistent workgroups (as many as fit the device at once) that take
   // candidates from a counter
   IPP_LAUNCH(c, s, "k_db_small",
@@ -1547,7 +1546,9 @@ ipp_status ipp_deblend(void* ctx, const ipp_frame* frames, int32_t n,
                                      std::min(n, 65535)),
                                 dim3(kBlock), 0, s, w));
   IPP_LAUNCH(c, s, "k_db_write",
-             hipLaunchKernelGGL(k_db_write, g1, dim3(64), 0, s, w, *cand,
+             hipLaunchKernelGGL(k_db_write,
+                                dim3(grid_for(rows, kWaves, 16384)),
+                                dim3(kBlock), 0, s, w, *cand,
                                 off, tot, pool, pool_units, cnt, ooff, *obj,
                                 parent));
   IPP_LAUNCH(c, s, "k_db_offsets",

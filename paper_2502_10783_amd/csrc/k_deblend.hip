@@ -6,8 +6,9 @@
 //   k_scan64_*   exclusive scans (scratch offsets, then object offsets)
 //   k_db_small   boxes of up to kDbSmallBox pixels, a wavefront each
 //   k_db_large   larger boxes, a workgroup each
-//   k_db_write   per candidate: object ids into the object maps, the
-//                objects' rows (frame, label, parent, pixel count, box)
+//   k_db_write   a wavefront per candidate: object ids into the object
+//                maps, the objects' rows (frame, label, parent, pixel
+//                count, box)
 //   k_db_offsets per-frame object offsets and count
 //   k_db_flags   BLENDED on the objects of split candidates (after the
 //                pre-analysis kernel has filled the rows)
@@ -1039,15 +1040,24 @@ __global__ __launch_bounds__(kBlock) void k_db_zero(Work wk) {
   }
 }
 
-// One thread per candidate: its objects' rows and their ids in the map.
-__global__ __launch_bounds__(64) void k_db_write(
+// One wavefront per candidate: its objects' rows (lane-parallel), then its
+// bounding box in rounds of 64 pixels (positions stepped without division):
+// the ids in the object map and, for a split candidate, each object's pixel
+// count and box, reduced over the round per object and added to its row
+// with one atomic per object and round (integer sums, minima and maxima:
+// the same whatever the order).
+__global__ __launch_bounds__(kBlock) void k_db_write(
     Work wk, ipp_sources cand, const int64_t* off, const int64_t* tot,
     const char* pool, int64_t pool_units, const int64_t* cnt,
     const int64_t* ooff, ipp_sources obj, int32_t* parent) {
   const long long n = table_rows(cand);
   const bool fits = *tot <= pool_units;
-  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-       r < n; r += (long long)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long wid =
+      blockIdx.x * (long long)kWaves +
+      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const long long nw = (long long)gridDim.x * kWaves;
+  for (long long r = wid; r < n; r += nw) {
     const int f = cand.frame[r];
     const FrameDev fr = wk.frames[f];
     const int lab = cand.label[r];
@@ -1056,7 +1066,7 @@ __global__ __launch_bounds__(64) void k_db_write(
     const int k = (int)cnt[r];
     const int x0 = cand.xmin[r], y0 = cand.ymin[r];
     const int bw = cand.xmax[r] - x0 + 1, bh = cand.ymax[r] - y0 + 1;
-    for (int j = 0; j < k; ++j) {
+    for (int j = lane; j < k; j += kWave) {
       const int64_t o = base + j;
       if (o >= obj.capacity) break;
       obj.frame[o] = f;
@@ -1077,32 +1087,73 @@ __global__ __launch_bounds__(64) void k_db_write(
       }
     }
     const int32_t id0 = (int32_t)(base - first + 1);
+    const int64_t A = (int64_t)bw * bh;
+    const int dy = kWave / bw, dx = kWave - (kWave / bw) * bw;
+    int y = lane / bw, x = lane - (lane / bw) * bw;
     if (k == 1 || !fits || cand.npix[r] < 2) {
-      for (int y = 0; y < bh; ++y)
-        for (int x = 0; x < bw; ++x) {
+      for (int64_t e0 = 0; e0 < A; e0 += kWave) {
+        if (e0 + lane < A) {
           const int64_t q = (int64_t)(y0 + y) * fr.w + x0 + x;
           if (fr.labels[q] == lab) fr.objects[q] = id0;
         }
+        y += dy;
+        x += dx;
+        if (x >= bw) {
+          x -= bw;
+          ++y;
+        }
+      }
       continue;
     }
-    const int64_t A = (int64_t)bw * bh;
+    // the rows' initial values are in memory before the atomics below
+    // (this wave's stores completed; the atomics are performed in the
+    // same L2): a workgroup-scope release, which waits for them without
+    // the device-scope cache write-back
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     const db::Pool s =
         db::carve((char*)pool + off[r] * 256, A, cand.npix[r]);
-    for (int y = 0; y < bh; ++y)
-      for (int x = 0; x < bw; ++x) {
-        const int a = s.asg[y * bw + x];
-        if (a < 0) continue;
-        const int64_t q = (int64_t)(y0 + y) * fr.w + x0 + x;
-        fr.objects[q] = id0 + a;
-        const int64_t o = base + a;
-        if (o >= obj.capacity) continue;
-        obj.npix[o] += 1;
-        const int px = x0 + x, py = y0 + y;
-        if (px < obj.xmin[o]) obj.xmin[o] = px;
-        if (px > obj.xmax[o]) obj.xmax[o] = px;
-        if (py < obj.ymin[o]) obj.ymin[o] = py;
-        if (py > obj.ymax[o]) obj.ymax[o] = py;
+    for (int64_t e0 = 0; e0 < A; e0 += kWave) {
+      const int64_t e = e0 + lane;
+      int a = -1;
+      const int px = x0 + x, py = y0 + y;
+      if (e < A) {
+        a = s.asg[e];
+        if (a >= 0) fr.objects[(int64_t)py * fr.w + px] = id0 + a;
       }
+      y += dy;
+      x += dx;
+      if (x >= bw) {
+        x -= bw;
+        ++y;
+      }
+      bool act = a >= 0 && base + a < obj.capacity;
+      uint64_t left = ballot(act);
+      while (left) {
+        const int lead = __ffsll((unsigned long long)left) - 1;
+        const int k0 = __builtin_amdgcn_readlane(a, lead);
+        const bool in = act && a == k0;
+        const uint64_t m = ballot(in);
+        left &= ~m;
+        int xn = in ? px : 0x7FFFFFFF, xm = in ? px : -1;
+        int yn = in ? py : 0x7FFFFFFF, ym = in ? py : -1;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+          xn = min(xn, __shfl_xor(xn, o, kWave));
+          xm = max(xm, __shfl_xor(xm, o, kWave));
+          yn = min(yn, __shfl_xor(yn, o, kWave));
+          ym = max(ym, __shfl_xor(ym, o, kWave));
+        }
+        if (lane == lead) {
+          const int64_t o = base + k0;
+          atomicAdd(&obj.npix[o], (int32_t)__popcll(m));
+          atomicMin(&obj.xmin[o], xn);
+          atomicMax(&obj.xmax[o], xm);
+          atomicMin(&obj.ymin[o], yn);
+          atomicMax(&obj.ymax[o], ym);
+        }
+        act = act && !in;
+      }
+    }
   }
 }
 
