@@ -29,6 +29,7 @@ constexpr int kEdges = 36;      // pixel edges per axis of a window, r <= 16
 // r + 1 row lines, so it passes through at most 2r + 3 squares.
 constexpr int kCutCap = 8 * 16 + 16;
 constexpr int kTaskCap = 3 * kCutCap;
+constexpr int kTaskCapF = 4 * kCutCap;   // the forward's list (4 circles)
 
 // A source's window of pixels: columns [xa, xa + nwx), rows [ya, ya + nwy).
 // Loads take 32-bit byte offsets from a wave-uniform row base (the window's
@@ -144,16 +145,19 @@ struct Window {
 // the centre (a pixel's distances are sums of one of each: the same two
 // rounded squares and the same addition as computing them per pixel) and,
 // at every column (row) edge q, the roots sqrt(r^2 - min(|q|, r)^2) of the
-// three circles (aperture, outer, inner), for the exact overlaps.
-struct WinTables {
+// NC circles (aperture, outer, inner, and a second aperture r_x when NC is
+// 4), for the exact overlaps.
+template <int NC>
+struct WinTablesT {
   double2 colT[kEdges];
   double2 rowT[kEdges];
-  double sq[3 * 2 * kEdges];       // [circle][axis][edge]
+  double sq[NC * 2 * kEdges];      // [circle][axis][edge]
 
   __device__ void fill(const Window& W, double cx, double cy, double r_ap,
-                       double r_in, double r_out, int lane) {
+                       double r_in, double r_out, int lane,
+                       double r_x = 0.0) {
     const double ra2 = r_ap * r_ap, ri2 = r_in * r_in;
-    const double ro2 = r_out * r_out;
+    const double ro2 = r_out * r_out, rx2 = r_x * r_x;
     const int ne = (W.nwx > W.nwy ? W.nwx : W.nwy) + 1;   // <= kEdges
     for (int e = lane; e < 2 * ne; e += kWave) {
       const bool col = e < ne;
@@ -172,6 +176,7 @@ struct WinTables {
         sq[ax + j] = edge_root(q, r_ap, ra2);
         sq[2 * kEdges + ax + j] = edge_root(q, r_out, ro2);
         sq[4 * kEdges + ax + j] = edge_root(q, r_in, ri2);
+        if constexpr (NC > 3) sq[6 * kEdges + ax + j] = edge_root(q, r_x, rx2);
       }
     }
   }
@@ -184,6 +189,7 @@ struct WinTables {
     *far2 = tc.y + tr.y;
   }
 };
+using WinTables = WinTablesT<3>;
 
 // Circle of a task: 0 the aperture, 1 the outer, 2 the inner annulus circle.
 __device__ __forceinline__ void task_circle(double r_ap, double r_in,
@@ -193,20 +199,30 @@ __device__ __forceinline__ void task_circle(double r_ap, double r_in,
   *r = rr;
   *r2 = rr * rr;
 }
+// The same with circle 3, a second aperture r_x.
+__device__ __forceinline__ void task_circle4(double r_ap, double r_in,
+                                             double r_out, double r_x, int c,
+                                             double* r, double* r2) {
+  const double rr = c == 0 ? r_ap : (c == 1 ? r_out : (c == 2 ? r_in : r_x));
+  *r = rr;
+  *r2 = rr * rr;
+}
 
-template <int NS>
+// NC: circles of the window tables (4 with a second aperture).
+template <int NS, int NC = 3>
 struct ApLds {
+  static constexpr int kCap = NC > 3 ? kTaskCapF : kTaskCap;
   // the annulus values as they are found; once read into registers, the
   // sort's transposes and then the sorted values
   double xs[NS + kWave];
   // pixels cut by a circle: circle << 12 | wy << 6 | wx (circle 0: the
-  // aperture, 1: the outer and 2: the inner annulus circle).  The lists
-  // start kWave slots in from either end and their counts are clamped
-  // round by round, so a round's appends stay inside the array without a
-  // bound test per lane (the values lists likewise: the count stays at most
-  // NS, and xs has kWave slots more).
-  int tk[kTaskCap + 2 * kWave];
-  WinTables T;
+  // aperture, 1: the outer and 2: the inner annulus circle, 3: the second
+  // aperture).  The lists start kWave slots in from either end and their
+  // counts are clamped round by round, so a round's appends stay inside the
+  // array without a bound test per lane (the values lists likewise: the
+  // count stays at most NS, and xs has kWave slots more).
+  int tk[kCap + 2 * kWave];
+  WinTablesT<NC> T;
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -378,19 +394,27 @@ struct ApOut {
   double vlo, vhi;     // the sky survivors' value range (empty: vlo > vhi)
   uint32_t flags;
   double dfx, dfy;     // dF/dcx, dF/dcy (GRAD)
+  double raw_x, a_x;   // raw and a_ap of the second aperture (r_x > 0)
 };
 
 // With GRAD, `norm` (wave-uniform) asks for the flux sums only (raw, not
 // the derivative sums) and its absence for the derivative only (no raw).
-template <int NS, bool GRAD>
+// r_x > 0 (wave-uniform) adds the flux sums of a second aperture of that
+// radius about the same centre, over the same sky: the refinement's
+// normaliser taken in the evaluation of its first step.
+template <int NS, bool GRAD, int NC = 3>
 __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
                                double r_ap, double cx, double cy,
-                               ApLds<NS>& L, const double* atan_lds,
-                               int lane, bool norm = true) {
+                               ApLds<NS, NC>& L, const double* atan_lds,
+                               int lane, bool norm = true,
+                               double r_x = 0.0) {
+  constexpr int kCapT = ApLds<NS, NC>::kCap;
   constexpr int PL = NS / kWave;
   constexpr int P = PL == 4 ? 2 : (PL == 8 ? 3 : 4);
   static_assert((1 << P) == PL, "NS is 256, 512 or 1024");
-  const double R = r_ap > p.r_out ? r_ap : p.r_out;
+  const bool dual = NC > 3 && r_x > 0.0;
+  double R = r_ap > p.r_out ? r_ap : p.r_out;
+  R = r_x > R ? r_x : R;
   // window bounds: wave-uniform values, kept in scalar registers
   Window W;
   W.init(fr, __builtin_amdgcn_readfirstlane((int)ceil(cx - R - 0.5)),
@@ -399,8 +423,8 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
          __builtin_amdgcn_readfirstlane((int)floor(cy + R + 0.5)));
   // squared radii as the membership predicates form them
   const double ra2 = r_ap * r_ap, ri2 = p.r_in * p.r_in;
-  const double ro2 = p.r_out * p.r_out;
-  L.T.fill(W, cx, cy, r_ap, p.r_in, p.r_out, lane);
+  const double ro2 = p.r_out * p.r_out, rx2 = r_x * r_x;
+  L.T.fill(W, cx, cy, r_ap, p.r_in, p.r_out, lane, r_x);
   wave_lds_sync();
 
   // ---- walk the window: sums, annulus values, cut pixels ---------------
@@ -410,6 +434,8 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   int nfull = 0;                       // pixels wholly inside the aperture
   int nann = 0, nt0 = 0, nt1 = 0;      // wave-uniform list lengths
   double raw = 0.0;                    // per lane: sum of v over them
+  int nfull_x = 0;                     // the same for the second aperture
+  double raw_x = 0.0;
   uint64_t bad_ap = 0, bad_ann = 0;    // lanes of members not ok
   W.walk<4>(lane, [&](bool live, int q, bool ok, double v, uint64_t mok,
                       uint64_t mlive) {
@@ -439,16 +465,29 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     const uint64_t b1 = ba & ~ballot(far2 <= ro2);
     const uint64_t b2 = ba & ballot(near2 < ri2);
     if (c0) L.tk[kWave + nt0 + lanes_before(b0)] = q;
-    nt0 = min(nt0 + (int)__popcll(b0), kTaskCap);
+    nt0 = min(nt0 + (int)__popcll(b0), kCapT);
     if (c1)
-      L.tk[kWave + kTaskCap - 1 - (nt1 + lanes_before(b1))] = (1 << 12) | q;
-    nt1 = min(nt1 + (int)__popcll(b1), kTaskCap);
+      L.tk[kWave + kCapT - 1 - (nt1 + lanes_before(b1))] = (1 << 12) | q;
+    nt1 = min(nt1 + (int)__popcll(b1), kCapT);
     if (c2)
-      L.tk[kWave + kTaskCap - 1 - (nt1 + lanes_before(b2))] = (2 << 12) | q;
-    nt1 = min(nt1 + (int)__popcll(b2), kTaskCap);
+      L.tk[kWave + kCapT - 1 - (nt1 + lanes_before(b2))] = (2 << 12) | q;
+    nt1 = min(nt1 + (int)__popcll(b2), kCapT);
+    if (dual) {
+      // the second aperture: whole pixels summed, cut ones listed with
+      // the aperture's from the front
+      const bool x_whole = far2 <= rx2;
+      const uint64_t m_x = mlive & mok & ballot(near2 < rx2);
+      const uint64_t m_xw = ballot(x_whole);
+      nfull_x += __popcll(m_x & m_xw);
+      if (live & ok & (near2 < rx2) & x_whole) raw_x += v;
+      const uint64_t b3 = m_x & ~m_xw;
+      if (live & ok & (near2 < rx2) & !x_whole)
+        L.tk[kWave + nt0 + lanes_before(b3)] = (3 << 12) | q;
+      nt0 = min(nt0 + (int)__popcll(b3), kCapT);
+    }
   });
   // not reachable: NS bounds the ring, and the task lists cannot meet
-  if (nt0 + nt1 > kTaskCap) { nt0 = min(nt0, kTaskCap); nt1 = kTaskCap - nt0; }
+  if (nt0 + nt1 > kCapT) { nt0 = min(nt0, kCapT); nt1 = kCapT - nt0; }
   ApOut o;
   o.flags = 0;                         // wave-uniform
   if (bad_ap) o.flags |= IPP_SRC_APERTURE_OFF_EDGE;
@@ -542,7 +581,7 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   // by w - 1 for the outer circle and by -w for the inner one (a pixel cut
   // by both gets w_out - w_in).  With GRAD the centre derivatives of the
   // same overlaps (chords at the pixel's corners) are summed alongside.
-  double acut = 0.0, dnum = 0.0, dden = 0.0;
+  double acut = 0.0, dnum = 0.0, dden = 0.0, acut_x = 0.0;
   double tvx = 0.0, tvy = 0.0, tax = 0.0, tay = 0.0;   // aperture terms
   double svx = 0.0, svy = 0.0, swx = 0.0, swy = 0.0;   // sky terms
   const int ntk = nt0 + nt1;
@@ -553,11 +592,12 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
     int co = 0;
     asm volatile("" : "+s"(co));
     const double* coef = atan_lds + co;
-    const int t = L.tk[kWave + (j < nt0 ? j : kTaskCap - nt1 + (j - nt0))];
+    const int t = L.tk[kWave + (j < nt0 ? j : kCapT - nt1 + (j - nt0))];
     const int c = t >> 12, wx = t & 63, wy = (t >> 6) & 63;
     const int px = W.xa + wx, py = W.ya + wy;
     double r, r2;
-    task_circle(r_ap, p.r_in, p.r_out, c, &r, &r2);
+    if constexpr (NC > 3) task_circle4(r_ap, p.r_in, p.r_out, r_x, c, &r, &r2);
+    else task_circle(r_ap, p.r_in, p.r_out, c, &r, &r2);
     const double* sq = L.T.sq + c * 2 * kEdges;
     const double hx0 = sq[wx], hx1 = sq[wx + 1];
     const double xs0 = sq[kEdges + wy], xs1 = sq[kEdges + wy + 1];
@@ -574,6 +614,9 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
         tvx += v * gx; tvy += v * gy;
         tax += gx; tay += gy;
       }
+    } else if (c == 3) {
+      acut_x += w;
+      raw_x += w * v;
     } else if (v >= vlo && v <= vhi) {
       const double dw = c == 1 ? w - 1.0 : -w;
       dden += dw;
@@ -588,6 +631,11 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   }
   o.a_ap = (double)nfull + wave_sum(acut);
   o.raw = !GRAD || norm ? wave_sum(raw) : 0.0;
+  o.raw_x = o.a_x = 0.0;
+  if (dual) {
+    o.a_x = (double)nfull_x + wave_sum(acut_x);
+    o.raw_x = wave_sum(raw_x);
+  }
   o.num = su + wave_sum(dnum);
   o.den = (double)(bnd - a) + wave_sum(dden);
   o.dfx = o.dfy = 0.0;
@@ -655,13 +703,15 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
 // Centroid refinement of one source: the normaliser F_ap(c0) with p's
 // aperture, then `steps` ascent steps c <- c + eta g dF_rc/dc (g =
 // 1 / F_ap(c0)), each step's derivative taken with that step's sky clip
-// mask, all in this wave.  Sources with g = 0 (F_ap(c0) <= 0 or not a
-// number) stay in place, and so does a centre that leaves the valid range.
+// mask, all in this wave.  The first step's evaluation (at c0) also takes
+// the normaliser, as the flux of a second aperture over the same sky.
+// Sources with g = 0 (F_ap(c0) <= 0 or not a number) stay in place, and so
+// does a centre that leaves the valid range.
 template <int NS>
 __device__ void refine_one(const Work& wk, const ipp_params& p,
                            double r_c, double eta, int steps,
                            const ipp_sources& src, double* xo, double* yo,
-                           long long row, ApLds<NS>& L,
+                           long long row, ApLds<NS, 4>& L,
                            const double* atan_lds) {
   int lane = threadIdx.x & (kWave - 1);
   asm volatile("" : "+v"(lane));
@@ -669,23 +719,22 @@ __device__ void refine_one(const Work& wk, const ipp_params& p,
   double cx = src.x[row], cy = src.y[row];
   if ((f >= 0 && f < wk.nframes) && centre_ok(cx, cy)) {
     const FrameDev fr = wk.frames[f];   // f is wave-uniform: SGPRs
-    // k = -1: the normaliser (its derivative is not used); one call site,
-    // so that the photometry is inlined once
+    // one call site, so that the photometry is inlined once
     double g = 0.0;
-    for (int k = -1; k < steps; ++k) {
-      const ApOut o = aperture_eval<NS, true>(fr, p, k < 0 ? p.r_ap : r_c,
-                                              cx, cy, L, atan_lds, lane,
-                                              k < 0);
-      if (k < 0) {
+    for (int k = 0; k < steps; ++k) {
+      const ApOut o = aperture_eval<NS, true, 4>(fr, p, r_c, cx, cy, L,
+                                                 atan_lds, lane, false,
+                                                 k == 0 ? p.r_ap : 0.0);
+      if (k == 0) {
         const double sky0 = o.den > 0.0 ? o.num / o.den : 0.0;
-        const double F0 = o.raw - sky0 * o.a_ap;
+        const double F0 = o.raw_x - sky0 * o.a_x;
         g = F0 > 0.0 ? 1.0 / F0 : 0.0;
-      } else {
-        const double dx = g * o.dfx, dy = g * o.dfy;
-        cx = cx + eta * dx;
-        cy = cy + eta * dy;
+        if (g == 0.0) break;
       }
-      if (g == 0.0 || !centre_ok(cx, cy)) break;
+      const double dx = g * o.dfx, dy = g * o.dfy;
+      cx = cx + eta * dx;
+      cy = cy + eta * dy;
+      if (!centre_ok(cx, cy)) break;
     }
   }
   if (lane == 0) {
@@ -725,7 +774,7 @@ __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_refine_t(
     Work wk, ipp_params p, double r_c, double eta, int steps,
     ipp_sources src, double* xo, double* yo) {
-  __shared__ ApLds<NS> L[kWaves];
+  __shared__ ApLds<NS, 4> L[kWaves];
   __shared__ double atan_lds[kAtanTerms];
   if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
   __syncthreads();
@@ -735,7 +784,7 @@ __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_refine_t(
       blockIdx.x * (long long)kWaves +
       __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const long long nw = (long long)gridDim.x * kWaves;
-  ApLds<NS>& mine = L[threadIdx.x / kWave];
+  ApLds<NS, 4>& mine = L[threadIdx.x / kWave];
   for (long long row = wid; row < nrows; row += nw)
     refine_one<NS>(wk, p, r_c, eta, steps, src, xo, yo, row, mine, atan_lds);
 }
