@@ -874,10 +874,12 @@ def run_pipeline(workload, args, dev, quick=False):
     # algorithmic flops of the photometry launches of one step
     fl_fwd = aperture_flops_per_source(p.r_ap, p.r_in, p.r_out)
     fl_rc = aperture_flops_per_source(REFINE_RC, p.r_in, p.r_out)
-    # (the refinement: the normaliser with the default aperture, then per
-    # step a forward and a backward at r_c, all in k_refine)
+    # (the refinement: per step a forward and a backward at r_c, all in
+    # k_refine; the normaliser's aperture is taken in the first step's
+    # evaluation over that step's sky, so it adds its own circle only)
+    fl_norm = aperture_flops_per_source(p.r_ap, 0.0, 0.0)
     flops = {"k_aperture": nsrc * fl_fwd,
-             "k_refine": (nsrc * (fl_fwd + 2 * fl_rc * REFINE_STEPS)
+             "k_refine": (nsrc * (fl_norm + 2 * fl_rc * REFINE_STEPS)
                           if refine else 0.0)}
     dom = max(kern, key=lambda k: kern[k]["ms_total"])
     roof = roofline(kern, dom, npx, flops)
