@@ -264,10 +264,18 @@ __device__ __forceinline__ double kron_radius(double num, double den,
 
 // Pass 2 over window pixels [e_begin, e_end) (raster order): members of
 // the open ellipse whose four corners lie inside it add v and area 1, the
-// other members are listed (LDS, kCut pixels of the window at a time) and
-// add w v and w, w the exact overlap; a member off the frame or not finite
-// sets edge.  Each lane accumulates its pixels in window order, then its
-// listed pixels; the pixel loads of kChunk rounds are issued before any is
+// other members are listed and add w v and w, w the exact overlap; a
+// member off the frame or not finite sets edge.  Membership is the exact
+// predicate min_q < R^2, but most pixels are settled by their centre
+// without it: min_q <= q(centre), and sqrt(min_q) >= sqrt(q(centre)) - m
+// with m the largest sqrt(q) of a half-pixel corner offset, so a centre
+// with q below R^2 (1 - 1e-9) is a member and one above (R + m)^2
+// (1 + 1e-9) is not (margins no rounding here can cross); the pixels in
+// between (a band along the boundary) are listed and tested exactly, all
+// lanes busy.  Per chunk of kCut / 2 window pixels the band is listed
+// from the back of `cut`, the cut members from its front.  Each lane
+// accumulates the settled members in window order, then the band's, then
+// the cut ones; the pixel loads of kChunk rounds are issued before any is
 // used (clamped into the frame; only members use them).
 __device__ void kron_pass2(const FrameDev& fr, const KronRow& r,
                            const Ell& el, double R, const KronWin& kw,
@@ -279,15 +287,41 @@ __device__ void kron_pass2(const FrameDev& fr, const KronRow& r,
   const double R2 = R * R;
   // corners inside: q det <= R^2 det (1 - 1e-12), no division
   const double lim = R2 * det * (1.0 - 1e-12);
+  const double m = sqrt(0.25 * (X + Y + 2.0 * fabs(xy)) / det);
+  const double lim_in = R2 * det * (1.0 - 1e-9);
+  const double lim_out = (R + m) * (R + m) * det * (1.0 + 1e-9);
+  auto qd = [&](double dx, double dy) {
+    return Y * dx * dx + X * dy * dy - 2.0 * xy * dx * dy;
+  };
+  // a member pixel with its loaded values: edge, a whole pixel, or listed
+  auto member = [&](int px, int py, float I, float B, int pos, bool* listed,
+                    int* lpos) {
+    const bool in = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
+    if (!in || !isfinite(I)) {
+      edge = true;
+      return;
+    }
+    const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
+    const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
+    if (qd(x0, y0) <= lim && qd(x1, y0) <= lim && qd(x0, y1) <= lim &&
+        qd(x1, y1) <= lim) {
+      fs += (double)I - (double)B;
+      as += 1.0;
+    } else {
+      *listed = true;
+      *lpos = pos;
+    }
+  };
   const int nwx = kw.nwx;
   if (nwx <= 0 || e_end <= e_begin) return;
   // window positions stepped round by round without division
   const int dwr = kWave / nwx, dwc = kWave - dwr * nwx;
   const int el0 = e_begin + lane;
   int sy = el0 / nwx, sx = el0 - (el0 / nwx) * nwx;
-  for (int e0 = e_begin; e0 < e_end; e0 += kCut) {
-    int ncut = 0;
-    const int e1 = min(e_end, e0 + kCut);
+  constexpr int kPart = kCut / 2;      // window pixels per chunk
+  for (int e0 = e_begin; e0 < e_end; e0 += kPart) {
+    int ncut = 0, nband = 0;
+    const int e1 = min(e_end, e0 + kPart);
     for (int eb = e0; eb < e1; eb += kChunk * kWave) {
       float Iv[kChunk], Bv[kChunk];
       int wys[kChunk], wxs[kChunk];
@@ -311,38 +345,55 @@ __device__ void kron_pass2(const FrameDev& fr, const KronRow& r,
       for (int c = 0; c < kChunk; ++c) {
         if (eb + c * kWave >= e1) break;             // wave-uniform
         const int e = eb + c * kWave + lane;
-        bool listed = false;
+        bool listed = false, band = false;
         int pos = 0;
         if (e < e1) {
           const int wy = wys[c], wx = wxs[c];
           const int py = kw.ya + wy, px = kw.xa + wx;
-          const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
-          const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
-          // the pixel meets the open ellipse: an exact predicate
-          if (min_q(X, Y, xy, det, x0, x1, y0, y1) < R2) {
-            const bool in = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
-            const float I = Iv[c];
-            if (!in || !isfinite(I)) {
-              edge = true;
-            } else {
-              auto qd = [&](double dx, double dy) {
-                return Y * dx * dx + X * dy * dy - 2.0 * xy * dx * dy;
-              };
-              if (qd(x0, y0) <= lim && qd(x1, y0) <= lim &&
-                  qd(x0, y1) <= lim && qd(x1, y1) <= lim) {
-                fs += (double)I - (double)Bv[c];
-                as += 1.0;
-              } else {
-                listed = true;
-                pos = (wy << 16) | wx;
-              }
-            }
+          pos = (wy << 16) | wx;
+          const double qc = qd((double)px - cx, (double)py - cy);
+          if (qc <= lim_in) {
+            int lp = 0;
+            member(px, py, Iv[c], Bv[c], pos, &listed, &lp);
+          } else {
+            band = !(qc >= lim_out);
           }
         }
+        const uint64_t bb = ballot(band);
+        if (band) cut[kCut - 1 - (nband + lanes_before(bb))] = pos;
+        nband += __popcll(bb);
         const uint64_t b = ballot(listed);
         if (listed) cut[ncut + lanes_before(b)] = pos;
         ncut += __popcll(b);
       }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the band: the exact predicate, then as any member
+    for (int j0 = 0; j0 < nband; j0 += kWave) {
+      const int j = j0 + lane;
+      bool listed = false;
+      int pos = 0;
+      if (j < nband) {
+        const int t = cut[kCut - 1 - j];
+        const int wx = t & 0xFFFF, wy = t >> 16;
+        const int px = kw.xa + wx, py = kw.ya + wy;
+        const double x0 = (double)px - 0.5 - cx, x1 = (double)px + 0.5 - cx;
+        const double y0 = (double)py - 0.5 - cy, y1 = (double)py + 0.5 - cy;
+        if (min_q(X, Y, xy, det, x0, x1, y0, y1) < R2) {
+          const bool in = px >= 0 && px < fr.w && py >= 0 && py < fr.h;
+          float I = 0.0f, B = 0.0f;
+          if (in) {
+            I = fr.pix[(int64_t)py * fr.pitch + px];
+            B = fr.bkg[(int64_t)py * fr.w + px];
+          }
+          member(px, py, I, B, t, &listed, &pos);
+        }
+      }
+      const uint64_t b = ballot(listed);
+      if (listed) cut[ncut + lanes_before(b)] = pos;
+      ncut += __popcll(b);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
