@@ -721,7 +721,8 @@ def run_gray(args):
 
 def run_plain(ctx, frames, p, tables, refine):
     """Eager per-frame path: one background, detect, count, photometry (and
-    refinement) call per frame."""
+    refinement) call per frame; with the refinement the photometry is
+    written by the refinement's first evaluation, as in the batched step."""
     from dataclasses import replace
     from paper_2502_10783_amd import _lib as L
     p_eager = replace(p, flags=p.flags | L.IPP_F_NO_GRAPH)
@@ -731,12 +732,14 @@ def run_plain(ctx, frames, p, tables, refine):
         d = ctx.detect([f], bg["bkg"], bg["rms"], p, table=t)
         k = t.count()                             # host sync per frame
         n += k
-        ctx.photometry([f], bg["bkg"], d["table"], p)
-        if refine and k:
+        if not refine:
+            ctx.photometry([f], bg["bkg"], d["table"], p)
+        elif k:
             ctx.refine_centroids([f], bg["bkg"], t, p_eager,
                                  steps=REFINE_STEPS, r_c=REFINE_RC,
                                  use_count=True,
-                                 x_out=t.extra_x, y_out=t.extra_y)
+                                 x_out=t.extra_x, y_out=t.extra_y,
+                                 write_photometry=True)
     return n
 
 
@@ -810,12 +813,17 @@ def run_pipeline(workload, args, dev, quick=False):
     xr = torch.empty(cap, dtype=torch.float64, device=dev)
     yr = torch.empty(cap, dtype=torch.float64, device=dev)
 
+    # with the refinement, the photometry of every candidate is written by
+    # the refinement's first evaluation (its sky is that evaluation's)
+    # instead of a separate photometry launch
     def step():
-        ctx.process_batch(frames, p, table=table, outputs=outputs)
+        ctx.process_batch(frames, p, table=table, outputs=outputs,
+                          photometry=not refine)
         if refine:
             ctx.refine_centroids(frames, outputs["bkg"], table, p,
                                  steps=REFINE_STEPS, r_c=REFINE_RC,
-                                 use_count=True, x_out=xr, y_out=yr)
+                                 use_count=True, x_out=xr, y_out=yr,
+                                 write_photometry=True)
 
     steps = args.steps if not quick else max(3, args.steps)
     log(f"[{workload}] warmup")

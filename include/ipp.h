@@ -70,6 +70,16 @@ enum {
 #define IPP_F_NO_GRAPH 2u   /* ipp_process_batch and ipp_refine_centroids
                                launch their kernels one by one instead of
                                capturing and replaying a HIP graph         */
+#define IPP_F_NO_PHOTOMETRY 4u      /* ipp_process_batch stops after the
+                                       source table: the photometry columns
+                                       are left to ipp_photometry or to
+                                       ipp_refine_centroids with the next
+                                       flag                                */
+#define IPP_F_REFINE_PHOTOMETRY 8u  /* ipp_refine_centroids also writes the
+                                       photometry of ipp_photometry at the
+                                       starting centres (flux_ap, sky,
+                                       area_ap, area_ann; flags or'ed in),
+                                       taken in its first evaluation       */
 
 /* Per-frame flags (uint32 per frame). */
 #define IPP_FRAME_NO_VALID_MESH 1u  /* no node had min_valid pixels: every
@@ -290,7 +300,13 @@ ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
  * src->x and src->y themselves); the table's other columns are untouched.
  * r_c in (0, 16], eta finite, steps in [0, 1000].  One kernel launch: a
  * wavefront takes each row through the normaliser and every step (forward
- * and gradient from the same exact overlaps).  Needs
+ * and gradient from the same exact overlaps; the normaliser is the flux
+ * of a second aperture in the first step's evaluation, over that step's
+ * sky).  With IPP_F_REFINE_PHOTOMETRY in p->flags that evaluation's
+ * photometry with p's aperture at the starting centre is also written to
+ * the table's flux_ap, sky, area_ap, area_ann and flags (which must then
+ * be given), equal to ipp_photometry's up to the order of binary64 sums,
+ * also when steps is 0.  Needs
  * ipp_refine_workspace_bytes of workspace (the frame descriptors; rows is
  * checked, not counted).  The launch is replayed from a captured HIP graph
  * when called again with the same signature.

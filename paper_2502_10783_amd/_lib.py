@@ -23,6 +23,8 @@ IPP_E_WORKSPACE = -5
 IPP_EST_SEXTRACTOR, IPP_EST_MEDIAN, IPP_EST_MEAN, IPP_EST_MODE = 0, 1, 2, 3
 IPP_F_WRITE_RMS = 1
 IPP_F_NO_GRAPH = 2
+IPP_F_NO_PHOTOMETRY = 4
+IPP_F_REFINE_PHOTOMETRY = 8
 IPP_TUNE_MESH = 1
 IPP_TUNE_TILE = 2
 IPP_MAP_LINEAR, IPP_MAP_LOG, IPP_MAP_EXP, IPP_MAP_POWER = 0, 1, 2, 3

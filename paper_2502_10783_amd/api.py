@@ -354,11 +354,13 @@ class Context:
     def refine_centroids(self, frames, bkg, table: SourceTable,
                          params: Params, steps: int = 10, eta: float = 3.0,
                          r_c: float = 2.0, x_out=None, y_out=None,
-                         use_count=False):
+                         use_count=False, write_photometry=False):
         """Gradient-ascent centroid refinement of the table rows (frame, x,
         y) on the frames and their background maps: returns the refined
         (x, y) float64 tensors of `capacity` rows (x_out, y_out if given;
-        they may be the table's own x and y columns)."""
+        they may be the table's own x and y columns).  write_photometry:
+        the table's photometry columns at the starting centres are written
+        too, from the first evaluation (as photometry() writes them)."""
         n = len(frames)
         maps = (L.IppMaps * n)()
         for i in range(n):
@@ -384,6 +386,8 @@ class Context:
             y_out = torch.empty(cap, dtype=torch.float64, device=dev)
         src = table.to_c(n_total=use_count)
         pc = params.to_c()
+        if write_photometry:
+            pc.flags |= L.IPP_F_REFINE_PHOTOMETRY
         self._check(self.lib.ipp_refine_centroids(
             self.h, fc, n, maps, C.byref(pc), C.byref(src), float(r_c),
             float(eta), int(steps), _ptr(x_out), _ptr(y_out), _stream()))
@@ -695,10 +699,12 @@ class Context:
 
     def process_batch(self, frames, params: Params, capacity=None,
                       table: Optional[SourceTable] = None, outputs=None,
-                      write_rms=False, masks=None):
+                      write_rms=False, masks=None, photometry=True):
         """Pipeline mode (Sec. 2.1): the whole path for a batch (masks:
         optional uint8 tensors, non-zero = pixel left out of the
-        background statistics)."""
+        background statistics).  photometry=False stops after the source
+        table (the photometry columns then come from photometry() or from
+        refine_centroids(write_photometry=True))."""
         self.ensure(frames, params)
         n = len(frames)
         dev = frames[0].device
@@ -726,6 +732,8 @@ class Context:
         p = Params(**{f.name: getattr(params, f.name) for f in fields(params)})
         if write_rms:
             p.flags |= L.IPP_F_WRITE_RMS
+        if not photometry:
+            p.flags |= L.IPP_F_NO_PHOTOMETRY
         # frame flags and diagnostics are overwritten by every call: reuse
         # the caller's buffers so repeated calls keep the same device
         # addresses (they are part of the captured graph's signature)

@@ -641,15 +641,25 @@ ipp_status run_refine(IppCtx* c, const Work& w, const ipp_params& p,
   const double ro = p.r_out + std::sqrt(2.0);
   const double ring = M_PI * (ro * ro - ri * ri) + 16.0;
   const dim3 g(grid_for(src.capacity, kWaves, 16384)), b(kBlock);
+  const bool phot = (p.flags & IPP_F_REFINE_PHOTOMETRY) != 0;
+#define IPP_REFINE(NS)                                                       \
+  do {                                                                       \
+    if (phot)                                                                \
+      IPP_LAUNCH(c, s, "k_refine",                                           \
+                 hipLaunchKernelGGL((k_refine_t<NS, true>), g, b, 0, s, w,   \
+                                    p, r_c, eta, steps, src, xo, yo));       \
+    else                                                                     \
+      IPP_LAUNCH(c, s, "k_refine",                                           \
+                 hipLaunchKernelGGL((k_refine_t<NS, false>), g, b, 0, s, w,  \
+                                    p, r_c, eta, steps, src, xo, yo));       \
+  } while (0)
   if (ring <= 256)
-    IPP_LAUNCH(c, s, "k_refine", hipLaunchKernelGGL((k_refine_t<256>), g, b,
-               0, s, w, p, r_c, eta, steps, src, xo, yo));
+    IPP_REFINE(256);
   else if (ring <= 512)
-    IPP_LAUNCH(c, s, "k_refine", hipLaunchKernelGGL((k_refine_t<512>), g, b,
-               0, s, w, p, r_c, eta, steps, src, xo, yo));
+    IPP_REFINE(512);
   else if (ring <= 1024)
-    IPP_LAUNCH(c, s, "k_refine", hipLaunchKernelGGL((k_refine_t<1024>), g, b,
-               0, s, w, p, r_c, eta, steps, src, xo, yo));
+    IPP_REFINE(1024);
+#undef IPP_REFINE
   else
     return fail(c, IPP_E_UNSUPPORTED, "aperture radii too large");
   return IPP_OK;
@@ -702,6 +712,7 @@ ipp_status run_batch(IppCtx* c, const Plan& P, const Work& w,
   if ((st = run_mesh(c, P, w, p, s)) != IPP_OK) return st;
   if ((st = run_detect(c, P, w, p, src, true, write_rms, diag, s)) != IPP_OK)
     return st;
+  if (p.flags & IPP_F_NO_PHOTOMETRY) return IPP_OK;
   return run_aperture(c, w, p, src, nullptr, s);
 }
 
@@ -1139,6 +1150,12 @@ ipp_status ipp_refine_centroids(void* ctx, const ipp_frame* frames,
                                        "eta must be finite");
   if (steps < 0 || steps > 1000)
     return fail(c, IPP_E_INVALID_ARG, "steps must be in [0, 1000]");
+  if (p && (p->flags & IPP_F_REFINE_PHOTOMETRY) &&
+      (!src->flux_ap || !src->sky || !src->area_ap || !src->area_ann ||
+       !src->flags))
+    return fail(c, IPP_E_INVALID_ARG,
+                "IPP_F_REFINE_PHOTOMETRY: flux_ap, sky, area_ap, area_ann "
+                "and flags are required");
   Plan P;
   ipp_status st = prepare(c, frames, n, p, kPlanFrames, &P);
   if (st != IPP_OK) return st;

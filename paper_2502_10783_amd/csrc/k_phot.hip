@@ -395,6 +395,7 @@ struct ApOut {
   uint32_t flags;
   double dfx, dfy;     // dF/dcx, dF/dcy (GRAD)
   double raw_x, a_x;   // raw and a_ap of the second aperture (r_x > 0)
+  uint32_t flags_x;    // flags of the second aperture's photometry
 };
 
 // With GRAD, `norm` (wave-uniform) asks for the flux sums only (raw, not
@@ -402,7 +403,7 @@ struct ApOut {
 // r_x > 0 (wave-uniform) adds the flux sums of a second aperture of that
 // radius about the same centre, over the same sky: the refinement's
 // normaliser taken in the evaluation of its first step.
-template <int NS, bool GRAD, int NC = 3>
+template <int NS, bool GRAD, int NC = 3, bool XFLAGS = false>
 __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
                                double r_ap, double cx, double cy,
                                ApLds<NS, NC>& L, const double* atan_lds,
@@ -436,6 +437,7 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   double raw = 0.0;                    // per lane: sum of v over them
   int nfull_x = 0;                     // the same for the second aperture
   double raw_x = 0.0;
+  uint64_t bad_x = 0;
   uint64_t bad_ap = 0, bad_ann = 0;    // lanes of members not ok
   W.walk<4>(lane, [&](bool live, int q, bool ok, double v, uint64_t mok,
                       uint64_t mlive) {
@@ -476,7 +478,9 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
       // the second aperture: whole pixels summed, cut ones listed with
       // the aperture's from the front
       const bool x_whole = far2 <= rx2;
-      const uint64_t m_x = mlive & mok & ballot(near2 < rx2);
+      const uint64_t m_xa = mlive & ballot(near2 < rx2);
+      if constexpr (XFLAGS) bad_x |= m_xa & ~mok;
+      const uint64_t m_x = m_xa & mok;
       const uint64_t m_xw = ballot(x_whole);
       nfull_x += __popcll(m_x & m_xw);
       if (live & ok & (near2 < rx2) & x_whole) raw_x += v;
@@ -492,6 +496,8 @@ __device__ ApOut aperture_eval(const FrameDev& fr, const ipp_params& p,
   o.flags = 0;                         // wave-uniform
   if (bad_ap) o.flags |= IPP_SRC_APERTURE_OFF_EDGE;
   if (bad_ann) o.flags |= IPP_SRC_ANNULUS_OFF_EDGE;
+  o.flags_x = (bad_x ? IPP_SRC_APERTURE_OFF_EDGE : 0u) |
+              (bad_ann ? IPP_SRC_ANNULUS_OFF_EDGE : 0u);
   wave_lds_sync();
 
   // ---- sort the annulus values ------------------------------------------
@@ -704,30 +710,43 @@ __device__ void aperture_one(const Work& wk, const ipp_params& p,
 // aperture, then `steps` ascent steps c <- c + eta g dF_rc/dc (g =
 // 1 / F_ap(c0)), each step's derivative taken with that step's sky clip
 // mask, all in this wave.  The first step's evaluation (at c0) also takes
-// the normaliser, as the flux of a second aperture over the same sky.
-// Sources with g = 0 (F_ap(c0) <= 0 or not a number) stay in place, and so
-// does a centre that leaves the valid range.
-template <int NS>
+// the normaliser, as the flux of a second aperture over the same sky; with
+// `phot` that evaluation's photometry (p's aperture at c0) is written to
+// the row as aperture_one writes it.  Sources with g = 0 (F_ap(c0) <= 0 or
+// not a number) stay in place, and so does a centre that leaves the valid
+// range.
+template <int NS, bool PHOT>
 __device__ void refine_one(const Work& wk, const ipp_params& p,
                            double r_c, double eta, int steps,
                            const ipp_sources& src, double* xo, double* yo,
                            long long row, ApLds<NS, 4>& L,
-                           const double* atan_lds) {
+                           const double* atan_lds, void* const* cols) {
   int lane = threadIdx.x & (kWave - 1);
   asm volatile("" : "+v"(lane));
   const int f = src.frame[row];
   double cx = src.x[row], cy = src.y[row];
   if ((f >= 0 && f < wk.nframes) && centre_ok(cx, cy)) {
     const FrameDev fr = wk.frames[f];   // f is wave-uniform: SGPRs
-    // one call site, so that the photometry is inlined once
+    // one call site, so that the photometry is inlined once; with phot
+    // and no steps the first evaluation is still taken
     double g = 0.0;
-    for (int k = 0; k < steps; ++k) {
-      const ApOut o = aperture_eval<NS, true, 4>(fr, p, r_c, cx, cy, L,
-                                                 atan_lds, lane, false,
-                                                 k == 0 ? p.r_ap : 0.0);
+    const int nev = steps > 0 ? steps : (PHOT ? 1 : 0);
+    for (int k = 0; k < nev; ++k) {
+      const ApOut o = aperture_eval<NS, true, 4, PHOT>(
+          fr, p, r_c, cx, cy, L, atan_lds, lane, false,
+          k == 0 ? p.r_ap : 0.0);
       if (k == 0) {
         const double sky0 = o.den > 0.0 ? o.num / o.den : 0.0;
         const double F0 = o.raw_x - sky0 * o.a_x;
+        if (PHOT && lane == 0) {
+          ((double*)cols[0])[row] = F0;
+          ((double*)cols[1])[row] = sky0;
+          ((double*)cols[2])[row] = o.a_x;
+          ((double*)cols[3])[row] = o.den;
+          ((uint32_t*)cols[4])[row] |=
+              o.flags_x | (o.den > 0.0 ? 0u : IPP_SRC_NO_SKY);
+        }
+        if (k == steps) break;
         g = F0 > 0.0 ? 1.0 / F0 : 0.0;
         if (g == 0.0) break;
       }
@@ -736,6 +755,12 @@ __device__ void refine_one(const Work& wk, const ipp_params& p,
       cy = cy + eta * dy;
       if (!centre_ok(cx, cy)) break;
     }
+  } else if (PHOT && lane == 0) {
+    ((double*)cols[0])[row] = __builtin_nan("");
+    ((double*)cols[1])[row] = __builtin_nan("");
+    ((double*)cols[2])[row] = 0.0;
+    ((double*)cols[3])[row] = 0.0;
+    ((uint32_t*)cols[4])[row] |= IPP_SRC_APERTURE_OFF_EDGE | IPP_SRC_NO_SKY;
   }
   if (lane == 0) {
     xo[row] = cx;
@@ -768,15 +793,28 @@ __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 4 : 1))) void k_aperture_t(
     aperture_one<NS>(wk, p, src, sky_lohi, row, mine, atan_lds);
 }
 
-// Centroid refinement: one wavefront per row, every step in the wave.
-template <int NS>
+// Centroid refinement: one wavefront per row, every step in the wave
+// (PHOT: the photometry of the first evaluation is written too; a
+// variant of its own, so that the plain refinement keeps its registers).
+template <int NS, bool PHOT>
 __global__ __launch_bounds__(kBlock)
 __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_refine_t(
     Work wk, ipp_params p, double r_c, double eta, int steps,
     ipp_sources src, double* xo, double* yo) {
   __shared__ ApLds<NS, 4> L[kWaves];
   __shared__ double atan_lds[kAtanTerms];
+  // the photometry columns' addresses, read from LDS where they are
+  // written: kept in scalar registers across the row loop they would push
+  // the kernel's scalar registers into spills
+  __shared__ void* cols[5];
   if (threadIdx.x < kAtanTerms) atan_lds[threadIdx.x] = atan_coef(threadIdx.x);
+  if (PHOT && threadIdx.x == 0) {
+    cols[0] = src.flux_ap;
+    cols[1] = src.sky;
+    cols[2] = src.area_ap;
+    cols[3] = src.area_ann;
+    cols[4] = src.flags;
+  }
   __syncthreads();
   long long nrows = src.capacity;
   if (src.n_total && *src.n_total < nrows) nrows = *src.n_total;
@@ -786,16 +824,22 @@ __attribute__((amdgpu_waves_per_eu(NS <= 512 ? 3 : 1))) void k_refine_t(
   const long long nw = (long long)gridDim.x * kWaves;
   ApLds<NS, 4>& mine = L[threadIdx.x / kWave];
   for (long long row = wid; row < nrows; row += nw)
-    refine_one<NS>(wk, p, r_c, eta, steps, src, xo, yo, row, mine, atan_lds);
+    refine_one<NS, PHOT>(wk, p, r_c, eta, steps, src, xo, yo, row, mine,
+                         atan_lds, cols);
 }
 
-template __global__ void k_refine_t<256>(Work, ipp_params, double, double,
-                                         int, ipp_sources, double*, double*);
-template __global__ void k_refine_t<512>(Work, ipp_params, double, double,
-                                         int, ipp_sources, double*, double*);
-template __global__ void k_refine_t<1024>(Work, ipp_params, double, double,
-                                          int, ipp_sources, double*, double*);
-
+template __global__ void k_refine_t<256, false>(Work, ipp_params, double,
+    double, int, ipp_sources, double*, double*);
+template __global__ void k_refine_t<256, true>(Work, ipp_params, double,
+    double, int, ipp_sources, double*, double*);
+template __global__ void k_refine_t<512, false>(Work, ipp_params, double,
+    double, int, ipp_sources, double*, double*);
+template __global__ void k_refine_t<512, true>(Work, ipp_params, double,
+    double, int, ipp_sources, double*, double*);
+template __global__ void k_refine_t<1024, false>(Work, ipp_params, double,
+    double, int, ipp_sources, double*, double*);
+template __global__ void k_refine_t<1024, true>(Work, ipp_params, double,
+    double, int, ipp_sources, double*, double*);
 template __global__ void k_aperture_t<256>(Work, ipp_params, ipp_sources,
                                            double*);
 template __global__ void k_aperture_t<512>(Work, ipp_params, ipp_sources,

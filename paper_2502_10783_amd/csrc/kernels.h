@@ -55,8 +55,9 @@ __global__ void k_aperture_bwd_t(Work wk, ipp_params p, ipp_sources src,
                                  double* dxy);
 
 // Centroid refinement, every step of a row in one wavefront: xo, yo get
-// the refined centres.  Rows: min(capacity, *n_total).
-template <int NS>
+// the refined centres; PHOT: the photometry columns of the first
+// evaluation as well.  Rows: min(capacity, *n_total).
+template <int NS, bool PHOT>
 __global__ void k_refine_t(Work wk, ipp_params p, double r_c, double eta,
                            int steps, ipp_sources src, double* xo,
                            double* yo);
