@@ -297,7 +297,8 @@ ipp_status ipp_photometry_backward(void* ctx, const ipp_frame* frames,
  * ipp_photometry_backward with each step's annulus clip mask held fixed.
  * Rows with F_ap(c0) <= 0 (or not a number) stay where they are.
  * x_out, y_out: device double[capacity], the refined centres (they may be
- * src->x and src->y themselves); the table's other columns are untouched.
+ * src->x and src->y themselves); the table's other columns are untouched
+ * unless IPP_F_REFINE_PHOTOMETRY is set (below).
  * r_c in (0, 16], eta finite, steps in [0, 1000].  One kernel launch: a
  * wavefront takes each row through the normaliser and every step (forward
  * and gradient from the same exact overlaps; the normaliser is the flux
