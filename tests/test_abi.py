@@ -154,3 +154,20 @@ def test_deblend_kron_refine_host_checks(lib):
     assert lib.ipp_asinh_backward_noalloc(None, None, None, None, None, 0,
                                           1.0, 1.0,
                                           None) == L.IPP_E_INVALID_ARG
+
+
+def test_binding_constants_match_the_header():
+    """Every IPP_ macro of include/ipp.h with a plain integer value that the
+    binding also names has the same value there (flags, per-source and
+    per-frame bits)."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include",
+                            "ipp.h")).read()
+    seen = 0
+    for name, val in re.findall(r"#define\s+(IPP_\w+)\s+(\d+)u?\b", hdr):
+        if hasattr(L, name):
+            assert getattr(L, name) == int(val), name
+            seen += 1
+    assert L.IPP_F_NO_PHOTOMETRY == 4 and L.IPP_F_REFINE_PHOTOMETRY == 8
+    assert seen >= 4
