@@ -975,7 +975,7 @@ def main():
                          "(a kernel of known traffic, to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single "
+        print("bench.py measures one GPU: the library runs on a single "
               "MI355X and has no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)

@@ -31,7 +31,7 @@ Intelligence Era"):
 * ``gray``       -- Sec. 2.2.6: the zscale display range, linear /
   logarithmic / exponential / power-law maps and histogram equalization.
 * ``refine``     -- gradient-ascent centroid refinement on the photometry
-  adjoint (this build's addition).
+  adjoint (an addition to the paper's method).
 
 Where the paper leaves a step open, the reading taken is stated in the
 docstring of the function that implements it.  Every floating-point value is

@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper's photometry measures each object at its detected position
-(Sec. 2.2.5); this build adds a differentiable photometry so positions can
-be refined by gradients.  The rule (this build's reading; the paper has
+(Sec. 2.2.5); this library adds a differentiable photometry so positions can
+be refined by gradients.  The rule (this library's reading; the paper has
 none): maximise J(c) = F_rc(c) / F_ap(c0), the sky-subtracted flux in an
 aperture of radius r_c (default 2 px) normalised by the flux in the default
 aperture at the starting point, by `steps` plain ascent steps
